@@ -1,0 +1,105 @@
+"""Planted mistakes: each mutation of the oracle source must make some pin fail.
+
+The mutated copy is compiled into a temporary directory on the CPU; the oracle
+source itself is never modified.
+"""
+import os
+import tempfile
+
+import pytest
+
+import oracle
+import test_oracle_pins as P
+
+MUTATIONS = [
+    ("getrf update sign",
+     "for (int i = j + 1; i < n; ++i) EL(A, lda, i, c) -= EL(A, lda, i, j) * u;",
+     "for (int i = j + 1; i < n; ++i) EL(A, lda, i, c) += EL(A, lda, i, j) * u;",
+     [P.test_getrf_matches_lapack]),
+    ("fig4 line 13 and->or",
+     "if (delta > tol && delta > tol * fmax",
+     "if (delta > tol || delta > tol * fmax",
+     [P.test_likely_sympd_conditions]),
+    ("fig4 line 15 >= -> >",
+     "if (fabs(a_ij) >= max_diag) return 0;",
+     "if (fabs(a_ij) > max_diag) return 0;",
+     [P.test_likely_sympd_conditions]),
+    ("fig4 line 15 tests the upper element",
+     "if (fabs(a_ij) >= max_diag) return 0;",
+     "if (fabs(a_ji) >= max_diag) return 0;",
+     [P.test_likely_sympd_conditions]),
+    ("fig4 line 16 >= -> >",
+     "if ((fabs(a_ij) + fabs(a_ji)) >= (EL(A, lda, i, i) + EL(A, lda, j, j))) return 0;",
+     "if ((fabs(a_ij) + fabs(a_ji)) > (EL(A, lda, i, i) + EL(A, lda, j, j))) return 0;",
+     [P.test_likely_sympd_conditions]),
+    ("band scan off by one",
+     "if (last >= 0 && last - j > kl) kl = last - j;\n  }\n  *kl_out",
+     "if (last >= 0 && last - j > kl) kl = last - j + 1;\n  }\n  *kl_out",
+     [P.test_band_scan_all_4x4_patterns]),
+    ("25% rule equality",
+     "return 4 * nnz <= n * n;",
+     "return 4 * nnz < n * n;",
+     [P.test_band_rule_counts_positions_exactly]),
+    ("trsv transposed operand",
+     "  if (lower_system) {\n    for (int i = 0; i < n; ++i) {\n      double s = x[i];\n      for (int j = 0; j < i; ++j) {\n        const double a = trans ? EL(T, ldt, j, i) : EL(T, ldt, i, j);",
+     "  if (lower_system) {\n    for (int i = 0; i < n; ++i) {\n      double s = x[i];\n      for (int j = 0; j < i; ++j) {\n        const double a = trans ? EL(T, ldt, i, j) : EL(T, ldt, j, i);",
+     [P.test_trsv_matches_lapack]),
+    ("potrf skips the diagonal update",
+     "for (int i = c; i < n; ++i) EL(A, lda, i, c) -= EL(A, lda, i, j) * l_cj;",
+     "for (int i = c + 1; i < n; ++i) EL(A, lda, i, c) -= EL(A, lda, i, j) * l_cj;",
+     [P.test_potrf_matches_lapack_and_failure_column]),
+    ("gbtrf fill extent too short",
+     "const int ju = imin(n - 1, j + kl + ku);",
+     "const int ju = imin(n - 1, j + ku);",
+     [P.test_band_lu_equals_dense_lu]),
+    ("estimator uses inv(A) where inv(A)^T is due",
+     "  apply(ctx, 2, x); ++ns;\n  {\n    int j = iamax(n, x);",
+     "  apply(ctx, 1, x); ++ns;\n  {\n    int j = iamax(n, x);",
+     [P.test_rcond_against_lapack_estimators]),
+    ("rcond drops the matrix norm",
+     "return (1.0 / ainvnm) / anorm;",
+     "return (1.0 / ainvnm);",
+     [P.test_rcond_is_lower_bound_and_close]),
+    ("getrs transposed solves in the wrong order",
+     "      orc_trsv(1, 1, 0, n, LU, lda, b);\n      orc_trsv(0, 1, 1, n, LU, lda, b);",
+     "      orc_trsv(0, 1, 1, n, LU, lda, b);\n      orc_trsv(1, 1, 0, n, LU, lda, b);",
+     [P.test_getrf_matches_lapack]),
+    ("jacobi rotation sign",
+     "EL(U, ldu, i, p) = c * up - s * uq;",
+     "EL(U, ldu, i, p) = c * up + s * uq;",
+     [P.test_jacobi_prescribed_singular_values]),
+    ("svd truncation level",
+     "const double cut = ORC_EPS * smax;",
+     "const double cut = 1e-3 * smax;",
+     [P.test_svd_lstsq_min_norm_matches_lapack]),
+    ("rule <= instead of <",
+     "  if (failed) res->fallback = 1;\n  else if (res->rcond != res->rcond) res->fallback = 3;\n  else if (res->rcond < thr) res->fallback = 2;\n  if (res->fallback) {\n    if (no_approx) {",
+     "  if (failed) res->fallback = 1;\n  else if (res->rcond != res->rcond) res->fallback = 3;\n  else if (res->rcond <= thr) res->fallback = 2;\n  if (res->fallback) {\n    if (no_approx) {",
+     [P.test_rule_threshold_is_half_eps]),
+    ("berr drops ||b||",
+     "    const double den = anorm_inf * xn + bn;\n    const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);\n    if (per_rhs)",
+     "    const double den = anorm_inf * xn;\n    const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);\n    if (per_rhs)",
+     [P.test_berr_definition]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pins", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, old, new, pins):
+    src = open(oracle.SRC_PATH).read()
+    assert src.count(old) == 1, f"mutation anchor not unique: {name}"
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "mut.c")
+        with open(path, "w") as f:
+            f.write(src.replace(old, new))
+        hdr = os.path.join(os.path.dirname(oracle.SRC_PATH), "ada_oracle.h")
+        with open(os.path.join(d, "ada_oracle.h"), "w") as f:
+            f.write(open(hdr).read())
+        so = oracle.build(src=path, out=os.path.join(d, "libmut.so"))
+        mutant = oracle.Oracle(so)
+        caught = False
+        for pin in pins:
+            try:
+                pin(o=mutant)
+            except (AssertionError, Exception):
+                caught = True
+        assert caught, f"no pin caught the planted mistake: {name}"
