@@ -1,0 +1,134 @@
+/*
+ * ada.h -- C ABI of libada, an MI355X (gfx950) implementation of the adaptive
+ * solver for square systems A X = B of Sanderson & Curtin, "An Adaptive Solver
+ * for Systems of Linear Equations" (arXiv 2007.11208).
+ *
+ * What a solve computes (Section II of the paper):
+ *   1. detection, in this order: banded (Section II-A: band widths from a
+ *      column scan; banded when the band holds at most 25% of the n*n
+ *      elements), upper or lower triangular (Section II-B), likely symmetric
+ *      positive definite (Section II-C, Fig. 4); otherwise general;
+ *   2. the matching factorise-and-solve: banded LU with partial pivoting,
+ *      triangular substitution, Cholesky (whose failure re-routes to LU), or
+ *      LU with partial pivoting (Section II-D);
+ *   3. the reciprocal condition number (1-norm) of the routed factorisation;
+ *   4. when a solver fails or rcond < threshold (default 0.5*eps, Section II-E)
+ *      the minimum-norm least-squares solution from an SVD of the original A
+ *      (here a one-sided Jacobi SVD), unless disabled.
+ *
+ * Conventions common to every entry point:
+ *   - matrices are column-major FP64 in DEVICE memory owned by the caller;
+ *     element (i,j) of a matrix with leading dimension ld is at M[i + j*ld];
+ *   - A and B are never modified; X may not alias A or B;
+ *   - the library never allocates device memory inside a solve: every scratch
+ *     buffer comes from the caller's `work` area (size from ada_workspace_size);
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream); all
+ *     device work is ordered on it. ada_solve blocks until its result is known;
+ *   - return value: ADA_OK (0) or a negative ADA_ERR_* code; on error
+ *     ada_last_error() names the cause (thread-local text);
+ *   - a context may be shared by threads; a workspace or stream may not be
+ *     shared by concurrent calls.
+ */
+#ifndef ADA_H
+#define ADA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ADA_ABI_VERSION 1
+
+/* return codes */
+enum {
+  ADA_OK = 0,
+  ADA_ERR_ARG = -1,                  /* bad n/nrhs/ld/layout/workspace, NULL pointer */
+  ADA_ERR_NONFINITE = -2,            /* A or B holds NaN or Inf (rejected before any solve) */
+  ADA_ERR_SINGULAR = -3,             /* fallback needed but opts.no_approx = 1; X holds the routed x */
+  ADA_ERR_NOMEM = -4,                /* host allocation failed */
+  ADA_ERR_HIP = -5,                  /* a HIP runtime call failed, or a device wait timed out */
+  ADA_ERR_FALLBACK_INFEASIBLE = -6   /* SVD fallback of a band-layout system too large to expand */
+};
+
+/* detected structure (Section II detection order; bit-exact with the definition) */
+enum { ADA_CLASS_GENERAL = 0, ADA_CLASS_BANDED = 1, ADA_CLASS_TRI_UPPER = 2, ADA_CLASS_TRI_LOWER = 3,
+       ADA_CLASS_SYMPD = 4 };
+/* solver whose x is returned */
+enum { ADA_ROUTE_NONE = 0, ADA_ROUTE_BAND_LU = 1, ADA_ROUTE_TRI = 2, ADA_ROUTE_CHOL = 3, ADA_ROUTE_LU = 4,
+       ADA_ROUTE_SVD = 5 };
+/* input layout */
+enum { ADA_LAYOUT_DENSE = 0, ADA_LAYOUT_BAND = 1 };
+/* why the SVD fallback ran (Section II-E): */
+enum { ADA_FALLBACK_NONE = 0, ADA_FALLBACK_FAILURE = 1, ADA_FALLBACK_RCOND = 2, ADA_FALLBACK_RCOND_NAN = 3 };
+
+typedef struct ada_ctx_s* ada_ctx;
+
+typedef struct {
+  uint32_t struct_size;     /* = sizeof(ada_opts); lets the ABI grow */
+  int32_t no_approx;        /* 1: never run the SVD fallback (the optional argument of Section II-E);
+                               the call then returns ADA_ERR_SINGULAR when the fallback is due */
+  double rcond_threshold;   /* fallback when rcond < this; a negative value selects 0.5*eps */
+  int32_t layout;           /* ADA_LAYOUT_DENSE, or ADA_LAYOUT_BAND: A holds LAPACK band storage,
+                               A[ku_in + i - j + j*lda] = A(i,j) for max(0,j-ku_in) <= i <= min(n-1,j+kl_in),
+                               lda >= kl_in+ku_in+1; entries outside the stored band are zero */
+  int32_t kl_in, ku_in;     /* stored band widths for ADA_LAYOUT_BAND */
+  int32_t force_general;    /* 1: skip detection, always LU (the paper's "standard" solver, Section III) */
+  int32_t want_berr;        /* 1: compute result.berr (normwise backward error) on the device */
+} ada_opts;
+
+typedef struct {
+  int32_t cls;              /* ADA_CLASS_*; GENERAL when force_general */
+  int32_t kl, ku;           /* exact band widths of A (-1 when detection was skipped) */
+  int32_t route;            /* ADA_ROUTE_* of the returned x */
+  int32_t chol_failed;      /* 1 when Cholesky failed and the system was re-solved by LU */
+  int32_t fallback;         /* ADA_FALLBACK_* */
+  int32_t info;             /* 1-based column of the first zero pivot / zero diagonal / failed Cholesky pivot */
+  int32_t rank;             /* SVD route: number of singular values > eps*sigma_max; else n */
+  int32_t sweeps;           /* SVD route: Jacobi sweeps */
+  int32_t nsolves;          /* solves spent by the condition estimate */
+  int32_t refine_iters;     /* reserved (0) */
+  int32_t pad;
+  double rcond;             /* reciprocal 1-norm condition estimate of the routed factorisation; NaN if none */
+  double berr;              /* max over columns of ||b-Ax||_inf / (||A||_inf ||x||_inf + ||b||_inf); NaN unless want_berr */
+} ada_result;
+
+/* Create a context bound to HIP device `device` (loads nothing else; cheap).
+ * Returns ADA_OK or ADA_ERR_HIP / ADA_ERR_NOMEM. */
+int ada_create(ada_ctx* out, int device);
+void ada_destroy(ada_ctx ctx);
+
+/* Thread-local description of the last error returned on this thread ("" if none). */
+const char* ada_last_error(void);
+
+/* Fill opts with the defaults (threshold 0.5*eps, dense layout, berr on). */
+void ada_opts_default(ada_opts* opts);
+
+/* Bytes of device workspace ada_solve needs for this shape and these options
+ * (opts NULL = defaults). Returns 0 for invalid arguments. Pure host function. */
+size_t ada_workspace_size(int n, int nrhs, const ada_opts* opts);
+
+/* Adaptive solve of A X = B (Section II): detection, routed factorisation and
+ * solve, condition estimate, SVD least-squares fallback.
+ *   n >= 1, nrhs >= 1; A: device, lda >= n (dense) or per opts.layout;
+ *   B: device n x nrhs, ldb >= n; X: device n x nrhs, ldx >= n (output);
+ *   work: device, >= ada_workspace_size(n, nrhs, opts) bytes, 256-byte aligned;
+ *   result: host pointer, filled on ADA_OK and on ADA_ERR_SINGULAR;
+ *   stream: hipStream_t or NULL.
+ * Blocking: returns after the result is known (X is complete on `stream`). */
+int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
+              int ldx, void* work, size_t work_bytes, const ada_opts* opts, ada_result* result, void* stream);
+
+/* ---- instrumentation (not part of the method) ----
+ * When enabled, the library records HIP events around every launch of the
+ * dense trailing-update kernel (the FP64 MFMA GEMM) and accumulates its launch
+ * count, total device time and algorithmic flops. */
+int ada_profile_enable(ada_ctx ctx, int on);
+int ada_profile_read(ada_ctx ctx, int64_t* launches, double* total_ms, double* total_flops);
+int ada_profile_reset(ada_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADA_H */

@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libada (the C ABI in include/ada.h).
+
+Argument marshalling only: tensors are checked, laid out column-major, given a
+workspace from PyTorch's caching allocator and handed to ``ada_solve`` with the
+current HIP stream. Every step of the solve runs in the library's kernels.
+Importing this module does not load the library; the first call does, and it
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libada.so")
+
+OK, ERR_ARG, ERR_NONFINITE, ERR_SINGULAR, ERR_NOMEM, ERR_HIP, ERR_FALLBACK_INFEASIBLE = 0, -1, -2, -3, -4, -5, -6
+CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD = 0, 1, 2, 3, 4
+ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD = 0, 1, 2, 3, 4, 5
+LAYOUT_DENSE, LAYOUT_BAND = 0, 1
+CLASS_NAMES = {0: "general", 1: "banded", 2: "tri_upper", 3: "tri_lower", 4: "sympd"}
+ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("no_approx", ctypes.c_int32),
+                ("rcond_threshold", ctypes.c_double), ("layout", ctypes.c_int32),
+                ("kl_in", ctypes.c_int32), ("ku_in", ctypes.c_int32), ("force_general", ctypes.c_int32),
+                ("want_berr", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("cls", ctypes.c_int32), ("kl", ctypes.c_int32), ("ku", ctypes.c_int32),
+                ("route", ctypes.c_int32), ("chol_failed", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("info", ctypes.c_int32), ("rank", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("nsolves", ctypes.c_int32), ("refine_iters", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rcond", ctypes.c_double), ("berr", ctypes.c_double)]
+
+
+class AdaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ada error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libada.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        L.ada_create.argtypes = [ctypes.POINTER(vp), i]
+        L.ada_create.restype = i
+        L.ada_destroy.argtypes = [vp]
+        L.ada_destroy.restype = None
+        L.ada_last_error.argtypes = []
+        L.ada_last_error.restype = ctypes.c_char_p
+        L.ada_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        L.ada_opts_default.restype = None
+        L.ada_workspace_size.argtypes = [i, i, ctypes.POINTER(Opts)]
+        L.ada_workspace_size.restype = sz
+        L.ada_solve.argtypes = [vp, i, i, vp, i, vp, i, vp, i, vp, sz, ctypes.POINTER(Opts), ctypes.POINTER(Result), vp]
+        L.ada_solve.restype = i
+        L.ada_profile_enable.argtypes = [vp, i]
+        L.ada_profile_enable.restype = i
+        L.ada_profile_reset.argtypes = [vp]
+        L.ada_profile_reset.restype = i
+        L.ada_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.ada_profile_read.restype = i
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().ada_last_error().decode(errors="replace")
+
+
+def make_opts(no_approx=False, rcond_threshold=-1.0, layout=LAYOUT_DENSE, kl_in=0, ku_in=0, force_general=False,
+              want_berr=True) -> Opts:
+    o = Opts()
+    lib().ada_opts_default(ctypes.byref(o))
+    o.no_approx = int(no_approx)
+    o.rcond_threshold = float(rcond_threshold)
+    o.layout = int(layout)
+    o.kl_in = int(kl_in)
+    o.ku_in = int(ku_in)
+    o.force_general = int(force_general)
+    o.want_berr = int(want_berr)
+    return o
+
+
+def workspace_size(n: int, nrhs: int, opts: Opts | None = None) -> int:
+    return int(lib().ada_workspace_size(n, nrhs, ctypes.byref(opts) if opts is not None else None))
+
+
+class Context:
+    """Owns an ada_ctx bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib().ada_create(ctypes.byref(h), int(device))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().ada_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, on: bool = True):
+        lib().ada_profile_enable(self.handle, int(on))
+
+    def profile_reset(self):
+        lib().ada_profile_reset(self.handle)
+
+    def profile_read(self):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        fl = ctypes.c_double()
+        lib().ada_profile_read(self.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl))
+        return n.value, ms.value, fl.value
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    c = _contexts.get(device)
+    if c is None:
+        c = Context(device)
+        _contexts[device] = c
+    return c
+
+
+def _colmajor(t):
+    """A column-major view of a 2-D tensor (copies only when needed)."""
+    import torch
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    if t.dtype != torch.float64:
+        raise TypeError("ada works on float64 tensors")
+    if t.shape[1] == 1:
+        return t if t.stride(0) == 1 else t.contiguous()
+    if t.stride(0) == 1 and t.stride(1) >= max(1, t.shape[0]):
+        return t
+    return t.t().contiguous().t()
+
+
+def _ld(t) -> int:
+    """Leading dimension of a column-major 2-D tensor (a single column has ld = rows)."""
+    return t.stride(1) if t.shape[1] > 1 else max(1, t.shape[0])
+
+
+@dataclass
+class SolveResult:
+    cls: str
+    kl: int
+    ku: int
+    route: str
+    chol_failed: bool
+    fallback: int
+    info: int
+    rank: int
+    sweeps: int
+    nsolves: int
+    rcond: float
+    berr: float
+    status: int = OK
+
+
+def _result(r: Result, status: int) -> SolveResult:
+    return SolveResult(CLASS_NAMES.get(r.cls, str(r.cls)), r.kl, r.ku, ROUTE_NAMES.get(r.route, str(r.route)),
+                       bool(r.chol_failed), r.fallback, r.info, r.rank, r.sweeps, r.nsolves, r.rcond, r.berr, status)
+
+
+def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, want_berr=True, layout="dense",
+          kl_in=0, ku_in=0, out=None, work=None, ctx: Context | None = None, raise_on_error=True):
+    """Adaptive solve of A X = B on the GPU.
+
+    A: (n, n) float64 CUDA tensor, or for layout="band" the (kl_in+ku_in+1, n)
+    LAPACK band storage (A[ku_in+i-j, j] = A(i, j)). B: (n,) or (n, nrhs).
+    Returns (X, SolveResult). On ERR_SINGULAR (no_approx) X holds the routed
+    solution and the result says why the fallback was due.
+    """
+    import torch
+    dev = A.device
+    if dev.type != "cuda":
+        raise ValueError("A must be a CUDA tensor")
+    vec = B.dim() == 1
+    Ac = _colmajor(A)
+    Bc = _colmajor(B)
+    n = Bc.shape[0]
+    nrhs = Bc.shape[1]
+    lay = LAYOUT_BAND if layout == "band" else LAYOUT_DENSE
+    if lay == LAYOUT_DENSE and (Ac.shape[0] != Ac.shape[1] or Ac.shape[0] != n):
+        raise ValueError("A must be n x n and match B")
+    if lay == LAYOUT_BAND and Ac.shape[1] != n:
+        raise ValueError("band storage must have n columns")
+    opts = make_opts(no_approx, rcond_threshold, lay, kl_in, ku_in, force_general, want_berr)
+    ws = workspace_size(n, nrhs, opts)
+    if ws == 0:
+        raise ValueError("invalid shape for the workspace query")
+    if work is None or work.numel() < ws:
+        work = torch.empty(ws, dtype=torch.uint8, device=dev)
+    if out is None:
+        X = torch.empty((nrhs, n), dtype=torch.float64, device=dev).t()
+    else:
+        X = out
+    c = ctx or context(dev.index or 0)
+    res = Result()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().ada_solve(c.handle, n, nrhs, Ac.data_ptr(), _ld(Ac), Bc.data_ptr(), _ld(Bc),
+                         X.data_ptr(), _ld(X), work.data_ptr(), work.numel(), ctypes.byref(opts),
+                         ctypes.byref(res), ctypes.c_void_p(stream))
+    if rc not in (OK, ERR_SINGULAR):
+        if raise_on_error:
+            raise AdaError(rc, last_error())
+        return None, SolveResult("", -1, -1, "none", False, 0, 0, 0, 0, 0, math.nan, math.nan, rc)
+    out_x = X[:, 0] if vec else X
+    return out_x, _result(res, rc)

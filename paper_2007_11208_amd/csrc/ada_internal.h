@@ -1,0 +1,212 @@
+// Internal declarations of libada (HIP, gfx950). Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace ada {
+
+constexpr double kEps = 2.220446049250313080847e-16;  // 2^-52, gap between 1 and the next double
+constexpr int kWave = 64;
+constexpr long kSpinLimit = 1L << 22;  // bounded waits: every spinning wave eventually exits
+
+// Device-side record of one solve. Lives at the start of the workspace.
+struct DevRec {
+  // ---- detection (one pass over A) ----
+  int kl, ku;                 // exact band widths (atomicMax)
+  int nonfinite;              // any NaN/Inf in A or B
+  int sym_bad;                // a pair violated Fig. 4 line 13 or line 16
+  int diag_nonpos;            // some A_jj <= 0 (Fig. 4 line 8)
+  int diag_zero_first;        // first j with A_jj == 0, +1 (INT_MAX if none)
+  unsigned long long max_diag_bits;   // max diagonal entry (bit pattern; valid when all > 0)
+  unsigned long long max_lower_bits;  // max |A_ij|, i > j (bit pattern of a non-negative double)
+  // ---- factorisation ----
+  int info;                   // first failing pivot column, 1-based (INT_MAX if none)
+  int chol_info;              // Cholesky failure column (INT_MAX if none)
+  int stop;                   // 1 once the routed factorisation has failed: later kernels skip their work
+  int timeout;                // a bounded device wait gave up
+  // ---- condition estimate (state machine of Hager/Higham) ----
+  int est_phase;              // 0 done, 1 = inv(A) solve due, 2 = inv(A)^T solve due
+  int est_stage;              // position in the algorithm
+  int est_iter;               // iteration counter (starts at 2 after the first transposed solve)
+  int est_j;                  // current unit-vector index
+  int est_nsolves;
+  int pad0;
+  double est;                 // current estimate of ||inv(A)||_1
+  double anorm1;              // ||A||_1 of the routed matrix
+  double anorm_inf;           // ||A||_inf (backward error)
+  double rcond;
+  // ---- result ----
+  int x_nonfinite;
+  int rank;
+  double berr;
+  double sigma_max;
+  int jacobi_rotated;         // a rotation happened in the current sweep
+  int sweeps;                 // Jacobi sweeps used
+  // ---- synchronisation counters (zeroed per solve) ----
+  unsigned int counters[512];  // grid barriers / tickets, one per launch that needs one
+};
+
+// Raise a kernel's dynamic-LDS limit when a launch needs more than the default
+// 64 KB (static LDS counts against the same 160 KB). `done` caches the largest
+// value already granted for that kernel.
+inline hipError_t ensure_lds(const void* fn, size_t bytes, size_t& done) {
+  if (bytes <= 65536 || bytes <= done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done = bytes;
+  else (void)hipGetLastError();
+  return e;
+}
+
+// Size-class helpers
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// -------- device helpers --------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+// argmax of |v| with ties to the lowest index (the IxAMAX convention); idx < 0 marks "no candidate"
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    double v2 = __shfl_xor(v, o, 64);
+    int i2 = __shfl_xor(idx, o, 64);
+    bool take = (i2 >= 0) && (idx < 0 || v2 > v || (v2 == v && i2 < idx));
+    if (take) { v = v2; idx = i2; }
+  }
+}
+
+__device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+__device__ __forceinline__ unsigned agent_load(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int agent_load(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double relaxed_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void relaxed_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns hipGetLastError().
+
+// detection
+hipError_t launch_fill_int(int* p, int v, size_t count, hipStream_t st);
+hipError_t launch_init_rec(DevRec* rec, hipStream_t st);
+hipError_t launch_detect_dense(int n, const double* A, int lda, DevRec* rec, double* pcol, double* prow,
+                               double* col_lo_diag, double* row_lo_diag, double* diag, hipStream_t st);
+hipError_t launch_check_finite(int rows, int cols, const double* M, int ld, DevRec* rec, hipStream_t st);
+hipError_t launch_norms_reduce(int n, const double* pcol, const double* prow, const double* col_lo_diag,
+                               const double* row_lo_diag, double* col_total, double* col_sym, double* row_total,
+                               hipStream_t st);
+// mode: 0 general (max col_total), 1 symmetric from the lower triangle (max col_sym); also sets anorm_inf
+hipError_t launch_anorm(int n, const double* col_total, const double* col_sym, const double* row_total, int mode,
+                        DevRec* rec, hipStream_t st);
+hipError_t launch_detect_band(int n, int kl_in, int ku_in, const double* AB, int ldab, DevRec* rec,
+                              hipStream_t st);
+
+// dense copies and permutations
+hipError_t launch_copy(int rows, int cols, const double* S, int lds, double* D, int ldd, hipStream_t st);
+hipError_t launch_iota(int* p, int n, hipStream_t st);
+hipError_t launch_gather_rows(int n, int nrhs, const int* perm, const double* S, int lds, double* D, int ldd,
+                              const int* pred, int pred_val, hipStream_t st);
+hipError_t launch_scatter_rows(int n, int nrhs, const int* perm, const double* S, int lds, double* D, int ldd,
+                               const int* pred, int pred_val, hipStream_t st);
+
+// FP64 MFMA GEMM: C -= A * op(B); op(B) = B (k x n) or B^T (B is n x k); lower: only tiles meeting i >= j
+hipError_t launch_gemm_sub(int m, int n, int k, const double* A, int lda, const double* B, int ldb, bool transB,
+                           double* C, int ldc, bool lower, const int* skip_if_nonzero, hipStream_t st,
+                           hipEvent_t ev0, hipEvent_t ev1);
+
+// LU
+struct PanelScratch {
+  double* slot_val;   // [2][64]
+  int* slot_row;      // [2][64]
+  double* slot_rows;  // [2][64][128]
+  double* diag_rows;  // [2][128]
+  int* moves;         // [2*128+1]: count, then (dst,src) pairs
+};
+hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec,
+                              unsigned* counter, PanelScratch ps, hipStream_t st);
+hipError_t launch_laswp_moves(int n, int k0, int nbw, double* W, int ldw, const int* moves, int* perm,
+                              DevRec* rec, hipStream_t st);
+hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st);
+
+// Cholesky
+hipError_t launch_potrf_diag(int k0, int nbw, double* W, int ldw, DevRec* rec, hipStream_t st);
+hipError_t launch_trsm_rltn(int k0, int nbw, int mrows, double* W, int ldw, const DevRec* rec, hipStream_t st);
+
+// triangular solve, decoupled blocks. Solves op(T) X = X in place, T n x n (ldt).
+//  lower: T is lower triangular (else upper); trans: use T^T; unit: implicit unit diagonal.
+//  flags: >= ceil(n/64) ints, epoch: value that marks a finished block in this launch;
+//  ticket: a zeroed counter; pred/pred_val: run only when *pred == pred_val (pred may be NULL).
+hipError_t launch_trsm_dec(int n, int nrhs, const double* T, int ldt, bool lower, bool trans, bool unit, double* X,
+                           int ldx, int* flags, int epoch, unsigned* ticket, DevRec* rec, const int* pred,
+                           int pred_val, hipStream_t st);
+
+// band
+hipError_t launch_band_pack_dense(int n, int kl, int ku, const double* A, int lda, double* GB, int ldgb,
+                                  hipStream_t st);
+hipError_t launch_band_pack_band(int n, int kl, int ku, const double* AB, int ldab, int ku_in, double* GB,
+                                 int ldgb, hipStream_t st);
+hipError_t launch_band_norms(int n, int kl, int ku, const double* GB, int ldgb, DevRec* rec, hipStream_t st);
+hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, DevRec* rec, hipStream_t st);
+hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv, bool trans,
+                        double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
+hipError_t launch_band_resid(int n, int kl, int ku, int nrhs, const double* AB, int ldab, int ku_in,
+                             const double* B, int ldb, const double* X, int ldx, double* R, int ldr,
+                             hipStream_t st);
+hipError_t launch_band_to_dense(int n, int kl_in, int ku_in, const double* AB, int ldab, double* A, int lda,
+                                hipStream_t st);
+
+// condition estimate
+hipError_t launch_est_init(int n, double* v, DevRec* rec, hipStream_t st);
+hipError_t launch_est_step(int n, int slot_type, const double* result, double* next_in, double* xi, DevRec* rec,
+                           hipStream_t st);
+hipError_t launch_finalize_rcond(DevRec* rec, hipStream_t st);
+
+// residual and backward error
+hipError_t launch_resid_gemv(int n, int nrhs, const double* A, int lda, const double* B, int ldb, const double* X,
+                             int ldx, double* R, int ldr, double* P, hipStream_t st);
+hipError_t launch_x_finite(int n, int nrhs, const double* X, int ldx, DevRec* rec, hipStream_t st);
+hipError_t launch_mark_stop(DevRec* rec, hipStream_t st);
+hipError_t launch_berr(int n, int nrhs, const double* R, int ldr, const double* B, int ldb, const double* X,
+                       int ldx, double* per_col, DevRec* rec, hipStream_t st);
+
+// Jacobi SVD least squares
+hipError_t launch_set_identity(int n, double* V, int ldv, hipStream_t st);
+hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, int max_sweeps, DevRec* rec,
+                               hipStream_t st);
+hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, DevRec* rec,
+                               hipStream_t st);
+hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st);
+hipError_t launch_svd_apply(int n, int nrhs, const double* U, int ldu, const double* V, int ldv, const double* B,
+                            int ldb, double* X, int ldx, double* sigma, double* T, DevRec* rec, hipStream_t st);
+
+}  // namespace ada

@@ -1,0 +1,662 @@
+// C ABI of libada: argument checks, workspace layout and the host side of the
+// adaptive solve (Section II of Sanderson & Curtin): detection pass -> route
+// -> condition estimate -> fallback rule -> SVD least squares. The host reads
+// the device record twice per solve (after detection, to pick the route, and
+// at the end); everything between is stream-ordered device work, with the
+// condition estimate's control flow kept on the device.
+#include <cfloat>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ada.h"
+#include "ada_internal.h"
+
+using namespace ada;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(ADA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kNB = 128;          // LU / Cholesky block width
+constexpr int kDenseMax = 16384;  // dense routes: the panel kernel spreads at most 64 x 256 rows
+constexpr int kBandKdMax = 31;    // band kernels: kl + ku
+constexpr int kBandDenseMax = 4096;  // band-layout input expanded to dense when needed (not banded / SVD)
+constexpr int kJacobiSmall = 256;    // one-workgroup Jacobi up to this n
+
+struct Plan {
+  size_t total = 0;
+  // offsets (bytes)
+  size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, slot_val, slot_row,
+      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense;
+  int n, nrhs, ldw, T64, nflags;
+  bool dense, band, band_dense;
+};
+
+size_t take(size_t& cur, size_t bytes) {
+  size_t off = align_up(cur, 256);
+  cur = off + align_up(bytes, 256);
+  return off;
+}
+
+bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
+  if (n < 1 || nrhs < 1) return false;
+  p = Plan();
+  p.n = n;
+  p.nrhs = nrhs;
+  p.band = o.layout == ADA_LAYOUT_BAND;
+  p.dense = !p.band || n <= kBandDenseMax;
+  p.band_dense = p.band && p.dense;
+  const size_t N = (size_t)n;
+  p.ldw = n;
+  p.T64 = (n + 63) / 64;
+  p.nflags = p.T64;
+  size_t cur = 0;
+  p.rec = take(cur, sizeof(DevRec));
+  p.ipiv = take(cur, N * 4);
+  p.perm = take(cur, N * 4);
+  p.flags = take(cur, (size_t)p.nflags * 4);
+  p.ev = take(cur, N * 8);
+  p.et = take(cur, N * 8);
+  p.exi = take(cur, N * 8);
+  p.R = take(cur, N * nrhs * 8);
+  p.percol = take(cur, (size_t)nrhs * 8);
+  if (p.dense) p.P = take(cur, (size_t)((n + 511) / 512) * 8 * N * 8);
+  // W: dense working copy (LU/Cholesky factor, Jacobi U) and/or the band factor (2kl+ku+1 rows)
+  size_t wrows = (size_t)n;
+  if (p.band) {
+    const size_t ldgb = (size_t)(2 * o.kl_in + o.ku_in + 1);
+    wrows = p.dense ? (ldgb > N ? ldgb : N) : ldgb;
+  }
+  p.W = take(cur, wrows * N * 8);
+  if (p.dense) {
+    const size_t T = (size_t)p.T64;
+    p.pcol = take(cur, T * N * 8);
+    p.prow = take(cur, T * N * 8);
+    p.cld = take(cur, N * 8);
+    p.rld = take(cur, N * 8);
+    p.diag = take(cur, N * 8);
+    p.ctot = take(cur, N * 8);
+    p.csym = take(cur, N * 8);
+    p.rtot = take(cur, N * 8);
+    p.V = take(cur, N * N * 8);
+    p.T = take(cur, N * nrhs * 8);
+    p.sigma = take(cur, N * 8);
+    p.slot_val = take(cur, 2 * 64 * 8);
+    p.slot_row = take(cur, 2 * 64 * 4);
+    p.slot_rows = take(cur, 2 * 64 * 128 * 8);
+    p.diag_rows = take(cur, 2 * 128 * 8);
+    p.moves = take(cur, (1 + 2 * 256) * 4);
+    if (p.band) p.Adense = take(cur, N * N * 8);  // dense expansion of band-layout input
+  }
+  p.total = cur + 256;
+  return true;
+}
+
+ada_opts defaults() {
+  ada_opts o;
+  memset(&o, 0, sizeof(o));
+  o.struct_size = sizeof(ada_opts);
+  o.rcond_threshold = -1.0;
+  o.layout = ADA_LAYOUT_DENSE;
+  o.want_berr = 1;
+  return o;
+}
+
+bool read_opts(const ada_opts* in, ada_opts& o) {
+  o = defaults();
+  if (!in) return true;
+  if (in->struct_size < sizeof(uint32_t) || in->struct_size > sizeof(ada_opts)) return false;
+  memcpy(&o, in, in->struct_size);
+  return true;
+}
+
+bool is_banded(int64_t n, int64_t kl, int64_t ku) {
+  const int64_t nnz = n * (kl + ku + 1) - kl * (kl + 1) / 2 - ku * (ku + 1) / 2;
+  return 4 * nnz <= n * n;
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  memcpy(&d, &b, 8);
+  return d;
+}
+
+}  // namespace
+
+struct ada_ctx_s {
+  int device = 0;
+  DevRec* host_rec = nullptr;  // pinned
+  std::mutex mu;
+  // profiling of the trailing-update GEMM
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0, prof_flops = 0.0;
+  std::vector<double> pending_flops;
+};
+
+namespace {
+
+// Everything one solve needs on the host side.
+struct Solve {
+  ada_ctx ctx;
+  hipStream_t st;
+  Plan p;
+  char* base;
+  DevRec* rec;
+  int n, nrhs;
+  int counter_idx = 0;
+  int epoch = 0;
+
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+  unsigned* next_counter() {
+    if (counter_idx >= 512) return nullptr;
+    return &rec->counters[counter_idx++];
+  }
+  hipEvent_t ev() {
+    if (!ctx->prof) return nullptr;
+    if (ctx->ev_used >= ctx->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ctx->ev_used++];
+  }
+  int gemm(int m, int nn, int k, const double* A, int lda, const double* B, int ldb, bool transB, double* C, int ldc,
+           bool lower) {
+    hipEvent_t e0 = ev(), e1 = ev();
+    HIPCHK(launch_gemm_sub(m, nn, k, A, lda, B, ldb, transB, C, ldc, lower, &rec->stop, st, e0, e1));
+    if (e0 && e1) {
+      double fl;
+      if (lower) {
+        fl = 2.0 * (double)k * ((double)m * (m + 1) / 2.0);  // algorithmic: the lower triangle only
+      } else {
+        fl = 2.0 * (double)m * nn * k;
+      }
+      ctx->pending_flops.push_back(fl);
+    }
+    return ADA_OK;
+  }
+  // op(T) X = X, nrhs <= 64 per launch (split otherwise)
+  int trsm(const double* T, int ldt, bool lower, bool trans, bool unit, double* X, int ldx, int nr, const int* pred,
+           int pv) {
+    for (int c0 = 0; c0 < nr; c0 += 64) {
+      const int cnt = nr - c0 < 64 ? nr - c0 : 64;
+      unsigned* tk = next_counter();
+      if (!tk) return fail(ADA_ERR_ARG, "too many device synchronisation counters for this size");
+      HIPCHK(launch_trsm_dec(n, cnt, T, ldt, lower, trans, unit, X + (size_t)c0 * ldx, ldx, at<int>(p.flags), ++epoch,
+                             tk, rec, pred, pv, st));
+    }
+    return ADA_OK;
+  }
+  int sync_read() {
+    HIPCHK(hipMemcpyAsync(ctx->host_rec, rec, sizeof(DevRec), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ADA_OK;
+  }
+};
+
+#define TRY(expr)               \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != ADA_OK) return r_; \
+  } while (0)
+
+// ---------------------------------------------------------------- routes
+// Each route leaves X = the routed solution (when the factorisation succeeded),
+// rec->info / rec->stop, rec->anorm1, and runs the condition estimate.
+
+int estimate(Solve& s, int route_kind, const double* F, int ldf, bool tri_lower, int kl, int ku) {
+  // route_kind: 0 LU (F = LU, perm), 1 Cholesky (F = L), 2 triangular (F = A), 3 band (F = GB)
+  const int n = s.n;
+  double* v = s.at<double>(s.p.ev);
+  double* t = s.at<double>(s.p.et);
+  double* xi = s.at<double>(s.p.exi);
+  int* phase = &s.rec->est_phase;
+  HIPCHK(launch_est_init(n, v, s.rec, s.st));
+  for (int slot = 0; slot < 11; ++slot) {
+    const int type = (slot % 2 == 0) ? 1 : 2;
+    const double* result = v;
+    if (route_kind == 0) {
+      const int* perm = s.at<int>(s.p.perm);
+      if (type == 1) {
+        HIPCHK(launch_gather_rows(n, 1, perm, v, n, t, n, phase, 1, s.st));
+        TRY(s.trsm(F, ldf, true, false, true, t, n, 1, phase, 1));
+        TRY(s.trsm(F, ldf, false, false, false, t, n, 1, phase, 1));
+      } else {
+        TRY(s.trsm(F, ldf, false, true, false, v, n, 1, phase, 2));
+        TRY(s.trsm(F, ldf, true, true, true, v, n, 1, phase, 2));
+        HIPCHK(launch_scatter_rows(n, 1, perm, v, n, t, n, phase, 2, s.st));
+      }
+      result = t;
+    } else if (route_kind == 1) {
+      TRY(s.trsm(F, ldf, true, false, false, v, n, 1, phase, type));
+      TRY(s.trsm(F, ldf, true, true, false, v, n, 1, phase, type));
+    } else if (route_kind == 2) {
+      TRY(s.trsm(F, ldf, tri_lower, type == 2, false, v, n, 1, phase, type));
+    } else {
+      const int ldgb = 2 * kl + ku + 1;
+      HIPCHK(launch_gbtrs(n, kl, ku, 1, F, ldgb, s.at<int>(s.p.ipiv), type == 2, v, n, phase, type, s.st));
+    }
+    HIPCHK(launch_est_step(n, type, result, v, xi, s.rec, s.st));
+  }
+  HIPCHK(launch_finalize_rcond(s.rec, s.st));
+  return ADA_OK;
+}
+
+int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, double* X, int ldx) {
+  const int n = s.n, ldw = s.p.ldw;
+  double* W = s.at<double>(s.p.W);
+  int* ipiv = s.at<int>(s.p.ipiv);
+  int* perm = s.at<int>(s.p.perm);
+  HIPCHK(launch_copy(n, n, A, lda, W, ldw, s.st));
+  HIPCHK(launch_iota(perm, n, s.st));
+  PanelScratch ps{s.at<double>(s.p.slot_val), s.at<int>(s.p.slot_row), s.at<double>(s.p.slot_rows),
+                  s.at<double>(s.p.diag_rows), s.at<int>(s.p.moves)};
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int nbw = n - k0 < kNB ? n - k0 : kNB;
+    unsigned* ctr = s.next_counter();
+    if (!ctr) return fail(ADA_ERR_ARG, "too many device synchronisation counters for this size");
+    HIPCHK(launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, ctr, ps, s.st));
+    HIPCHK(launch_laswp_moves(n, k0, nbw, W, ldw, ps.moves, perm, s.rec, s.st));
+    const int rest = n - k0 - nbw;
+    if (rest > 0) {
+      HIPCHK(launch_trsm_llnu(k0, nbw, rest, W, ldw, s.rec, s.st));
+      TRY(s.gemm(rest, rest, nbw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, W + k0 + (size_t)(k0 + nbw) * ldw, ldw, false,
+                 W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw, ldw, false));
+    }
+  }
+  // X = U^{-1} L^{-1} P B
+  int* stop = &s.rec->stop;
+  HIPCHK(launch_gather_rows(n, s.nrhs, perm, B, ldb, X, ldx, stop, 0, s.st));
+  TRY(s.trsm(W, ldw, true, false, true, X, ldx, s.nrhs, stop, 0));
+  TRY(s.trsm(W, ldw, false, false, false, X, ldx, s.nrhs, stop, 0));
+  return estimate(s, 0, W, ldw, false, 0, 0);
+}
+
+int route_chol(Solve& s, const double* A, int lda, const double* B, int ldb, double* X, int ldx) {
+  const int n = s.n, ldw = s.p.ldw;
+  double* W = s.at<double>(s.p.W);
+  HIPCHK(launch_copy(n, n, A, lda, W, ldw, s.st));
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int nbw = n - k0 < kNB ? n - k0 : kNB;
+    HIPCHK(launch_potrf_diag(k0, nbw, W, ldw, s.rec, s.st));
+    const int rest = n - k0 - nbw;
+    if (rest > 0) {
+      HIPCHK(launch_trsm_rltn(k0, nbw, rest, W, ldw, s.rec, s.st));
+      TRY(s.gemm(rest, rest, nbw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, true,
+                 W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw, ldw, true));
+    }
+  }
+  int* stop = &s.rec->stop;
+  HIPCHK(launch_copy(n, s.nrhs, B, ldb, X, ldx, s.st));
+  TRY(s.trsm(W, ldw, true, false, false, X, ldx, s.nrhs, stop, 0));
+  TRY(s.trsm(W, ldw, true, true, false, X, ldx, s.nrhs, stop, 0));
+  return estimate(s, 1, W, ldw, false, 0, 0);
+}
+
+int route_tri(Solve& s, const double* A, int lda, bool lower, const double* B, int ldb, double* X, int ldx) {
+  int* stop = &s.rec->stop;
+  HIPCHK(launch_copy(s.n, s.nrhs, B, ldb, X, ldx, s.st));
+  TRY(s.trsm(A, lda, lower, false, false, X, ldx, s.nrhs, stop, 0));
+  return estimate(s, 2, A, lda, lower, 0, 0);
+}
+
+int route_band(Solve& s, const double* GB, int kl, int ku, const double* B, int ldb, double* X, int ldx) {
+  // GB already packed and its norms recorded
+  const int n = s.n, ldgb = 2 * kl + ku + 1;
+  HIPCHK(launch_gbtrf(n, kl, ku, const_cast<double*>(GB), ldgb, s.at<int>(s.p.ipiv), s.rec, s.st));
+  int* stop = &s.rec->stop;
+  HIPCHK(launch_copy(n, s.nrhs, B, ldb, X, ldx, s.st));
+  HIPCHK(launch_gbtrs(n, kl, ku, s.nrhs, GB, ldgb, s.at<int>(s.p.ipiv), false, X, ldx, stop, 0, s.st));
+  return estimate(s, 3, GB, ldgb, false, kl, ku);
+}
+
+int route_svd(Solve& s, const double* A, int lda, const double* B, int ldb, double* X, int ldx, double* Wbuf,
+              double* Vbuf, double* Tbuf) {
+  const int n = s.n;
+  HIPCHK(launch_copy(n, n, A, lda, Wbuf, n, s.st));
+  HIPCHK(launch_set_identity(n, Vbuf, n, s.st));
+  if (n <= kJacobiSmall) {
+    HIPCHK(launch_jacobi_small(n, Wbuf, n, Vbuf, n, 30, s.rec, s.st));
+  } else {
+    const int m = (n + 1) & ~1;
+    int sweeps = 0;
+    for (; sweeps < 30; ++sweeps) {
+      HIPCHK(launch_clear_rotated(s.rec, s.st));
+      for (int r = 0; r < m - 1; ++r) HIPCHK(launch_jacobi_round(n, m, r, Wbuf, n, Vbuf, n, s.rec, s.st));
+      TRY(s.sync_read());
+      if (!s.ctx->host_rec->jacobi_rotated) { ++sweeps; break; }
+    }
+    s.ctx->host_rec->sweeps = sweeps;
+    HIPCHK(hipMemcpyAsync(&s.rec->sweeps, &s.ctx->host_rec->sweeps, sizeof(int), hipMemcpyHostToDevice, s.st));
+  }
+  HIPCHK(launch_svd_apply(n, s.nrhs, Wbuf, n, Vbuf, n, B, ldb, X, ldx, s.at<double>(s.p.sigma), Tbuf, s.rec, s.st));
+  return ADA_OK;
+}
+
+int backward_error_dense(Solve& s, const double* A, int lda, const double* B, int ldb, const double* X, int ldx) {
+  const int n = s.n, nrhs = s.nrhs;
+  double* R = s.at<double>(s.p.R);
+  if (nrhs <= 8) {
+    HIPCHK(launch_resid_gemv(n, nrhs, A, lda, B, ldb, X, ldx, R, n, s.at<double>(s.p.P), s.st));
+  } else {
+    HIPCHK(launch_copy(n, nrhs, B, ldb, R, n, s.st));
+    HIPCHK(launch_gemm_sub(n, nrhs, n, A, lda, X, ldx, false, R, n, false, nullptr, s.st, nullptr, nullptr));
+  }
+  HIPCHK(launch_berr(n, nrhs, R, n, B, ldb, X, ldx, s.at<double>(s.p.percol), s.rec, s.st));
+  return ADA_OK;
+}
+
+void fill_result(ada_result* r, const DevRec& h, int cls, int kl, int ku, int route, int chol_failed, int fallback,
+                 int n) {
+  memset(r, 0, sizeof(*r));
+  r->cls = cls;
+  r->kl = kl;
+  r->ku = ku;
+  r->route = route;
+  r->chol_failed = chol_failed;
+  r->fallback = fallback;
+  r->info = 0;
+  r->rank = n;
+  r->rcond = h.rcond;
+  r->berr = h.berr;
+  r->nsolves = h.est_nsolves;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ada_create(ada_ctx* out, int device) {
+  if (!out) return fail(ADA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(ADA_ERR_ARG, "device out of range");
+  ada_ctx c = new (std::nothrow) ada_ctx_s();
+  if (!c) return fail(ADA_ERR_NOMEM, "context allocation");
+  c->device = device;
+  HIPCHK(hipSetDevice(device));
+  hipError_t e = hipHostMalloc((void**)&c->host_rec, sizeof(DevRec), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(ADA_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return ADA_OK;
+}
+
+void ada_destroy(ada_ctx ctx) {
+  if (!ctx) return;
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->host_rec) (void)hipHostFree(ctx->host_rec);
+  delete ctx;
+}
+
+const char* ada_last_error(void) { return g_err.c_str(); }
+
+void ada_opts_default(ada_opts* o) {
+  if (o) *o = defaults();
+}
+
+size_t ada_workspace_size(int n, int nrhs, const ada_opts* opts) {
+  ada_opts o;
+  if (!read_opts(opts, o)) return 0;
+  Plan p;
+  if (!make_plan(n, nrhs, o, p)) return 0;
+  return p.total;
+}
+
+int ada_profile_enable(ada_ctx ctx, int on) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  ctx->prof = on != 0;
+  return ADA_OK;
+}
+
+int ada_profile_reset(ada_ctx ctx) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  ctx->prof_launches = 0;
+  ctx->prof_ms = 0.0;
+  ctx->prof_flops = 0.0;
+  return ADA_OK;
+}
+
+int ada_profile_read(ada_ctx ctx, int64_t* launches, double* total_ms, double* total_flops) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  if (launches) *launches = ctx->prof_launches;
+  if (total_ms) *total_ms = ctx->prof_ms;
+  if (total_flops) *total_flops = ctx->prof_flops;
+  return ADA_OK;
+}
+
+static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
+                      int ldx, void* work, size_t work_bytes, const ada_opts& o, ada_result* result,
+                      hipStream_t st) {
+  Plan p;
+  if (!make_plan(n, nrhs, o, p)) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
+  if (!work || work_bytes < p.total)
+    return fail(ADA_ERR_ARG, "workspace too small: need " + std::to_string(p.total) + " bytes");
+  if (((uintptr_t)work & 255) != 0) return fail(ADA_ERR_ARG, "workspace must be 256-byte aligned");
+  Solve s;
+  s.ctx = ctx;
+  s.st = st;
+  s.p = p;
+  s.base = static_cast<char*>(work);
+  s.rec = s.at<DevRec>(p.rec);
+  s.n = n;
+  s.nrhs = nrhs;
+  DevRec& h = *ctx->host_rec;
+  ctx->ev_used = 0;
+  ctx->pending_flops.clear();
+  const double thr = o.rcond_threshold < 0.0 ? 0.5 * DBL_EPSILON : o.rcond_threshold;
+
+  HIPCHK(launch_init_rec(s.rec, st));
+  HIPCHK(launch_fill_int(s.at<int>(p.flags), 0, (size_t)p.nflags, st));
+
+  int cls = ADA_CLASS_GENERAL, kl = -1, ku = -1;
+  int route = ADA_ROUTE_NONE, chol_failed = 0, fallback = 0, info = 0;
+  const double* Ad = A;  // dense view of A (band-layout input: expanded copy when needed)
+  int ldad = lda;
+  bool band_route_from_band_layout = false;
+  int bkl = 0, bku = 0;
+
+  if (o.layout == ADA_LAYOUT_BAND) {
+    if (o.kl_in < 0 || o.ku_in < 0 || o.kl_in >= n || o.ku_in >= n || lda < o.kl_in + o.ku_in + 1)
+      return fail(ADA_ERR_ARG, "band layout: need 0 <= kl_in, ku_in < n and lda >= kl_in + ku_in + 1");
+    HIPCHK(launch_detect_band(n, o.kl_in, o.ku_in, A, lda, s.rec, st));
+    HIPCHK(launch_check_finite(n, nrhs, B, ldb, s.rec, st));
+    TRY(s.sync_read());
+    if (h.nonfinite) return fail(ADA_ERR_NONFINITE, "A or B holds NaN or Inf");
+    kl = h.kl;
+    ku = h.ku;
+    if (o.force_general || !is_banded(n, kl, ku) || kl + ku > kBandKdMax) {
+      if (!p.dense) {
+        return fail(o.force_general || !is_banded(n, kl, ku) ? ADA_ERR_FALLBACK_INFEASIBLE : ADA_ERR_ARG,
+                    "band-layout system needs the dense path but n exceeds the dense expansion limit");
+      }
+      double* Ax = s.at<double>(p.Adense);
+      HIPCHK(launch_band_to_dense(n, o.kl_in, o.ku_in, A, lda, Ax, n, st));
+      Ad = Ax;
+      ldad = n;
+      HIPCHK(launch_init_rec(s.rec, st));
+    } else {
+      band_route_from_band_layout = true;
+      cls = ADA_CLASS_BANDED;
+      bkl = kl;
+      bku = ku;
+    }
+  }
+
+  if (!band_route_from_band_layout) {
+    if (n > kDenseMax) return fail(ADA_ERR_ARG, "dense routes support n <= 16384");
+    HIPCHK(launch_detect_dense(n, Ad, ldad, s.rec, s.at<double>(p.pcol), s.at<double>(p.prow), s.at<double>(p.cld),
+                               s.at<double>(p.rld), s.at<double>(p.diag), st));
+    HIPCHK(launch_check_finite(n, nrhs, B, ldb, s.rec, st));
+    HIPCHK(launch_norms_reduce(n, s.at<double>(p.pcol), s.at<double>(p.prow), s.at<double>(p.cld),
+                               s.at<double>(p.rld), s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot),
+                               st));
+    TRY(s.sync_read());
+    if (h.nonfinite) return fail(ADA_ERR_NONFINITE, "A or B holds NaN or Inf");
+    if (o.force_general) {
+      cls = ADA_CLASS_GENERAL;
+      kl = ku = -1;
+    } else {
+      kl = h.kl;
+      ku = h.ku;
+      if (is_banded(n, kl, ku)) cls = ADA_CLASS_BANDED;
+      else if (kl == 0) cls = ADA_CLASS_TRI_UPPER;
+      else if (ku == 0) cls = ADA_CLASS_TRI_LOWER;
+      else {
+        const double max_diag = bits_to_double(h.max_diag_bits);
+        const double max_lower = bits_to_double(h.max_lower_bits);
+        const bool sympd = !h.diag_nonpos && !h.sym_bad && (max_lower < max_diag);
+        cls = sympd ? ADA_CLASS_SYMPD : ADA_CLASS_GENERAL;
+      }
+    }
+  }
+
+  // ---------------- route
+  double* W = s.at<double>(p.W);
+  const int norm_mode = (cls == ADA_CLASS_SYMPD) ? 1 : 0;
+  if (!band_route_from_band_layout)
+    HIPCHK(launch_anorm(n, s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot), norm_mode, s.rec, st));
+  if (cls == ADA_CLASS_GENERAL) {
+    route = ADA_ROUTE_LU;
+    TRY(route_lu(s, Ad, ldad, B, ldb, X, ldx));
+  } else if (cls == ADA_CLASS_SYMPD) {
+    route = ADA_ROUTE_CHOL;
+    TRY(route_chol(s, Ad, ldad, B, ldb, X, ldx));
+    TRY(s.sync_read());
+    if (h.timeout) return fail(ADA_ERR_HIP, "a bounded device wait timed out");
+    if (h.chol_info != INT_MAX) {
+      // Cholesky failed: not sympd after all -> LU on the original A
+      chol_failed = 1;
+      route = ADA_ROUTE_LU;
+      HIPCHK(launch_init_rec(s.rec, st));
+      HIPCHK(launch_anorm(n, s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot), 0, s.rec, st));
+      TRY(route_lu(s, Ad, ldad, B, ldb, X, ldx));
+    }
+  } else if (cls == ADA_CLASS_TRI_UPPER || cls == ADA_CLASS_TRI_LOWER) {
+    route = ADA_ROUTE_TRI;
+    if (h.diag_zero_first != INT_MAX) {
+      info = h.diag_zero_first;  // zero on the diagonal: the triangular solver fails
+    } else {
+      TRY(route_tri(s, Ad, ldad, cls == ADA_CLASS_TRI_LOWER, B, ldb, X, ldx));
+    }
+  } else {  // banded
+    route = ADA_ROUTE_BAND_LU;
+    if (!band_route_from_band_layout) {
+      bkl = kl;
+      bku = ku;
+      if (bkl + bku > kBandKdMax) return fail(ADA_ERR_ARG, "band kernels support kl + ku <= 31");
+    }
+    const int ldgb = 2 * bkl + bku + 1;
+    if (band_route_from_band_layout)
+      HIPCHK(launch_band_pack_band(n, bkl, bku, A, lda, o.ku_in, W, ldgb, st));
+    else
+      HIPCHK(launch_band_pack_dense(n, bkl, bku, Ad, ldad, W, ldgb, st));
+    HIPCHK(launch_band_norms(n, bkl, bku, W, ldgb, s.rec, st));
+    TRY(route_band(s, W, bkl, bku, B, ldb, X, ldx));
+  }
+  // backward error of the routed x (also flags a non-finite x)
+  if (info == 0) {
+    if (band_route_from_band_layout) {
+      HIPCHK(launch_band_resid(n, o.kl_in, o.ku_in, nrhs, A, lda, o.ku_in, B, ldb, X, ldx, s.at<double>(p.R), n, st));
+      HIPCHK(launch_berr(n, nrhs, s.at<double>(p.R), n, B, ldb, X, ldx, s.at<double>(p.percol), s.rec, st));
+    } else if (o.want_berr) {
+      TRY(backward_error_dense(s, Ad, ldad, B, ldb, X, ldx));
+    } else {
+      HIPCHK(launch_x_finite(n, nrhs, X, ldx, s.rec, st));
+    }
+  }
+  TRY(s.sync_read());
+  if (h.timeout) return fail(ADA_ERR_HIP, "a bounded device wait timed out");
+  if (info == 0 && h.info != INT_MAX) info = h.info;
+  const double rcond = info ? NAN : h.rcond;
+  if (info || h.x_nonfinite) fallback = ADA_FALLBACK_FAILURE;
+  else if (rcond != rcond) fallback = ADA_FALLBACK_RCOND_NAN;
+  else if (rcond < thr) fallback = ADA_FALLBACK_RCOND;
+
+  // record the profiled GEMM launches
+  if (ctx->prof) {
+    for (size_t i = 0; i + 1 < ctx->ev_used && i / 2 < ctx->pending_flops.size(); i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ctx->ev_pool[i], ctx->ev_pool[i + 1]) == hipSuccess) {
+        ctx->prof_ms += ms;
+        ctx->prof_flops += ctx->pending_flops[i / 2];
+        ctx->prof_launches += 1;
+      }
+    }
+  }
+
+  fill_result(result, h, cls, kl, ku, route, chol_failed, fallback, n);
+  result->info = info;
+  result->rcond = rcond;
+  result->berr = (o.want_berr || band_route_from_band_layout) && info == 0 ? h.berr : NAN;
+  if (!fallback) return ADA_OK;
+  if (o.no_approx) return fail(ADA_ERR_SINGULAR, "the fallback is due (solver failure or rcond below threshold) "
+                                                 "but no_approx is set");
+  // ---------------- SVD least-squares fallback on the original A
+  if (!p.dense) return fail(ADA_ERR_FALLBACK_INFEASIBLE, "SVD fallback of a band-layout system this large");
+  if (o.layout == ADA_LAYOUT_BAND && Ad == A) {
+    double* Ax = s.at<double>(p.Adense);
+    HIPCHK(launch_band_to_dense(n, o.kl_in, o.ku_in, A, lda, Ax, n, st));
+    Ad = Ax;
+    ldad = n;
+  }
+  double* Ws = W;
+  double* Vs = s.at<double>(p.V);
+  double* Ts = s.at<double>(p.T);
+  TRY(route_svd(s, Ad, ldad, B, ldb, X, ldx, Ws, Vs, Ts));
+  if (o.want_berr || o.layout == ADA_LAYOUT_BAND) {
+    if (o.layout == ADA_LAYOUT_BAND) {
+      HIPCHK(launch_band_resid(n, o.kl_in, o.ku_in, nrhs, A, lda, o.ku_in, B, ldb, X, ldx, s.at<double>(p.R), n, st));
+      HIPCHK(launch_berr(n, nrhs, s.at<double>(p.R), n, B, ldb, X, ldx, s.at<double>(p.percol), s.rec, st));
+    } else {
+      TRY(backward_error_dense(s, Ad, ldad, B, ldb, X, ldx));
+    }
+  }
+  TRY(s.sync_read());
+  result->route = ADA_ROUTE_SVD;
+  result->rank = h.rank;
+  result->sweeps = h.sweeps;
+  result->berr = (o.want_berr || o.layout == ADA_LAYOUT_BAND) ? h.berr : NAN;
+  return ADA_OK;
+}
+
+int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
+              void* work, size_t work_bytes, const ada_opts* opts, ada_result* result, void* stream) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  if (!A || !B || !X || !result) return fail(ADA_ERR_ARG, "NULL matrix or result pointer");
+  ada_opts o;
+  if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
+  if (o.layout != ADA_LAYOUT_DENSE && o.layout != ADA_LAYOUT_BAND) return fail(ADA_ERR_ARG, "unknown layout");
+  if (n < 1 || nrhs < 1) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
+  if (o.layout == ADA_LAYOUT_DENSE && lda < n) return fail(ADA_ERR_ARG, "lda < n");
+  if (ldb < n || ldx < n) return fail(ADA_ERR_ARG, "ldb or ldx < n");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  HIPCHK(hipSetDevice(ctx->device));
+  return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, o, result,
+                    static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,447 @@
+// Banded route (Section II-A): the compact band format (one diagonal per row
+// of a dense array, with kl extra rows for the fill of row interchanges), LU
+// with partial pivoting restricted to the kl+1 candidate rows of each column,
+// the band solves, and the band norms.
+//
+// Element (i,j) of the working band lives at GB[(kl+ku) + i - j + j*ldgb],
+// ldgb >= 2kl+ku+1. Partial pivoting makes the factorisation a chain of n
+// dependent column steps; it runs in one compute wave that keeps the active
+// (kl+1) x (kl+ku+1) window in registers (lane = column of the window), while
+// three loader waves stream the next chunks of the band into an LDS ring, so
+// the chain never waits on HBM. The solves use the same scheme with lane =
+// right-hand side.
+#include "ada_internal.h"
+
+#include <climits>
+
+namespace ada {
+
+
+__global__ void k_band_pack_dense(int n, int kl, int ku, const double* __restrict__ A, int lda,
+                                  double* __restrict__ GB, int ldgb) {
+  const int kd = kl + ku;
+  const size_t total = (size_t)ldgb * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % ldgb), j = (int)(e / ldgb);
+    const int i = r - kd + j;  // row of this storage slot
+    double v = 0.0;
+    if (r >= kl && i >= 0 && i < n && i - j <= kl) v = A[(size_t)i + (size_t)j * lda];
+    GB[e] = v;
+  }
+}
+
+hipError_t launch_band_pack_dense(int n, int kl, int ku, const double* A, int lda, double* GB, int ldgb,
+                                  hipStream_t st) {
+  size_t total = (size_t)ldgb * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_band_pack_dense, dim3(blocks), dim3(256), 0, st, n, kl, ku, A, lda, GB, ldgb);
+  return hipGetLastError();
+}
+
+// from LAPACK band storage AB[ku_in + i - j + j*ldab] (any stored width >= the true one)
+__global__ void k_band_pack_band(int n, int kl, int ku, const double* __restrict__ AB, int ldab, int ku_in,
+                                 double* __restrict__ GB, int ldgb) {
+  const int kd = kl + ku;
+  const size_t total = (size_t)ldgb * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % ldgb), j = (int)(e / ldgb);
+    const int i = r - kd + j;
+    double v = 0.0;
+    if (r >= kl && i >= 0 && i < n && i - j <= kl) v = AB[(size_t)(ku_in + i - j) + (size_t)j * ldab];
+    GB[e] = v;
+  }
+}
+
+hipError_t launch_band_pack_band(int n, int kl, int ku, const double* AB, int ldab, int ku_in, double* GB,
+                                 int ldgb, hipStream_t st) {
+  size_t total = (size_t)ldgb * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_band_pack_band, dim3(blocks), dim3(256), 0, st, n, kl, ku, AB, ldab, ku_in, GB, ldgb);
+  return hipGetLastError();
+}
+
+__global__ void k_band_to_dense(int n, int kl_in, int ku_in, const double* __restrict__ AB, int ldab,
+                                double* __restrict__ A, int lda) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    double v = 0.0;
+    if (i - j <= kl_in && j - i <= ku_in) v = AB[(size_t)(ku_in + i - j) + (size_t)j * ldab];
+    A[(size_t)i + (size_t)j * lda] = v;
+  }
+}
+
+hipError_t launch_band_to_dense(int n, int kl_in, int ku_in, const double* AB, int ldab, double* A, int lda,
+                                hipStream_t st) {
+  size_t total = (size_t)n * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_band_to_dense, dim3(blocks), dim3(256), 0, st, n, kl_in, ku_in, AB, ldab, A, lda);
+  return hipGetLastError();
+}
+
+// ||A||_1 (max column sum) and ||A||_inf (max row sum) of the band before factorisation
+__global__ void k_band_norms(int n, int kl, int ku, const double* __restrict__ GB, int ldgb, DevRec* rec) {
+  const int kd = kl + ku;
+  double c1 = 0.0, ri = 0.0;
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = max(0, x - ku); i <= min(n - 1, x + kl); ++i) s += fabs(GB[(size_t)(kd + i - x) + (size_t)x * ldgb]);
+    c1 = fmax(c1, s);
+    double r = 0.0;
+    for (int j = max(0, x - kl); j <= min(n - 1, x + ku); ++j) r += fabs(GB[(size_t)(kd + x - j) + (size_t)j * ldgb]);
+    ri = fmax(ri, r);
+  }
+  c1 = wave_max(c1);
+  ri = wave_max(ri);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(reinterpret_cast<unsigned long long*>(&rec->anorm1), dbits(c1));
+    atomicMax(reinterpret_cast<unsigned long long*>(&rec->anorm_inf), dbits(ri));
+  }
+}
+
+hipError_t launch_band_norms(int n, int kl, int ku, const double* GB, int ldgb, DevRec* rec, hipStream_t st) {
+  int blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_band_norms, dim3(blocks), dim3(256), 0, st, n, kl, ku, GB, ldgb, rec);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- factorisation
+// Band kernels need kl + ku <= BAND_KD_MAX (the window spans one lane per column).
+constexpr int BAND_KD_MAX = 31;
+constexpr int BCH2 = 32;  // chunk length; the LDS rings hold 4 chunks
+
+template <int KLM>
+__global__ __launch_bounds__(256) void k_gbtrf(int n, int kl, int ku, double* __restrict__ GB, int ldgb,
+                                               int* __restrict__ ipiv, DevRec* rec) {
+  const int kd = kl + ku;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  constexpr int SL = 4 * BCH2;
+  extern __shared__ double ring[];  // ring[(col % SL) * ldgb + r] = original GB column
+  const int nch = (n + BCH2 - 1) / BCH2;
+  auto load_chunk = [&](int q) {
+    if (q < 0 || q >= nch) return;
+    const int c0 = q * BCH2, c1 = min(n, c0 + BCH2);
+    const int cnt = (c1 - c0) * ldgb;
+    for (int e = t - 64; e < cnt; e += 192) {
+      const int r = e % ldgb, c = c0 + e / ldgb;
+      ring[(size_t)(c % SL) * ldgb + r] = GB[(size_t)r + (size_t)c * ldgb];
+    }
+  };
+  auto R = [&](int off, int col) -> double { return ring[(size_t)(col % SL) * ldgb + off]; };
+
+  if (w >= 1) { load_chunk(0); load_chunk(1); }
+  __syncthreads();
+  double v[KLM + 1];
+#pragma unroll
+  for (int r = 0; r <= KLM; ++r) v[r] = 0.0;
+  if (w == 0 && lane <= kd && lane < n) {
+#pragma unroll
+    for (int r = 0; r <= KLM; ++r)
+      if (r <= kl && r < n) v[r] = R(kd + r - lane, lane);
+  }
+  int info = INT_MAX;
+  for (int q = 0; q < nch; ++q) {
+    if (w >= 1) load_chunk(q + 2);
+    if (w == 0) {
+      const int jend = min(n, (q + 1) * BCH2);
+      for (int j = q * BCH2; j < jend; ++j) {
+        const int lm = min(kl, n - 1 - j);
+        int p = 0;
+        if (lane == 0) {
+          double best = fabs(v[0]);
+#pragma unroll
+          for (int r = 1; r <= KLM; ++r)
+            if (r <= lm && fabs(v[r]) > best) { best = fabs(v[r]); p = r; }
+          ipiv[j] = j + p;
+        }
+        p = __shfl(p, 0, 64);
+        if (p != 0) {
+#pragma unroll
+          for (int r = 1; r <= KLM; ++r)
+            if (r == p) { const double tmp = v[0]; v[0] = v[r]; v[r] = tmp; }
+        }
+        const double piv = __shfl(v[0], 0, 64);
+        if (piv == 0.0) {
+          if (info == INT_MAX) info = j + 1;
+        } else {
+          if (lane == 0) {
+#pragma unroll
+            for (int r = 1; r <= KLM; ++r)
+              if (r <= lm) v[r] = v[r] / piv;
+          }
+          double l[KLM + 1];
+#pragma unroll
+          for (int r = 1; r <= KLM; ++r) l[r] = __shfl(v[r], 0, 64);
+          if (lane >= 1 && lane <= kd && j + lane < n) {
+#pragma unroll
+            for (int r = 1; r <= KLM; ++r)
+              if (r <= lm) v[r] = fma(-l[r], v[0], v[r]);
+          }
+        }
+        // column j is final (U(j,j) and the multipliers); row j of U is final in every lane
+        if (lane == 0) {
+#pragma unroll
+          for (int r = 0; r <= KLM; ++r)
+            if (r <= lm) GB[(size_t)(kd + r) + (size_t)j * ldgb] = v[r];
+        } else if (lane <= kd && j + lane < n) {
+          GB[(size_t)(kd - lane) + (size_t)(j + lane) * ldgb] = v[0];
+        }
+        // slide the window one column right and one row down
+#pragma unroll
+        for (int r = 0; r < KLM; ++r) v[r] = __shfl_down(v[r + 1], 1, 64);
+        v[KLM] = 0.0;
+        const int col = j + 1 + lane;
+        if (lane == kd) {
+#pragma unroll
+          for (int r = 0; r < KLM; ++r)
+            v[r] = (r < kl && col < n && j + 1 + r < n) ? R(r, col) : 0.0;
+        }
+        if (lane <= kd) {
+          const int row = j + 1 + kl;
+          const double nv = (row < n && col < n) ? R(kd + kl - lane, col) : 0.0;
+#pragma unroll
+          for (int r = 0; r <= KLM; ++r)
+            if (r == kl) v[r] = nv;
+        } else {
+#pragma unroll
+          for (int r = 0; r <= KLM; ++r) v[r] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (w == 0 && lane == 0 && info != INT_MAX) {
+    atomicMin(&rec->info, info);
+    rec->stop = 1;
+  }
+}
+
+hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, DevRec* rec, hipStream_t st) {
+  const int kd = kl + ku;
+  if (kd > BAND_KD_MAX) return hipErrorInvalidValue;
+  const size_t lds = (size_t)4 * BCH2 * ldgb * sizeof(double);
+#define ADA_GBTRF(K)                                                                                         \
+  do {                                                                                                       \
+    static size_t done = 0;                                                                                  \
+    hipError_t e = ensure_lds((const void*)k_gbtrf<K>, lds, done);                                          \
+    if (e != hipSuccess) return e;                                                                           \
+    hipLaunchKernelGGL(k_gbtrf<K>, dim3(1), dim3(256), lds, st, n, kl, ku, GB, ldgb, ipiv, rec);            \
+  } while (0)
+  if (kl <= 4) ADA_GBTRF(4);
+  else if (kl <= 8) ADA_GBTRF(8);
+  else if (kl <= 16) ADA_GBTRF(16);
+  else ADA_GBTRF(32);
+#undef ADA_GBTRF
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- solves
+// trans = 0: A x = b with A = P0 L0 P1 L1 ... U: forward (interchange, unit
+//            lower band) then backward with U (kl+ku super-diagonals);
+// trans = 1: A^T x = b: U^T forward, then L^T backward with the interchanges
+//            applied in reverse order.
+// One compute wave, lane = right-hand side (nrhs <= 32 per launch). Band
+// columns, pivots and the right-hand-side rows are streamed through LDS rings
+// by three loader waves two chunks ahead of the compute wave.
+template <int KW>
+__global__ __launch_bounds__(256) void k_gbtrs(int n, int kl, int ku, int nrhs, const double* __restrict__ GB,
+                                               int ldgb, const int* __restrict__ ipiv, int trans, double* X, int ldx,
+                                               const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  const int kd = kl + ku;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  constexpr int SL = 4 * BCH2;
+  extern __shared__ double lds[];
+  double* ring = lds;                                     // [SL][ldgb]
+  double* xr = ring + (size_t)SL * ldgb;                  // [SL][nrhs]
+  int* pring = reinterpret_cast<int*>(xr + (size_t)SL * nrhs);  // [SL]
+  const int nch = (n + BCH2 - 1) / BCH2;
+  const bool active = w == 0 && lane < nrhs;
+  double* x = X + (size_t)lane * ldx;
+
+  auto load_chunk = [&](int q) {
+    if (q < 0 || q >= nch) return;
+    const int c0 = q * BCH2, c1 = min(n, c0 + BCH2);
+    const int cnt = (c1 - c0) * ldgb;
+    for (int e = t - 64; e < cnt; e += 192) {
+      const int r = e % ldgb, c = c0 + e / ldgb;
+      ring[(size_t)(c % SL) * ldgb + r] = GB[(size_t)r + (size_t)c * ldgb];
+    }
+    const int xc = (c1 - c0) * nrhs;
+    for (int e = t - 64; e < xc; e += 192) {
+      const int cc = e % nrhs, row = c0 + e / nrhs;
+      xr[(size_t)(row % SL) * nrhs + cc] = X[(size_t)row + (size_t)cc * ldx];
+    }
+    for (int c = c0 + t - 64; c < c1; c += 192) pring[c % SL] = ipiv[c];
+  };
+  auto R = [&](int off, int col) -> double { return ring[(size_t)(col % SL) * ldgb + off]; };
+  auto XR = [&](int row) -> double { return xr[(size_t)(row % SL) * nrhs + lane]; };
+
+  double win[KW + 1];
+  // ------------------------------------------------ pass 1: rows in increasing order
+  if (w >= 1) { load_chunk(0); load_chunk(1); }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r <= KW; ++r) win[r] = 0.0;
+  if (!trans && active) {
+#pragma unroll
+    for (int r = 0; r <= KW; ++r)
+      if (r <= kl && r < n) win[r] = XR(r);
+  }
+  for (int q = 0; q < nch; ++q) {
+    if (w >= 1) load_chunk(q + 2);
+    if (active) {
+      const int jend = min(n, (q + 1) * BCH2);
+      for (int j = q * BCH2; j < jend; ++j) {
+        if (!trans) {
+          // y = L^{-1} P b; window win[r] = b_{j+r}
+          const int lm = min(kl, n - 1 - j);
+          const int p = pring[j % SL] - j;
+          if (p != 0) {
+#pragma unroll
+            for (int r = 1; r <= KW; ++r)
+              if (r == p) { const double tmp = win[0]; win[0] = win[r]; win[r] = tmp; }
+          }
+#pragma unroll
+          for (int r = 1; r <= KW; ++r)
+            if (r <= lm) win[r] = fma(-R(kd + r, j), win[0], win[r]);
+          x[j] = win[0];
+#pragma unroll
+          for (int r = 0; r < KW; ++r) win[r] = win[r + 1];
+          win[KW] = 0.0;
+          const int nr = j + 1 + kl;
+          const double nv = nr < n ? XR(nr) : 0.0;
+#pragma unroll
+          for (int r = 0; r <= KW; ++r)
+            if (r == kl) win[r] = nv;
+        } else {
+          // z = U^{-T} b: z_j = (b_j - sum_k U(j-k, j) z_{j-k}) / U(j,j); win[k-1] = z_{j-k}
+          double s = XR(j);
+#pragma unroll
+          for (int k = 1; k <= KW; ++k)
+            if (k <= kd && j - k >= 0) s = fma(-R(kd - k, j), win[k - 1], s);
+          s = s / R(kd, j);
+          x[j] = s;
+#pragma unroll
+          for (int k = KW; k >= 1; --k) win[k] = win[k - 1];
+          win[0] = s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // ------------------------------------------------ pass 2: rows in decreasing order
+  if (w >= 1) { load_chunk(nch - 1); load_chunk(nch - 2); }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r <= KW; ++r) win[r] = 0.0;
+  if (trans && active) win[0] = XR(n - 1);
+  for (int q = nch - 1; q >= 0; --q) {
+    if (w >= 1) load_chunk(q - 2);
+    if (active) {
+      const int jbeg = q * BCH2;
+      for (int j = min(n, (q + 1) * BCH2) - 1; j >= jbeg; --j) {
+        if (!trans) {
+          // x_j = (y_j - sum_k U(j, j+k) x_{j+k}) / U(j,j); win[k-1] = x_{j+k}
+          double s = XR(j);
+#pragma unroll
+          for (int k = 1; k <= KW; ++k)
+            if (k <= kd && j + k < n) s = fma(-R(kd - k, j + k), win[k - 1], s);
+          s = s / R(kd, j);
+          x[j] = s;
+#pragma unroll
+          for (int k = KW; k >= 1; --k) win[k] = win[k - 1];
+          win[0] = s;
+        } else {
+          // w_j = z_j - sum_r L(j+r, j) w_{j+r}, then interchange j <-> ipiv[j].
+          // win[r] = current value at position j+r; position j+kl becomes final after this step.
+          const int lm = min(kl, n - 1 - j);
+          double s = win[0];
+#pragma unroll
+          for (int r = 1; r <= KW; ++r)
+            if (r <= lm) s = fma(-R(kd + r, j), win[r], s);
+          win[0] = s;
+          const int p = pring[j % SL] - j;
+          if (p != 0) {
+#pragma unroll
+            for (int r = 1; r <= KW; ++r)
+              if (r == p) { const double tmp = win[0]; win[0] = win[r]; win[r] = tmp; }
+          }
+          if (j + kl < n) {
+            double out = 0.0;
+#pragma unroll
+            for (int r = 0; r <= KW; ++r)
+              if (r == kl) out = win[r];
+            x[j + kl] = out;
+          }
+          if (j > 0) {
+#pragma unroll
+            for (int r = KW; r >= 1; --r) win[r] = win[r - 1];
+            win[0] = XR(j - 1);
+          } else {
+#pragma unroll
+            for (int r = 0; r < KW; ++r)
+              if (r < kl && r < n) x[r] = win[r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv, bool trans,
+                        double* X, int ldx, const int* pred, int pred_val, hipStream_t st) {
+  const int kd = kl + ku;
+  if (nrhs < 1 || kd > BAND_KD_MAX) return hipErrorInvalidValue;
+  for (int c0 = 0; c0 < nrhs; c0 += 32) {
+    const int nr = nrhs - c0 < 32 ? nrhs - c0 : 32;
+    const size_t lds = (size_t)4 * BCH2 * ldgb * sizeof(double) + (size_t)4 * BCH2 * nr * sizeof(double) +
+                       (size_t)4 * BCH2 * sizeof(int);
+    double* Xc = X + (size_t)c0 * ldx;
+#define ADA_GBTRS(K)                                                                                         \
+  do {                                                                                                       \
+    static size_t done = 0;                                                                                  \
+    hipError_t e = ensure_lds((const void*)k_gbtrs<K>, lds, done);                                          \
+    if (e != hipSuccess) return e;                                                                           \
+    hipLaunchKernelGGL(k_gbtrs<K>, dim3(1), dim3(256), lds, st, n, kl, ku, nr, GB, ldgb, ipiv, (int)trans, Xc, \
+                       ldx, pred, pred_val);                                                                 \
+  } while (0)
+    const int kw = kd > kl ? kd : kl;
+    if (kw <= 8) ADA_GBTRS(8);
+    else if (kw <= 16) ADA_GBTRS(16);
+    else ADA_GBTRS(32);
+#undef ADA_GBTRS
+  }
+  return hipGetLastError();
+}
+
+// R = B - A X for band-layout input (AB[ku_in + i - j + j*ldab])
+__global__ void k_band_resid(int n, int kl, int ku, int nrhs, const double* __restrict__ AB, int ldab, int ku_in,
+                             const double* __restrict__ B, int ldb, const double* __restrict__ X, int ldx,
+                             double* __restrict__ R, int ldr) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int c = 0; c < nrhs; ++c) {
+      double s = B[(size_t)i + (size_t)c * ldb];
+      for (int j = max(0, i - kl); j <= min(n - 1, i + ku); ++j)
+        s = fma(-AB[(size_t)(ku_in + i - j) + (size_t)j * ldab], X[(size_t)j + (size_t)c * ldx], s);
+      R[(size_t)i + (size_t)c * ldr] = s;
+    }
+  }
+}
+
+hipError_t launch_band_resid(int n, int kl, int ku, int nrhs, const double* AB, int ldab, int ku_in,
+                             const double* B, int ldb, const double* X, int ldx, double* R, int ldr,
+                             hipStream_t st) {
+  int blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_band_resid, dim3(blocks), dim3(256), 0, st, n, kl, ku, nrhs, AB, ldab, ku_in, B, ldb, X, ldx,
+                     R, ldr);
+  return hipGetLastError();
+}
+
+}  // namespace ada

@@ -1,0 +1,334 @@
+// LU with partial pivoting (Section II-D), right-looking and blocked by 128
+// columns. Per block column k0:
+//   k_getrf_panel    factor the m x nb panel W[k0:n, k0:k0+nb] with partial
+//                    pivoting (ties to the lowest row), rows spread over P
+//                    workgroups that keep the panel in registers;
+//   k_laswp_moves    apply the panel's row interchanges to every other column
+//                    (and to the permutation vector used by the solves);
+//   k_trsm_llnu      U12 = L11^{-1} A12 (unit lower, substitution per column);
+//   k_gemm_sub       A22 -= L21 U12 on the matrix cores (gemm.hip).
+//
+// The panel needs one cross-workgroup exchange per column (the pivot search
+// spans all m rows): every workgroup publishes its best candidate and that
+// candidate's row, then all of them meet at a counter; every workgroup then
+// picks the same winner (largest modulus, lowest row on ties) and applies the
+// swap and the rank-1 update to the rows it holds. All waits are bounded.
+#include "ada_internal.h"
+
+#include <climits>
+
+namespace ada {
+
+constexpr int PNB = 128;    // panel width
+constexpr int PROWS = 256;  // panel rows per workgroup = threads per workgroup (one row per thread)
+
+__device__ void grid_wait(unsigned* counter, unsigned target, DevRec* rec) {
+  long spins = 0;
+  while (agent_load(counter) < target) {
+    if (++spins > kSpinLimit) {
+      atomicOr(&rec->timeout, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Each panel row is held in registers by two threads (columns 0-63 and
+// 64-127). The half that holds the current column rotates its registers left
+// by one after every column step, so the current column is always its d[0] and
+// every register index is a constant. Row interchanges are not moved through
+// memory: each row carries its current position `pos`; the pivot row takes
+// position s and the row that sat at s takes the pivot's old position, exactly
+// as an explicit interchange would. Rows are written to their final positions
+// at the end and the list of moved rows is handed to k_laswp_moves.
+constexpr int HC = 64;                 // columns per thread
+constexpr int PTH = 2 * PROWS;         // 512 threads: half h = t / PROWS, row = t % PROWS
+__global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, double* __restrict__ W, int ldw,
+                                                     int* __restrict__ ipiv, DevRec* rec, unsigned* counter,
+                                                     PanelScratch ps) {
+  if (rec->stop) return;
+  const int m = n - k0;
+  const int P = gridDim.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int h = t / PROWS, r = t % PROWS;
+  const int wg = blockIdx.x;
+  const int prow = wg * PROWS + r;
+  const bool rvalid = prow < m;
+  int pos = rvalid ? prow : INT_MAX;
+
+  __shared__ double s_u[PNB];
+  __shared__ double s_l[PROWS];
+  __shared__ double s_cv[4];
+  __shared__ int s_cp[4];
+  __shared__ int s_bp, s_win_pos, s_win_wg;
+  __shared__ double s_bv;
+  extern __shared__ double s_rows[];  // P x PNB candidate rows (P > 1)
+
+  if (wg == 0 && t == 0) __hip_atomic_store(ps.moves, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+  double d[HC];
+  {
+    const double* src = W + (size_t)(k0 + min(prow, m - 1)) + (size_t)k0 * ldw;
+#pragma unroll
+    for (int c = 0; c < HC; ++c) d[c] = src[(size_t)min(HC * h + c, nbw - 1) * ldw];
+#pragma unroll
+    for (int c = 0; c < HC; ++c)
+      if (!rvalid || HC * h + c >= nbw) d[c] = 0.0;
+  }
+
+  for (int s = 0; s < nbw; ++s) {
+    const int par = s & 1;
+    const int hc = s / HC;          // half holding column s (its d[0])
+    const int sl = s % HC;          // rotations that half has done so far
+    const bool cur = (h == hc);
+    // 1. this workgroup's candidate: largest |A(row, s)| over rows at positions >= s, lowest position on ties
+    if (cur) {
+      double v = -1.0;
+      int key = -1;
+      if (rvalid && pos >= s) {
+        v = fabs(d[0]);
+        key = pos;
+      }
+      wave_argmax(v, key);
+      if (lane == 0) { s_cv[w - 4 * hc] = v; s_cp[w - 4 * hc] = key; }
+    }
+    __syncthreads();
+    if (t == 0) {
+      double bv = s_cv[0];
+      int bp = s_cp[0];
+      for (int q = 1; q < 4; ++q) {
+        const int k2 = s_cp[q];
+        const double v2 = s_cv[q];
+        if (k2 >= 0 && (bp < 0 || v2 > bv || (v2 == bv && k2 < bp))) { bv = v2; bp = k2; }
+      }
+      s_bv = bv;
+      s_bp = bp;
+    }
+    __syncthreads();
+    const int bp = s_bp;
+    if (P == 1) {
+      if (rvalid && pos == bp) {
+#pragma unroll
+        for (int c = 0; c < HC; ++c) s_u[HC * h + c] = d[c];
+      }
+      if (t == 0) s_win_pos = bp;
+      __syncthreads();
+    } else {
+      // 2. publish (value, position) and the candidate row, then meet at the counter
+      double* myslot = ps.slot_rows + ((size_t)par * 64 + wg) * PNB;
+      if (rvalid && pos == bp) {
+#pragma unroll
+        for (int c = 0; c < HC; ++c) relaxed_store(myslot + HC * h + c, d[c]);
+        __threadfence();
+      }
+      if (t == 0) {
+        relaxed_store(ps.slot_val + par * 64 + wg, s_bv);
+        __hip_atomic_store(ps.slot_row + par * 64 + wg, bp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+      if (t == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        grid_wait(counter, (unsigned)(s + 1) * (unsigned)P, rec);
+      }
+      __syncthreads();
+      // 3. read every candidate (value, position, row) in one round trip; all workgroups pick the same winner
+      for (int e = t; e < P * PNB; e += PTH) s_rows[e] = relaxed_load(ps.slot_rows + (size_t)par * 64 * PNB + e);
+      if (t < 64) {
+        double cv = -1.0;
+        int ck = -1, cw = t;
+        if (t < P) {
+          cv = relaxed_load(ps.slot_val + par * 64 + t);
+          ck = __hip_atomic_load(ps.slot_row + par * 64 + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double v2 = __shfl_xor(cv, o, 64);
+          const int k2 = __shfl_xor(ck, o, 64);
+          const int w2 = __shfl_xor(cw, o, 64);
+          if (k2 >= 0 && (ck < 0 || v2 > cv || (v2 == cv && k2 < ck))) { cv = v2; ck = k2; cw = w2; }
+        }
+        if (t == 0) { s_win_pos = ck; s_win_wg = cw; }
+      }
+      __syncthreads();
+      if (t < PNB) s_u[t] = s_rows[s_win_wg * PNB + t];
+      __syncthreads();
+    }
+    const int p = s_win_pos;
+    if (wg == 0 && t == 0) ipiv[k0 + s] = k0 + p;
+    // 4. the interchange of positions s and p (bookkeeping only)
+    const bool is_win = rvalid && pos == p;
+    if (rvalid && pos == s && !is_win) pos = p;
+    if (is_win) pos = s;
+    // s_u holds the pivot row in the frames of the two halves: half hc rotated by sl, the others not
+    const double piv = s_u[HC * hc];
+    if (piv == 0.0) {
+      // exact zero pivot: the factorisation has failed (info = first such column)
+      if (wg == 0 && t == 0) atomicMin(&rec->info, k0 + s + 1);
+      __syncthreads();
+    } else {
+      // 5. multiplier (current half) and rank-1 update of this row
+      if (cur && rvalid && pos > s) {
+        const double l = d[0] / piv;
+        d[0] = l;
+        s_l[r] = l;
+      }
+      __syncthreads();
+      if (rvalid && pos > s && h >= hc) {
+        const double l = s_l[r];
+        // current half: columns s+1 .. in d[1 .. live-1]; later halves: all their columns below nbw
+        const int live = cur ? min(HC - sl, nbw - s) : (nbw - HC * h);
+#pragma unroll
+        for (int c = 0; c < HC; ++c)
+          if ((!cur || c >= 1) && c < live) d[c] = fma(-l, s_u[HC * h + c], d[c]);
+      }
+    }
+    // 6. rotate the current half: the finished column moves to the back
+    if (cur) {
+      const double f = d[0];
+#pragma unroll
+      for (int c = 0; c < HC - 1; ++c) d[c] = d[c + 1];
+      d[HC - 1] = f;
+    }
+    __syncthreads();
+  }
+  // half h was rotated rot times (HC rotations restore the order): d[c] holds column HC*h + (c + rot) % HC
+  if (rvalid) {
+    const int rot = max(0, min(HC, nbw - HC * h)) % HC;
+    double* dst = W + (size_t)(k0 + pos) + (size_t)k0 * ldw;
+#pragma unroll
+    for (int c = 0; c < HC; ++c) {
+      const int col = HC * h + (c + rot) % HC;
+      if (col < nbw) dst[(size_t)col * ldw] = d[c];
+    }
+    if (h == 0 && pos != prow) {
+      const int idx = atomicAdd(ps.moves, 1);
+      ps.moves[1 + 2 * idx] = k0 + pos;   // destination row
+      ps.moves[2 + 2 * idx] = k0 + prow;  // source row
+    }
+  }
+}
+
+hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec,
+                              unsigned* counter, PanelScratch ps, hipStream_t st) {
+  const int m = n - k0;
+  const int P = (m + PROWS - 1) / PROWS;
+  if (P > 64) return hipErrorInvalidValue;  // n - k0 <= 16384 per panel
+  const size_t lds = P > 1 ? (size_t)P * PNB * sizeof(double) : 0;
+  hipLaunchKernelGGL(k_getrf_panel, dim3(P), dim3(PTH), lds, st, n, k0, nbw, W, ldw, ipiv, rec, counter, ps);
+  return hipGetLastError();
+}
+
+// Apply the panel's row moves to all columns outside the panel (32 per
+// workgroup) and, in workgroup 0, to the permutation vector.
+__global__ __launch_bounds__(256) void k_laswp_moves(int n, int k0, int nbw, double* __restrict__ W, int ldw,
+                                                     const int* __restrict__ moves, int* __restrict__ perm,
+                                                     DevRec* rec) {
+  if (rec->stop) return;
+  if (rec->info != INT_MAX) {
+    // the panel met an exact zero pivot: the routed solve has failed; later kernels skip
+    if (blockIdx.x == 0 && threadIdx.x == 0) rec->stop = 1;
+    return;
+  }
+  const int cnt = moves[0];
+  if (cnt == 0) return;
+  __shared__ double sv[2 * PNB][33];
+  __shared__ int sp[2 * PNB];
+  const int t = threadIdx.x;
+  const int outside = n - nbw;
+  const int c0 = blockIdx.x * 32;
+  if (c0 < outside) {
+    for (int mi = t; mi < cnt; mi += blockDim.x) {
+      const int src = moves[2 + 2 * mi];
+      for (int c = 0; c < 32; ++c) {
+        const int oc = c0 + c;
+        if (oc >= outside) break;
+        const int col = oc < k0 ? oc : oc + nbw;
+        sv[mi][c] = W[(size_t)src + (size_t)col * ldw];
+      }
+    }
+  }
+  if (blockIdx.x == 0)
+    for (int mi = t; mi < cnt; mi += blockDim.x) sp[mi] = perm[moves[2 + 2 * mi]];
+  __syncthreads();
+  if (c0 < outside) {
+    for (int mi = t; mi < cnt; mi += blockDim.x) {
+      const int dst = moves[1 + 2 * mi];
+      for (int c = 0; c < 32; ++c) {
+        const int oc = c0 + c;
+        if (oc >= outside) break;
+        const int col = oc < k0 ? oc : oc + nbw;
+        W[(size_t)dst + (size_t)col * ldw] = sv[mi][c];
+      }
+    }
+  }
+  if (blockIdx.x == 0)
+    for (int mi = t; mi < cnt; mi += blockDim.x) perm[moves[1 + 2 * mi]] = sp[mi];
+}
+
+hipError_t launch_laswp_moves(int n, int k0, int nbw, double* W, int ldw, const int* moves, int* perm,
+                              DevRec* rec, hipStream_t st) {
+  const int outside = n - nbw;
+  int grid = (outside + 31) / 32;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_laswp_moves, dim3(grid), dim3(256), 0, st, n, k0, nbw, W, ldw, moves, perm, rec);
+  return hipGetLastError();
+}
+
+// U12 = L11^{-1} A12 with L11 the unit lower nbw x nbw block at W(k0,k0) and
+// A12 = W(k0:k0+nbw, k0+nbw : k0+nbw+ncols). One thread per column; L11 is
+// staged in LDS and read as a broadcast; each column is solved by forward
+// substitution in chunks of 32 rows held in registers.
+__global__ __launch_bounds__(256) void k_trsm_llnu(int k0, int nbw, int ncols, double* __restrict__ W, int ldw,
+                                                   const DevRec* rec) {
+  if (rec->stop) return;
+  extern __shared__ double sL[];  // sL[col * nbw + row]
+  const int t = threadIdx.x;
+  for (int e = t; e < nbw * nbw; e += blockDim.x) {
+    const int r = e % nbw, c = e / nbw;
+    sL[e] = W[(size_t)(k0 + r) + (size_t)(k0 + c) * ldw];
+  }
+  __syncthreads();
+  const int jc = blockIdx.x * blockDim.x + t;
+  if (jc >= ncols) return;
+  double* col = W + (size_t)(k0 + nbw + jc) * ldw + k0;
+  const int nch = (nbw + 31) / 32;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = ch * 32;
+    double x[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) x[r] = (r0 + r < nbw) ? col[r0 + r] : 0.0;
+    for (int p = 0; p < ch; ++p) {
+      const int c0 = p * 32;
+      for (int cc = 0; cc < 32; ++cc) {
+        const double y = col[c0 + cc];
+        const double* lc = sL + (size_t)(c0 + cc) * nbw + r0;
+#pragma unroll
+        for (int r = 0; r < 32; ++r)
+          if (r0 + r < nbw) x[r] = fma(-lc[r], y, x[r]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const double* lc = sL + (size_t)(r0 + i) * nbw + r0;
+#pragma unroll
+      for (int r = i + 1; r < 32; ++r)
+        if (r0 + r < nbw) x[r] = fma(-lc[r], x[i], x[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+      if (r0 + r < nbw) col[r0 + r] = x[r];
+  }
+}
+
+hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  const size_t lds = (size_t)nbw * nbw * sizeof(double);
+  static size_t done = 0;
+  hipError_t e = ensure_lds((const void*)k_trsm_llnu, lds, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_trsm_llnu, dim3((ncols + 255) / 256), dim3(256), lds, st, k0, nbw, ncols, W, ldw, rec);
+  return hipGetLastError();
+}
+
+}  // namespace ada

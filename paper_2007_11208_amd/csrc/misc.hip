@@ -1,0 +1,235 @@
+// Copies, row permutations, the residual R = B - A X and the normwise
+// backward error max_k ||r_k||_inf / (||A||_inf ||x_k||_inf + ||b_k||_inf)
+// (an accuracy metric; the paper does not define one).
+#include "ada_internal.h"
+
+namespace ada {
+
+__global__ void k_copy(int rows, int cols, const double* __restrict__ S, int lds, double* __restrict__ D, int ldd) {
+  const size_t total = (size_t)rows * cols;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e % rows, j = e / rows;
+    D[i + j * ldd] = S[i + j * lds];
+  }
+}
+
+hipError_t launch_copy(int rows, int cols, const double* S, int lds, double* D, int ldd, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  size_t total = (size_t)rows * cols;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, rows, cols, S, lds, D, ldd);
+  return hipGetLastError();
+}
+
+__global__ void k_iota(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
+}
+
+hipError_t launch_iota(int* p, int n, hipStream_t st) {
+  int blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_iota, dim3(blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+// D[i,:] = S[perm[i],:]  (P b, perm[i] = original row now at position i)
+__global__ void k_gather_rows(int n, int nrhs, const int* __restrict__ perm, const double* __restrict__ S, int lds,
+                              double* __restrict__ D, int ldd, const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  const size_t total = (size_t)n * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    D[(size_t)i + (size_t)c * ldd] = S[(size_t)perm[i] + (size_t)c * lds];
+  }
+}
+
+// D[perm[i],:] = S[i,:]  (P^T w)
+__global__ void k_scatter_rows(int n, int nrhs, const int* __restrict__ perm, const double* __restrict__ S, int lds,
+                               double* __restrict__ D, int ldd, const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  const size_t total = (size_t)n * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    D[(size_t)perm[i] + (size_t)c * ldd] = S[(size_t)i + (size_t)c * lds];
+  }
+}
+
+hipError_t launch_gather_rows(int n, int nrhs, const int* perm, const double* S, int lds, double* D, int ldd,
+                              const int* pred, int pred_val, hipStream_t st) {
+  size_t total = (size_t)n * nrhs;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_gather_rows, dim3(blocks), dim3(256), 0, st, n, nrhs, perm, S, lds, D, ldd, pred, pred_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(int n, int nrhs, const int* perm, const double* S, int lds, double* D, int ldd,
+                               const int* pred, int pred_val, hipStream_t st) {
+  size_t total = (size_t)n * nrhs;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(blocks), dim3(256), 0, st, n, nrhs, perm, S, lds, D, ldd, pred, pred_val);
+  return hipGetLastError();
+}
+
+// R = B - A X for up to 8 right-hand sides: rows over threads, the n columns of A
+// split into chunks over blockIdx.y; partial sums go to P[chunk][c][i] and are
+// added in chunk order by k_resid_sum (deterministic).
+constexpr int RCH = 512;  // columns of A per chunk
+__global__ __launch_bounds__(256) void k_resid_part(int n, int nrhs, const double* __restrict__ A, int lda,
+                                                    const double* __restrict__ X, int ldx, double* __restrict__ P) {
+  __shared__ double sx[64][8];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.y * RCH, j1 = min(n, j0 + RCH);
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int jb = j0; jb < j1; jb += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 8; e += blockDim.x) {
+      const int jj = e / 8, c = e % 8;
+      sx[jj][c] = (jb + jj < j1 && c < nrhs) ? X[(size_t)(jb + jj) + (size_t)c * ldx] : 0.0;
+    }
+    __syncthreads();
+    if (i < n) {
+      const int jn = min(64, j1 - jb);
+      for (int jj = 0; jj < jn; ++jj) {
+        const double a = A[(size_t)i + (size_t)(jb + jj) * lda];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fma(a, sx[jj][c], acc[c]);
+      }
+    }
+  }
+  if (i < n)
+    for (int c = 0; c < nrhs; ++c) P[((size_t)blockIdx.y * nrhs + c) * n + i] = acc[c];
+}
+
+__global__ void k_resid_sum(int n, int nrhs, int nch, const double* __restrict__ B, int ldb,
+                            const double* __restrict__ P, double* __restrict__ R, int ldr) {
+  const size_t total = (size_t)n * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    double s = 0.0;
+    for (int q = 0; q < nch; ++q) s += P[((size_t)q * nrhs + c) * n + i];
+    R[(size_t)i + (size_t)c * ldr] = B[(size_t)i + (size_t)c * ldb] - s;
+  }
+}
+
+// P must hold ceil(n/RCH) * nrhs * n doubles (nrhs <= 8); for more right-hand
+// sides the caller uses the matrix-core GEMM.
+hipError_t launch_resid_gemv(int n, int nrhs, const double* A, int lda, const double* B, int ldb, const double* X,
+                             int ldx, double* R, int ldr, double* P, hipStream_t st) {
+  if (nrhs > 8) return hipErrorInvalidValue;
+  const int nch = (n + RCH - 1) / RCH;
+  hipLaunchKernelGGL(k_resid_part, dim3((n + 255) / 256, nch), dim3(256), 0, st, n, nrhs, A, lda, X, ldx, P);
+  size_t total = (size_t)n * nrhs;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_resid_sum, dim3(blocks), dim3(256), 0, st, n, nrhs, nch, B, ldb, P, R, ldr);
+  return hipGetLastError();
+}
+
+// one workgroup per right-hand side
+__global__ __launch_bounds__(256) void k_berr_col(int n, const double* __restrict__ R, int ldr,
+                                                  const double* __restrict__ B, int ldb,
+                                                  const double* __restrict__ X, int ldx, double* per_col,
+                                                  DevRec* rec) {
+  const int c = blockIdx.x;
+  double rn = 0.0, xn = 0.0, bn = 0.0;
+  int nf = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = R[(size_t)i + (size_t)c * ldr];
+    const double x = X[(size_t)i + (size_t)c * ldx];
+    const double b = B[(size_t)i + (size_t)c * ldb];
+    nf |= !isfinite(x);
+    rn = fmax(rn, fabs(r));
+    xn = fmax(xn, fabs(x));
+    bn = fmax(bn, fabs(b));
+  }
+  rn = wave_max(rn);
+  xn = wave_max(xn);
+  bn = wave_max(bn);
+  nf = wave_or(nf);
+  __shared__ double s[4][3];
+  __shared__ int snf[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { s[w][0] = rn; s[w][1] = xn; s[w][2] = bn; snf[w] = nf; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b2 = 0, d = 0;
+    int f = 0;
+    for (int q = 0; q < 4; ++q) { a = fmax(a, s[q][0]); b2 = fmax(b2, s[q][1]); d = fmax(d, s[q][2]); f |= snf[q]; }
+    const double den = rec->anorm_inf * b2 + d;
+    double eta = den > 0.0 ? a / den : (a > 0.0 ? INFINITY : 0.0);
+    if (f) eta = __longlong_as_double(0x7ff8000000000000LL);
+    per_col[c] = eta;
+    if (f) atomicOr(&rec->x_nonfinite, 1);
+  }
+}
+
+__global__ void k_berr_max(int nrhs, const double* per_col, DevRec* rec) {
+  double m = 0.0;
+  bool nan = false;
+  for (int c = 0; c < nrhs; ++c) {
+    const double v = per_col[c];
+    if (v != v) nan = true;
+    else m = fmax(m, v);
+  }
+  rec->berr = nan ? __longlong_as_double(0x7ff8000000000000LL) : m;
+}
+
+hipError_t launch_berr(int n, int nrhs, const double* R, int ldr, const double* B, int ldb, const double* X,
+                       int ldx, double* per_col, DevRec* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_berr_col, dim3(nrhs), dim3(256), 0, st, n, R, ldr, B, ldb, X, ldx, per_col, rec);
+  hipLaunchKernelGGL(k_berr_max, dim3(1), dim3(1), 0, st, nrhs, per_col, rec);
+  return hipGetLastError();
+}
+
+// x finiteness only (used when the backward error is not requested)
+__global__ void k_x_finite(int n, int nrhs, const double* __restrict__ X, int ldx, DevRec* rec) {
+  const size_t total = (size_t)n * nrhs;
+  int bad = 0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e % n, c = e / n;
+    bad |= !isfinite(X[i + c * ldx]);
+  }
+  bad = wave_or(bad);
+  if ((threadIdx.x & 63) == 0 && bad) atomicOr(&rec->x_nonfinite, 1);
+}
+
+hipError_t launch_x_finite(int n, int nrhs, const double* X, int ldx, DevRec* rec, hipStream_t st) {
+  size_t total = (size_t)n * nrhs;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_x_finite, dim3(blocks), dim3(256), 0, st, n, nrhs, X, ldx, rec);
+  return hipGetLastError();
+}
+
+__global__ void k_set_identity(int n, double* V, int ldv) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e % n, j = e / n;
+    V[i + j * ldv] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_set_identity(int n, double* V, int ldv, hipStream_t st) {
+  size_t total = (size_t)n * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_set_identity, dim3(blocks), dim3(256), 0, st, n, V, ldv);
+  return hipGetLastError();
+}
+
+// mark the routed solve as failed when the factorisation reported a zero pivot
+__global__ void k_mark_stop(DevRec* rec) {
+  if (rec->info != 0x7fffffff) rec->stop = 1;
+}
+
+hipError_t launch_mark_stop(DevRec* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_stop, dim3(1), dim3(1), 0, st, rec);
+  return hipGetLastError();
+}
+
+}  // namespace ada

@@ -1,0 +1,248 @@
+// SVD-based minimum-norm least-squares fallback (Section II-E) by one-sided
+// (Hestenes) Jacobi on the columns of U (a copy of A), with V accumulating the
+// rotations. Pairs are visited in round-robin (tournament) order, so the
+// n/2 pairs of a round are disjoint and are rotated in parallel. A pair is
+// rotated when |u_p^T u_q| > n*eps*||u_p|| ||u_q||, with Rutishauser's
+// formulas. After convergence sigma_j = ||u_j||, and
+// x = sum_{sigma_j > eps*sigma_max} v_j (u_j^T b) / sigma_j^2.
+#include "ada_internal.h"
+
+namespace ada {
+
+__device__ __forceinline__ void rr_pair(int m, int r, int pi, int& a, int& b) {
+  if (pi == 0) {
+    a = r;
+    b = m - 1;
+  } else {
+    a = (r + pi) % (m - 1);
+    b = (r - pi + m - 1) % (m - 1);
+  }
+}
+
+__device__ __forceinline__ void rotation(double alpha, double beta, double gamma, double& c, double& s) {
+  const double zeta = (beta - alpha) / (2.0 * gamma);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = c * t;
+}
+
+// whole algorithm in one workgroup (small n); U, V stay in L2
+__global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* U, int ldu, double* V, int ldv, int max_sweeps,
+                                                       DevRec* rec) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+  const int m = (n + 1) & ~1;
+  const double tol = (double)n * kEps;
+  __shared__ int s_rot;
+  int sweeps = 0;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    if (t == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      for (int pi = w; pi < m / 2; pi += nw) {
+        int a, b;
+        rr_pair(m, r, pi, a, b);
+        if (a >= n || b >= n) continue;
+        const int p = min(a, b), q = max(a, b);
+        double* up = U + (size_t)p * ldu;
+        double* uq = U + (size_t)q * ldu;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < n; i += 64) {
+          const double x = up[i], y = uq[i];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+        double c, s;
+        rotation(al, be, ga, c, s);
+        for (int i = lane; i < n; i += 64) {
+          const double x = up[i], y = uq[i];
+          up[i] = c * x - s * y;
+          uq[i] = s * x + c * y;
+        }
+        double* vp = V + (size_t)p * ldv;
+        double* vq = V + (size_t)q * ldv;
+        for (int i = lane; i < n; i += 64) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = c * x - s * y;
+          vq[i] = s * x + c * y;
+        }
+        if (lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (!rot) { ++sweeps; break; }
+  }
+  if (t == 0) rec->sweeps = sweeps;
+}
+
+hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, int max_sweeps, DevRec* rec,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), 0, st, n, U, ldu, V, ldv, max_sweeps, rec);
+  return hipGetLastError();
+}
+
+// one round of the tournament, one pair per workgroup
+__global__ __launch_bounds__(256) void k_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv,
+                                                      DevRec* rec) {
+  int a, b;
+  rr_pair(m, round, blockIdx.x, a, b);
+  if (a >= n || b >= n) return;
+  const int p = min(a, b), q = max(a, b);
+  const int t = threadIdx.x;
+  double* up = U + (size_t)p * ldu;
+  double* uq = U + (size_t)q * ldu;
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = t; i < n; i += blockDim.x) {
+    const double x = up[i], y = uq[i];
+    al = fma(x, x, al);
+    be = fma(y, y, be);
+    ga = fma(x, y, ga);
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  __shared__ double s[3][4];
+  const int w = t >> 6;
+  if ((t & 63) == 0) { s[0][w] = al; s[1][w] = be; s[2][w] = ga; }
+  __syncthreads();
+  al = s[0][0] + s[0][1] + s[0][2] + s[0][3];
+  be = s[1][0] + s[1][1] + s[1][2] + s[1][3];
+  ga = s[2][0] + s[2][1] + s[2][2] + s[2][3];
+  const double tol = (double)n * kEps;
+  if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) return;
+  double c, sn;
+  rotation(al, be, ga, c, sn);
+  for (int i = t; i < n; i += blockDim.x) {
+    const double x = up[i], y = uq[i];
+    up[i] = c * x - sn * y;
+    uq[i] = sn * x + c * y;
+  }
+  double* vp = V + (size_t)p * ldv;
+  double* vq = V + (size_t)q * ldv;
+  for (int i = t; i < n; i += blockDim.x) {
+    const double x = vp[i], y = vq[i];
+    vp[i] = c * x - sn * y;
+    vq[i] = sn * x + c * y;
+  }
+  if (t == 0) atomicOr(&rec->jacobi_rotated, 1);
+}
+
+hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, DevRec* rec,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_round, dim3(m / 2), dim3(256), 0, st, n, m, round, U, ldu, V, ldv, rec);
+  return hipGetLastError();
+}
+
+__global__ void k_clear_rotated(DevRec* rec) { rec->jacobi_rotated = 0; }
+
+hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_rotated, dim3(1), dim3(1), 0, st, rec);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_colnorms(int n, const double* U, int ldu, double* sigma) {
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double x = U[(size_t)i + (size_t)j * ldu];
+    s = fma(x, x, s);
+  }
+  s = wave_sum(s);
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) sigma[j] = sqrt(sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(1024) void k_sigma_stats(int n, const double* sigma, DevRec* rec) {
+  __shared__ double sm[16];
+  __shared__ int sc[16];
+  double m = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) m = fmax(m, sigma[j]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double mx = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) mx = fmax(mx, sm[q]);
+  const double cut = kEps * mx;
+  int cnt = 0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) cnt += sigma[j] > cut ? 1 : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += sc[q];
+    rec->sigma_max = mx;
+    rec->rank = tot;
+  }
+}
+
+// T[k][c] = (u_k^T b_c) / sigma_k^2 for kept k, else 0 ; one workgroup per k
+__global__ __launch_bounds__(256) void k_utb(int n, int nrhs, const double* U, int ldu, const double* B, int ldb,
+                                             const double* sigma, const DevRec* rec, double* T) {
+  const int k = blockIdx.x;
+  const double sk = sigma[k];
+  const bool keep = sk > kEps * rec->sigma_max;
+  __shared__ double sh[4];
+  for (int c = 0; c < nrhs; ++c) {
+    double s = 0.0;
+    if (keep)
+      for (int i = threadIdx.x; i < n; i += blockDim.x)
+        s = fma(U[(size_t)i + (size_t)k * ldu], B[(size_t)i + (size_t)c * ldb], s);
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) T[(size_t)k + (size_t)c * n] = keep ? (sh[0] + sh[1] + sh[2] + sh[3]) / (sk * sk) : 0.0;
+    __syncthreads();
+  }
+}
+
+// X = V T, eight right-hand sides per pass
+__global__ __launch_bounds__(256) void k_vt(int n, int nrhs, int c0, const double* V, int ldv, const double* T,
+                                            double* X, int ldx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double st[64][8];
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  const int nc = min(8, nrhs - c0);
+  for (int kb = 0; kb < n; kb += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 8; e += blockDim.x) {
+      const int kk = e / 8, c = e % 8;
+      st[kk][c] = (kb + kk < n && c < nc) ? T[(size_t)(kb + kk) + (size_t)(c0 + c) * n] : 0.0;
+    }
+    __syncthreads();
+    if (i < n) {
+      const int kn = min(64, n - kb);
+      for (int kk = 0; kk < kn; ++kk) {
+        const double v = V[(size_t)i + (size_t)(kb + kk) * ldv];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fma(v, st[kk][c], acc[c]);
+      }
+    }
+  }
+  if (i < n)
+    for (int c = 0; c < nc; ++c) X[(size_t)i + (size_t)(c0 + c) * ldx] = acc[c];
+}
+
+hipError_t launch_svd_apply(int n, int nrhs, const double* U, int ldu, const double* V, int ldv, const double* B,
+                            int ldb, double* X, int ldx, double* sigma, double* T, DevRec* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorms, dim3(n), dim3(256), 0, st, n, U, ldu, sigma);
+  hipLaunchKernelGGL(k_sigma_stats, dim3(1), dim3(1024), 0, st, n, sigma, rec);
+  hipLaunchKernelGGL(k_utb, dim3(n), dim3(256), 0, st, n, nrhs, U, ldu, B, ldb, sigma, rec, T);
+  for (int c0 = 0; c0 < nrhs; c0 += 8)
+    hipLaunchKernelGGL(k_vt, dim3((n + 255) / 256), dim3(256), 0, st, n, nrhs, c0, V, ldv, T, X, ldx);
+  return hipGetLastError();
+}
+
+}  // namespace ada
