@@ -62,6 +62,13 @@ inline hipError_t ensure_lds(const void* fn, size_t bytes, size_t& done) {
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // -------- device helpers --------
+// value of v in lane l (l uniform across the wave)
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -179,6 +186,25 @@ hipError_t launch_band_norms(int n, int kl, int ku, const double* GB, int ldgb, 
 hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, DevRec* rec, hipStream_t st);
 hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv, bool trans,
                         double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
+// band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles
+enum { SW_L = 0, SW_U = 1, SW_UT = 2, SW_LT = 3 };
+constexpr int LC = 512;  // steps per chunk of the parallel band sweeps
+struct BandSweep {
+  const double* GB;
+  int ldgb, kl, ku, n;
+  const int* ipiv;
+  int nrhs_all;
+  int piece;  // steps staged in LDS at a time
+};
+struct BandScratch {
+  double* Phi;
+  double* phi;
+  double* entry;
+};
+hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv,
+                                bool trans, double* X, int ldx, double* T, int ldt, BandScratch sc, const int* pred,
+                                int pred_val, hipStream_t st);
+size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs);
 hipError_t launch_band_resid(int n, int kl, int ku, int nrhs, const double* AB, int ldab, int ku_in,
                              const double* B, int ldb, const double* X, int ldx, double* R, int ldr,
                              hipStream_t st);

@@ -38,12 +38,14 @@ constexpr int kDenseMax = 16384;  // dense routes: the panel kernel spreads at m
 constexpr int kBandKdMax = 31;    // band kernels: kl + ku
 constexpr int kBandDenseMax = 4096;  // band-layout input expanded to dense when needed (not banded / SVD)
 constexpr int kJacobiSmall = 256;    // one-workgroup Jacobi up to this n
+constexpr int kBandChunkMin = 2 * LC;  // band solves parallel over the rows from this n on
 
 struct Plan {
   size_t total = 0;
   // offsets (bytes)
   size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, slot_val, slot_row,
-      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense;
+      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc;
+  size_t bsc_doubles;
   int n, nrhs, ldw, T64, nflags;
   bool dense, band, band_dense;
 };
@@ -75,7 +77,15 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
   p.et = take(cur, N * 8);
   p.exi = take(cur, N * 8);
   p.R = take(cur, N * nrhs * 8);
+  p.T = take(cur, N * nrhs * 8);
   p.percol = take(cur, (size_t)nrhs * 8);
+  {
+    // scratch of the row-parallel band solves: the band width of band-layout
+    // input, the widest band the kernels take otherwise
+    const int kd = p.band ? (o.kl_in + o.ku_in) : kBandKdMax;
+    p.bsc_doubles = band_chunked_scratch_doubles(n, kd, 0, nrhs);
+    p.bsc = take(cur, p.bsc_doubles * 8);
+  }
   if (p.dense) p.P = take(cur, (size_t)((n + 511) / 512) * 8 * N * 8);
   // W: dense working copy (LU/Cholesky factor, Jacobi U) and/or the band factor (2kl+ku+1 rows)
   size_t wrows = (size_t)n;
@@ -95,7 +105,6 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     p.csym = take(cur, N * 8);
     p.rtot = take(cur, N * 8);
     p.V = take(cur, N * N * 8);
-    p.T = take(cur, N * nrhs * 8);
     p.sigma = take(cur, N * 8);
     p.slot_val = take(cur, 2 * 64 * 8);
     p.slot_row = take(cur, 2 * 64 * 4);
@@ -224,6 +233,24 @@ struct Solve {
 // Each route leaves X = the routed solution (when the factorisation succeeded),
 // rec->info / rec->stop, rec->anorm1, and runs the condition estimate.
 
+// op(A) X = X with the band LU in GB (in place; T: n x nrhs scratch)
+int band_solve(Solve& s, const double* GB, int kl, int ku, bool trans, double* X, int ldx, int nrhs, double* T,
+               int ldt, const int* pred, int pred_val) {
+  const int n = s.n, ldgb = 2 * kl + ku + 1;
+  const int* ipiv = s.at<int>(s.p.ipiv);
+  if (n >= kBandChunkMin) {
+    if (band_chunked_scratch_doubles(n, kl, ku, nrhs) > s.p.bsc_doubles)
+      return fail(ADA_ERR_ARG, "band scratch smaller than the band width needs");
+    double* b = s.at<double>(s.p.bsc);
+    const size_t nch = (size_t)(n + LC - 1) / LC, S = (size_t)(kl + ku > 1 ? kl + ku : 1);
+    BandScratch sc{b, b + nch * S * S, b + nch * S * S + nch * (size_t)nrhs * S};
+    HIPCHK(launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, T, ldt, sc, pred, pred_val, s.st));
+  } else {
+    HIPCHK(launch_gbtrs(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, pred, pred_val, s.st));
+  }
+  return ADA_OK;
+}
+
 int estimate(Solve& s, int route_kind, const double* F, int ldf, bool tri_lower, int kl, int ku) {
   // route_kind: 0 LU (F = LU, perm), 1 Cholesky (F = L), 2 triangular (F = A), 3 band (F = GB)
   const int n = s.n;
@@ -253,8 +280,7 @@ int estimate(Solve& s, int route_kind, const double* F, int ldf, bool tri_lower,
     } else if (route_kind == 2) {
       TRY(s.trsm(F, ldf, tri_lower, type == 2, false, v, n, 1, phase, type));
     } else {
-      const int ldgb = 2 * kl + ku + 1;
-      HIPCHK(launch_gbtrs(n, kl, ku, 1, F, ldgb, s.at<int>(s.p.ipiv), type == 2, v, n, phase, type, s.st));
+      TRY(band_solve(s, F, kl, ku, type == 2, v, n, 1, t, n, phase, type));
     }
     HIPCHK(launch_est_step(n, type, result, v, xi, s.rec, s.st));
   }
@@ -326,7 +352,7 @@ int route_band(Solve& s, const double* GB, int kl, int ku, const double* B, int 
   HIPCHK(launch_gbtrf(n, kl, ku, const_cast<double*>(GB), ldgb, s.at<int>(s.p.ipiv), s.rec, s.st));
   int* stop = &s.rec->stop;
   HIPCHK(launch_copy(n, s.nrhs, B, ldb, X, ldx, s.st));
-  HIPCHK(launch_gbtrs(n, kl, ku, s.nrhs, GB, ldgb, s.at<int>(s.p.ipiv), false, X, ldx, stop, 0, s.st));
+  TRY(band_solve(s, GB, kl, ku, false, X, ldx, s.nrhs, s.at<double>(s.p.T), n, stop, 0));
   return estimate(s, 3, GB, ldgb, false, kl, ku);
 }
 

@@ -114,17 +114,24 @@ hipError_t launch_band_norms(int n, int kl, int ku, const double* GB, int ldgb, 
 constexpr int BAND_KD_MAX = 31;
 constexpr int BCH2 = 32;  // chunk length; the LDS rings hold 4 chunks
 
+// Window of the band LU at step j: columns j .. j+kd, rows j .. j+kl. Lane c
+// (c < W = kd+1) permanently owns the columns congruent to c modulo W, so the
+// window advances without moving data between lanes: the lane whose column is
+// finished takes the column that enters on the right. Each lane keeps rows
+// j .. j+kl of its column in registers; the scalars the step broadcasts (pivot
+// index, pivot, multipliers) are read with readlane. LDS ring: 4 chunks of
+// `chf` columns, streamed by three loader waves two chunks ahead.
 template <int KLM>
 __global__ __launch_bounds__(256) void k_gbtrf(int n, int kl, int ku, double* __restrict__ GB, int ldgb,
-                                               int* __restrict__ ipiv, DevRec* rec) {
-  const int kd = kl + ku;
+                                               int* __restrict__ ipiv, DevRec* rec, int chf) {
+  const int kd = kl + ku, W = kd + 1;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  constexpr int SL = 4 * BCH2;
+  const int SL = 4 * chf;
   extern __shared__ double ring[];  // ring[(col % SL) * ldgb + r] = original GB column
-  const int nch = (n + BCH2 - 1) / BCH2;
+  const int nch = (n + chf - 1) / chf;
   auto load_chunk = [&](int q) {
     if (q < 0 || q >= nch) return;
-    const int c0 = q * BCH2, c1 = min(n, c0 + BCH2);
+    const int c0 = q * chf, c1 = min(n, c0 + chf);
     const int cnt = (c1 - c0) * ldgb;
     for (int e = t - 64; e < cnt; e += 192) {
       const int r = e % ldgb, c = c0 + e / ldgb;
@@ -138,78 +145,83 @@ __global__ __launch_bounds__(256) void k_gbtrf(int n, int kl, int ku, double* __
   double v[KLM + 1];
 #pragma unroll
   for (int r = 0; r <= KLM; ++r) v[r] = 0.0;
-  if (w == 0 && lane <= kd && lane < n) {
+  if (w == 0 && lane < W && lane < n) {
 #pragma unroll
     for (int r = 0; r <= KLM; ++r)
       if (r <= kl && r < n) v[r] = R(kd + r - lane, lane);
   }
   int info = INT_MAX;
+  int cl = 0;  // lane holding column j
   for (int q = 0; q < nch; ++q) {
     if (w >= 1) load_chunk(q + 2);
     if (w == 0) {
-      const int jend = min(n, (q + 1) * BCH2);
-      for (int j = q * BCH2; j < jend; ++j) {
+      const int jend = min(n, (q + 1) * chf);
+      for (int j = q * chf; j < jend; ++j) {
+        int o = lane - cl;  // this lane's column is j + o
+        if (o < 0) o += W;
+        const int mycol = j + o;
+        // the entry that joins this lane's registers for step j+1 (prefetched now, off the chain)
+        const int o1 = (o == 0) ? kd : o - 1;  // offset of this lane's column at step j+1
+        const int col1 = j + 1 + o1;
+        const int row1 = j + 1 + kl;
+        const double nxt = (lane < W && row1 < n && col1 < n) ? R(kd + kl - o1, col1) : 0.0;
         const int lm = min(kl, n - 1 - j);
+        // pivot search in the lane of column j (first maximum)
         int p = 0;
-        if (lane == 0) {
+        if (lane == cl) {
           double best = fabs(v[0]);
 #pragma unroll
-          for (int r = 1; r <= KLM; ++r)
-            if (r <= lm && fabs(v[r]) > best) { best = fabs(v[r]); p = r; }
+          for (int r = 1; r <= KLM; ++r) {
+            const double a = fabs(v[r]);
+            const bool take = (r <= lm) && (a > best);
+            best = take ? a : best;
+            p = take ? r : p;
+          }
           ipiv[j] = j + p;
         }
-        p = __shfl(p, 0, 64);
-        if (p != 0) {
+        p = __builtin_amdgcn_readlane(p, cl);
 #pragma unroll
-          for (int r = 1; r <= KLM; ++r)
-            if (r == p) { const double tmp = v[0]; v[0] = v[r]; v[r] = tmp; }
+        for (int r = 1; r <= KLM; ++r) {
+          const bool sw = (r == p);
+          const double a = v[0], b = v[r];
+          v[0] = sw ? b : a;
+          v[r] = sw ? a : b;
         }
-        const double piv = __shfl(v[0], 0, 64);
+        const double piv = read_lane(v[0], cl);
         if (piv == 0.0) {
           if (info == INT_MAX) info = j + 1;
         } else {
-          if (lane == 0) {
+          const double rp = 1.0 / piv;
+          if (lane == cl) {
 #pragma unroll
             for (int r = 1; r <= KLM; ++r)
-              if (r <= lm) v[r] = v[r] / piv;
+              if (r <= lm) v[r] *= rp;
           }
           double l[KLM + 1];
 #pragma unroll
-          for (int r = 1; r <= KLM; ++r) l[r] = __shfl(v[r], 0, 64);
-          if (lane >= 1 && lane <= kd && j + lane < n) {
+          for (int r = 1; r <= KLM; ++r) l[r] = read_lane(v[r], cl);
+          if (lane < W && o >= 1 && mycol < n) {
 #pragma unroll
             for (int r = 1; r <= KLM; ++r)
               if (r <= lm) v[r] = fma(-l[r], v[0], v[r]);
           }
         }
-        // column j is final (U(j,j) and the multipliers); row j of U is final in every lane
-        if (lane == 0) {
+        // column j is final (U(j,j) and the multipliers); row j of U is final in every other lane
+        if (lane == cl) {
 #pragma unroll
           for (int r = 0; r <= KLM; ++r)
             if (r <= lm) GB[(size_t)(kd + r) + (size_t)j * ldgb] = v[r];
-        } else if (lane <= kd && j + lane < n) {
-          GB[(size_t)(kd - lane) + (size_t)(j + lane) * ldgb] = v[0];
+        } else if (lane < W && mycol < n) {
+          GB[(size_t)(kd - o) + (size_t)mycol * ldgb] = v[0];
         }
-        // slide the window one column right and one row down
+        // advance: rows move up one register; the finished lane starts column j+W (fill rows are zero)
 #pragma unroll
-        for (int r = 0; r < KLM; ++r) v[r] = __shfl_down(v[r + 1], 1, 64);
+        for (int r = 0; r < KLM; ++r) v[r] = (lane == cl) ? 0.0 : v[r + 1];
         v[KLM] = 0.0;
-        const int col = j + 1 + lane;
-        if (lane == kd) {
 #pragma unroll
-          for (int r = 0; r < KLM; ++r)
-            v[r] = (r < kl && col < n && j + 1 + r < n) ? R(r, col) : 0.0;
-        }
-        if (lane <= kd) {
-          const int row = j + 1 + kl;
-          const double nv = (row < n && col < n) ? R(kd + kl - lane, col) : 0.0;
-#pragma unroll
-          for (int r = 0; r <= KLM; ++r)
-            if (r == kl) v[r] = nv;
-        } else {
-#pragma unroll
-          for (int r = 0; r <= KLM; ++r) v[r] = 0.0;
-        }
+        for (int r = 0; r <= KLM; ++r)
+          if (r == kl) v[r] = nxt;
+        cl = (cl + 1 == W) ? 0 : cl + 1;
       }
     }
     __syncthreads();
@@ -223,13 +235,14 @@ __global__ __launch_bounds__(256) void k_gbtrf(int n, int kl, int ku, double* __
 hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, DevRec* rec, hipStream_t st) {
   const int kd = kl + ku;
   if (kd > BAND_KD_MAX) return hipErrorInvalidValue;
-  const size_t lds = (size_t)4 * BCH2 * ldgb * sizeof(double);
+  const int chf = ldgb <= 32 ? 128 : 64;  // chunk length > kd + 1 keeps the window inside two chunks
+  const size_t lds = (size_t)4 * chf * ldgb * sizeof(double);
 #define ADA_GBTRF(K)                                                                                         \
   do {                                                                                                       \
     static size_t done = 0;                                                                                  \
     hipError_t e = ensure_lds((const void*)k_gbtrf<K>, lds, done);                                          \
     if (e != hipSuccess) return e;                                                                           \
-    hipLaunchKernelGGL(k_gbtrf<K>, dim3(1), dim3(256), lds, st, n, kl, ku, GB, ldgb, ipiv, rec);            \
+    hipLaunchKernelGGL(k_gbtrf<K>, dim3(1), dim3(256), lds, st, n, kl, ku, GB, ldgb, ipiv, rec, chf);       \
   } while (0)
   if (kl <= 4) ADA_GBTRF(4);
   else if (kl <= 8) ADA_GBTRF(8);

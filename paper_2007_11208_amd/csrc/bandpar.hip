@@ -1,0 +1,346 @@
+// Band solves for long bands (Section II-A route), parallel over the rows.
+//
+// Each sweep of a band solve (L with interchanges forward, U backward, U^T
+// forward, L^T with interchanges backward) is a linear recurrence on a short
+// state vector: the S values later rows still need (S = kl for the L sweeps,
+// kl+ku for the U sweeps). Cut the n steps into chunks of LC steps; a chunk
+// maps its entry state s to its exit state Phi s + phi. So
+//   phase 1  every chunk computes Phi (propagating the S unit vectors with zero
+//            input) and phi (propagating the right-hand side from a zero
+//            state), all chunks in parallel;
+//   phase 2  one short sequential scan over the chunks gives every chunk its
+//            true entry state;
+//   phase 3  every chunk replays its steps from that state and writes its rows.
+// A sweep reads one buffer and writes another (chunks read rows that a
+// neighbouring chunk writes). The band data is staged through LDS in pieces.
+#include "ada_internal.h"
+
+namespace ada {
+
+constexpr int CPW = 4;  // chunks per workgroup (one group of 64 threads each)
+constexpr size_t kLdsMax = 160 * 1024;
+
+__host__ __device__ inline int sweep_state(int kind, int kl, int ku) {
+  return (kind == SW_L || kind == SW_LT) ? kl : kl + ku;
+}
+__host__ __device__ inline bool sweep_fwd(int kind) { return kind == SW_L || kind == SW_UT; }
+
+struct Stage {
+  double* col;  // [piece + 2*halo][ldgb]
+  int* piv;     // [piece + 2*halo]
+  int base;     // first staged column
+};
+
+// One step of a sweep. st: state; in: value entering at this step; returns the
+// value finalised by the step in `out` and its row in `outpos` (-1 for none).
+template <int KIND, int SM>
+__device__ __forceinline__ void band_step(double (&st)[SM], int S, double in, int j, int n, int kl, int kd,
+                                          int ldgb, const Stage& sg, double& out, int& outpos) {
+  const double* colj = sg.col + (size_t)(j - sg.base) * ldgb;
+  if (KIND == SW_L) {
+    // window: positions j .. j+kl-1 (state) and b_{j+kl} (in); interchange, emit y_j, eliminate
+    double w[SM + 1];
+#pragma unroll
+    for (int r = 0; r < SM; ++r) w[r] = st[r];
+    w[SM] = 0.0;
+#pragma unroll
+    for (int r = 0; r <= SM; ++r)
+      if (r == kl) w[r] = in;
+    const int p = sg.piv[j - sg.base] - j;
+#pragma unroll
+    for (int r = 1; r <= SM; ++r) {
+      const bool sw = (r == p);
+      const double a = w[0], b = w[r];
+      w[0] = sw ? b : a;
+      w[r] = sw ? a : b;
+    }
+    out = w[0];
+    outpos = j;
+    const int lm = min(kl, n - 1 - j);
+#pragma unroll
+    for (int r = 1; r <= SM; ++r)
+      if (r <= lm) w[r] = fma(-colj[kd + r], w[0], w[r]);
+#pragma unroll
+    for (int r = 0; r < SM; ++r) st[r] = (r < S) ? w[r + 1] : 0.0;
+  } else if (KIND == SW_U) {
+    // x_j = (y_j - sum_k U(j, j+k) x_{j+k}) / U(j,j); st[k-1] = x_{j+k}
+    double s = in;
+#pragma unroll
+    for (int k = 1; k <= SM; ++k)
+      if (k <= kd && j + k < n) s = fma(-sg.col[(size_t)(j + k - sg.base) * ldgb + kd - k], st[k - 1], s);
+    s = s / colj[kd];
+    out = s;
+    outpos = j;
+#pragma unroll
+    for (int k = SM - 1; k >= 1; --k) st[k] = st[k - 1];
+    st[0] = s;
+  } else if (KIND == SW_UT) {
+    // z_j = (b_j - sum_k U(j-k, j) z_{j-k}) / U(j,j); st[k-1] = z_{j-k}
+    double s = in;
+#pragma unroll
+    for (int k = 1; k <= SM; ++k)
+      if (k <= kd && j - k >= 0) s = fma(-colj[kd - k], st[k - 1], s);
+    s = s / colj[kd];
+    out = s;
+    outpos = j;
+#pragma unroll
+    for (int k = SM - 1; k >= 1; --k) st[k] = st[k - 1];
+    st[0] = s;
+  } else {
+    // window: z_j (in) and positions j+1 .. j+kl (state). w_j = z_j - sum_r L(j+r, j) w_{j+r};
+    // interchange j <-> ipiv[j]; position j+kl is then final.
+    double w[SM + 1];
+    w[0] = in;
+#pragma unroll
+    for (int r = 1; r <= SM; ++r) w[r] = st[r - 1];
+    const int lm = min(kl, n - 1 - j);
+    double s = w[0];
+#pragma unroll
+    for (int r = 1; r <= SM; ++r)
+      if (r <= lm) s = fma(-colj[kd + r], w[r], s);
+    w[0] = s;
+    const int p = sg.piv[j - sg.base] - j;
+#pragma unroll
+    for (int r = 1; r <= SM; ++r) {
+      const bool sw = (r == p);
+      const double a = w[0], b = w[r];
+      w[0] = sw ? b : a;
+      w[r] = sw ? a : b;
+    }
+    out = 0.0;
+#pragma unroll
+    for (int r = 0; r <= SM; ++r)
+      if (r == kl) out = w[r];
+    outpos = (j + kl < n) ? j + kl : -1;
+#pragma unroll
+    for (int r = 0; r < SM; ++r) st[r] = (r < S) ? w[r] : 0.0;
+  }
+}
+
+// Physical chunk handled by group g of this workgroup (scan order -> rows).
+__device__ __forceinline__ int phys_chunk(int kind, int nchunks, int scan_idx) {
+  return sweep_fwd(kind) ? scan_idx : nchunks - 1 - scan_idx;
+}
+
+// All threads of the workgroup call this together; group g (threads 64g..64g+63)
+// runs scan chunk blockIdx.x*CPW+g. mode 0: homogeneous (no input, no output);
+// mode 1: particular (input, no output); mode 2: replay (input and output).
+template <int KIND, int SM>
+__device__ void run_chunk(const BandSweep& B, int nchunks, bool live, int S, double (&st)[SM], int mode,
+                          const double* xin, double* xout, double* lds) {
+  const int n = B.n, kl = B.kl, kd = B.kl + B.ku, ldgb = B.ldgb;
+  const bool fwd = sweep_fwd(KIND);
+  const int halo = kd + 1;
+  const int piece = B.piece;
+  const int span = piece + 2 * halo;
+  const int g = threadIdx.x / 64;
+  double* gcol = lds;                                           // CPW x span x ldgb
+  int* gpiv = reinterpret_cast<int*>(lds + (size_t)CPW * span * ldgb);  // CPW x span
+  const int sc = blockIdx.x * CPW + g;
+  const int ph = phys_chunk(KIND, nchunks, sc < nchunks ? sc : nchunks - 1);
+  const int s0 = ph * LC, s1 = min(n, s0 + LC);
+  for (int pc = 0; pc < LC; pc += piece) {
+    __syncthreads();
+    for (int gg = 0; gg < CPW; ++gg) {
+      const int scg = blockIdx.x * CPW + gg;
+      if (scg >= nchunks) break;
+      const int pg = phys_chunk(KIND, nchunks, scg);
+      const int g0 = pg * LC, g1 = min(n, g0 + LC);
+      const int base = fwd ? (g0 + pc - halo) : (g1 - pc - piece - halo);
+      double* dc = gcol + (size_t)gg * span * ldgb;
+      int* dp = gpiv + gg * span;
+      for (int e = threadIdx.x; e < span * ldgb; e += blockDim.x) {
+        const int r = e % ldgb, c = base + e / ldgb;
+        dc[e] = (c >= 0 && c < n) ? B.GB[(size_t)r + (size_t)c * ldgb] : 0.0;
+      }
+      for (int e = threadIdx.x; e < span; e += blockDim.x) {
+        const int c = base + e;
+        dp[e] = (c >= 0 && c < n) ? B.ipiv[c] : c;
+      }
+    }
+    __syncthreads();
+    if (!live) continue;
+    Stage sg;
+    sg.col = gcol + (size_t)g * span * ldgb;
+    sg.piv = gpiv + g * span;
+    sg.base = fwd ? (s0 + pc - halo) : (s1 - pc - piece - halo);
+    for (int k = 0; k < piece; ++k) {
+      const int j = fwd ? (s0 + pc + k) : (s1 - 1 - pc - k);
+      if (j < s0 || j >= s1) break;
+      double in = 0.0;
+      if (mode != 0) {
+        if (KIND == SW_L) in = (j + kl < n) ? xin[j + kl] : 0.0;
+        else in = xin[j];
+      }
+      double out;
+      int outpos;
+      band_step<KIND, SM>(st, S, in, j, n, kl, kd, ldgb, sg, out, outpos);
+      if (mode == 2 && outpos >= 0) xout[outpos] = out;
+    }
+  }
+  // the L^T sweep ends with positions 0 .. kl-1 in the state of the chunk holding row 0
+  if (KIND == SW_LT && mode == 2 && live && ph == 0)
+#pragma unroll
+    for (int r = 0; r < SM; ++r)
+      if (r < S && r < n) xout[r] = st[r];
+}
+
+// phase 1: mode 0 -> Phi (thread v of a group propagates unit vector e_v, v < S);
+//          mode 1 -> phi for right-hand sides c0 .. c0+nc-1 (thread v handles c0+v).
+template <int KIND, int SM>
+__global__ __launch_bounds__(256) void k_band_phase1(BandSweep B, int nchunks, int mode, int c0, int nc,
+                                                     const double* X, int ldx, double* Phi, double* phi,
+                                                     const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  extern __shared__ double lds[];
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  const int g = threadIdx.x / 64, v = threadIdx.x % 64;
+  const int sc = blockIdx.x * CPW + g;
+  const bool live = sc < nchunks && (mode == 0 ? v < S : v < nc);
+  double st[SM];
+#pragma unroll
+  for (int r = 0; r < SM; ++r) st[r] = (mode == 0 && r == v) ? 1.0 : 0.0;
+  const double* xc = X + (size_t)(c0 + (v < nc ? v : 0)) * ldx;
+  run_chunk<KIND, SM>(B, nchunks, live, S, st, mode, xc, nullptr, lds);
+  if (!live) return;
+  if (mode == 0) {
+#pragma unroll
+    for (int r = 0; r < SM; ++r)
+      if (r < S) Phi[((size_t)sc * S + r) * S + v] = st[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < SM; ++r)
+      if (r < S) phi[((size_t)sc * B.nrhs_all + c0 + v) * S + r] = st[r];
+  }
+}
+
+// phase 2: entry state of every chunk (scan order), one wave per right-hand
+// side; lane r holds component r of the running state.
+template <int KIND>
+__global__ __launch_bounds__(64) void k_band_phase2(BandSweep B, int nchunks, const double* X, int ldx,
+                                                    const double* Phi, const double* phi, double* entry,
+                                                    const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  extern __shared__ double lds[];
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  const int c = blockIdx.x, r = threadIdx.x;
+  const int nb = max(1, 12000 / (S * S + S));  // chunks per batch staged in LDS
+  double* sP = lds;                            // nb x S x S
+  double* sp = sP + (size_t)nb * S * S;        // nb x S
+  double cur = (KIND == SW_L && r < S && r < B.n) ? X[(size_t)r + (size_t)c * ldx] : 0.0;
+  for (int q0 = 0; q0 < nchunks; q0 += nb) {
+    const int cnt = min(nb, nchunks - q0);
+    __syncthreads();
+    for (int e = r; e < cnt * S * S; e += 64) sP[e] = Phi[(size_t)q0 * S * S + e];
+    for (int e = r; e < cnt * S; e += 64) {
+      const int q = e / S, k = e % S;
+      sp[e] = phi[((size_t)(q0 + q) * B.nrhs_all + c) * S + k];
+    }
+    __syncthreads();
+    for (int q = 0; q < cnt; ++q) {
+      if (r < S) entry[((size_t)(q0 + q) * B.nrhs_all + c) * S + r] = cur;
+      const double* P = sP + (size_t)q * S * S + (size_t)(r < S ? r : 0) * S;
+      double s = sp[q * S + (r < S ? r : 0)];
+      for (int k = 0; k < S; ++k) s = fma(P[k], read_lane(cur, k), s);
+      cur = (r < S) ? s : 0.0;
+    }
+  }
+}
+
+// phase 3: replay every chunk from its entry state (right-hand sides c0 .. c0+nc-1).
+template <int KIND, int SM>
+__global__ __launch_bounds__(256) void k_band_phase3(BandSweep B, int nchunks, int c0, int nc, const double* Xin,
+                                                     int ldi, double* Xout, int ldo, const double* entry,
+                                                     const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  extern __shared__ double lds[];
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  const int g = threadIdx.x / 64, v = threadIdx.x % 64;
+  const int sc = blockIdx.x * CPW + g;
+  const bool live = sc < nchunks && v < nc;
+  double st[SM];
+#pragma unroll
+  for (int r = 0; r < SM; ++r) st[r] = (live && r < S) ? entry[((size_t)sc * B.nrhs_all + c0 + v) * S + r] : 0.0;
+  const int c = c0 + (v < nc ? v : 0);
+  run_chunk<KIND, SM>(B, nchunks, live, S, st, 2, Xin + (size_t)c * ldi, Xout + (size_t)c * ldo, lds);
+}
+
+// LDS of the phase 1 / phase 3 kernels for a given piece length
+static size_t chunk_lds(int piece, int kd, int ldgb) {
+  const size_t span = (size_t)piece + 2 * (size_t)(kd + 1);
+  return (size_t)CPW * span * ldgb * sizeof(double) + (size_t)CPW * span * sizeof(int) + 16;
+}
+
+template <int KIND, int SM>
+static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* Xout, int ldo, BandScratch sc,
+                        const int* pred, int pred_val, hipStream_t st) {
+  const int nchunks = (B.n + LC - 1) / LC;
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  const size_t lds13 = chunk_lds(B.piece, B.kl + B.ku, B.ldgb);
+  static size_t done1 = 0, done3 = 0;
+  hipError_t e = ensure_lds((const void*)k_band_phase1<KIND, SM>, lds13, done1);
+  if (e != hipSuccess) return e;
+  e = ensure_lds((const void*)k_band_phase3<KIND, SM>, lds13, done3);
+  if (e != hipSuccess) return e;
+  const int grid = (nchunks + CPW - 1) / CPW;
+  if (S > 0) {
+    hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 0, 0, 0, Xin, ldi,
+                       sc.Phi, sc.phi, pred, pred_val);
+    for (int c0 = 0; c0 < B.nrhs_all; c0 += 64) {
+      const int nc = B.nrhs_all - c0 < 64 ? B.nrhs_all - c0 : 64;
+      hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 1, c0, nc, Xin,
+                         ldi, sc.Phi, sc.phi, pred, pred_val);
+    }
+    const int nb = 12000 / (S * S + S) > 1 ? 12000 / (S * S + S) : 1;
+    const size_t lds2 = (size_t)nb * (S * S + S) * sizeof(double);
+    static size_t done2 = 0;
+    e = ensure_lds((const void*)k_band_phase2<KIND>, lds2, done2);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_band_phase2<KIND>), dim3(B.nrhs_all), dim3(64), lds2, st, B, nchunks, Xin, ldi, sc.Phi,
+                       sc.phi, sc.entry, pred, pred_val);
+  } else {
+    // no state (kl = 0 for the L sweeps): every chunk starts from the empty state
+  }
+  for (int c0 = 0; c0 < B.nrhs_all; c0 += 64) {
+    const int nc = B.nrhs_all - c0 < 64 ? B.nrhs_all - c0 : 64;
+    hipLaunchKernelGGL((k_band_phase3<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, c0, nc, Xin, ldi,
+                       Xout, ldo, sc.entry, pred, pred_val);
+  }
+  return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t sweep_any(const BandSweep& B, const double* Xin, int ldi, double* Xout, int ldo, BandScratch sc,
+                            const int* pred, int pred_val, hipStream_t st) {
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  if (S <= 8) return sweep<KIND, 8>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, st);
+  if (S <= 16) return sweep<KIND, 16>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, st);
+  return sweep<KIND, 32>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, st);
+}
+
+hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv,
+                                bool trans, double* X, int ldx, double* T, int ldt, BandScratch sc, const int* pred,
+                                int pred_val, hipStream_t st) {
+  if (kl + ku > 31 || nrhs < 1) return hipErrorInvalidValue;
+  int piece = 64;
+  while (piece > 8 && chunk_lds(piece, kl + ku, ldgb) > kLdsMax) piece /= 2;
+  if (chunk_lds(piece, kl + ku, ldgb) > kLdsMax) return hipErrorInvalidValue;
+  BandSweep B{GB, ldgb, kl, ku, n, ipiv, nrhs, piece};
+  hipError_t e;
+  if (!trans) {
+    e = sweep_any<SW_L>(B, X, ldx, T, ldt, sc, pred, pred_val, st);
+    if (e != hipSuccess) return e;
+    return sweep_any<SW_U>(B, T, ldt, X, ldx, sc, pred, pred_val, st);
+  }
+  e = sweep_any<SW_UT>(B, X, ldx, T, ldt, sc, pred, pred_val, st);
+  if (e != hipSuccess) return e;
+  return sweep_any<SW_LT>(B, T, ldt, X, ldx, sc, pred, pred_val, st);
+}
+
+size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs) {
+  const size_t nchunks = (size_t)(n + LC - 1) / LC;
+  const size_t S = (size_t)(kl + ku) > 1 ? (size_t)(kl + ku) : 1;
+  return nchunks * S * S + 2 * nchunks * (size_t)nrhs * S + 64;
+}
+
+}  // namespace ada

@@ -88,12 +88,15 @@ __global__ __launch_bounds__(256) void k_trsm_rltn(int k0, int nbw, int mrows, d
     for (int c = 0; c < 32; ++c) x[c] = (c0 + c < nbw) ? row[(size_t)(c0 + c) * ldw] : 0.0;
     for (int p = 0; p < ch; ++p) {
       const int p0 = p * 32;
+      double y[32];
+#pragma unroll
+      for (int pc = 0; pc < 32; ++pc) y[pc] = row[(size_t)(p0 + pc) * ldw];  // solved entries, loaded together
+#pragma unroll
       for (int pc = 0; pc < 32; ++pc) {
-        const double y = row[(size_t)(p0 + pc) * ldw];
         const double* lc = sL + (size_t)(p0 + pc) * nbw + c0;  // L11(c0+c, p0+pc)
 #pragma unroll
         for (int c = 0; c < 32; ++c)
-          if (c0 + c < nbw) x[c] = fma(-lc[c], y, x[c]);
+          if (c0 + c < nbw) x[c] = fma(-lc[c], y[pc], x[c]);
       }
     }
 #pragma unroll

@@ -33,16 +33,16 @@ __device__ void grid_wait(unsigned* counter, unsigned target, DevRec* rec) {
   }
 }
 
-// Each panel row is held in registers by two threads (columns 0-63 and
-// 64-127). The half that holds the current column rotates its registers left
+// Each panel row is held in registers by four threads (32 columns each). The
+// part that holds the current column rotates its registers left
 // by one after every column step, so the current column is always its d[0] and
 // every register index is a constant. Row interchanges are not moved through
 // memory: each row carries its current position `pos`; the pivot row takes
 // position s and the row that sat at s takes the pivot's old position, exactly
 // as an explicit interchange would. Rows are written to their final positions
 // at the end and the list of moved rows is handed to k_laswp_moves.
-constexpr int HC = 64;                 // columns per thread
-constexpr int PTH = 2 * PROWS;         // 512 threads: half h = t / PROWS, row = t % PROWS
+constexpr int HC = 32;                 // columns per thread
+constexpr int PTH = (PNB / HC) * PROWS;  // 1024 threads: part h = t / PROWS holds columns HC*h .. HC*h+HC-1
 __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, double* __restrict__ W, int ldw,
                                                      int* __restrict__ ipiv, DevRec* rec, unsigned* counter,
                                                      PanelScratch ps) {
@@ -68,9 +68,13 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
 
   double d[HC];
   {
-    const double* src = W + (size_t)(k0 + min(prow, m - 1)) + (size_t)k0 * ldw;
+    // column pointers are uniform per wave, the row offset is per thread: one register per address
+    const int row = k0 + min(prow, m - 1);
 #pragma unroll
-    for (int c = 0; c < HC; ++c) d[c] = src[(size_t)min(HC * h + c, nbw - 1) * ldw];
+    for (int c = 0; c < HC; ++c) {
+      const double* colp = W + (size_t)(k0 + min(HC * h + c, nbw - 1)) * ldw;
+      d[c] = colp[row];
+    }
 #pragma unroll
     for (int c = 0; c < HC; ++c)
       if (!rvalid || HC * h + c >= nbw) d[c] = 0.0;
@@ -162,44 +166,45 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
     if (is_win) pos = s;
     // s_u holds the pivot row in the frames of the two halves: half hc rotated by sl, the others not
     const double piv = s_u[HC * hc];
-    if (piv == 0.0) {
-      // exact zero pivot: the factorisation has failed (info = first such column)
-      if (wg == 0 && t == 0) atomicMin(&rec->info, k0 + s + 1);
-      __syncthreads();
-    } else {
-      // 5. multiplier (current half) and rank-1 update of this row
-      if (cur && rvalid && pos > s) {
-        const double l = d[0] / piv;
-        d[0] = l;
-        s_l[r] = l;
-      }
-      __syncthreads();
-      if (rvalid && pos > s && h >= hc) {
-        const double l = s_l[r];
-        // current half: columns s+1 .. in d[1 .. live-1]; later halves: all their columns below nbw
-        const int live = cur ? min(HC - sl, nbw - s) : (nbw - HC * h);
+    if (piv == 0.0 && wg == 0 && t == 0) atomicMin(&rec->info, k0 + s + 1);  // exact zero pivot: failure
+    // 5. multiplier (current part) and rank-1 update of this row; straight-line selects keep d[] in place
+    const bool active = piv != 0.0 && rvalid && pos > s;
+    double l = 0.0;
+    if (cur) {
+      l = active ? d[0] / piv : 0.0;
+      d[0] = active ? l : d[0];
+      s_l[r] = l;
+    }
+    __syncthreads();
+    l = s_l[r];
+    {
+      // current part: columns s+1.. sit in d[1 .. live-1]; later parts: every column below nbw
+      const int live = cur ? min(HC - sl, nbw - s) : (nbw - HC * h);
+      const int first = cur ? 1 : 0;
+      const bool upd = active && h >= hc;
 #pragma unroll
-        for (int c = 0; c < HC; ++c)
-          if ((!cur || c >= 1) && c < live) d[c] = fma(-l, s_u[HC * h + c], d[c]);
+      for (int c = 0; c < HC; ++c) {
+        const double nv = fma(-l, s_u[HC * h + c], d[c]);
+        d[c] = (upd && c >= first && c < live) ? nv : d[c];
       }
     }
-    // 6. rotate the current half: the finished column moves to the back
-    if (cur) {
+    // 6. rotate the current part: the finished column moves to the back
+    {
       const double f = d[0];
 #pragma unroll
-      for (int c = 0; c < HC - 1; ++c) d[c] = d[c + 1];
-      d[HC - 1] = f;
+      for (int c = 0; c < HC - 1; ++c) d[c] = cur ? d[c + 1] : d[c];
+      d[HC - 1] = cur ? f : d[HC - 1];
     }
     __syncthreads();
   }
   // half h was rotated rot times (HC rotations restore the order): d[c] holds column HC*h + (c + rot) % HC
   if (rvalid) {
     const int rot = max(0, min(HC, nbw - HC * h)) % HC;
-    double* dst = W + (size_t)(k0 + pos) + (size_t)k0 * ldw;
+    const int row = k0 + pos;
 #pragma unroll
     for (int c = 0; c < HC; ++c) {
       const int col = HC * h + (c + rot) % HC;
-      if (col < nbw) dst[(size_t)col * ldw] = d[c];
+      if (col < nbw) W[(size_t)(k0 + col) * ldw + row] = d[c];
     }
     if (h == 0 && pos != prow) {
       const int idx = atomicAdd(ps.moves, 1);
@@ -300,12 +305,15 @@ __global__ __launch_bounds__(256) void k_trsm_llnu(int k0, int nbw, int ncols, d
     for (int r = 0; r < 32; ++r) x[r] = (r0 + r < nbw) ? col[r0 + r] : 0.0;
     for (int p = 0; p < ch; ++p) {
       const int c0 = p * 32;
+      double y[32];
+#pragma unroll
+      for (int cc = 0; cc < 32; ++cc) y[cc] = col[c0 + cc];  // solved rows, loaded together
+#pragma unroll
       for (int cc = 0; cc < 32; ++cc) {
-        const double y = col[c0 + cc];
         const double* lc = sL + (size_t)(c0 + cc) * nbw + r0;
 #pragma unroll
         for (int r = 0; r < 32; ++r)
-          if (r0 + r < nbw) x[r] = fma(-lc[r], y, x[r]);
+          if (r0 + r < nbw) x[r] = fma(-lc[r], y[cc], x[r]);
       }
     }
 #pragma unroll

@@ -274,3 +274,31 @@ def test_band_layout_input(ada):
     xs2, r2 = ada.solve(T(ab2), T(b), layout="band", kl_in=kl + 2, ku_in=ku + 2)
     assert (r2.kl, r2.ku) == (kl, ku)
     assert np.max(np.abs(xs2.cpu().numpy() - xr)) <= 1e-12 * np.max(np.abs(xr))
+
+
+def _pivoting_band(n, kl, ku, rng, shift=1.0):
+    """Band storage of a band matrix whose diagonal is not dominant for small shifts (row interchanges)."""
+    ab = rng.standard_normal((kl + ku + 1, n))
+    ab[ku, :] += np.where(ab[ku, :] >= 0, shift, -shift)
+    return np.asfortranarray(ab)
+
+
+@pytest.mark.parametrize("n,kl,ku,nrhs,shift", [(1024, 3, 2, 1, 1.0), (1025, 3, 2, 2, 1.0), (1500, 0, 4, 1, 1.0),
+                                                (1500, 4, 0, 3, 1.0), (5000, 1, 1, 1, 1.0), (4099, 16, 15, 2, 1.0),
+                                                (3000, 31, 0, 1, 16.0), (3000, 0, 31, 1, 16.0), (2600, 5, 5, 70, 1.0),
+                                                (20000, 5, 5, 1, 1.0), (2048, 2, 9, 4, 4.0)])
+def test_band_row_parallel_solve(ada, n, kl, ku, nrhs, shift):
+    # long bands take the row-parallel (chunked) band solve, forward and transposed (estimator)
+    print(f"band n={n} kl={kl} ku={ku} nrhs={nrhs}", flush=True)
+    rng = np.random.default_rng(n * 31 + kl * 7 + ku)
+    ab = _pivoting_band(n, kl, ku, rng, shift)
+    b = rng.standard_normal((n, nrhs))
+    xs, r = ada.solve(T(ab), T(b), layout="band", kl_in=kl, ku_in=ku, raise_on_error=False)
+    torch.cuda.synchronize()
+    xr, rr = O.solve_band(ab, kl, ku, b)
+    assert r.status == rr["status"] == 0, ada.last_error()
+    assert (r.cls, r.kl, r.ku, r.route) == ("banded", kl, ku, "band_lu")
+    assert 0.5 * rr["rcond"] <= r.rcond <= 2 * rr["rcond"], (r.rcond, rr["rcond"])
+    assert r.berr <= max(1e-13, 4 * rr["berr"]), (r.berr, rr["berr"])
+    tol = 32 * n * EPS / rr["rcond"] * max(1.0, np.max(np.abs(xr)))
+    assert np.max(np.abs(xs.cpu().numpy().reshape(xr.shape) - xr)) <= tol
