@@ -1,0 +1,242 @@
+"""Throughput of the adaptive FP64 solve on one MI355X.
+
+One step solves the five single large systems of the paper-shaped workload
+once each (dense general n=8192, SPD n=8192, lower-triangular n=8192 with
+scaled off-diagonals, banded n=1,000,000 with kl=ku=5 in band layout, and
+symmetric-indefinite n=4096, whose Cholesky fails and re-routes to LU), with
+nrhs right-hand sides each. Inputs are seeded, synthetic and resident in HBM
+before the timed region; every solve's backward error is checked against the
+1e-10 bar. Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs 1|64] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2007_11208_amd import workloads as W  # noqa: E402
+
+METRIC = "solves/s + TFLOP/s vs plain FP64 solve at ≤1e-10 backward err; p50/p99 latency"
+SYSTEMS = ("dense", "spd", "lower_scaled", "banded", "symindef")
+BERR_BAR = 1e-10
+
+# single-kernel families and the kernel behind each (the roofline is quoted for one kernel)
+FAMILY_KERNEL = {
+    "gemm": ("k_gemm_sub", "gemm.hip", "mfma"),
+    "panel": ("k_getrf_panel", "lu.hip", "hbm"),
+    "laswp": ("k_laswp_moves", "lu.hip", "hbm"),
+    "trsm_block": ("k_trsm_llnu/k_trsm_rltn", "lu.hip", "alu"),
+    "potrf": ("k_potrf_diag", "chol.hip", "alu"),
+    "trsv": ("k_trsm_dec", "trsv.hip", "hbm"),
+    "gbtrf": ("k_gbtrf", "band.hip", "hbm"),
+    "detect": ("k_detect_dense", "detect.hip", "hbm"),
+}
+PEAK = {"mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
+
+
+def algorithmic_flops(name: str, n: int, nrhs: int, route: str, kl: int = 0, ku: int = 0) -> float:
+    """Flops the routed method must do (factorisation + solve), not the dense work it avoids."""
+    if route == "lu":
+        return 2.0 * n ** 3 / 3.0 + 2.0 * n * n * nrhs
+    if route == "chol":
+        return n ** 3 / 3.0 + 2.0 * n * n * nrhs
+    if route == "tri":
+        return float(n) * n * nrhs
+    if route == "band_lu":
+        return 2.0 * n * kl * (kl + ku) + 2.0 * n * (2 * kl + ku + 1) * nrhs
+    return float("nan")
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else float("nan")
+
+
+def traffic_for(kernel_src: str, kernel: str):
+    """Measured HBM bytes per launch from the committed counter summary, if the kernel is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    ent = table.get(kernel)
+    if not ent:
+        return None
+    with open(os.path.join(ROOT, "paper_2007_11208_amd", "csrc", kernel_src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if ent.get("src_sha256") != sha:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(nrhs: int, budget_s: float = 25.0):
+    """The oracle on this host's cores over a bounded sample of the same step."""
+    import oracle
+    O = oracle.get()
+    cores = O.num_threads()
+    per = {}
+    spent = 0.0
+    sample_n = 2048
+    for name in ("banded", "lower_scaled", "symindef", "spd", "dense"):
+        cubic = name in ("dense", "spd", "symindef")
+        full_n = 4096 if name == "symindef" else (8192 if name != "banded" else 1_000_000)
+        n = sample_n if cubic else None
+        a, b, lay = W.large_case(name, nrhs=nrhs, n=n)
+        t0 = time.perf_counter()
+        if lay[0] == "band":
+            O.solve_band(a, lay[1], lay[2], b)
+        else:
+            O.solve(a, b)
+        dt = time.perf_counter() - t0
+        spent += dt
+        scale = (full_n / sample_n) ** 3 if cubic else 1.0
+        per[name] = dt * scale
+        if spent > budget_s:
+            break
+    if len(per) < len(SYSTEMS):
+        return None
+    step = sum(per.values())
+    sample = ("one oracle solve of each system; banded n=1e6 and lower-triangular n=8192 at full size, "
+              f"dense/SPD/symmetric-indefinite at n={sample_n} scaled by (n/{sample_n})^3 to full size")
+    return {"value": len(SYSTEMS) / step, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample,
+            "per_system_s": {k: round(v, 4) for k, v in per.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--systems", default=",".join(SYSTEMS))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only copy this many MiB device-to-device three times (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the solver runs each system on a single device; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2007_11208_amd import ada
+
+    dev = torch.device("cuda:0")
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
+    names = [s for s in args.systems.split(",") if s]
+    cases = []
+    for name in names:
+        a, b, lay = W.large_case(name, nrhs=args.nrhs)
+        A = torch.from_numpy(np.asfortranarray(a)).to(dev)
+        B = torch.from_numpy(np.asfortranarray(b)).to(dev)
+        kw = dict(layout="band", kl_in=lay[1], ku_in=lay[2]) if lay[0] == "band" else {}
+        n = B.shape[0]
+        opts = ada.make_opts(layout=ada.LAYOUT_BAND if kw else ada.LAYOUT_DENSE, kl_in=kw.get("kl_in", 0),
+                             ku_in=kw.get("ku_in", 0))
+        work = torch.empty(ada.workspace_size(n, args.nrhs, opts), dtype=torch.uint8, device=dev)
+        X = torch.empty((args.nrhs, n), dtype=torch.float64, device=dev).t()
+        cases.append((name, A, B, kw, work, X, n))
+        del a, b
+    torch.cuda.synchronize()
+    ctx = ada.context(0)
+
+    def step(lat, info):
+        for name, A, B, kw, work, X, n in cases:
+            t0 = time.perf_counter()
+            _, r = ada.solve(A, B, out=X, work=work, ctx=ctx, **kw)  # returns after the result is known
+            dt = time.perf_counter() - t0
+            if lat is not None:
+                lat[name].append(dt)
+                info[name] = r
+
+    for _ in range(args.warmup):
+        step(None, None)
+    lat = {c[0]: [] for c in cases}
+    info = {}
+    ctx.profile_reset()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_times = []
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        step(lat, info)
+        step_times.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ctx.profile(False)
+    prof = ctx.profile_all()
+
+    per_sys = {}
+    flops_step = 0.0
+    worst_berr = 0.0
+    for name, A, B, kw, work, X, n in cases:
+        r = info[name]
+        fl = algorithmic_flops(name, n, args.nrhs, r.route, r.kl, r.ku)
+        flops_step += fl
+        worst_berr = max(worst_berr, r.berr)
+        per_sys[name] = {"n": n, "class": r.cls, "route": r.route, "rcond": r.rcond, "berr": r.berr,
+                         "p50_ms": round(pct(lat[name], 50) * 1e3, 3), "p99_ms": round(pct(lat[name], 99) * 1e3, 3),
+                         "tflops": round(fl / pct(lat[name], 50) / 1e12, 4)}
+        if not (r.berr <= BERR_BAR):
+            print(f"backward error {r.berr} of {name} above {BERR_BAR}", file=sys.stderr)
+            sys.exit(1)
+
+    nsolves = len(cases) * args.steps
+    value = nsolves / total
+
+    # roofline of the dominant single-kernel family over the timed region
+    fam = max(FAMILY_KERNEL, key=lambda f: prof[f][1])
+    launches, ms, fl, by = prof[fam]
+    kernel, src, bound = FAMILY_KERNEL[fam]
+    peak, unit = PEAK[bound]
+    if bound == "hbm":
+        achieved = by / (ms * 1e-3) / 1e9
+    else:
+        achieved = fl / (ms * 1e-3) / 1e12
+    traffic = traffic_for(src, kernel)
+    roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 6), "traffic": traffic, "kernel": kernel,
+                "launches": launches, "avg_us": round(ms * 1e3 / max(1, launches), 2),
+                "share_of_step": round(ms * 1e-3 / total, 4),
+                "per_launch": {"flops": fl / max(1, launches), "bytes": by / max(1, launches)}}
+    families = {f: {"launches": v[0], "ms": round(v[1], 3)} for f, v in prof.items() if v[0]}
+
+    cpu = None
+    if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
+        cpu = cpu_baseline(args.nrhs)
+
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "single large systems: dense general n=8192, SPD n=8192, lower-triangular n=8192 "
+                               "(off-diagonals / sqrt(n)), banded n=1e6 kl=ku=5 band layout, symmetric-indefinite "
+                               f"n=4096; nrhs={args.nrhs}", "systems": names, "nrhs": args.nrhs},
+        "tflops": round(flops_step * args.steps / total / 1e12, 4),
+        "p50_step_ms": round(pct(step_times, 50) * 1e3, 3), "p99_step_ms": round(pct(step_times, 99) * 1e3, 3),
+        "max_berr": worst_berr, "per_system": per_sys, "kernel_families": families,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -121,11 +121,28 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
               int ldx, void* work, size_t work_bytes, const ada_opts* opts, ada_result* result, void* stream);
 
 /* ---- instrumentation (not part of the method) ----
- * When enabled, the library records HIP events around every launch of the
- * dense trailing-update kernel (the FP64 MFMA GEMM) and accumulates its launch
- * count, total device time and algorithmic flops. */
+ * When enabled, the library records HIP events on the solve's stream around
+ * every launch of the kernel families below and accumulates, per family, the
+ * launch count, the total device time between the events and the algorithmic
+ * flops and HBM bytes of those launches (what the method must compute and
+ * move, not what the kernel happens to do). Reading is per family. */
+enum {
+  ADA_KF_GEMM = 0,   /* trailing update of LU / Cholesky (FP64 MFMA) */
+  ADA_KF_PANEL = 1,  /* LU panel with partial pivoting */
+  ADA_KF_LASWP = 2,  /* row interchanges left and right of the panel */
+  ADA_KF_TRSM_BLOCK = 3, /* block-row / block-column triangular solve inside a factorisation */
+  ADA_KF_POTRF = 4,  /* Cholesky diagonal block */
+  ADA_KF_TRSV = 5,   /* triangular solves (routed solves and estimator) */
+  ADA_KF_GBTRF = 6,  /* band LU with partial pivoting */
+  ADA_KF_GBTRS = 7,  /* band solves (one record per solve, several kernels) */
+  ADA_KF_DETECT = 8, /* dense structure scan */
+  ADA_KF_JACOBI = 9, /* one-sided Jacobi rounds */
+  ADA_KF_COUNT = 10
+};
 int ada_profile_enable(ada_ctx ctx, int on);
-int ada_profile_read(ada_ctx ctx, int64_t* launches, double* total_ms, double* total_flops);
+/* kind: ADA_KF_*; any output pointer may be NULL. */
+int ada_profile_read(ada_ctx ctx, int kind, int64_t* launches, double* total_ms, double* total_flops,
+                     double* total_bytes);
 int ada_profile_reset(ada_ctx ctx);
 
 #ifdef __cplusplus

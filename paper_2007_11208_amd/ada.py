@@ -20,6 +20,8 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_SINGULAR, ERR_NOMEM, ERR_HIP, ERR_FALLBACK_INFEA
 CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD = 0, 1, 2, 3, 4
 ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD = 0, 1, 2, 3, 4, 5
 LAYOUT_DENSE, LAYOUT_BAND = 0, 1
+# kernel families of the instrumentation (ADA_KF_*)
+KERNEL_FAMILIES = ("gemm", "panel", "laswp", "trsm_block", "potrf", "trsv", "gbtrf", "gbtrs", "detect", "jacobi")
 CLASS_NAMES = {0: "general", 1: "banded", 2: "tri_upper", 3: "tri_lower", 4: "sympd"}
 ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd"}
 
@@ -71,8 +73,8 @@ def lib() -> ctypes.CDLL:
         L.ada_profile_enable.restype = i
         L.ada_profile_reset.argtypes = [vp]
         L.ada_profile_reset.restype = i
-        L.ada_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
-                                       ctypes.POINTER(ctypes.c_double)]
+        L.ada_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.ada_profile_read.restype = i
         _lib = L
     return _lib
@@ -128,12 +130,20 @@ class Context:
     def profile_reset(self):
         lib().ada_profile_reset(self.handle)
 
-    def profile_read(self):
+    def profile_read(self, family: str):
+        """(launches, total_ms, algorithmic flops, algorithmic bytes) of one kernel family."""
         n = ctypes.c_int64()
         ms = ctypes.c_double()
         fl = ctypes.c_double()
-        lib().ada_profile_read(self.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl))
-        return n.value, ms.value, fl.value
+        by = ctypes.c_double()
+        rc = lib().ada_profile_read(self.handle, KERNEL_FAMILIES.index(family), ctypes.byref(n), ctypes.byref(ms),
+                                    ctypes.byref(fl), ctypes.byref(by))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+        return n.value, ms.value, fl.value, by.value
+
+    def profile_all(self) -> dict:
+        return {f: self.profile_read(f) for f in KERNEL_FAMILIES}
 
 
 _contexts: dict[int, Context] = {}

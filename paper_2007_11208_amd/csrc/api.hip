@@ -152,13 +152,20 @@ struct ada_ctx_s {
   int device = 0;
   DevRec* host_rec = nullptr;  // pinned
   std::mutex mu;
-  // profiling of the trailing-update GEMM
+  // per-family launch timing (instrumentation)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  int64_t prof_launches = 0;
-  double prof_ms = 0.0, prof_flops = 0.0;
-  std::vector<double> pending_flops;
+  struct Pending {
+    int kind;
+    double flops, bytes;
+    size_t e0, e1;
+  };
+  std::vector<Pending> pending;
+  struct Acc {
+    int64_t launches = 0;
+    double ms = 0.0, flops = 0.0, bytes = 0.0;
+  } acc[ADA_KF_COUNT];
 };
 
 namespace {
@@ -180,28 +187,35 @@ struct Solve {
     if (counter_idx >= 512) return nullptr;
     return &rec->counters[counter_idx++];
   }
-  hipEvent_t ev() {
-    if (!ctx->prof) return nullptr;
+  // index of a recorded event in the pool, or -1 (profiling off / no event)
+  long ev_record() {
+    if (!ctx->prof) return -1;
     if (ctx->ev_used >= ctx->ev_pool.size()) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
       ctx->ev_pool.push_back(e);
     }
-    return ctx->ev_pool[ctx->ev_used++];
+    if (hipEventRecord(ctx->ev_pool[ctx->ev_used], st) != hipSuccess) return -1;
+    return (long)ctx->ev_used++;
+  }
+  // run `launch` (returns hipError_t); when profiling, bracket it with events of family `kind`
+  template <class F>
+  hipError_t timed(int kind, double flops, double bytes, F&& launch) {
+    if (kind < 0) return launch();
+    const long e0 = ev_record();
+    const hipError_t e = launch();
+    const long e1 = ev_record();
+    if (e0 >= 0 && e1 >= 0) ctx->pending.push_back({kind, flops, bytes, (size_t)e0, (size_t)e1});
+    return e;
   }
   int gemm(int m, int nn, int k, const double* A, int lda, const double* B, int ldb, bool transB, double* C, int ldc,
            bool lower) {
-    hipEvent_t e0 = ev(), e1 = ev();
-    HIPCHK(launch_gemm_sub(m, nn, k, A, lda, B, ldb, transB, C, ldc, lower, &rec->stop, st, e0, e1));
-    if (e0 && e1) {
-      double fl;
-      if (lower) {
-        fl = 2.0 * (double)k * ((double)m * (m + 1) / 2.0);  // algorithmic: the lower triangle only
-      } else {
-        fl = 2.0 * (double)m * nn * k;
-      }
-      ctx->pending_flops.push_back(fl);
-    }
+    // algorithmic flops: the lower triangle only for the symmetric update
+    const double fl = lower ? 2.0 * (double)k * ((double)m * (m + 1) / 2.0) : 2.0 * (double)m * nn * k;
+    const double by = 8.0 * ((double)m * k + (double)nn * k + 2.0 * (lower ? (double)m * (m + 1) / 2.0 : (double)m * nn));
+    HIPCHK(timed(ADA_KF_GEMM, fl, by, [&] {
+      return launch_gemm_sub(m, nn, k, A, lda, B, ldb, transB, C, ldc, lower, &rec->stop, st, nullptr, nullptr);
+    }));
     return ADA_OK;
   }
   // op(T) X = X, nrhs <= 64 per launch (split otherwise)
@@ -211,8 +225,14 @@ struct Solve {
       const int cnt = nr - c0 < 64 ? nr - c0 : 64;
       unsigned* tk = next_counter();
       if (!tk) return fail(ADA_ERR_ARG, "too many device synchronisation counters for this size");
-      HIPCHK(launch_trsm_dec(n, cnt, T, ldt, lower, trans, unit, X + (size_t)c0 * ldx, ldx, at<int>(p.flags), ++epoch,
-                             tk, rec, pred, pv, st));
+      const double nn = (double)n;
+      const int ep = ++epoch;
+      // estimator solves are predicated on the estimator's state (some do not run): not timed
+      const int kind = pred == &rec->est_phase ? -1 : ADA_KF_TRSV;
+      HIPCHK(timed(kind, nn * nn * cnt, 8.0 * (nn * (nn + 1) / 2.0 + 2.0 * nn * cnt), [&] {
+        return launch_trsm_dec(n, cnt, T, ldt, lower, trans, unit, X + (size_t)c0 * ldx, ldx, at<int>(p.flags), ep,
+                               tk, rec, pred, pv, st);
+      }));
     }
     return ADA_OK;
   }
@@ -238,15 +258,24 @@ int band_solve(Solve& s, const double* GB, int kl, int ku, bool trans, double* X
                int ldt, const int* pred, int pred_val) {
   const int n = s.n, ldgb = 2 * kl + ku + 1;
   const int* ipiv = s.at<int>(s.p.ipiv);
+  // algorithmic: 2 flops per factor entry (kl of L, kl+ku+1 of U per column) per right-hand side;
+  // reads the factor rows and pivots, reads and writes X
+  const double nn = (double)n, fe = nn * (2.0 * kl + ku + 1);
+  const double fl = 2.0 * fe * nrhs, by = 8.0 * fe + 4.0 * nn + 16.0 * nn * nrhs;
+  const int kind = pred == &s.rec->est_phase ? -1 : ADA_KF_GBTRS;
   if (n >= kBandChunkMin) {
     if (band_chunked_scratch_doubles(n, kl, ku, nrhs) > s.p.bsc_doubles)
       return fail(ADA_ERR_ARG, "band scratch smaller than the band width needs");
     double* b = s.at<double>(s.p.bsc);
     const size_t nch = (size_t)(n + LC - 1) / LC, S = (size_t)(kl + ku > 1 ? kl + ku : 1);
     BandScratch sc{b, b + nch * S * S, b + nch * S * S + nch * (size_t)nrhs * S};
-    HIPCHK(launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, T, ldt, sc, pred, pred_val, s.st));
+    HIPCHK(s.timed(kind, fl, by, [&] {
+      return launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, T, ldt, sc, pred, pred_val, s.st);
+    }));
   } else {
-    HIPCHK(launch_gbtrs(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, pred, pred_val, s.st));
+    HIPCHK(s.timed(kind, fl, by, [&] {
+      return launch_gbtrs(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, pred, pred_val, s.st);
+    }));
   }
   return ADA_OK;
 }
@@ -301,11 +330,17 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
     const int nbw = n - k0 < kNB ? n - k0 : kNB;
     unsigned* ctr = s.next_counter();
     if (!ctr) return fail(ADA_ERR_ARG, "too many device synchronisation counters for this size");
-    HIPCHK(launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, ctr, ps, s.st));
-    HIPCHK(launch_laswp_moves(n, k0, nbw, W, ldw, ps.moves, perm, s.rec, s.st));
+    const double m = (double)(n - k0), b = (double)nbw;
+    // panel: sum over its columns s of 2 (m - s - 1)(b - s - 1) + (m - s - 1); reads and writes m x b
+    const double pfl = b * (b - 1) * (3.0 * m - b - 1) / 3.0 + b * m - b * (b + 1) / 2.0;
+    HIPCHK(s.timed(ADA_KF_PANEL, pfl, 16.0 * m * b,
+                   [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, ctr, ps, s.st); }));
+    HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * (n - nbw),
+                   [&] { return launch_laswp_moves(n, k0, nbw, W, ldw, ps.moves, perm, s.rec, s.st); }));
     const int rest = n - k0 - nbw;
     if (rest > 0) {
-      HIPCHK(launch_trsm_llnu(k0, nbw, rest, W, ldw, s.rec, s.st));
+      HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * rest, 8.0 * (b * b / 2.0 + 2.0 * b * rest),
+                     [&] { return launch_trsm_llnu(k0, nbw, rest, W, ldw, s.rec, s.st); }));
       TRY(s.gemm(rest, rest, nbw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, W + k0 + (size_t)(k0 + nbw) * ldw, ldw, false,
                  W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw, ldw, false));
     }
@@ -324,10 +359,13 @@ int route_chol(Solve& s, const double* A, int lda, const double* B, int ldb, dou
   HIPCHK(launch_copy(n, n, A, lda, W, ldw, s.st));
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int nbw = n - k0 < kNB ? n - k0 : kNB;
-    HIPCHK(launch_potrf_diag(k0, nbw, W, ldw, s.rec, s.st));
+    const double b = (double)nbw;
+    HIPCHK(s.timed(ADA_KF_POTRF, b * b * b / 3.0, 8.0 * b * b,
+                   [&] { return launch_potrf_diag(k0, nbw, W, ldw, s.rec, s.st); }));
     const int rest = n - k0 - nbw;
     if (rest > 0) {
-      HIPCHK(launch_trsm_rltn(k0, nbw, rest, W, ldw, s.rec, s.st));
+      HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * rest, 8.0 * (b * b / 2.0 + 2.0 * b * rest),
+                     [&] { return launch_trsm_rltn(k0, nbw, rest, W, ldw, s.rec, s.st); }));
       TRY(s.gemm(rest, rest, nbw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, true,
                  W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw, ldw, true));
     }
@@ -349,7 +387,16 @@ int route_tri(Solve& s, const double* A, int lda, bool lower, const double* B, i
 int route_band(Solve& s, const double* GB, int kl, int ku, const double* B, int ldb, double* X, int ldx) {
   // GB already packed and its norms recorded
   const int n = s.n, ldgb = 2 * kl + ku + 1;
-  HIPCHK(launch_gbtrf(n, kl, ku, const_cast<double*>(GB), ldgb, s.at<int>(s.p.ipiv), s.rec, s.st));
+  {
+    // algorithmic: per column kl multipliers and a kl x (kl + ku) update; reads the kl+ku+1 band rows,
+    // writes the 2kl+ku+1 factor rows and the pivots
+    const double nn = (double)n;
+    const double fl = nn * ((double)kl + 2.0 * kl * (kl + ku));
+    const double by = 8.0 * nn * (kl + ku + 1) + 8.0 * nn * ldgb + 4.0 * nn;
+    HIPCHK(s.timed(ADA_KF_GBTRF, fl, by, [&] {
+      return launch_gbtrf(n, kl, ku, const_cast<double*>(GB), ldgb, s.at<int>(s.p.ipiv), s.rec, s.st);
+    }));
+  }
   int* stop = &s.rec->stop;
   HIPCHK(launch_copy(n, s.nrhs, B, ldb, X, ldx, s.st));
   TRY(band_solve(s, GB, kl, ku, false, X, ldx, s.nrhs, s.at<double>(s.p.T), n, stop, 0));
@@ -460,18 +507,35 @@ int ada_profile_enable(ada_ctx ctx, int on) {
 
 int ada_profile_reset(ada_ctx ctx) {
   if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
-  ctx->prof_launches = 0;
-  ctx->prof_ms = 0.0;
-  ctx->prof_flops = 0.0;
+  for (auto& a : ctx->acc) a = ada_ctx_s::Acc();
   return ADA_OK;
 }
 
-int ada_profile_read(ada_ctx ctx, int64_t* launches, double* total_ms, double* total_flops) {
+int ada_profile_read(ada_ctx ctx, int kind, int64_t* launches, double* total_ms, double* total_flops,
+                     double* total_bytes) {
   if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
-  if (launches) *launches = ctx->prof_launches;
-  if (total_ms) *total_ms = ctx->prof_ms;
-  if (total_flops) *total_flops = ctx->prof_flops;
+  if (kind < 0 || kind >= ADA_KF_COUNT) return fail(ADA_ERR_ARG, "kind is not an ADA_KF_* value");
+  const auto& a = ctx->acc[kind];
+  if (launches) *launches = a.launches;
+  if (total_ms) *total_ms = a.ms;
+  if (total_flops) *total_flops = a.flops;
+  if (total_bytes) *total_bytes = a.bytes;
   return ADA_OK;
+}
+
+// fold the timed launches of the finished part of a solve into the per-family totals
+static void collect_profile(ada_ctx ctx) {
+  if (!ctx->prof) return;
+  for (const auto& q : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev_pool[q.e0], ctx->ev_pool[q.e1]) != hipSuccess) continue;
+    auto& a = ctx->acc[q.kind];
+    a.launches += 1;
+    a.ms += ms;
+    a.flops += q.flops;
+    a.bytes += q.bytes;
+  }
+  ctx->pending.clear();
 }
 
 static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
@@ -492,7 +556,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   s.nrhs = nrhs;
   DevRec& h = *ctx->host_rec;
   ctx->ev_used = 0;
-  ctx->pending_flops.clear();
+  ctx->pending.clear();
   const double thr = o.rcond_threshold < 0.0 ? 0.5 * DBL_EPSILON : o.rcond_threshold;
 
   HIPCHK(launch_init_rec(s.rec, st));
@@ -534,8 +598,10 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
 
   if (!band_route_from_band_layout) {
     if (n > kDenseMax) return fail(ADA_ERR_ARG, "dense routes support n <= 16384");
-    HIPCHK(launch_detect_dense(n, Ad, ldad, s.rec, s.at<double>(p.pcol), s.at<double>(p.prow), s.at<double>(p.cld),
-                               s.at<double>(p.rld), s.at<double>(p.diag), st));
+    HIPCHK(s.timed(ADA_KF_DETECT, 0.0, 8.0 * (double)n * n, [&] {
+      return launch_detect_dense(n, Ad, ldad, s.rec, s.at<double>(p.pcol), s.at<double>(p.prow), s.at<double>(p.cld),
+                               s.at<double>(p.rld), s.at<double>(p.diag), st);
+    }));
     HIPCHK(launch_check_finite(n, nrhs, B, ldb, s.rec, st));
     HIPCHK(launch_norms_reduce(n, s.at<double>(p.pcol), s.at<double>(p.prow), s.at<double>(p.cld),
                                s.at<double>(p.rld), s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot),
@@ -622,17 +688,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   else if (rcond != rcond) fallback = ADA_FALLBACK_RCOND_NAN;
   else if (rcond < thr) fallback = ADA_FALLBACK_RCOND;
 
-  // record the profiled GEMM launches
-  if (ctx->prof) {
-    for (size_t i = 0; i + 1 < ctx->ev_used && i / 2 < ctx->pending_flops.size(); i += 2) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ctx->ev_pool[i], ctx->ev_pool[i + 1]) == hipSuccess) {
-        ctx->prof_ms += ms;
-        ctx->prof_flops += ctx->pending_flops[i / 2];
-        ctx->prof_launches += 1;
-      }
-    }
-  }
+  collect_profile(ctx);
 
   fill_result(result, h, cls, kl, ku, route, chol_failed, fallback, n);
   result->info = info;
@@ -662,6 +718,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
     }
   }
   TRY(s.sync_read());
+  collect_profile(ctx);
   result->route = ADA_ROUTE_SVD;
   result->rank = h.rank;
   result->sweeps = h.sweeps;
