@@ -232,9 +232,191 @@ __global__ __launch_bounds__(256) void k_gbtrf(int n, int kl, int ku, double* __
   }
 }
 
+// Band LU for 1 <= kl <= 8 with the band width a compile-time constant. Same
+// window as k_gbtrf (lane = column, rows j .. j+KL in registers), but each
+// step is straight-line code: the register holding row 0 at step j becomes
+// row KL at step j+1, so the j loop is unrolled KL+1 times with the register
+// names rotated at compile time and no data moves between registers; the
+// usual case, no interchange, is told by one comparison and one ballot; the
+// interchange itself is a uniform branch. Results go into the LDS ring and
+// the loader waves write whole finished chunks back to HBM.
+template <int KL>
+struct GbWave {
+  static constexpr int R = KL + 1;
+  double v[R];
+  int o;        // column offset of this lane's column from the current step j
+  int slot;     // ring offset (doubles) of this lane's column
+  int cl;       // lane holding column j (uniform)
+  int info;     // first zero pivot, 1-based (uniform)
+  int pv;       // pivot of step j for lane j % 64, stored every 64 steps
+  int kd, W, ldgb, RS, n, lane;
+  double* ring;
+  int* ipiv;
+
+  template <int S>
+  __device__ __forceinline__ void step(int j) {
+#define VR(r) v[((r) + S) % R]
+    // pivot: first maximum of |column j| over rows j .. j+KL (rows past n hold zeros)
+    bool ge = true;
+#pragma unroll
+    for (int r = 1; r <= KL; ++r) ge = ge && (fabs(VR(0)) >= fabs(VR(r)));
+    const unsigned long long keep = __ballot(ge);
+    int p = 0;
+    if (!((keep >> cl) & 1ull)) {
+      double best = fabs(VR(0));
+      int pp = 0;
+#pragma unroll
+      for (int r = 1; r <= KL; ++r) {
+        const double a = fabs(VR(r));
+        const bool take = a > best;
+        best = take ? a : best;
+        pp = take ? r : pp;
+      }
+      p = __builtin_amdgcn_readlane(pp, cl);
+#pragma unroll
+      for (int r = 1; r <= KL; ++r) {
+        if (p == r) {
+          const double a = VR(0);
+          VR(0) = VR(r);
+          VR(r) = a;
+        }
+      }
+    }
+    pv = (lane == (j & 63)) ? j + p : pv;
+    if ((j & 63) == 63 || j == n - 1) {
+      const int g0 = j & ~63;
+      if (g0 + lane <= j) ipiv[g0 + lane] = pv;
+    }
+    const double piv = read_lane(VR(0), cl);
+    double rp = 0.0;
+    if (piv == 0.0) {
+      info = min(info, j + 1);
+    } else {
+      rp = 1.0 / piv;
+    }
+    double l[R];
+#pragma unroll
+    for (int r = 1; r <= KL; ++r) l[r] = read_lane(VR(r), cl) * rp;
+#pragma unroll
+    for (int r = 1; r <= KL; ++r) VR(r) = fma(-l[r], VR(0), VR(r));
+    // row j of U (and U(j,j) in lane cl); the multipliers of column j
+    if (lane < W) ring[slot + (kd - o)] = VR(0);
+    if (lane == cl) {
+#pragma unroll
+      for (int r = 1; r <= KL; ++r) ring[slot + kd + r] = l[r];
+    }
+    // advance: lane cl takes column j+W (rows j+1 .. j+KL of it are zero); every lane
+    // receives the entry of row j+1+KL of its column
+    const bool fin = lane == cl;
+    const int o2 = fin ? kd : o - 1;
+    int s2 = slot + W * ldgb;
+    s2 = s2 >= RS ? s2 - RS : s2;
+    slot = fin ? s2 : slot;
+    o = o2;
+    double nx = 0.0;
+    if (j + 1 + KL < n && lane < W) nx = ring[slot + kd + KL - o2];
+    if (fin) {
+#pragma unroll
+      for (int r = 1; r <= KL; ++r) VR(r) = 0.0;
+    }
+    VR(0) = nx;
+    cl = __builtin_amdgcn_readfirstlane((cl + 1 == W) ? 0 : cl + 1);
+#undef VR
+  }
+};
+
+template <int KL, int S>
+struct GbUnroll {
+  __device__ __forceinline__ static void run(GbWave<KL>& g, int j, int jend) {
+    if (j + S >= jend) return;
+    g.template step<S>(j + S);
+    GbUnroll<KL, S + 1>::run(g, j, jend);
+  }
+};
+template <int KL>
+struct GbUnroll<KL, KL + 1> {
+  __device__ __forceinline__ static void run(GbWave<KL>&, int, int) {}
+};
+
+template <int KL>
+__global__ __launch_bounds__(256) void k_gbtrf_k(int n, int ku, double* __restrict__ GB, int ldgb,
+                                                 int* __restrict__ ipiv, DevRec* rec, int chf) {
+  const int kd = KL + ku, W = kd + 1;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int SL = 4 * chf;
+  extern __shared__ double ring[];  // ring[(col % SL) * ldgb + r]
+  const int nch = (n + chf - 1) / chf;
+  auto load_chunk = [&](int q) {
+    if (q < 0 || q > nch + 1) return;
+    const int c0 = q * chf;
+    const int cnt = chf * ldgb;
+    for (int e = t - 64; e < cnt; e += 192) {
+      const int r = e % ldgb, c = c0 + e / ldgb;
+      ring[(size_t)(c % SL) * ldgb + r] = c < n ? GB[(size_t)r + (size_t)c * ldgb] : 0.0;
+    }
+  };
+  auto store_chunk = [&](int q, int tid, int nthr) {
+    if (q < 0 || q >= nch) return;
+    const int c0 = q * chf, c1 = min(n, c0 + chf);
+    const int cnt = (c1 - c0) * ldgb;
+    for (int e = tid; e < cnt; e += nthr) {
+      const int r = e % ldgb, c = c0 + e / ldgb;
+      GB[(size_t)r + (size_t)c * ldgb] = ring[(size_t)(c % SL) * ldgb + r];
+    }
+  };
+  if (w >= 1) { load_chunk(0); load_chunk(1); }
+  __syncthreads();
+  GbWave<KL> g;
+  g.kd = kd; g.W = W; g.ldgb = ldgb; g.RS = SL * ldgb; g.n = n; g.lane = lane; g.ring = ring; g.ipiv = ipiv;
+  g.cl = 0; g.info = INT_MAX; g.pv = 0;
+  g.o = lane < W ? lane : 0;
+  g.slot = lane < W ? lane * ldgb : 0;
+#pragma unroll
+  for (int r = 0; r <= KL; ++r) g.v[r] = (lane < W && lane < n && r < n) ? ring[lane * ldgb + kd + r - lane] : 0.0;
+  for (int q = 0; q < nch; ++q) {
+    if (w >= 1) {
+      load_chunk(q + 2);
+      store_chunk(q - 1, t - 64, 192);
+    } else {
+      const int jend = min(n, (q + 1) * chf);
+      for (int j = q * chf; j < jend; j += KL + 1) GbUnroll<KL, 0>::run(g, j, jend);
+    }
+    __syncthreads();
+  }
+  store_chunk(nch - 1, t, 256);
+  if (w == 0 && lane == 0 && g.info != INT_MAX) {
+    atomicMin(&rec->info, g.info);
+    rec->stop = 1;
+  }
+}
+
 hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, DevRec* rec, hipStream_t st) {
   const int kd = kl + ku;
   if (kd > BAND_KD_MAX) return hipErrorInvalidValue;
+  if (kl >= 1 && kl <= 8) {
+    // chunk length: a multiple of kl+1 (whole unrolled groups) and > kd + 1 (the window spans two chunks)
+    const int chf = (kl + 1) * ((ldgb <= 32 ? 128 : 64) / (kl + 1));
+    const size_t lds = (size_t)4 * chf * ldgb * sizeof(double);
+#define ADA_GBTRF_K(K)                                                                                       \
+  case K: {                                                                                                  \
+    static size_t done = 0;                                                                                  \
+    hipError_t e = ensure_lds((const void*)k_gbtrf_k<K>, lds, done);                                        \
+    if (e != hipSuccess) return e;                                                                           \
+    hipLaunchKernelGGL(k_gbtrf_k<K>, dim3(1), dim3(256), lds, st, n, ku, GB, ldgb, ipiv, rec, chf);         \
+    return hipGetLastError();                                                                                \
+  }
+    switch (kl) {
+      ADA_GBTRF_K(1)
+      ADA_GBTRF_K(2)
+      ADA_GBTRF_K(3)
+      ADA_GBTRF_K(4)
+      ADA_GBTRF_K(5)
+      ADA_GBTRF_K(6)
+      ADA_GBTRF_K(7)
+      ADA_GBTRF_K(8)
+    }
+#undef ADA_GBTRF_K
+  }
   const int chf = ldgb <= 32 ? 128 : 64;  // chunk length > kd + 1 keeps the window inside two chunks
   const size_t lds = (size_t)4 * chf * ldgb * sizeof(double);
 #define ADA_GBTRF(K)                                                                                         \
