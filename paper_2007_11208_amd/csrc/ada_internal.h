@@ -31,7 +31,7 @@ struct DevRec {
   int est_iter;               // iteration counter (starts at 2 after the first transposed solve)
   int est_j;                  // current unit-vector index
   int est_nsolves;
-  int pad0;
+  int band_spec_bad;          // the chunked band LU's speculation failed (zero pivot or no agreement)
   double est;                 // current estimate of ||inv(A)||_1
   double anorm1;              // ||A||_1 of the routed matrix
   double anorm_inf;           // ||A||_inf (backward error)
@@ -183,7 +183,15 @@ hipError_t launch_band_pack_dense(int n, int kl, int ku, const double* A, int ld
 hipError_t launch_band_pack_band(int n, int kl, int ku, const double* AB, int ldab, int ku_in, double* GB,
                                  int ldgb, hipStream_t st);
 hipError_t launch_band_norms(int n, int kl, int ku, const double* GB, int ldgb, DevRec* rec, hipStream_t st);
-hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, DevRec* rec, hipStream_t st);
+// band LU: GBin packed band (read only), GB factor (may equal GBin only for kl = 0 or kl > 8);
+// spec_scratch: doubles for the chunked speculative factorisation (see gbtrf_spec_plan), may be null
+struct GbSpecPlan {
+  int L, nchunks, nsnap;
+  size_t snap_doubles, exit_doubles;
+};
+GbSpecPlan gbtrf_spec_plan(int n, int kl, int ku);
+hipError_t launch_gbtrf(int n, int kl, int ku, const double* GBin, double* GB, int ldgb, int* ipiv, DevRec* rec,
+                        double* spec_scratch, size_t spec_doubles, hipStream_t st);
 hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv, bool trans,
                         double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
 // band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles

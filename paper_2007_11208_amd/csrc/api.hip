@@ -44,8 +44,8 @@ struct Plan {
   size_t total = 0;
   // offsets (bytes)
   size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, slot_val, slot_row,
-      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc;
-  size_t bsc_doubles;
+      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec;
+  size_t bsc_doubles, gbspec_doubles;
   int n, nrhs, ldw, T64, nflags;
   bool dense, band, band_dense;
 };
@@ -94,6 +94,21 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     wrows = p.dense ? (ldgb > N ? ldgb : N) : ldgb;
   }
   p.W = take(cur, wrows * N * 8);
+  {
+    // band LU: the packed band it reads (the factor goes to W) and the scratch of its chunked form
+    const int kl = p.band ? o.kl_in : 8, ku = p.band ? o.ku_in : kBandKdMax - 8;
+    const size_t ldgb = (size_t)(2 * kl + ku + 1);
+    // the detected widths may be narrower than the stored ones: size for the largest need
+    p.gbspec_doubles = 0;
+    for (int a = 1; a <= (kl < 8 ? kl : 8); ++a)
+      for (int b = 0; b <= ku && a + b <= kBandKdMax; ++b) {
+        GbSpecPlan sp = gbtrf_spec_plan(n, a, b);
+        const size_t d = sp.nchunks >= 2 ? sp.snap_doubles + sp.exit_doubles : 0;
+        if (d > p.gbspec_doubles) p.gbspec_doubles = d;
+      }
+    p.gbspec = take(cur, p.gbspec_doubles * 8 + 8);
+    if (p.band && !p.dense) p.gb0 = take(cur, ldgb * N * 8);
+  }
   if (p.dense) {
     const size_t T = (size_t)p.T64;
     p.pcol = take(cur, T * N * 8);
@@ -104,7 +119,8 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     p.ctot = take(cur, N * 8);
     p.csym = take(cur, N * 8);
     p.rtot = take(cur, N * 8);
-    p.V = take(cur, N * N * 8);
+    p.V = take(cur, (N > 64 ? N : 64) * N * 8);
+    if (!(p.band && !p.dense)) p.gb0 = p.V;  // the Jacobi V is not in use on the band route
     p.sigma = take(cur, N * 8);
     p.slot_val = take(cur, 2 * 64 * 8);
     p.slot_row = take(cur, 2 * 64 * 4);
@@ -384,8 +400,9 @@ int route_tri(Solve& s, const double* A, int lda, bool lower, const double* B, i
   return estimate(s, 2, A, lda, lower, 0, 0);
 }
 
-int route_band(Solve& s, const double* GB, int kl, int ku, const double* B, int ldb, double* X, int ldx) {
-  // GB already packed and its norms recorded
+int route_band(Solve& s, const double* GB0, double* GB, int kl, int ku, const double* B, int ldb, double* X,
+               int ldx) {
+  // GB0: the packed band (its norms already recorded); the factor goes to GB
   const int n = s.n, ldgb = 2 * kl + ku + 1;
   {
     // algorithmic: per column kl multipliers and a kl x (kl + ku) update; reads the kl+ku+1 band rows,
@@ -394,7 +411,8 @@ int route_band(Solve& s, const double* GB, int kl, int ku, const double* B, int 
     const double fl = nn * ((double)kl + 2.0 * kl * (kl + ku));
     const double by = 8.0 * nn * (kl + ku + 1) + 8.0 * nn * ldgb + 4.0 * nn;
     HIPCHK(s.timed(ADA_KF_GBTRF, fl, by, [&] {
-      return launch_gbtrf(n, kl, ku, const_cast<double*>(GB), ldgb, s.at<int>(s.p.ipiv), s.rec, s.st);
+      return launch_gbtrf(n, kl, ku, GB0, GB, ldgb, s.at<int>(s.p.ipiv), s.rec, s.at<double>(s.p.gbspec),
+                          s.p.gbspec_doubles, s.st);
     }));
   }
   int* stop = &s.rec->stop;
@@ -662,12 +680,13 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
       if (bkl + bku > kBandKdMax) return fail(ADA_ERR_ARG, "band kernels support kl + ku <= 31");
     }
     const int ldgb = 2 * bkl + bku + 1;
+    double* G0 = s.at<double>(p.gb0);
     if (band_route_from_band_layout)
-      HIPCHK(launch_band_pack_band(n, bkl, bku, A, lda, o.ku_in, W, ldgb, st));
+      HIPCHK(launch_band_pack_band(n, bkl, bku, A, lda, o.ku_in, G0, ldgb, st));
     else
-      HIPCHK(launch_band_pack_dense(n, bkl, bku, Ad, ldad, W, ldgb, st));
-    HIPCHK(launch_band_norms(n, bkl, bku, W, ldgb, s.rec, st));
-    TRY(route_band(s, W, bkl, bku, B, ldb, X, ldx));
+      HIPCHK(launch_band_pack_dense(n, bkl, bku, Ad, ldad, G0, ldgb, st));
+    HIPCHK(launch_band_norms(n, bkl, bku, G0, ldgb, s.rec, st));
+    TRY(route_band(s, G0, W, bkl, bku, B, ldb, X, ldx));
   }
   // backward error of the routed x (also flags a non-finite x)
   if (info == 0) {

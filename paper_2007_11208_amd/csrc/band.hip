@@ -232,14 +232,47 @@ __global__ __launch_bounds__(256) void k_gbtrf(int n, int kl, int ku, double* __
   }
 }
 
-// Band LU for 1 <= kl <= 8 with the band width a compile-time constant. Same
-// window as k_gbtrf (lane = column, rows j .. j+KL in registers), but each
-// step is straight-line code: the register holding row 0 at step j becomes
-// row KL at step j+1, so the j loop is unrolled KL+1 times with the register
-// names rotated at compile time and no data moves between registers; the
-// usual case, no interchange, is told by one comparison and one ballot; the
-// interchange itself is a uniform branch. Results go into the LDS ring and
-// the loader waves write whole finished chunks back to HBM.
+// Band LU for 1 <= kl <= 8 with the band width a compile-time constant,
+// out of place (reads the packed band `in`, writes the factor `out`).
+//
+// Step j of the factorisation depends on the earlier steps only through the
+// active window (rows j .. j+kl of columns j .. j+kl+ku), so the chain can be
+// cut into chunks of L steps that run at once:
+//   mode 0  every chunk starts from a guess of its entry window (the original
+//           entries, i.e. no influence of the rows above) and runs its L steps,
+//           keeping snapshots of the window at its first group starts and its
+//           exit window;
+//   mode 1  chunk c (c >= 1) restarts from the exit window of chunk c-1 and
+//           compares its window, bit for bit, with chunk c's mode-0 snapshots;
+//           once they agree, every later step of chunk c is what mode 0
+//           computed, so it stops. A chunk whose window does not agree within
+//           the snapshots, or any zero pivot, marks the speculation failed;
+//   mode 2  the plain sequential factorisation, launched in every case and
+//           predicated on that mark.
+// When the speculation holds, the result is bit-identical to the sequential
+// one: chunk 0 starts exact, and by induction every chunk's mode-0 exit window
+// is exact once its successor's check has passed. On diagonally dominant
+// bands the window forgets its entry state within a few dozen steps.
+//
+// Within a chunk, one wave runs the chain (lane = window column, rows j ..
+// j+KL in registers); the register holding row 0 at step j becomes row KL at
+// step j+1, so the loop is unrolled KL+1 times with the register names
+// rotated at compile time; the usual case, no interchange, is told by one
+// comparison and one ballot; three loader waves stream the band into an LDS
+// ring.
+struct GbSpec {
+  const double* in;
+  double* out;
+  int* ipiv;
+  DevRec* rec;
+  double* snap;    // [chunk][nsnap][KL+1][64]
+  double* exitst;  // [chunk][KL+1][64]
+  int L;           // steps per chunk (a multiple of the ring chunk)
+  int nsnap;       // snapshots per chunk (at group starts)
+  int mode;
+  const int* pred;  // mode 2: run only when *pred != 0 (null: always)
+};
+
 template <int KL>
 struct GbWave {
   static constexpr int R = KL + 1;
@@ -247,10 +280,10 @@ struct GbWave {
   int o;        // column offset of this lane's column from the current step j
   int slot;     // ring offset (doubles) of this lane's column
   int cl;       // lane holding column j (uniform)
-  int info;     // first zero pivot, 1-based (uniform)
-  int pv;       // pivot of step j for lane j % 64, stored every 64 steps
+  int bad;      // a zero pivot was met (uniform)
   int kd, W, ldgb, RS, n, lane;
-  double* ring;
+  const double* ring;
+  double* out;
   int* ipiv;
 
   template <int S>
@@ -282,15 +315,11 @@ struct GbWave {
         }
       }
     }
-    pv = (lane == (j & 63)) ? j + p : pv;
-    if ((j & 63) == 63 || j == n - 1) {
-      const int g0 = j & ~63;
-      if (g0 + lane <= j) ipiv[g0 + lane] = pv;
-    }
+    if (lane == 0) ipiv[j] = j + p;
     const double piv = read_lane(VR(0), cl);
     double rp = 0.0;
     if (piv == 0.0) {
-      info = min(info, j + 1);
+      bad = min(bad, j + 1);
     } else {
       rp = 1.0 / piv;
     }
@@ -299,11 +328,12 @@ struct GbWave {
     for (int r = 1; r <= KL; ++r) l[r] = read_lane(VR(r), cl) * rp;
 #pragma unroll
     for (int r = 1; r <= KL; ++r) VR(r) = fma(-l[r], VR(0), VR(r));
-    // row j of U (and U(j,j) in lane cl); the multipliers of column j
-    if (lane < W) ring[slot + (kd - o)] = VR(0);
+    // row j of U (U(j,j) from lane cl), then the multipliers of column j
+    if (lane < W && j + o < n) out[(size_t)(kd - o) + (size_t)(j + o) * ldgb] = VR(0);
     if (lane == cl) {
+      double* col = out + (size_t)j * ldgb + kd;
 #pragma unroll
-      for (int r = 1; r <= KL; ++r) ring[slot + kd + r] = l[r];
+      for (int r = 1; r <= KL; ++r) col[r] = l[r];
     }
     // advance: lane cl takes column j+W (rows j+1 .. j+KL of it are zero); every lane
     // receives the entry of row j+1+KL of its column
@@ -339,71 +369,154 @@ struct GbUnroll<KL, KL + 1> {
 };
 
 template <int KL>
-__global__ __launch_bounds__(256) void k_gbtrf_k(int n, int ku, double* __restrict__ GB, int ldgb,
-                                                 int* __restrict__ ipiv, DevRec* rec, int chf) {
+__global__ __launch_bounds__(256) void k_gbtrf_k(int n, int ku, int ldgb, int chf, GbSpec sp) {
+  constexpr int R = KL + 1;
+  if (sp.pred && *sp.pred == 0) return;
   const int kd = KL + ku, W = kd + 1;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int c = sp.mode == 1 ? blockIdx.x + 1 : blockIdx.x;  // chunk
+  const int s0 = c * sp.L, s1 = min(n, s0 + sp.L);
+  const bool last = s1 == n;
   const int SL = 4 * chf;
-  extern __shared__ double ring[];  // ring[(col % SL) * ldgb + r]
-  const int nch = (n + chf - 1) / chf;
+  extern __shared__ double ring[];  // ring[((col - s0) % SL) * ldgb + r] = original band column col
+  __shared__ int s_done;
+  const int nq = (s1 - s0 + chf - 1) / chf;
   auto load_chunk = [&](int q) {
-    if (q < 0 || q > nch + 1) return;
-    const int c0 = q * chf;
+    if (q < 0 || q > nq + 1) return;
+    const int c0 = s0 + q * chf;
     const int cnt = chf * ldgb;
     for (int e = t - 64; e < cnt; e += 192) {
-      const int r = e % ldgb, c = c0 + e / ldgb;
-      ring[(size_t)(c % SL) * ldgb + r] = c < n ? GB[(size_t)r + (size_t)c * ldgb] : 0.0;
+      const int r = e % ldgb, cc = c0 + e / ldgb;
+      ring[(size_t)((cc - s0) % SL) * ldgb + r] = cc < n ? sp.in[(size_t)r + (size_t)cc * ldgb] : 0.0;
     }
   };
-  auto store_chunk = [&](int q, int tid, int nthr) {
-    if (q < 0 || q >= nch) return;
-    const int c0 = q * chf, c1 = min(n, c0 + chf);
-    const int cnt = (c1 - c0) * ldgb;
-    for (int e = tid; e < cnt; e += nthr) {
-      const int r = e % ldgb, c = c0 + e / ldgb;
-      GB[(size_t)r + (size_t)c * ldgb] = ring[(size_t)(c % SL) * ldgb + r];
-    }
-  };
+  if (t == 0) s_done = 0;
   if (w >= 1) { load_chunk(0); load_chunk(1); }
   __syncthreads();
   GbWave<KL> g;
-  g.kd = kd; g.W = W; g.ldgb = ldgb; g.RS = SL * ldgb; g.n = n; g.lane = lane; g.ring = ring; g.ipiv = ipiv;
-  g.cl = 0; g.info = INT_MAX; g.pv = 0;
+  g.kd = kd; g.W = W; g.ldgb = ldgb; g.RS = SL * ldgb; g.n = n; g.lane = lane; g.ring = ring;
+  g.out = sp.out; g.ipiv = sp.ipiv;
+  g.cl = 0; g.bad = INT_MAX;
   g.o = lane < W ? lane : 0;
   g.slot = lane < W ? lane * ldgb : 0;
+  double* snapc = sp.snap + (size_t)c * sp.nsnap * R * 64;
+  if (sp.mode == 1) {
+    const double* ex = sp.exitst + (size_t)(c - 1) * R * 64;
 #pragma unroll
-  for (int r = 0; r <= KL; ++r) g.v[r] = (lane < W && lane < n && r < n) ? ring[lane * ldgb + kd + r - lane] : 0.0;
-  for (int q = 0; q < nch; ++q) {
+    for (int r = 0; r < R; ++r) g.v[r] = ex[r * 64 + lane];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      g.v[r] = (lane < W && s0 + lane < n && s0 + r < n) ? ring[lane * ldgb + kd + r - lane] : 0.0;
+  }
+  double sn[R];  // mode 1: the snapshot due at the next group start
+#pragma unroll
+  for (int r = 0; r < R; ++r) sn[r] = (sp.mode == 1) ? snapc[r * 64 + lane] : 0.0;
+  int grp = 0;
+  for (int q = 0; q < nq; ++q) {
     if (w >= 1) {
       load_chunk(q + 2);
-      store_chunk(q - 1, t - 64, 192);
     } else {
-      const int jend = min(n, (q + 1) * chf);
-      for (int j = q * chf; j < jend; j += KL + 1) GbUnroll<KL, 0>::run(g, j, jend);
+      const int jend = min(s1, s0 + (q + 1) * chf);
+      bool stop = false;
+      for (int j = s0 + q * chf; j < jend; j += R) {
+        if (sp.mode == 0 && grp < sp.nsnap) {
+          double* d = snapc + (size_t)grp * R * 64;
+#pragma unroll
+          for (int r = 0; r < R; ++r) d[r * 64 + lane] = g.v[r];
+        } else if (sp.mode == 1) {
+          if (grp < sp.nsnap) {
+            bool eq = true;
+#pragma unroll
+            for (int r = 0; r < R; ++r) eq = eq && (__double_as_longlong(g.v[r]) == __double_as_longlong(sn[r]));
+            if (__ballot(eq) == ~0ull) { stop = true; break; }
+            if (grp + 1 < sp.nsnap) {
+              const double* d = snapc + (size_t)(grp + 1) * R * 64;
+#pragma unroll
+              for (int r = 0; r < R; ++r) sn[r] = d[r * 64 + lane];
+            }
+          } else if (!last) {
+            // no agreement within the snapshots: the speculation does not hold here
+            if (lane == 0) atomicOr(&sp.rec->band_spec_bad, 1);
+            stop = true;
+            break;
+          }
+        }
+        GbUnroll<KL, 0>::run(g, j, jend);
+        ++grp;
+      }
+      if (stop && lane == 0) s_done = 1;
     }
     __syncthreads();
+    if (s_done) break;
   }
-  store_chunk(nch - 1, t, 256);
-  if (w == 0 && lane == 0 && g.info != INT_MAX) {
-    atomicMin(&rec->info, g.info);
-    rec->stop = 1;
+  if (w == 0) {
+    if (sp.mode == 2) {
+      if (lane == 0 && g.bad != INT_MAX) {
+        atomicMin(&sp.rec->info, g.bad);
+        sp.rec->stop = 1;
+      }
+    } else {
+      if (lane == 0 && g.bad != INT_MAX) atomicOr(&sp.rec->band_spec_bad, 1);
+      if (sp.mode == 0 && !last) {
+        // exit window in the order of the next chunk's start: column s1 + o at position o
+        double* ex = sp.exitst + (size_t)c * R * 64;
+        const int at = lane < W ? g.o : lane;
+#pragma unroll
+        for (int r = 0; r < R; ++r) ex[r * 64 + at] = g.v[r];
+      }
+    }
   }
 }
 
-hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, DevRec* rec, hipStream_t st) {
+// ring chunk length: a multiple of kl+1 (whole unrolled groups) and > kl+ku+1 (the window spans two chunks)
+static int gbtrf_chf(int kl, int ldgb) { return (kl + 1) * ((ldgb <= 32 ? 128 : 64) / (kl + 1)); }
+constexpr int kGbSpecChunks = 16;    // ring chunks per speculative chunk (at least)
+constexpr int kGbSpecSteps = 256;    // steps covered by the snapshots
+
+GbSpecPlan gbtrf_spec_plan(int n, int kl, int ku) {
+  GbSpecPlan p{};
+  if (kl < 1 || kl > 8 || kl + ku > BAND_KD_MAX) return p;
+  const int ldgb = 2 * kl + ku + 1;
+  const int chf = gbtrf_chf(kl, ldgb);
+  int q = (n + chf * 512 - 1) / (chf * 512);  // about 512 chunks at most
+  if (q < kGbSpecChunks / 4) q = kGbSpecChunks / 4;
+  p.L = chf * q;
+  p.nchunks = (n + p.L - 1) / p.L;
+  if (p.nchunks < 2) return GbSpecPlan{};
+  p.nsnap = (kGbSpecSteps + kl) / (kl + 1);
+  p.snap_doubles = (size_t)p.nchunks * p.nsnap * (kl + 1) * 64;
+  p.exit_doubles = (size_t)p.nchunks * (kl + 1) * 64;
+  return p;
+}
+
+hipError_t launch_gbtrf(int n, int kl, int ku, const double* GBin, double* GB, int ldgb, int* ipiv, DevRec* rec,
+                        double* spec_scratch, size_t spec_doubles, hipStream_t st) {
   const int kd = kl + ku;
   if (kd > BAND_KD_MAX) return hipErrorInvalidValue;
   if (kl >= 1 && kl <= 8) {
-    // chunk length: a multiple of kl+1 (whole unrolled groups) and > kd + 1 (the window spans two chunks)
-    const int chf = (kl + 1) * ((ldgb <= 32 ? 128 : 64) / (kl + 1));
+    const int chf = gbtrf_chf(kl, ldgb);
     const size_t lds = (size_t)4 * chf * ldgb * sizeof(double);
-#define ADA_GBTRF_K(K)                                                                                       \
-  case K: {                                                                                                  \
-    static size_t done = 0;                                                                                  \
-    hipError_t e = ensure_lds((const void*)k_gbtrf_k<K>, lds, done);                                        \
-    if (e != hipSuccess) return e;                                                                           \
-    hipLaunchKernelGGL(k_gbtrf_k<K>, dim3(1), dim3(256), lds, st, n, ku, GB, ldgb, ipiv, rec, chf);         \
-    return hipGetLastError();                                                                                \
+    GbSpecPlan sp = gbtrf_spec_plan(n, kl, ku);
+    const bool spec = sp.nchunks >= 2 && spec_scratch && sp.snap_doubles + sp.exit_doubles <= spec_doubles;
+    GbSpec a{GBin, GB, ipiv, rec, spec_scratch, spec ? spec_scratch + sp.snap_doubles : nullptr, spec ? sp.L : n,
+             sp.nsnap, 2, nullptr};
+#define ADA_GBTRF_K(K)                                                                                  \
+  case K: {                                                                                             \
+    static size_t done = 0;                                                                             \
+    hipError_t e = ensure_lds((const void*)k_gbtrf_k<K>, lds, done);                                   \
+    if (e != hipSuccess) return e;                                                                      \
+    if (spec) {                                                                                         \
+      a.mode = 0;                                                                                       \
+      hipLaunchKernelGGL(k_gbtrf_k<K>, dim3(sp.nchunks), dim3(256), lds, st, n, ku, ldgb, chf, a);     \
+      a.mode = 1;                                                                                       \
+      hipLaunchKernelGGL(k_gbtrf_k<K>, dim3(sp.nchunks - 1), dim3(256), lds, st, n, ku, ldgb, chf, a); \
+      a.mode = 2;                                                                                       \
+      a.L = n;                                                                                          \
+      a.pred = &rec->band_spec_bad;                                                                     \
+    }                                                                                                   \
+    hipLaunchKernelGGL(k_gbtrf_k<K>, dim3(1), dim3(256), lds, st, n, ku, ldgb, chf, a);                \
+    return hipGetLastError();                                                                           \
   }
     switch (kl) {
       ADA_GBTRF_K(1)
@@ -416,6 +529,11 @@ hipError_t launch_gbtrf(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, 
       ADA_GBTRF_K(8)
     }
 #undef ADA_GBTRF_K
+  }
+  // other widths: the general in-place kernel on a copy of the band
+  if (GB != GBin) {
+    hipError_t e = hipMemcpyAsync(GB, GBin, sizeof(double) * (size_t)ldgb * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
   }
   const int chf = ldgb <= 32 ? 128 : 64;  // chunk length > kd + 1 keeps the window inside two chunks
   const size_t lds = (size_t)4 * chf * ldgb * sizeof(double);
