@@ -205,10 +205,14 @@ struct BandSweep {
   int piece;  // steps staged in LDS at a time
 };
 struct BandScratch {
-  double* Phi;
-  double* phi;
-  double* entry;
+  double* Phi;    // chunk maps (homogeneous part), nchunks x S x S
+  double* phi;    // chunk maps (particular part), nchunks x nrhs x S
+  double* entry;  // entry state of every chunk, nchunks x nrhs x S
+  double* Msup;   // composed maps of the scan groups
+  double* msup;
+  double* esup;   // entry state of every scan group
 };
+BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs);
 hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv,
                                 bool trans, double* X, int ldx, double* T, int ldt, BandScratch sc, const int* pred,
                                 int pred_val, hipStream_t st);

@@ -282,9 +282,7 @@ int band_solve(Solve& s, const double* GB, int kl, int ku, bool trans, double* X
   if (n >= kBandChunkMin) {
     if (band_chunked_scratch_doubles(n, kl, ku, nrhs) > s.p.bsc_doubles)
       return fail(ADA_ERR_ARG, "band scratch smaller than the band width needs");
-    double* b = s.at<double>(s.p.bsc);
-    const size_t nch = (size_t)(n + LC - 1) / LC, S = (size_t)(kl + ku > 1 ? kl + ku : 1);
-    BandScratch sc{b, b + nch * S * S, b + nch * S * S + nch * (size_t)nrhs * S};
+    BandScratch sc = band_chunked_scratch(s.at<double>(s.p.bsc), n, kl, ku, nrhs);
     HIPCHK(s.timed(kind, fl, by, [&] {
       return launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, T, ldt, sc, pred, pred_val, s.st);
     }));

@@ -17,7 +17,8 @@
 
 namespace ada {
 
-constexpr int CPW = 4;  // chunks per workgroup (one group of 64 threads each)
+constexpr int CPW = 4;   // chunks per workgroup (one group of 64 threads each)
+constexpr int NCB = 16;  // right-hand sides per launch of phases 1 and 3
 constexpr size_t kLdsMax = 160 * 1024;
 
 __host__ __device__ inline int sweep_state(int kind, int kl, int ku) {
@@ -123,19 +124,23 @@ __device__ __forceinline__ int phys_chunk(int kind, int nchunks, int scan_idx) {
 }
 
 // All threads of the workgroup call this together; group g (threads 64g..64g+63)
-// runs scan chunk blockIdx.x*CPW+g. mode 0: homogeneous (no input, no output);
-// mode 1: particular (input, no output); mode 2: replay (input and output).
+// runs scan chunk blockIdx.x*CPW+g, thread v of it right-hand side c0+v (v < nc)
+// in modes 1 and 2. mode 0: homogeneous (no input, no output); mode 1:
+// particular (input, no output); mode 2: replay (input and output). The band
+// columns, pivots and inputs of each piece are staged through LDS together.
 template <int KIND, int SM>
 __device__ void run_chunk(const BandSweep& B, int nchunks, bool live, int S, double (&st)[SM], int mode,
-                          const double* xin, double* xout, double* lds) {
+                          const double* X, int ldx, int c0, int nc, double* xout, double* lds) {
   const int n = B.n, kl = B.kl, kd = B.kl + B.ku, ldgb = B.ldgb;
   const bool fwd = sweep_fwd(KIND);
   const int halo = kd + 1;
   const int piece = B.piece;
   const int span = piece + 2 * halo;
-  const int g = threadIdx.x / 64;
-  double* gcol = lds;                                           // CPW x span x ldgb
-  int* gpiv = reinterpret_cast<int*>(lds + (size_t)CPW * span * ldgb);  // CPW x span
+  const int g = threadIdx.x / 64, v = threadIdx.x % 64;
+  const int ioff = (KIND == SW_L) ? kl : 0;  // the input row of step j is j + ioff
+  double* gcol = lds;                                     // CPW x span x ldgb
+  double* gx = lds + (size_t)CPW * span * ldgb;           // CPW x NCB x piece
+  int* gpiv = reinterpret_cast<int*>(gx + (size_t)CPW * NCB * piece);  // CPW x span
   const int sc = blockIdx.x * CPW + g;
   const int ph = phys_chunk(KIND, nchunks, sc < nchunks ? sc : nchunks - 1);
   const int s0 = ph * LC, s1 = min(n, s0 + LC);
@@ -157,6 +162,15 @@ __device__ void run_chunk(const BandSweep& B, int nchunks, bool live, int S, dou
         const int c = base + e;
         dp[e] = (c >= 0 && c < n) ? B.ipiv[c] : c;
       }
+      if (mode != 0) {
+        double* dx = gx + (size_t)gg * NCB * piece;
+        for (int e = threadIdx.x; e < nc * piece; e += blockDim.x) {
+          const int cc = e / piece, k = e % piece;
+          const int j = fwd ? (g0 + pc + k) : (g1 - 1 - pc - k);
+          const int row = j + ioff;
+          dx[e] = (j >= g0 && j < g1 && row < n) ? X[(size_t)row + (size_t)(c0 + cc) * ldx] : 0.0;
+        }
+      }
     }
     __syncthreads();
     if (!live) continue;
@@ -164,14 +178,11 @@ __device__ void run_chunk(const BandSweep& B, int nchunks, bool live, int S, dou
     sg.col = gcol + (size_t)g * span * ldgb;
     sg.piv = gpiv + g * span;
     sg.base = fwd ? (s0 + pc - halo) : (s1 - pc - piece - halo);
+    const double* xs = gx + (size_t)g * NCB * piece + (size_t)(v < nc ? v : 0) * piece;
     for (int k = 0; k < piece; ++k) {
       const int j = fwd ? (s0 + pc + k) : (s1 - 1 - pc - k);
       if (j < s0 || j >= s1) break;
-      double in = 0.0;
-      if (mode != 0) {
-        if (KIND == SW_L) in = (j + kl < n) ? xin[j + kl] : 0.0;
-        else in = xin[j];
-      }
+      const double in = (mode != 0) ? xs[k] : 0.0;
       double out;
       int outpos;
       band_step<KIND, SM>(st, S, in, j, n, kl, kd, ldgb, sg, out, outpos);
@@ -200,8 +211,7 @@ __global__ __launch_bounds__(256) void k_band_phase1(BandSweep B, int nchunks, i
   double st[SM];
 #pragma unroll
   for (int r = 0; r < SM; ++r) st[r] = (mode == 0 && r == v) ? 1.0 : 0.0;
-  const double* xc = X + (size_t)(c0 + (v < nc ? v : 0)) * ldx;
-  run_chunk<KIND, SM>(B, nchunks, live, S, st, mode, xc, nullptr, lds);
+  run_chunk<KIND, SM>(B, nchunks, live, S, st, mode, X, ldx, c0, nc, nullptr, lds);
   if (!live) return;
   if (mode == 0) {
 #pragma unroll
@@ -214,35 +224,141 @@ __global__ __launch_bounds__(256) void k_band_phase1(BandSweep B, int nchunks, i
   }
 }
 
-// phase 2: entry state of every chunk (scan order), one wave per right-hand
-// side; lane r holds component r of the running state.
-template <int KIND>
-__global__ __launch_bounds__(64) void k_band_phase2(BandSweep B, int nchunks, const double* X, int ldx,
-                                                    const double* Phi, const double* phi, double* entry,
-                                                    const int* pred, int pred_val) {
+// phase 2: entry state of every chunk, in three short launches over groups of
+// G consecutive chunks (scan order):
+//   2a  every group composes its chunk maps: M = Phi_last ... Phi_first, and
+//       m_c = the group's exit state from a zero entry, per right-hand side;
+//   2b  one wave per right-hand side chains the groups (lane r holds component
+//       r of the state);
+//   2c  every group replays its chunk maps from its entry and writes every
+//       chunk's entry state.
+template <int KIND, int SM>
+__global__ __launch_bounds__(64) void k_band_compose(BandSweep B, int nchunks, int G, const double* Phi,
+                                                     const double* phi, double* Msup, double* msup,
+                                                     const int* pred, int pred_val) {
   if (pred && *pred != pred_val) return;
-  extern __shared__ double lds[];
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  const int sg = blockIdx.x, t = threadIdx.x;
+  const int c = blockIdx.y * 64 + t;  // right-hand side of this lane
+  const int nr = B.nrhs_all;
+  const int q0 = sg * G, q1 = min(nchunks, q0 + G);
+  __shared__ double sP[SM * SM], sM[2][SM * SM];
+  for (int e = t; e < S * S; e += 64) sM[0][e] = (e / S == e % S) ? 1.0 : 0.0;
+  int cur = 0;
+  double m[SM], pf[SM];
+#pragma unroll
+  for (int r = 0; r < SM; ++r) {
+    m[r] = 0.0;
+    pf[r] = (c < nr && r < S && q0 < q1) ? phi[((size_t)q0 * nr + c) * S + r] : 0.0;
+  }
+  for (int q = q0; q < q1; ++q) {
+    __syncthreads();
+    for (int e = t; e < S * S; e += 64) sP[e] = Phi[(size_t)q * S * S + e];
+    __syncthreads();
+    if (blockIdx.y == 0) {
+      for (int e = t; e < S * S; e += 64) {
+        const int r = e / S, k = e % S;
+        double a = 0.0;
+        for (int u = 0; u < S; ++u) a = fma(sP[r * S + u], sM[cur][u * S + k], a);
+        sM[cur ^ 1][e] = a;
+      }
+      cur ^= 1;
+    }
+    double a[SM];
+#pragma unroll
+    for (int r = 0; r < SM; ++r) {
+      double x = pf[r];
+#pragma unroll
+      for (int u = 0; u < SM; ++u)
+        if (r < S && u < S) x = fma(sP[r * S + u], m[u], x);
+      a[r] = x;
+    }
+#pragma unroll
+    for (int r = 0; r < SM; ++r) {
+      m[r] = a[r];
+      pf[r] = (c < nr && r < S && q + 1 < q1) ? phi[((size_t)(q + 1) * nr + c) * S + r] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (blockIdx.y == 0)
+    for (int e = t; e < S * S; e += 64) Msup[(size_t)sg * S * S + e] = sM[cur][e];
+  if (c < nr) {
+#pragma unroll
+    for (int r = 0; r < SM; ++r)
+      if (r < S) msup[((size_t)sg * nr + c) * S + r] = m[r];
+  }
+}
+
+template <int KIND, int SM>
+__global__ __launch_bounds__(64) void k_band_chain(BandSweep B, int nsup, const double* X, int ldx,
+                                                   const double* Msup, const double* msup, double* esup,
+                                                   const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
   const int S = sweep_state(KIND, B.kl, B.ku);
   const int c = blockIdx.x, r = threadIdx.x;
-  const int nb = max(1, 12000 / (S * S + S));  // chunks per batch staged in LDS
-  double* sP = lds;                            // nb x S x S
-  double* sp = sP + (size_t)nb * S * S;        // nb x S
+  const int nr = B.nrhs_all;
   double cur = (KIND == SW_L && r < S && r < B.n) ? X[(size_t)r + (size_t)c * ldx] : 0.0;
-  for (int q0 = 0; q0 < nchunks; q0 += nb) {
-    const int cnt = min(nb, nchunks - q0);
-    __syncthreads();
-    for (int e = r; e < cnt * S * S; e += 64) sP[e] = Phi[(size_t)q0 * S * S + e];
-    for (int e = r; e < cnt * S; e += 64) {
-      const int q = e / S, k = e % S;
-      sp[e] = phi[((size_t)(q0 + q) * B.nrhs_all + c) * S + k];
+  const int rr = r < S ? r : 0;
+  double pm[SM], pa;
+#pragma unroll
+  for (int u = 0; u < SM; ++u) pm[u] = (u < S && nsup > 0) ? Msup[(size_t)rr * S + u] : 0.0;
+  pa = nsup > 0 ? msup[(size_t)c * S + rr] : 0.0;
+  for (int sg = 0; sg < nsup; ++sg) {
+    if (r < S) esup[((size_t)sg * nr + c) * S + r] = cur;
+    double a = pa;
+#pragma unroll
+    for (int u = 0; u < SM; ++u)
+      if (u < S) a = fma(pm[u], read_lane(cur, u), a);
+    // the next group's row of M and particular part, loaded before they are needed
+    if (sg + 1 < nsup) {
+      const double* M = Msup + (size_t)(sg + 1) * S * S + (size_t)rr * S;
+#pragma unroll
+      for (int u = 0; u < SM; ++u) pm[u] = u < S ? M[u] : 0.0;
+      pa = msup[((size_t)(sg + 1) * nr + c) * S + rr];
     }
+    cur = r < S ? a : 0.0;
+  }
+}
+
+template <int KIND, int SM>
+__global__ __launch_bounds__(64) void k_band_fill(BandSweep B, int nchunks, int G, const double* Phi,
+                                                  const double* phi, const double* esup, double* entry,
+                                                  const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  const int sg = blockIdx.x, t = threadIdx.x;
+  const int c = blockIdx.y * 64 + t;
+  const int nr = B.nrhs_all;
+  const int q0 = sg * G, q1 = min(nchunks, q0 + G);
+  __shared__ double sP[SM * SM];
+  double e[SM], pf[SM];
+#pragma unroll
+  for (int r = 0; r < SM; ++r) {
+    e[r] = (c < nr && r < S) ? esup[((size_t)sg * nr + c) * S + r] : 0.0;
+    pf[r] = (c < nr && r < S && q0 < q1) ? phi[((size_t)q0 * nr + c) * S + r] : 0.0;
+  }
+  for (int q = q0; q < q1; ++q) {
     __syncthreads();
-    for (int q = 0; q < cnt; ++q) {
-      if (r < S) entry[((size_t)(q0 + q) * B.nrhs_all + c) * S + r] = cur;
-      const double* P = sP + (size_t)q * S * S + (size_t)(r < S ? r : 0) * S;
-      double s = sp[q * S + (r < S ? r : 0)];
-      for (int k = 0; k < S; ++k) s = fma(P[k], read_lane(cur, k), s);
-      cur = (r < S) ? s : 0.0;
+    for (int k = t; k < S * S; k += 64) sP[k] = Phi[(size_t)q * S * S + k];
+    __syncthreads();
+    if (c < nr) {
+#pragma unroll
+      for (int r = 0; r < SM; ++r)
+        if (r < S) entry[((size_t)q * nr + c) * S + r] = e[r];
+    }
+    double a[SM];
+#pragma unroll
+    for (int r = 0; r < SM; ++r) {
+      double x = pf[r];
+#pragma unroll
+      for (int u = 0; u < SM; ++u)
+        if (r < S && u < S) x = fma(sP[r * S + u], e[u], x);
+      a[r] = x;
+    }
+#pragma unroll
+    for (int r = 0; r < SM; ++r) {
+      e[r] = a[r];
+      pf[r] = (c < nr && r < S && q + 1 < q1) ? phi[((size_t)(q + 1) * nr + c) * S + r] : 0.0;
     }
   }
 }
@@ -262,13 +378,21 @@ __global__ __launch_bounds__(256) void k_band_phase3(BandSweep B, int nchunks, i
 #pragma unroll
   for (int r = 0; r < SM; ++r) st[r] = (live && r < S) ? entry[((size_t)sc * B.nrhs_all + c0 + v) * S + r] : 0.0;
   const int c = c0 + (v < nc ? v : 0);
-  run_chunk<KIND, SM>(B, nchunks, live, S, st, 2, Xin + (size_t)c * ldi, Xout + (size_t)c * ldo, lds);
+  run_chunk<KIND, SM>(B, nchunks, live, S, st, 2, Xin, ldi, c0, nc, Xout + (size_t)c * ldo, lds);
 }
 
 // LDS of the phase 1 / phase 3 kernels for a given piece length
 static size_t chunk_lds(int piece, int kd, int ldgb) {
   const size_t span = (size_t)piece + 2 * (size_t)(kd + 1);
-  return (size_t)CPW * span * ldgb * sizeof(double) + (size_t)CPW * span * sizeof(int) + 16;
+  return (size_t)CPW * span * ldgb * sizeof(double) + (size_t)CPW * NCB * piece * sizeof(double) +
+         (size_t)CPW * span * sizeof(int) + 16;
+}
+
+// chunks per group of the two-level scan
+static int scan_group(int nchunks) {
+  int G = 1;
+  while (G * G < nchunks) ++G;
+  return G;
 }
 
 template <int KIND, int SM>
@@ -286,23 +410,24 @@ static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* 
   if (S > 0) {
     hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 0, 0, 0, Xin, ldi,
                        sc.Phi, sc.phi, pred, pred_val);
-    for (int c0 = 0; c0 < B.nrhs_all; c0 += 64) {
-      const int nc = B.nrhs_all - c0 < 64 ? B.nrhs_all - c0 : 64;
+    for (int c0 = 0; c0 < B.nrhs_all; c0 += NCB) {
+      const int nc = B.nrhs_all - c0 < NCB ? B.nrhs_all - c0 : NCB;
       hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 1, c0, nc, Xin,
                          ldi, sc.Phi, sc.phi, pred, pred_val);
     }
-    const int nb = 12000 / (S * S + S) > 1 ? 12000 / (S * S + S) : 1;
-    const size_t lds2 = (size_t)nb * (S * S + S) * sizeof(double);
-    static size_t done2 = 0;
-    e = ensure_lds((const void*)k_band_phase2<KIND>, lds2, done2);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_band_phase2<KIND>), dim3(B.nrhs_all), dim3(64), lds2, st, B, nchunks, Xin, ldi, sc.Phi,
-                       sc.phi, sc.entry, pred, pred_val);
+    const int G = scan_group(nchunks);
+    const int nsup = (nchunks + G - 1) / G;
+    hipLaunchKernelGGL((k_band_compose<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B,
+                       nchunks, G, sc.Phi, sc.phi, sc.Msup, sc.msup, pred, pred_val);
+    hipLaunchKernelGGL((k_band_chain<KIND, SM>), dim3(B.nrhs_all), dim3(64), 0, st, B, nsup, Xin, ldi, sc.Msup,
+                       sc.msup, sc.esup, pred, pred_val);
+    hipLaunchKernelGGL((k_band_fill<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B, nchunks,
+                       G, sc.Phi, sc.phi, sc.esup, sc.entry, pred, pred_val);
   } else {
     // no state (kl = 0 for the L sweeps): every chunk starts from the empty state
   }
-  for (int c0 = 0; c0 < B.nrhs_all; c0 += 64) {
-    const int nc = B.nrhs_all - c0 < 64 ? B.nrhs_all - c0 : 64;
+  for (int c0 = 0; c0 < B.nrhs_all; c0 += NCB) {
+    const int nc = B.nrhs_all - c0 < NCB ? B.nrhs_all - c0 : NCB;
     hipLaunchKernelGGL((k_band_phase3<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, c0, nc, Xin, ldi,
                        Xout, ldo, sc.entry, pred, pred_val);
   }
@@ -340,7 +465,22 @@ hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* G
 size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs) {
   const size_t nchunks = (size_t)(n + LC - 1) / LC;
   const size_t S = (size_t)(kl + ku) > 1 ? (size_t)(kl + ku) : 1;
-  return nchunks * S * S + 2 * nchunks * (size_t)nrhs * S + 64;
+  const size_t G = (size_t)scan_group((int)nchunks), nsup = (nchunks + G - 1) / G;
+  return nchunks * S * S + 2 * nchunks * (size_t)nrhs * S + nsup * S * S + 2 * nsup * (size_t)nrhs * S + 64;
+}
+
+BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs) {
+  const size_t nchunks = (size_t)(n + LC - 1) / LC;
+  const size_t S = (size_t)(kl + ku) > 1 ? (size_t)(kl + ku) : 1;
+  const size_t G = (size_t)scan_group((int)nchunks), nsup = (nchunks + G - 1) / G;
+  BandScratch sc;
+  sc.Phi = base;
+  sc.phi = sc.Phi + nchunks * S * S;
+  sc.entry = sc.phi + nchunks * (size_t)nrhs * S;
+  sc.Msup = sc.entry + nchunks * (size_t)nrhs * S;
+  sc.msup = sc.Msup + nsup * S * S;
+  sc.esup = sc.msup + nsup * (size_t)nrhs * S;
+  return sc;
 }
 
 }  // namespace ada

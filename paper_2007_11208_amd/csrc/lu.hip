@@ -5,7 +5,7 @@
 //                    workgroups that keep the panel in registers;
 //   k_laswp_moves    apply the panel's row interchanges to every other column
 //                    (and to the permutation vector used by the solves);
-//   k_trsm_llnu      U12 = L11^{-1} A12 (unit lower, substitution per column);
+//   k_trsm_lines     U12 = L11^{-1} A12 (unit lower; trsm_lines.hip);
 //   k_gemm_sub       A22 -= L21 U12 on the matrix cores (gemm.hip).
 //
 // The panel needs one cross-workgroup exchange per column (the pivot search
@@ -281,62 +281,4 @@ hipError_t launch_laswp_moves(int n, int k0, int nbw, double* W, int ldw, const 
 }
 
 // U12 = L11^{-1} A12 with L11 the unit lower nbw x nbw block at W(k0,k0) and
-// A12 = W(k0:k0+nbw, k0+nbw : k0+nbw+ncols). One thread per column; L11 is
-// staged in LDS and read as a broadcast; each column is solved by forward
-// substitution in chunks of 32 rows held in registers.
-__global__ __launch_bounds__(256) void k_trsm_llnu(int k0, int nbw, int ncols, double* __restrict__ W, int ldw,
-                                                   const DevRec* rec) {
-  if (rec->stop) return;
-  extern __shared__ double sL[];  // sL[col * nbw + row]
-  const int t = threadIdx.x;
-  for (int e = t; e < nbw * nbw; e += blockDim.x) {
-    const int r = e % nbw, c = e / nbw;
-    sL[e] = W[(size_t)(k0 + r) + (size_t)(k0 + c) * ldw];
-  }
-  __syncthreads();
-  const int jc = blockIdx.x * blockDim.x + t;
-  if (jc >= ncols) return;
-  double* col = W + (size_t)(k0 + nbw + jc) * ldw + k0;
-  const int nch = (nbw + 31) / 32;
-  for (int ch = 0; ch < nch; ++ch) {
-    const int r0 = ch * 32;
-    double x[32];
-#pragma unroll
-    for (int r = 0; r < 32; ++r) x[r] = (r0 + r < nbw) ? col[r0 + r] : 0.0;
-    for (int p = 0; p < ch; ++p) {
-      const int c0 = p * 32;
-      double y[32];
-#pragma unroll
-      for (int cc = 0; cc < 32; ++cc) y[cc] = col[c0 + cc];  // solved rows, loaded together
-#pragma unroll
-      for (int cc = 0; cc < 32; ++cc) {
-        const double* lc = sL + (size_t)(c0 + cc) * nbw + r0;
-#pragma unroll
-        for (int r = 0; r < 32; ++r)
-          if (r0 + r < nbw) x[r] = fma(-lc[r], y[cc], x[r]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-      const double* lc = sL + (size_t)(r0 + i) * nbw + r0;
-#pragma unroll
-      for (int r = i + 1; r < 32; ++r)
-        if (r0 + r < nbw) x[r] = fma(-lc[r], x[i], x[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < 32; ++r)
-      if (r0 + r < nbw) col[r0 + r] = x[r];
-  }
-}
-
-hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st) {
-  if (ncols <= 0) return hipSuccess;
-  const size_t lds = (size_t)nbw * nbw * sizeof(double);
-  static size_t done = 0;
-  hipError_t e = ensure_lds((const void*)k_trsm_llnu, lds, done);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trsm_llnu, dim3((ncols + 255) / 256), dim3(256), lds, st, k0, nbw, ncols, W, ldw, rec);
-  return hipGetLastError();
-}
-
 }  // namespace ada

@@ -1,0 +1,97 @@
+// Block triangular solves inside the blocked factorisations:
+//   LU (Section II-D)         U12 = L11^{-1} A12, L11 unit lower: every column of A12 is a line;
+//   Cholesky (Section II-C)   L21 = A21 L11^{-T}: every row of A21 is a line (x L11^T = a).
+// Both are forward substitution with the lower-triangular L11 on each line:
+//   for i: v_i /= L(i,i) (non-unit only); v_r -= L(r,i) v_i for r > i.
+// Eight threads share a line (thread g holds elements g, g+8, ..., g+120 in
+// registers), 32 lines per workgroup, so a 128 x 8064 block fills the chip;
+// L11 sits in LDS transposed (LDS row i = column i of L11), the solved v_i goes
+// to the line's other threads with one cross-lane read, and the loop over i is
+// unrolled so that every register index is a constant. Lanes are laid out so
+// that the loads and stores of the block are coalesced: consecutive lanes hold
+// consecutive rows of the matrix in both cases.
+#include "ada_internal.h"
+
+namespace ada {
+
+constexpr int TLB = 128;           // block width (the factorisation's panel width)
+constexpr int TLG = 8;             // threads per line
+constexpr int TLK = TLB / TLG;     // elements per thread
+constexpr int TLL = 256 / TLG;     // lines per workgroup
+
+template <bool LINE_IS_ROW, bool UNIT>
+__global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int nlines, double* __restrict__ W, int ldw,
+                                                    const DevRec* rec) {
+  if (rec->stop) return;
+  extern __shared__ double sL[];  // sL[i * TLB + r] = L11(r, i), r >= i; identity padding past nbw
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = LINE_IS_ROW ? (lane >> 3) : (lane & 7);
+  const int li = LINE_IS_ROW ? (lane & 7) : (lane >> 3);
+  const int line = blockIdx.x * TLL + w * 8 + li;
+  const bool live = line < nlines;
+  for (int e = t; e < TLB * TLB; e += 256) {
+    const int r = e % TLB, i = e / TLB;
+    double x = (r == i) ? 1.0 : 0.0;
+    if (r >= i && r < nbw && i < nbw) x = W[(size_t)(k0 + r) + (size_t)(k0 + i) * ldw];
+    sL[e] = x;
+  }
+  // element i of this line
+  auto at = [&](int i) -> double* {
+    return LINE_IS_ROW ? W + (size_t)(k0 + nbw + line) + (size_t)(k0 + i) * ldw
+                       : W + (size_t)(k0 + i) + (size_t)(k0 + nbw + line) * ldw;
+  };
+  double v[TLK];
+#pragma unroll
+  for (int k = 0; k < TLK; ++k) {
+    const int i = g + TLG * k;
+    v[k] = (live && i < nbw) ? *at(i) : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < TLB; ++i) {
+    const int ki = i / TLG, gi = i % TLG;
+    double xi = v[ki];
+    if (!UNIT) {
+      xi = xi / sL[i * TLB + i];
+      v[ki] = (g == gi) ? xi : v[ki];
+    }
+    const int src = LINE_IS_ROW ? (li + 8 * gi) : (gi + 8 * li);
+    xi = __shfl(xi, src, 64);
+    const double* Li = sL + i * TLB;
+#pragma unroll
+    for (int k = ki; k < TLK; ++k) {
+      const double l = Li[g + TLG * k];
+      if (k == ki) v[k] = (g > gi) ? fma(-l, xi, v[k]) : v[k];
+      else v[k] = fma(-l, xi, v[k]);
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int k = 0; k < TLK; ++k) {
+    const int i = g + TLG * k;
+    if (i < nbw) *at(i) = v[k];
+  }
+}
+
+template <bool LINE_IS_ROW, bool UNIT>
+static hipError_t launch_lines(int k0, int nbw, int nlines, double* W, int ldw, const DevRec* rec, hipStream_t st) {
+  if (nlines <= 0) return hipSuccess;
+  if (nbw > TLB) return hipErrorInvalidValue;
+  const size_t lds = (size_t)TLB * TLB * sizeof(double);
+  static size_t done = 0;
+  hipError_t e = ensure_lds((const void*)k_trsm_lines<LINE_IS_ROW, UNIT>, lds, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_trsm_lines<LINE_IS_ROW, UNIT>), dim3((nlines + TLL - 1) / TLL), dim3(256), lds, st, k0, nbw,
+                     nlines, W, ldw, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st) {
+  return launch_lines<false, true>(k0, nbw, ncols, W, ldw, rec, st);
+}
+
+hipError_t launch_trsm_rltn(int k0, int nbw, int mrows, double* W, int ldw, const DevRec* rec, hipStream_t st) {
+  return launch_lines<true, false>(k0, nbw, mrows, W, ldw, rec, st);
+}
+
+}  // namespace ada

@@ -286,7 +286,7 @@ def _pivoting_band(n, kl, ku, rng, shift=1.0):
 @pytest.mark.parametrize("n,kl,ku,nrhs,shift", [(1024, 3, 2, 1, 1.0), (1025, 3, 2, 2, 1.0), (1500, 0, 4, 1, 1.0),
                                                 (1500, 4, 0, 3, 1.0), (5000, 1, 1, 1, 1.0), (4099, 16, 15, 2, 1.0),
                                                 (3000, 31, 0, 1, 16.0), (3000, 0, 31, 1, 16.0), (2600, 5, 5, 70, 1.0),
-                                                (20000, 5, 5, 1, 1.0), (2048, 2, 9, 4, 4.0)])
+                                                (20000, 5, 5, 1, 1.0), (2048, 2, 9, 4, 4.0), (3000, 2, 1, 150, 3.0)])
 def test_band_row_parallel_solve(ada, n, kl, ku, nrhs, shift):
     # long bands take the row-parallel (chunked) band solve, forward and transposed (estimator)
     print(f"band n={n} kl={kl} ku={ku} nrhs={nrhs}", flush=True)
