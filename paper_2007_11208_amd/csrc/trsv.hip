@@ -144,11 +144,163 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
   if (t == 0) __hip_atomic_store(&flags[bi], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One right-hand side (the routed 1-RHS solves and every solve of the
+// condition estimate). The same decoupled scheme with the critical path cut
+// down: the tiles of earlier blocks are streamed through two LDS buffers
+// (the next tile's loads are in flight while the current one is used); the
+// tile next to the diagonal and the diagonal tile itself are staged, and the
+// reciprocals of the diagonal formed, before the wait for the block that
+// precedes this one, so that after the wait only that block's x (64 values),
+// one 64x64 product and the substitution remain. The substitution runs in one
+// wave with lane = row and the solved value broadcast by readlane.
+__global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__ T, int ldt, int lower, int trans,
+                                               int unit, double* x, int* flags, int epoch, unsigned* ticket,
+                                               DevRec* rec, const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  constexpr int LD = TB + 1;
+  const int t = threadIdx.x, lane = t & 63, cq = t >> 6;
+  const int nblk = (n + TB - 1) / TB;
+  __shared__ int s_tk;
+  if (t == 0) s_tk = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int tk = s_tk;
+  if (tk >= nblk) return;
+  const bool eff_lower = (lower != 0) != (trans != 0);
+  auto blk = [&](int q) { return eff_lower ? q : (nblk - 1 - q); };
+  const int bi = blk(tk);
+  const int r0 = bi * TB;
+  const int rows = min(TB, n - r0);
+
+  extern __shared__ double sm[];
+  double* tb0 = sm;             // [64][65]: tb[k * LD + r] = op(T)(r0 + r, c0 + k)
+  double* tb1 = tb0 + TB * LD;
+  double* td = tb1 + TB * LD;   // diagonal tile
+  double* sx = td + TB * LD;    // x of the block being applied
+  double* sacc = sx + TB;       // [4][64] partial sums
+  double* rdg = sacc + 4 * TB;  // reciprocals of the diagonal
+
+  // thread t stages 16 elements of a 64x64 tile: k = t / 4 * ... (coalesced in memory)
+  double st[16];
+  auto load_tile = [&](int c0, int cols) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u;
+      const int a = e % TB, b = e / TB;  // a runs along memory
+      const int r = trans ? b : a, k = trans ? a : b;
+      st[u] = (r < rows && k < cols) ? (trans ? T[(size_t)(c0 + k) + (size_t)(r0 + r) * ldt]
+                                               : T[(size_t)(r0 + r) + (size_t)(c0 + k) * ldt])
+                                     : 0.0;
+    }
+  };
+  auto store_tile = [&](double* dst) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u;
+      const int a = e % TB, b = e / TB;
+      const int r = trans ? b : a, k = trans ? a : b;
+      dst[k * LD + r] = st[u];
+    }
+  };
+  auto wait_flag = [&](int b) {
+    if (t == 0) {
+      long spins = 0;
+      while (agent_load(&flags[b]) != epoch) {
+        if (++spins > kSpinLimit) {
+          atomicOr(&rec->timeout, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(0);
+      }
+    }
+    __syncthreads();
+  };
+
+  const double bval = (cq == 0 && lane < rows) ? x[r0 + lane] : 0.0;
+  double acc = 0.0;
+  const int nfar = tk > 0 ? tk - 1 : 0;
+  if (nfar > 0) {
+    const int c0 = blk(0) * TB;
+    load_tile(c0, min(TB, n - c0));
+    store_tile(tb0);
+  }
+  __syncthreads();
+  for (int q = 0; q < nfar; ++q) {
+    double* cur = (q & 1) ? tb1 : tb0;
+    double* nxt = (q & 1) ? tb0 : tb1;
+    if (q + 1 < nfar) {
+      const int c1 = blk(q + 1) * TB;
+      load_tile(c1, min(TB, n - c1));
+    }
+    const int bj = blk(q), c0 = bj * TB, cols = min(TB, n - c0);
+    wait_flag(bj);
+    if (t < TB) sx[t] = t < cols ? x[c0 + t] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = fma(cur[(16 * cq + k) * LD + lane], sx[16 * cq + k], acc);
+    if (q + 1 < nfar) store_tile(nxt);
+    __syncthreads();
+  }
+  // the tile next to the diagonal and the diagonal tile, before the wait
+  double* near = (nfar & 1) ? tb1 : tb0;
+  int bn = -1, cn = 0, coln = 0;
+  if (tk > 0) {
+    bn = blk(tk - 1);
+    cn = bn * TB;
+    coln = min(TB, n - cn);
+    load_tile(cn, coln);
+    store_tile(near);
+  }
+  load_tile(r0, rows);
+  store_tile(td);
+  __syncthreads();
+  if (t < TB) rdg[t] = (t < rows) ? (unit ? 1.0 : 1.0 / td[t * LD + t]) : 1.0;
+  if (tk > 0) {
+    wait_flag(bn);
+    if (t < TB) sx[t] = t < coln ? x[cn + t] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = fma(near[(16 * cq + k) * LD + lane], sx[16 * cq + k], acc);
+  }
+  sacc[cq * TB + lane] = acc;
+  __syncthreads();
+  if (cq == 0) {
+    double a = bval - ((sacc[lane] + sacc[TB + lane]) + (sacc[2 * TB + lane] + sacc[3 * TB + lane]));
+    if (eff_lower) {
+      for (int i = 0; i < rows; ++i) {
+        const double xi = read_lane(a, i) * rdg[i];
+        const double l = td[i * LD + lane];
+        a = (lane == i) ? xi : a;
+        if (lane > i) a = fma(-l, xi, a);
+      }
+    } else {
+      for (int i = rows - 1; i >= 0; --i) {
+        const double xi = read_lane(a, i) * rdg[i];
+        const double l = td[i * LD + lane];
+        a = (lane == i) ? xi : a;
+        if (lane < i) a = fma(-l, xi, a);
+      }
+    }
+    if (lane < rows) x[r0 + lane] = a;
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) __hip_atomic_store(&flags[bi], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 hipError_t launch_trsm_dec(int n, int nrhs, const double* T, int ldt, bool lower, bool trans, bool unit, double* X,
                            int ldx, int* flags, int epoch, unsigned* ticket, DevRec* rec, const int* pred,
                            int pred_val, hipStream_t st) {
   if (nrhs < 1 || nrhs > 64) return hipErrorInvalidValue;
   const int nblk = (n + TB - 1) / TB;
+  if (nrhs == 1) {
+    const size_t lds1 = sizeof(double) * ((size_t)3 * TB * (TB + 1) + (size_t)6 * TB);
+    static size_t done1 = 0;
+    hipError_t e1 = ensure_lds((const void*)k_trsv1, lds1, done1);
+    if (e1 != hipSuccess) return e1;
+    hipLaunchKernelGGL(k_trsv1, dim3(nblk), dim3(256), lds1, st, n, T, ldt, (int)lower, (int)trans, (int)unit, X,
+                       flags, epoch, ticket, rec, pred, pred_val);
+    return hipGetLastError();
+  }
   const size_t lds = sizeof(double) * ((size_t)TB * nrhs * 2 + (size_t)TB * (TB + 1));
   static size_t done = 0;
   hipError_t e = ensure_lds((const void*)k_trsm_dec, lds, done);
