@@ -45,6 +45,7 @@ struct DevRec {
   int sweeps;                 // Jacobi sweeps used
   // ---- synchronisation counters (zeroed per solve) ----
   unsigned int counters[512];  // grid barriers / tickets, one per launch that needs one
+  int panel_flags[2 * 64];     // LU panel: per-workgroup publication epochs (two column parities)
 };
 
 // Raise a kernel's dynamic-LDS limit when a launch needs more than the default
@@ -119,6 +120,20 @@ __device__ __forceinline__ double relaxed_load(const double* p) {
 __device__ __forceinline__ void relaxed_store(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ int relaxed_load(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void relaxed_store(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Hand-off between workgroups without cache maintenance: the data and the flag
+// are written and read with agent-scope relaxed atomics (coherent across the
+// chip's L2s, no write-back or invalidation of whole caches), and the writer
+// waits until its data stores are complete before the flag store is issued.
+// A reader that has seen the flag then reads the data with agent-scope loads.
+__device__ __forceinline__ void wait_stores_done() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every earlier load/store of this wave has completed
+}
 
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns hipGetLastError().
@@ -159,8 +174,9 @@ struct PanelScratch {
   double* diag_rows;  // [2][128]
   int* moves;         // [2*128+1]: count, then (dst,src) pairs
 };
-hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec,
-                              unsigned* counter, PanelScratch ps, hipStream_t st);
+// seq: index of this panel within the solve (makes the publication epochs unique)
+hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec, int seq,
+                              PanelScratch ps, hipStream_t st);
 hipError_t launch_laswp_moves(int n, int k0, int nbw, double* W, int ldw, const int* moves, int* perm,
                               DevRec* rec, hipStream_t st);
 hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st);

@@ -342,13 +342,11 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
                   s.at<double>(s.p.diag_rows), s.at<int>(s.p.moves)};
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int nbw = n - k0 < kNB ? n - k0 : kNB;
-    unsigned* ctr = s.next_counter();
-    if (!ctr) return fail(ADA_ERR_ARG, "too many device synchronisation counters for this size");
     const double m = (double)(n - k0), b = (double)nbw;
     // panel: sum over its columns s of 2 (m - s - 1)(b - s - 1) + (m - s - 1); reads and writes m x b
     const double pfl = b * (b - 1) * (3.0 * m - b - 1) / 3.0 + b * m - b * (b + 1) / 2.0;
     HIPCHK(s.timed(ADA_KF_PANEL, pfl, 16.0 * m * b,
-                   [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, ctr, ps, s.st); }));
+                   [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, k0 / kNB, ps, s.st); }));
     HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * (n - nbw),
                    [&] { return launch_laswp_moves(n, k0, nbw, W, ldw, ps.moves, perm, s.rec, s.st); }));
     const int rest = n - k0 - nbw;

@@ -22,29 +22,68 @@ namespace ada {
 constexpr int PNB = 128;    // panel width
 constexpr int PROWS = 256;  // panel rows per workgroup = threads per workgroup (one row per thread)
 
-__device__ void grid_wait(unsigned* counter, unsigned target, DevRec* rec) {
-  long spins = 0;
-  while (agent_load(counter) < target) {
-    if (++spins > kSpinLimit) {
-      atomicOr(&rec->timeout, 1);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
+
+// Each panel row is held in registers by four threads, one per column
+// quarter (quarter h = waves 4h .. 4h+3, 32 columns each, d[c] = column
+// 32h + c), so whatever depends on the current column's quarter is uniform
+// across a wave: the current column is picked out of the registers by a
+// uniform branch on its index and the update of a quarter starts at its first
+// live column by a uniform jump into straight-line code. Row interchanges are
+// not moved through memory: each row carries its current position `pos`; the
+// pivot row takes position s and the row that sat at s takes the pivot's old
+// position, exactly as an explicit interchange would. Rows are written to
+// their final positions at the end and the list of moved rows is handed to
+// k_laswp_moves.
+//
+// With several workgroups, every column needs one exchange: each workgroup
+// publishes its best candidate (modulus, position, row) and then an epoch flag
+// of its own; wave 0 of every workgroup polls all the flags at once (one lane
+// per workgroup, no read-modify-write on a shared counter), picks the winner
+// (largest modulus, lowest position on ties) and stages the winner's row in
+// LDS. The hand-off uses agent-scope relaxed accesses and a wait for store
+// completion (no cache write-back or invalidation). All waits are bounded.
+constexpr int HC = 32;                   // columns per thread
+constexpr int PTH = (PNB / HC) * PROWS;  // 1024 threads
+
+// d[i] for a wave-uniform i (a branch tree, no register indexing)
+__device__ __forceinline__ double get_col(const double (&d)[HC], int i) {
+  double v = 0.0;
+  switch (i) {
+#define ADA_CASE(K) case K: v = d[K]; break;
+    ADA_CASE(0) ADA_CASE(1) ADA_CASE(2) ADA_CASE(3) ADA_CASE(4) ADA_CASE(5) ADA_CASE(6) ADA_CASE(7)
+    ADA_CASE(8) ADA_CASE(9) ADA_CASE(10) ADA_CASE(11) ADA_CASE(12) ADA_CASE(13) ADA_CASE(14) ADA_CASE(15)
+    ADA_CASE(16) ADA_CASE(17) ADA_CASE(18) ADA_CASE(19) ADA_CASE(20) ADA_CASE(21) ADA_CASE(22) ADA_CASE(23)
+    ADA_CASE(24) ADA_CASE(25) ADA_CASE(26) ADA_CASE(27) ADA_CASE(28) ADA_CASE(29) ADA_CASE(30) ADA_CASE(31)
+#undef ADA_CASE
+  }
+  return v;
+}
+__device__ __forceinline__ void set_col(double (&d)[HC], int i, double v) {
+  switch (i) {
+#define ADA_CASE(K) case K: d[K] = v; break;
+    ADA_CASE(0) ADA_CASE(1) ADA_CASE(2) ADA_CASE(3) ADA_CASE(4) ADA_CASE(5) ADA_CASE(6) ADA_CASE(7)
+    ADA_CASE(8) ADA_CASE(9) ADA_CASE(10) ADA_CASE(11) ADA_CASE(12) ADA_CASE(13) ADA_CASE(14) ADA_CASE(15)
+    ADA_CASE(16) ADA_CASE(17) ADA_CASE(18) ADA_CASE(19) ADA_CASE(20) ADA_CASE(21) ADA_CASE(22) ADA_CASE(23)
+    ADA_CASE(24) ADA_CASE(25) ADA_CASE(26) ADA_CASE(27) ADA_CASE(28) ADA_CASE(29) ADA_CASE(30) ADA_CASE(31)
+#undef ADA_CASE
+  }
+}
+// d[c] -= l * u[c] for c = first .. HC-1 (first wave-uniform): a jump into straight-line code
+__device__ __forceinline__ void update_from(double (&d)[HC], int first, double l, const double* u) {
+  switch (first) {
+#define ADA_CASE(K) case K: d[K] = fma(-l, u[K], d[K]); [[fallthrough]];
+    ADA_CASE(0) ADA_CASE(1) ADA_CASE(2) ADA_CASE(3) ADA_CASE(4) ADA_CASE(5) ADA_CASE(6) ADA_CASE(7)
+    ADA_CASE(8) ADA_CASE(9) ADA_CASE(10) ADA_CASE(11) ADA_CASE(12) ADA_CASE(13) ADA_CASE(14) ADA_CASE(15)
+    ADA_CASE(16) ADA_CASE(17) ADA_CASE(18) ADA_CASE(19) ADA_CASE(20) ADA_CASE(21) ADA_CASE(22) ADA_CASE(23)
+    ADA_CASE(24) ADA_CASE(25) ADA_CASE(26) ADA_CASE(27) ADA_CASE(28) ADA_CASE(29) ADA_CASE(30)
+    case 31: d[31] = fma(-l, u[31], d[31]);
+#undef ADA_CASE
+    default: break;
   }
 }
 
-// Each panel row is held in registers by four threads (32 columns each). The
-// part that holds the current column rotates its registers left
-// by one after every column step, so the current column is always its d[0] and
-// every register index is a constant. Row interchanges are not moved through
-// memory: each row carries its current position `pos`; the pivot row takes
-// position s and the row that sat at s takes the pivot's old position, exactly
-// as an explicit interchange would. Rows are written to their final positions
-// at the end and the list of moved rows is handed to k_laswp_moves.
-constexpr int HC = 32;                 // columns per thread
-constexpr int PTH = (PNB / HC) * PROWS;  // 1024 threads: part h = t / PROWS holds columns HC*h .. HC*h+HC-1
 __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, double* __restrict__ W, int ldw,
-                                                     int* __restrict__ ipiv, DevRec* rec, unsigned* counter,
+                                                     int* __restrict__ ipiv, DevRec* rec, int seq,
                                                      PanelScratch ps) {
   if (rec->stop) return;
   const int m = n - k0;
@@ -60,91 +99,89 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
   __shared__ double s_l[PROWS];
   __shared__ double s_cv[4];
   __shared__ int s_cp[4];
-  __shared__ int s_bp, s_win_pos, s_win_wg;
-  __shared__ double s_bv;
-  extern __shared__ double s_rows[];  // P x PNB candidate rows (P > 1)
+  __shared__ int s_win;
 
   if (wg == 0 && t == 0) __hip_atomic_store(ps.moves, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
   double d[HC];
   {
-    // column pointers are uniform per wave, the row offset is per thread: one register per address
     const int row = k0 + min(prow, m - 1);
+    const double* base = W + (size_t)(k0 + HC * h) * ldw + row;
 #pragma unroll
-    for (int c = 0; c < HC; ++c) {
-      const double* colp = W + (size_t)(k0 + min(HC * h + c, nbw - 1)) * ldw;
-      d[c] = colp[row];
-    }
-#pragma unroll
-    for (int c = 0; c < HC; ++c)
-      if (!rvalid || HC * h + c >= nbw) d[c] = 0.0;
+    for (int c = 0; c < HC; ++c) d[c] = (rvalid && HC * h + c < nbw) ? base[(size_t)c * ldw] : 0.0;
   }
+  // columns of quarter h that exist (the last panel may be narrower)
+  const int ncols = max(0, min(HC, nbw - HC * h));
 
   for (int s = 0; s < nbw; ++s) {
     const int par = s & 1;
-    const int hc = s / HC;          // half holding column s (its d[0])
-    const int sl = s % HC;          // rotations that half has done so far
+    const int hc = s / HC;  // quarter holding column s
+    const int sl = s % HC;  // its register
     const bool cur = (h == hc);
-    // 1. this workgroup's candidate: largest |A(row, s)| over rows at positions >= s, lowest position on ties
+    // 1. candidate of each wave of the current quarter: largest |A(row, s)| at positions >= s, lowest position on ties
     if (cur) {
       double v = -1.0;
       int key = -1;
+      const double x = get_col(d, sl);
       if (rvalid && pos >= s) {
-        v = fabs(d[0]);
+        v = fabs(x);
         key = pos;
       }
       wave_argmax(v, key);
       if (lane == 0) { s_cv[w - 4 * hc] = v; s_cp[w - 4 * hc] = key; }
     }
     __syncthreads();
-    if (t == 0) {
-      double bv = s_cv[0];
-      int bp = s_cp[0];
-      for (int q = 1; q < 4; ++q) {
-        const int k2 = s_cp[q];
-        const double v2 = s_cv[q];
-        if (k2 >= 0 && (bp < 0 || v2 > bv || (v2 == bv && k2 < bp))) { bv = v2; bp = k2; }
-      }
-      s_bv = bv;
-      s_bp = bp;
+    // the workgroup's candidate (every thread, same order)
+    double bv = s_cv[0];
+    int bp = s_cp[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      const int k2 = s_cp[q];
+      const double v2 = s_cv[q];
+      if (k2 >= 0 && (bp < 0 || v2 > bv || (v2 == bv && k2 < bp))) { bv = v2; bp = k2; }
     }
-    __syncthreads();
-    const int bp = s_bp;
+    const bool holder = rvalid && pos == bp;
+    int p;
     if (P == 1) {
-      if (rvalid && pos == bp) {
+      if (holder) {
 #pragma unroll
         for (int c = 0; c < HC; ++c) s_u[HC * h + c] = d[c];
       }
-      if (t == 0) s_win_pos = bp;
       __syncthreads();
+      p = bp;
     } else {
-      // 2. publish (value, position) and the candidate row, then meet at the counter
+      // 2. publish the candidate, then this workgroup's epoch flag
+      const int epoch = seq * 256 + s + 1;
       double* myslot = ps.slot_rows + ((size_t)par * 64 + wg) * PNB;
-      if (rvalid && pos == bp) {
+      if (holder) {
 #pragma unroll
         for (int c = 0; c < HC; ++c) relaxed_store(myslot + HC * h + c, d[c]);
-        __threadfence();
+        wait_stores_done();
       }
       if (t == 0) {
-        relaxed_store(ps.slot_val + par * 64 + wg, s_bv);
-        __hip_atomic_store(ps.slot_row + par * 64 + wg, bp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        relaxed_store(ps.slot_val + par * 64 + wg, bv);
+        relaxed_store(ps.slot_row + par * 64 + wg, bp);
+        wait_stores_done();
       }
       __syncthreads();
-      if (t == 0) {
-        __threadfence();
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        grid_wait(counter, (unsigned)(s + 1) * (unsigned)P, rec);
-      }
-      __syncthreads();
-      // 3. read every candidate (value, position, row) in one round trip; all workgroups pick the same winner
-      for (int e = t; e < P * PNB; e += PTH) s_rows[e] = relaxed_load(ps.slot_rows + (size_t)par * 64 * PNB + e);
-      if (t < 64) {
+      if (t == 0) relaxed_store(&rec->panel_flags[par * 64 + wg], epoch);
+      // 3. wave 0: wait for every flag (lane q polls workgroup q), pick the winner, stage its row
+      if (w == 0) {
         double cv = -1.0;
-        int ck = -1, cw = t;
-        if (t < P) {
-          cv = relaxed_load(ps.slot_val + par * 64 + t);
-          ck = __hip_atomic_load(ps.slot_row + par * 64 + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ck = -1;
+        if (lane < P) {
+          long spins = 0;
+          while (relaxed_load(&rec->panel_flags[par * 64 + lane]) != epoch) {
+            if (++spins > kSpinLimit) {
+              atomicOr(&rec->timeout, 1);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(0);
+          }
+          cv = relaxed_load(ps.slot_val + par * 64 + lane);
+          ck = relaxed_load(ps.slot_row + par * 64 + lane);
         }
+        int cw = lane;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
           const double v2 = __shfl_xor(cv, o, 64);
@@ -152,60 +189,39 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
           const int w2 = __shfl_xor(cw, o, 64);
           if (k2 >= 0 && (ck < 0 || v2 > cv || (v2 == cv && k2 < ck))) { cv = v2; ck = k2; cw = w2; }
         }
-        if (t == 0) { s_win_pos = ck; s_win_wg = cw; }
+        const double* win = ps.slot_rows + ((size_t)par * 64 + cw) * PNB;
+        s_u[lane] = relaxed_load(win + lane);
+        s_u[lane + 64] = relaxed_load(win + lane + 64);
+        if (lane == 0) s_win = ck;
       }
       __syncthreads();
-      if (t < PNB) s_u[t] = s_rows[s_win_wg * PNB + t];
-      __syncthreads();
+      p = s_win;
     }
-    const int p = s_win_pos;
     if (wg == 0 && t == 0) ipiv[k0 + s] = k0 + p;
     // 4. the interchange of positions s and p (bookkeeping only)
     const bool is_win = rvalid && pos == p;
     if (rvalid && pos == s && !is_win) pos = p;
     if (is_win) pos = s;
-    // s_u holds the pivot row in the frames of the two halves: half hc rotated by sl, the others not
-    const double piv = s_u[HC * hc];
+    const double piv = s_u[s];
     if (piv == 0.0 && wg == 0 && t == 0) atomicMin(&rec->info, k0 + s + 1);  // exact zero pivot: failure
-    // 5. multiplier (current part) and rank-1 update of this row; straight-line selects keep d[] in place
+    // 5. multiplier in the current quarter, to the other quarters through LDS; rank-1 update
     const bool active = piv != 0.0 && rvalid && pos > s;
-    double l = 0.0;
     if (cur) {
-      l = active ? d[0] / piv : 0.0;
-      d[0] = active ? l : d[0];
+      const double x = get_col(d, sl);
+      const double l = active ? x / piv : 0.0;
+      if (active) set_col(d, sl, l);
       s_l[r] = l;
     }
     __syncthreads();
-    l = s_l[r];
-    {
-      // current part: columns s+1.. sit in d[1 .. live-1]; later parts: every column below nbw
-      const int live = cur ? min(HC - sl, nbw - s) : (nbw - HC * h);
-      const int first = cur ? 1 : 0;
-      const bool upd = active && h >= hc;
-#pragma unroll
-      for (int c = 0; c < HC; ++c) {
-        const double nv = fma(-l, s_u[HC * h + c], d[c]);
-        d[c] = (upd && c >= first && c < live) ? nv : d[c];
-      }
-    }
-    // 6. rotate the current part: the finished column moves to the back
-    {
-      const double f = d[0];
-#pragma unroll
-      for (int c = 0; c < HC - 1; ++c) d[c] = cur ? d[c + 1] : d[c];
-      d[HC - 1] = cur ? f : d[HC - 1];
-    }
-    __syncthreads();
+    const double l = s_l[r];  // 0 for rows that are not updated: the update is then exact no-op
+    if (h > hc) update_from(d, 0, l, s_u + HC * h);
+    else if (cur && sl + 1 < HC) update_from(d, sl + 1, l, s_u + HC * h);
   }
-  // half h was rotated rot times (HC rotations restore the order): d[c] holds column HC*h + (c + rot) % HC
   if (rvalid) {
-    const int rot = max(0, min(HC, nbw - HC * h)) % HC;
     const int row = k0 + pos;
 #pragma unroll
-    for (int c = 0; c < HC; ++c) {
-      const int col = HC * h + (c + rot) % HC;
-      if (col < nbw) W[(size_t)(k0 + col) * ldw + row] = d[c];
-    }
+    for (int c = 0; c < HC; ++c)
+      if (c < ncols) W[(size_t)(k0 + HC * h + c) * ldw + row] = d[c];
     if (h == 0 && pos != prow) {
       const int idx = atomicAdd(ps.moves, 1);
       ps.moves[1 + 2 * idx] = k0 + pos;   // destination row
@@ -214,13 +230,12 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
   }
 }
 
-hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec,
-                              unsigned* counter, PanelScratch ps, hipStream_t st) {
+hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec, int seq,
+                              PanelScratch ps, hipStream_t st) {
   const int m = n - k0;
   const int P = (m + PROWS - 1) / PROWS;
   if (P > 64) return hipErrorInvalidValue;  // n - k0 <= 16384 per panel
-  const size_t lds = P > 1 ? (size_t)P * PNB * sizeof(double) : 0;
-  hipLaunchKernelGGL(k_getrf_panel, dim3(P), dim3(PTH), lds, st, n, k0, nbw, W, ldw, ipiv, rec, counter, ps);
+  hipLaunchKernelGGL(k_getrf_panel, dim3(P), dim3(PTH), 0, st, n, k0, nbw, W, ldw, ipiv, rec, seq, ps);
   return hipGetLastError();
 }
 

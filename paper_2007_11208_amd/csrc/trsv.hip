@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
     stage_tile(c0, cols);
     if (t == 0) {
       long spins = 0;
-      while (agent_load(&flags[bj]) != epoch) {
+      while (relaxed_load(&flags[bj]) != epoch) {
         if (++spins > kSpinLimit) {
           atomicOr(&rec->timeout, 1);
           break;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
     __syncthreads();
     for (int e = t; e < TB * nrhs; e += blockDim.x) {
       const int k = e % TB, c = e / TB;
-      xj[e] = (k < cols) ? X[(size_t)(c0 + k) + (size_t)c * ldx] : 0.0;
+      xj[e] = (k < cols) ? relaxed_load(X + (size_t)(c0 + k) + (size_t)c * ldx) : 0.0;
     }
     __syncthreads();
     {
@@ -137,11 +137,11 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
   __syncthreads();
   for (int e = t; e < TB * nrhs; e += blockDim.x) {
     const int r = e % TB, c = e / TB;
-    if (r < rows) X[(size_t)(r0 + r) + (size_t)c * ldx] = acc[e];
+    if (r < rows) relaxed_store(X + (size_t)(r0 + r) + (size_t)c * ldx, acc[e]);
   }
-  __threadfence();
+  wait_stores_done();
   __syncthreads();
-  if (t == 0) __hip_atomic_store(&flags[bi], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (t == 0) relaxed_store(&flags[bi], epoch);
 }
 
 // One right-hand side (the routed 1-RHS solves and every solve of the
@@ -152,7 +152,10 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
 // reciprocals of the diagonal formed, before the wait for the block that
 // precedes this one, so that after the wait only that block's x (64 values),
 // one 64x64 product and the substitution remain. The substitution runs in one
-// wave with lane = row and the solved value broadcast by readlane.
+// wave with lane = row and the solved value broadcast by readlane. The solved
+// block and its flag are handed over with agent-scope relaxed accesses (the
+// flag is stored once the block's stores are complete), so no cache
+// write-back or invalidation sits on the chain.
 __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__ T, int ldt, int lower, int trans,
                                                int unit, double* x, int* flags, int epoch, unsigned* ticket,
                                                DevRec* rec, const int* pred, int pred_val) {
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
   auto wait_flag = [&](int b) {
     if (t == 0) {
       long spins = 0;
-      while (agent_load(&flags[b]) != epoch) {
+      while (relaxed_load(&flags[b]) != epoch) {
         if (++spins > kSpinLimit) {
           atomicOr(&rec->timeout, 1);
           break;
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
     }
     const int bj = blk(q), c0 = bj * TB, cols = min(TB, n - c0);
     wait_flag(bj);
-    if (t < TB) sx[t] = t < cols ? x[c0 + t] : 0.0;
+    if (t < TB) sx[t] = t < cols ? relaxed_load(x + c0 + t) : 0.0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc = fma(cur[(16 * cq + k) * LD + lane], sx[16 * cq + k], acc);
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
   if (t < TB) rdg[t] = (t < rows) ? (unit ? 1.0 : 1.0 / td[t * LD + t]) : 1.0;
   if (tk > 0) {
     wait_flag(bn);
-    if (t < TB) sx[t] = t < coln ? x[cn + t] : 0.0;
+    if (t < TB) sx[t] = t < coln ? relaxed_load(x + cn + t) : 0.0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc = fma(near[(16 * cq + k) * LD + lane], sx[16 * cq + k], acc);
@@ -280,11 +283,11 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
         if (lane < i) a = fma(-l, xi, a);
       }
     }
-    if (lane < rows) x[r0 + lane] = a;
+    if (lane < rows) relaxed_store(x + r0 + lane, a);
+    wait_stores_done();
+    // wave 0 wrote the block: its lane 0 raises the flag once the stores are complete
+    if (lane == 0) relaxed_store(&flags[bi], epoch);
   }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) __hip_atomic_store(&flags[bi], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 hipError_t launch_trsm_dec(int n, int nrhs, const double* T, int ldt, bool lower, bool trans, bool unit, double* X,
