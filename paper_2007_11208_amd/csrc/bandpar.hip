@@ -154,9 +154,17 @@ __device__ void run_chunk(const BandSweep& B, int nchunks, bool live, int S, dou
       const int base = fwd ? (g0 + pc - halo) : (g1 - pc - piece - halo);
       double* dc = gcol + (size_t)gg * span * ldgb;
       int* dp = gpiv + gg * span;
-      for (int e = threadIdx.x; e < span * ldgb; e += blockDim.x) {
-        const int r = e % ldgb, c = base + e / ldgb;
-        dc[e] = (c >= 0 && c < n) ? B.GB[(size_t)r + (size_t)c * ldgb] : 0.0;
+      // the band columns base .. base+span-1 are contiguous in memory: 8 loads in flight per thread
+      for (int e0 = threadIdx.x; e0 < span * ldgb; e0 += 256 * 8) {
+        double tmp[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + 256 * u, c = base + e / ldgb;
+          tmp[u] = (e < span * ldgb && c >= 0 && c < n) ? B.GB[(size_t)base * ldgb + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (e0 + 256 * u < span * ldgb) dc[e0 + 256 * u] = tmp[u];
       }
       for (int e = threadIdx.x; e < span; e += blockDim.x) {
         const int c = base + e;

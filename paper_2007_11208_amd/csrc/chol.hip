@@ -12,41 +12,111 @@
 
 namespace ada {
 
-// Diagonal block (nbw <= 128) in LDS, column by column. Thread t works on row
-// r = t % 128 and on every other column of the update (parity t / 128), so
-// each step is one broadcast read of L(c, j) and one read-modify-write of
-// A(r, c) per column, with no index arithmetic beyond the loop.
+// Diagonal block (nbw <= 128) in LDS, in sub-blocks of 32 columns:
+//   1. wave 0 factors the 32x32 diagonal sub-block with lane = row and the
+//      row in registers (the column-j values of other rows come by readlane,
+//      so the 32 steps need no barrier);
+//   2. the rows below solve x L_kk^T = a (one thread per row, L_kk from LDS);
+//   3. the trailing lower triangle takes the symmetric rank-32 update.
+// A pivot that is not positive (or NaN) ends the factorisation: the matrix is
+// then not taken to be sympd and the system is re-solved by LU on the
+// original A (Section II-C).
+constexpr int PB = 32;
 __global__ __launch_bounds__(256) void k_potrf_diag(int k0, int nbw, double* __restrict__ W, int ldw, DevRec* rec) {
   if (rec->stop) return;
-  extern __shared__ double sA[];  // sA[c * ld + r], ld = nbw + 1
+  extern __shared__ double sA[];  // sA[c * ld + r], ld = nbw + 1 (lower triangle used)
   const int ld = nbw + 1;
-  const int t = threadIdx.x;
-  const int r = t & 127, half = t >> 7;
-  for (int e = t; e < nbw * nbw; e += blockDim.x) {
-    const int rr = e % nbw, c = e / nbw;
-    if (rr >= c) sA[c * ld + rr] = W[(size_t)(k0 + rr) + (size_t)(k0 + c) * ldw];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // 16 loads in flight per thread
+  for (int e0 = t; e0 < nbw * nbw; e0 += 256 * 16) {
+    double tmp[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u, rr = e % nbw, c = e / nbw;
+      tmp[u] = (e < nbw * nbw && rr >= c) ? W[(size_t)(k0 + rr) + (size_t)(k0 + c) * ldw] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u, rr = e % nbw, c = e / nbw;
+      if (e < nbw * nbw && rr >= c) sA[c * ld + rr] = tmp[u];
+    }
   }
   __shared__ int s_fail;
   if (t == 0) s_fail = 0;
   __syncthreads();
-  for (int j = 0; j < nbw; ++j) {
-    const double d = sA[j * ld + j];
-    if (!(d > 0.0)) {
-      if (t == 0) {
-        atomicMin(&rec->chol_info, k0 + j + 1);
-        rec->stop = 1;
-        s_fail = 1;
+  for (int kb = 0; kb < nbw; kb += PB) {
+    const int cb = min(PB, nbw - kb);
+    // 1. diagonal sub-block
+    if (w == 0) {
+      double v[PB];
+#pragma unroll
+      for (int j = 0; j < PB; ++j) v[j] = (lane < cb && j <= lane) ? sA[(kb + j) * ld + kb + lane] : 0.0;
+      int fail = 0;
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        if (j < cb && !fail) {
+          const double dj = read_lane(v[j], j);
+          if (!(dj > 0.0)) {
+            fail = j + 1;
+          } else {
+            const double sd = sqrt(dj);
+            v[j] = (lane == j) ? sd : (lane > j ? v[j] / sd : v[j]);
+#pragma unroll
+            for (int k = j + 1; k < PB; ++k) {
+              const double lkj = read_lane(v[j], k);
+              if (lane >= k && k < cb) v[k] = fma(-v[j], lkj, v[k]);
+            }
+          }
+        }
       }
-      break;
+      if (fail) {
+        if (lane == 0) {
+          atomicMin(&rec->chol_info, k0 + kb + fail);
+          rec->stop = 1;
+          s_fail = 1;
+        }
+      } else if (lane < cb) {
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+          if (j <= lane) sA[(kb + j) * ld + kb + lane] = v[j];
+      }
     }
-    const double sd = sqrt(d);
-    double lrj = 0.0;
-    if (r > j && r < nbw) lrj = sA[j * ld + r] / sd;
-    __syncthreads();  // every thread has read column j
-    if (half == 0 && r >= j && r < nbw) sA[j * ld + r] = (r == j) ? sd : lrj;
-    __syncthreads();  // column j of L is in place
-    if (r > j && r < nbw) {
-      for (int c = j + 1 + half; c <= r; c += 2) sA[c * ld + r] = fma(-lrj, sA[j * ld + c], sA[c * ld + r]);
+    __syncthreads();
+    if (s_fail) break;
+    const int r0 = kb + cb, rest = nbw - r0;
+    if (rest <= 0) break;
+    // 2. rows below: x L_kk^T = a
+    for (int i = t; i < rest; i += blockDim.x) {
+      const int r = r0 + i;
+      double x[PB];
+#pragma unroll
+      for (int j = 0; j < PB; ++j) x[j] = j < cb ? sA[(kb + j) * ld + r] : 0.0;
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        if (j < cb) {
+          x[j] = x[j] / sA[(kb + j) * ld + kb + j];
+#pragma unroll
+          for (int k = j + 1; k < PB; ++k)
+            if (k < cb) x[k] = fma(-x[j], sA[(kb + j) * ld + kb + k], x[k]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < PB; ++j)
+        if (j < cb) sA[(kb + j) * ld + r] = x[j];
+    }
+    __syncthreads();
+    // 3. trailing lower triangle: A(r, c) -= sum_j L(r, j) L(c, j), r >= c >= r0
+    for (int e = t; e < rest * 2; e += blockDim.x) {
+      const int r = r0 + e / 2, par = e % 2;
+      double lr[PB];
+#pragma unroll
+      for (int j = 0; j < PB; ++j) lr[j] = j < cb ? sA[(kb + j) * ld + r] : 0.0;
+      for (int c = r0 + par; c <= r; c += 2) {
+        double a = sA[c * ld + r];
+#pragma unroll
+        for (int j = 0; j < PB; ++j) a = fma(-lr[j], sA[(kb + j) * ld + c], a);
+        sA[c * ld + r] = a;
+      }
     }
     __syncthreads();
   }

@@ -29,11 +29,18 @@ __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int nlines,
   const int li = LINE_IS_ROW ? (lane & 7) : (lane >> 3);
   const int line = blockIdx.x * TLL + w * 8 + li;
   const bool live = line < nlines;
-  for (int e = t; e < TLB * TLB; e += 256) {
-    const int r = e % TLB, i = e / TLB;
-    double x = (r == i) ? 1.0 : 0.0;
-    if (r >= i && r < nbw && i < nbw) x = W[(size_t)(k0 + r) + (size_t)(k0 + i) * ldw];
-    sL[e] = x;
+  // 16 loads in flight per thread
+  for (int e0 = t; e0 < TLB * TLB; e0 += 256 * 16) {
+    double tmp[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u, r = e % TLB, i = e / TLB;
+      double x = (r == i) ? 1.0 : 0.0;
+      if (r >= i && r < nbw && i < nbw) x = W[(size_t)(k0 + r) + (size_t)(k0 + i) * ldw];
+      tmp[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sL[e0 + 256 * u] = tmp[u];
   }
   // element i of this line
   auto at = [&](int i) -> double* {

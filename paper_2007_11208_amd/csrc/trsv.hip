@@ -152,7 +152,8 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
 // reciprocals of the diagonal formed, before the wait for the block that
 // precedes this one, so that after the wait only that block's x (64 values),
 // one 64x64 product and the substitution remain. The substitution runs in one
-// wave with lane = row and the solved value broadcast by readlane. The solved
+// wave with lane = row, the row of the diagonal tile in registers and the
+// solved value broadcast by readlane, fully unrolled. The solved
 // block and its flag are handed over with agent-scope relaxed accesses (the
 // flag is stored once the block's stores are complete), so no cache
 // write-back or invalidation sits on the chain.
@@ -180,7 +181,6 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
   double* td = tb1 + TB * LD;   // diagonal tile
   double* sx = td + TB * LD;    // x of the block being applied
   double* sacc = sx + TB;       // [4][64] partial sums
-  double* rdg = sacc + 4 * TB;  // reciprocals of the diagonal
 
   // thread t stages 16 elements of a 64x64 tile: k = t / 4 * ... (coalesced in memory)
   double st[16];
@@ -256,31 +256,43 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
   load_tile(r0, rows);
   store_tile(td);
   __syncthreads();
-  if (t < TB) rdg[t] = (t < rows) ? (unit ? 1.0 : 1.0 / td[t * LD + t]) : 1.0;
+  // before the wait: the near tile's 16 values of this thread, and for wave 0 its row of the diagonal
+  // tile and the reciprocal of its diagonal entry, all in registers
+  double nr[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) nr[k] = (tk > 0) ? near[(16 * cq + k) * LD + lane] : 0.0;
+  double trow[TB];
+  double rd = 1.0;
+  if (cq == 0) {
+#pragma unroll
+    for (int i = 0; i < TB; ++i) trow[i] = td[i * LD + lane];
+    rd = (lane < rows && !unit) ? 1.0 / td[lane * LD + lane] : 1.0;
+  }
   if (tk > 0) {
     wait_flag(bn);
     if (t < TB) sx[t] = t < coln ? relaxed_load(x + cn + t) : 0.0;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc = fma(near[(16 * cq + k) * LD + lane], sx[16 * cq + k], acc);
+    for (int k = 0; k < 16; ++k) acc = fma(nr[k], sx[16 * cq + k], acc);
   }
   sacc[cq * TB + lane] = acc;
   __syncthreads();
   if (cq == 0) {
+    // substitution, lane = row; padded rows (past `rows`) hold zeros and stay zero
     double a = bval - ((sacc[lane] + sacc[TB + lane]) + (sacc[2 * TB + lane] + sacc[3 * TB + lane]));
     if (eff_lower) {
-      for (int i = 0; i < rows; ++i) {
-        const double xi = read_lane(a, i) * rdg[i];
-        const double l = td[i * LD + lane];
+#pragma unroll
+      for (int i = 0; i < TB; ++i) {
+        const double xi = read_lane(a * rd, i);
         a = (lane == i) ? xi : a;
-        if (lane > i) a = fma(-l, xi, a);
+        a = (lane > i) ? fma(-trow[i], xi, a) : a;
       }
     } else {
-      for (int i = rows - 1; i >= 0; --i) {
-        const double xi = read_lane(a, i) * rdg[i];
-        const double l = td[i * LD + lane];
+#pragma unroll
+      for (int i = TB - 1; i >= 0; --i) {
+        const double xi = read_lane(a * rd, i);
         a = (lane == i) ? xi : a;
-        if (lane < i) a = fma(-l, xi, a);
+        a = (lane < i) ? fma(-trow[i], xi, a) : a;
       }
     }
     if (lane < rows) relaxed_store(x + r0 + lane, a);
@@ -296,7 +308,7 @@ hipError_t launch_trsm_dec(int n, int nrhs, const double* T, int ldt, bool lower
   if (nrhs < 1 || nrhs > 64) return hipErrorInvalidValue;
   const int nblk = (n + TB - 1) / TB;
   if (nrhs == 1) {
-    const size_t lds1 = sizeof(double) * ((size_t)3 * TB * (TB + 1) + (size_t)6 * TB);
+    const size_t lds1 = sizeof(double) * ((size_t)3 * TB * (TB + 1) + (size_t)5 * TB);
     static size_t done1 = 0;
     hipError_t e1 = ensure_lds((const void*)k_trsv1, lds1, done1);
     if (e1 != hipSuccess) return e1;
