@@ -168,6 +168,10 @@ struct ada_ctx_s {
   int device = 0;
   DevRec* host_rec = nullptr;  // pinned
   std::mutex mu;
+  // look-ahead: the bulk of each trailing update runs on a second stream while
+  // the next panel / diagonal block is factored (fork and join by events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // per-family launch timing (instrumentation)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -204,34 +208,48 @@ struct Solve {
     return &rec->counters[counter_idx++];
   }
   // index of a recorded event in the pool, or -1 (profiling off / no event)
-  long ev_record() {
+  long ev_record(hipStream_t on) {
     if (!ctx->prof) return -1;
     if (ctx->ev_used >= ctx->ev_pool.size()) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return -1;
       ctx->ev_pool.push_back(e);
     }
-    if (hipEventRecord(ctx->ev_pool[ctx->ev_used], st) != hipSuccess) return -1;
+    if (hipEventRecord(ctx->ev_pool[ctx->ev_used], on) != hipSuccess) return -1;
     return (long)ctx->ev_used++;
   }
-  // run `launch` (returns hipError_t); when profiling, bracket it with events of family `kind`
+  // run `launch` (returns hipError_t); when profiling, bracket it with events of family `kind` on stream `on`
   template <class F>
-  hipError_t timed(int kind, double flops, double bytes, F&& launch) {
+  hipError_t timed(int kind, double flops, double bytes, F&& launch, hipStream_t on = nullptr) {
     if (kind < 0) return launch();
-    const long e0 = ev_record();
+    if (!on) on = st;
+    const long e0 = ev_record(on);
     const hipError_t e = launch();
-    const long e1 = ev_record();
+    const long e1 = ev_record(on);
     if (e0 >= 0 && e1 >= 0) ctx->pending.push_back({kind, flops, bytes, (size_t)e0, (size_t)e1});
     return e;
   }
   int gemm(int m, int nn, int k, const double* A, int lda, const double* B, int ldb, bool transB, double* C, int ldc,
-           bool lower) {
+           bool lower, hipStream_t on = nullptr) {
+    if (!on) on = st;
     // algorithmic flops: the lower triangle only for the symmetric update
     const double fl = lower ? 2.0 * (double)k * ((double)m * (m + 1) / 2.0) : 2.0 * (double)m * nn * k;
     const double by = 8.0 * ((double)m * k + (double)nn * k + 2.0 * (lower ? (double)m * (m + 1) / 2.0 : (double)m * nn));
     HIPCHK(timed(ADA_KF_GEMM, fl, by, [&] {
-      return launch_gemm_sub(m, nn, k, A, lda, B, ldb, transB, C, ldc, lower, &rec->stop, st, nullptr, nullptr);
-    }));
+      return launch_gemm_sub(m, nn, k, A, lda, B, ldb, transB, C, ldc, lower, &rec->stop, on, nullptr, nullptr);
+    }, on));
+    return ADA_OK;
+  }
+  // the side stream starts after everything enqueued on st so far
+  int fork() {
+    HIPCHK(hipEventRecord(ctx->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    return ADA_OK;
+  }
+  // st continues after everything enqueued on the side stream so far
+  int join() {
+    HIPCHK(hipEventRecord(ctx->ev_join, ctx->side));
+    HIPCHK(hipStreamWaitEvent(st, ctx->ev_join, 0));
     return ADA_OK;
   }
   // op(T) X = X, nrhs <= 64 per launch (split otherwise)
@@ -340,6 +358,10 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
   HIPCHK(launch_iota(perm, n, s.st));
   PanelScratch ps{s.at<double>(s.p.slot_val), s.at<int>(s.p.slot_row), s.at<double>(s.p.slot_rows),
                   s.at<double>(s.p.diag_rows), s.at<int>(s.p.moves)};
+  // look-ahead: the trailing update of block k is split into the next block column (on st, ahead of
+  // panel k+1) and the rest (on the side stream, alongside panel k+1); the interchanges of panel k+1
+  // wait for the rest, since they move rows in every column
+  bool pending = false;
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int nbw = n - k0 < kNB ? n - k0 : kNB;
     const double m = (double)(n - k0), b = (double)nbw;
@@ -347,16 +369,28 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
     const double pfl = b * (b - 1) * (3.0 * m - b - 1) / 3.0 + b * m - b * (b + 1) / 2.0;
     HIPCHK(s.timed(ADA_KF_PANEL, pfl, 16.0 * m * b,
                    [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, k0 / kNB, ps, s.st); }));
+    if (pending) TRY(s.join());
+    pending = false;
     HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * (n - nbw),
                    [&] { return launch_laswp_moves(n, k0, nbw, W, ldw, ps.moves, perm, s.rec, s.st); }));
     const int rest = n - k0 - nbw;
     if (rest > 0) {
       HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * rest, 8.0 * (b * b / 2.0 + 2.0 * b * rest),
                      [&] { return launch_trsm_llnu(k0, nbw, rest, W, ldw, s.rec, s.st); }));
-      TRY(s.gemm(rest, rest, nbw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, W + k0 + (size_t)(k0 + nbw) * ldw, ldw, false,
-                 W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw, ldw, false));
+      const double* L21 = W + (k0 + nbw) + (size_t)k0 * ldw;
+      const double* U12 = W + k0 + (size_t)(k0 + nbw) * ldw;
+      double* A22 = W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw;
+      const int nb2 = rest < kNB ? rest : kNB;
+      TRY(s.gemm(rest, nb2, nbw, L21, ldw, U12, ldw, false, A22, ldw, false));
+      if (rest > nb2) {
+        TRY(s.fork());
+        TRY(s.gemm(rest, rest - nb2, nbw, L21, ldw, U12 + (size_t)nb2 * ldw, ldw, false, A22 + (size_t)nb2 * ldw, ldw,
+                   false, s.ctx->side));
+        pending = true;
+      }
     }
   }
+  if (pending) TRY(s.join());
   // X = U^{-1} L^{-1} P B
   int* stop = &s.rec->stop;
   HIPCHK(launch_gather_rows(n, s.nrhs, perm, B, ldb, X, ldx, stop, 0, s.st));
@@ -369,6 +403,9 @@ int route_chol(Solve& s, const double* A, int lda, const double* B, int ldb, dou
   const int n = s.n, ldw = s.p.ldw;
   double* W = s.at<double>(s.p.W);
   HIPCHK(launch_copy(n, n, A, lda, W, ldw, s.st));
+  // look-ahead: the update of the next block column runs on st ahead of its diagonal block, the rest
+  // of the trailing triangle on the side stream alongside the next diagonal block and its column
+  bool pending = false;
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int nbw = n - k0 < kNB ? n - k0 : kNB;
     const double b = (double)nbw;
@@ -378,10 +415,22 @@ int route_chol(Solve& s, const double* A, int lda, const double* B, int ldb, dou
     if (rest > 0) {
       HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * rest, 8.0 * (b * b / 2.0 + 2.0 * b * rest),
                      [&] { return launch_trsm_rltn(k0, nbw, rest, W, ldw, s.rec, s.st); }));
-      TRY(s.gemm(rest, rest, nbw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, W + (k0 + nbw) + (size_t)k0 * ldw, ldw, true,
-                 W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw, ldw, true));
+      if (pending) TRY(s.join());
+      pending = false;
+      const double* L21 = W + (k0 + nbw) + (size_t)k0 * ldw;
+      double* A22 = W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw;
+      const int nb2 = rest < kNB ? rest : kNB;
+      // next block column (all rows below, rectangular; its upper part is never read)
+      TRY(s.gemm(rest, nb2, nbw, L21, ldw, L21, ldw, true, A22, ldw, false));
+      if (rest > nb2) {
+        TRY(s.fork());
+        TRY(s.gemm(rest - nb2, rest - nb2, nbw, L21 + nb2, ldw, L21 + nb2, ldw, true,
+                   A22 + nb2 + (size_t)nb2 * ldw, ldw, true, s.ctx->side));
+        pending = true;
+      }
     }
   }
+  if (pending) TRY(s.join());
   int* stop = &s.rec->stop;
   HIPCHK(launch_copy(n, s.nrhs, B, ldb, X, ldx, s.st));
   TRY(s.trsm(W, ldw, true, false, false, X, ldx, s.nrhs, stop, 0));
@@ -484,9 +533,12 @@ int ada_create(ada_ctx* out, int device) {
   c->device = device;
   HIPCHK(hipSetDevice(device));
   hipError_t e = hipHostMalloc((void**)&c->host_rec, sizeof(DevRec), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
-    delete c;
-    return fail(ADA_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    ada_destroy(c);
+    return fail(ADA_ERR_HIP, std::string("context set-up: ") + hipGetErrorString(e));
   }
   *out = c;
   return ADA_OK;
@@ -494,6 +546,10 @@ int ada_create(ada_ctx* out, int device) {
 
 void ada_destroy(ada_ctx ctx) {
   if (!ctx) return;
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->host_rec) (void)hipHostFree(ctx->host_rec);
   delete ctx;
