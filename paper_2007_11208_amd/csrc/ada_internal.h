@@ -31,6 +31,9 @@ struct DevRec {
   int est_iter;               // iteration counter (starts at 2 after the first transposed solve)
   int est_j;                  // current unit-vector index
   int est_nsolves;
+  int est_next;               // right-hand side the last decision asks for (0 none, 1 signs, 2 e_j, 3 alternating)
+  int est_next_tag;           // slot that decision belongs to
+  int pad1;
   int band_spec_bad;          // the chunked band LU's speculation failed (zero pivot or no agreement)
   double est;                 // current estimate of ||inv(A)||_1
   double anorm1;              // ||A||_1 of the routed matrix
@@ -212,7 +215,7 @@ hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int l
                         double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
 // band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles
 enum { SW_L = 0, SW_U = 1, SW_UT = 2, SW_LT = 3 };
-constexpr int LC = 512;  // steps per chunk of the parallel band sweeps
+constexpr int LC = 256;  // steps per chunk of the parallel band sweeps
 struct BandSweep {
   const double* GB;
   int ldgb, kl, ku, n;
@@ -241,8 +244,10 @@ hipError_t launch_band_to_dense(int n, int kl_in, int ku_in, const double* AB, i
 
 // condition estimate
 hipError_t launch_est_init(int n, double* v, DevRec* rec, hipStream_t st);
-hipError_t launch_est_step(int n, int slot_type, const double* result, double* next_in, double* xi, DevRec* rec,
-                           hipStream_t st);
+// tag: 1-based slot index, unique within one estimate; part: est_part_bytes() of scratch; counter: zeroed
+hipError_t launch_est_step(int n, int slot_type, int tag, const double* result, double* next_in, double* xi,
+                           DevRec* rec, void* part, unsigned* counter, hipStream_t st);
+size_t est_part_bytes();
 hipError_t launch_finalize_rcond(DevRec* rec, hipStream_t st);
 
 // residual and backward error

@@ -44,7 +44,7 @@ struct Plan {
   size_t total = 0;
   // offsets (bytes)
   size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, slot_val, slot_row,
-      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec;
+      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec, estpart;
   size_t bsc_doubles, gbspec_doubles;
   int n, nrhs, ldw, T64, nflags;
   bool dense, band, band_dense;
@@ -78,7 +78,8 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
   p.exi = take(cur, N * 8);
   p.R = take(cur, N * nrhs * 8);
   p.T = take(cur, N * nrhs * 8);
-  p.percol = take(cur, (size_t)nrhs * 8);
+  p.percol = take(cur, (size_t)nrhs * 8 * 4);
+  p.estpart = take(cur, est_part_bytes());
   {
     // scratch of the row-parallel band solves: the band width of band-layout
     // input, the widest band the kernels take otherwise
@@ -343,7 +344,9 @@ int estimate(Solve& s, int route_kind, const double* F, int ldf, bool tri_lower,
     } else {
       TRY(band_solve(s, F, kl, ku, type == 2, v, n, 1, t, n, phase, type));
     }
-    HIPCHK(launch_est_step(n, type, result, v, xi, s.rec, s.st));
+    unsigned* ctr = s.next_counter();
+    if (!ctr) return fail(ADA_ERR_ARG, "too many device synchronisation counters for this size");
+    HIPCHK(launch_est_step(n, type, slot + 1, result, v, xi, s.rec, s.at<char>(s.p.estpart), ctr, s.st));
   }
   HIPCHK(launch_finalize_rcond(s.rec, s.st));
   return ADA_OK;

@@ -259,16 +259,34 @@ __global__ __launch_bounds__(64) void k_band_compose(BandSweep B, int nchunks, i
     m[r] = 0.0;
     pf[r] = (c < nr && r < S && q0 < q1) ? phi[((size_t)q0 * nr + c) * S + r] : 0.0;
   }
+  constexpr int PE = (SM * SM + 63) / 64;  // map entries per thread
+  double pre[PE];                           // the next chunk's map, loaded one step ahead
+#pragma unroll
+  for (int u = 0; u < PE; ++u) {
+    const int e = t + 64 * u;
+    pre[u] = (q0 < q1 && e < S * S) ? Phi[(size_t)q0 * S * S + e] : 0.0;
+  }
   for (int q = q0; q < q1; ++q) {
     __syncthreads();
-    for (int e = t; e < S * S; e += 64) sP[e] = Phi[(size_t)q * S * S + e];
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      const int e = t + 64 * u;
+      if (e < S * S) sP[e] = pre[u];
+      pre[u] = (q + 1 < q1 && e < S * S) ? Phi[(size_t)(q + 1) * S * S + e] : 0.0;
+    }
     __syncthreads();
     if (blockIdx.y == 0) {
-      for (int e = t; e < S * S; e += 64) {
-        const int r = e / S, k = e % S;
-        double a = 0.0;
-        for (int u = 0; u < S; ++u) a = fma(sP[r * S + u], sM[cur][u * S + k], a);
-        sM[cur ^ 1][e] = a;
+#pragma unroll
+      for (int u = 0; u < PE; ++u) {
+        const int e = t + 64 * u;
+        if (e < S * S) {
+          const int r = e / S, k = e % S;
+          double a = 0.0;
+#pragma unroll
+          for (int v = 0; v < SM; ++v)
+            if (v < S) a = fma(sP[r * S + v], sM[cur][v * S + k], a);
+          sM[cur ^ 1][e] = a;
+        }
       }
       cur ^= 1;
     }
@@ -345,9 +363,21 @@ __global__ __launch_bounds__(64) void k_band_fill(BandSweep B, int nchunks, int 
     e[r] = (c < nr && r < S) ? esup[((size_t)sg * nr + c) * S + r] : 0.0;
     pf[r] = (c < nr && r < S && q0 < q1) ? phi[((size_t)q0 * nr + c) * S + r] : 0.0;
   }
+  constexpr int PE = (SM * SM + 63) / 64;
+  double pre[PE];
+#pragma unroll
+  for (int u = 0; u < PE; ++u) {
+    const int e = t + 64 * u;
+    pre[u] = (q0 < q1 && e < S * S) ? Phi[(size_t)q0 * S * S + e] : 0.0;
+  }
   for (int q = q0; q < q1; ++q) {
     __syncthreads();
-    for (int k = t; k < S * S; k += 64) sP[k] = Phi[(size_t)q * S * S + k];
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      const int e = t + 64 * u;
+      if (e < S * S) sP[e] = pre[u];
+      pre[u] = (q + 1 < q1 && e < S * S) ? Phi[(size_t)(q + 1) * S * S + e] : 0.0;
+    }
     __syncthreads();
     if (c < nr) {
 #pragma unroll

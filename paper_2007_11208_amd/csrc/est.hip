@@ -36,138 +36,162 @@ hipError_t launch_est_init(int n, double* v, DevRec* rec, hipStream_t st) {
 
 __device__ __forceinline__ double sgn1(double v) { return v >= 0.0 ? 1.0 : -1.0; }
 
-// One workgroup. `result` holds the vector the preceding solve produced,
-// `next_in` receives the next right-hand side (may alias `result`).
-__global__ __launch_bounds__(1024) void k_est_step(int n, int slot_type, const double* result, double* next_in,
-                                                   double* xi, DevRec* rec) {
-  if (rec->est_phase != slot_type) return;
-  const int t = threadIdx.x;
-  const int nw = blockDim.x >> 6;
-  __shared__ double s_d[16];
-  __shared__ int s_i[16];
-  __shared__ double s_sum, s_zl;
-  __shared__ int s_same, s_j;
-  const int stage = rec->est_stage;
+// One estimator step in two launches. k_est_reduce: every workgroup reduces
+// its part of the result (sum |y|, argmax |y| with the lowest index on ties,
+// agreement of sign(y) with the previous sign vector) into a partial record;
+// the last workgroup to finish (a counter) combines the partials in
+// workgroup order and takes the decision. k_est_write: every workgroup writes
+// its part of the next right-hand side the decision asks for. `result` holds
+// the vector the preceding solve produced; `next_in` receives the next
+// right-hand side (may alias `result`: each element is read and written by
+// the same thread).
+constexpr int EST_WG = 256;   // threads per workgroup
+constexpr int EST_MAXG = 256; // workgroups at most
 
-  // reductions over the result: sum|y|, argmax|y| (lowest index on ties), sign agreement with xi
-  double sum = 0.0;
-  double best = -1.0;
-  int bi = -1;
-  int same = 1;
-  for (int i = t; i < n; i += blockDim.x) {
+struct EstPart {
+  double sum, best;
+  int bi, same;
+};
+
+__global__ __launch_bounds__(EST_WG) void k_est_reduce(int n, int slot_type, int tag, const double* result,
+                                                       const double* xi, DevRec* rec, EstPart* part,
+                                                       unsigned* counter) {
+  if (rec->est_phase != slot_type) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int stage = rec->est_stage;
+  // contiguous range of this workgroup, strided by thread inside it (increasing indices per thread)
+  const int per = (n + G - 1) / G;
+  const int i0 = g * per, i1 = min(n, i0 + per);
+  double sum = 0.0, best = -1.0;
+  int bi = -1, same = 1;
+  for (int i = i0 + t; i < i1; i += EST_WG) {
     const double y = result[i];
-    sum += fabs(y);
     const double a = fabs(y);
+    sum += a;
     if (bi < 0 || a > best) { best = a; bi = i; }
     if (stage == 2 && sgn1(y) != xi[i]) same = 0;
   }
-  // (a strided loop visits indices in increasing order per thread, so the per-thread
-  // argmax already holds the lowest index among its ties)
   sum = wave_sum(sum);
   wave_argmax(best, bi);
   same = __all(same) ? 1 : 0;
-  const int lane = t & 63, w = t >> 6;
-  __shared__ int s_same_w[16];
-  if (lane == 0) { s_d[w] = best; s_i[w] = bi; s_same_w[w] = same; }
-  __shared__ double s_sum_w[16];
-  if (lane == 0) s_sum_w[w] = sum;
+  __shared__ double s_sum[EST_WG / 64], s_best[EST_WG / 64];
+  __shared__ int s_bi[EST_WG / 64], s_same[EST_WG / 64];
+  __shared__ int s_last;
+  if (lane == 0) { s_sum[w] = sum; s_best[w] = best; s_bi[w] = bi; s_same[w] = same; }
   __syncthreads();
   if (t == 0) {
     double tot = 0.0, b = -1.0;
     int ib = -1, sm = 1;
-    for (int q = 0; q < nw; ++q) {
-      tot += s_sum_w[q];
-      const int i2 = s_i[q];
-      const double v2 = s_d[q];
-      if (i2 >= 0 && (ib < 0 || v2 > b || (v2 == b && i2 < ib))) { b = v2; ib = i2; }
-      sm &= s_same_w[q];
+    for (int q = 0; q < EST_WG / 64; ++q) {
+      tot += s_sum[q];
+      if (s_bi[q] >= 0 && (ib < 0 || s_best[q] > b || (s_best[q] == b && s_bi[q] < ib))) { b = s_best[q]; ib = s_bi[q]; }
+      sm &= s_same[q];
     }
-    s_sum = tot;
-    s_j = ib;
-    s_same = sm;
-    s_zl = (stage == 3) ? fabs(result[rec->est_j]) : 0.0;
+    relaxed_store(&part[g].sum, tot);
+    relaxed_store(&part[g].best, b);
+    relaxed_store(&part[g].bi, ib);
+    relaxed_store(&part[g].same, sm);
+    wait_stores_done();
+    const unsigned old = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (old == (unsigned)(G - 1));
   }
   __syncthreads();
-  const double ysum = s_sum;
-  const int jmax = s_j;
-  // decide (thread 0), then write the next right-hand side (all threads)
-  __shared__ int s_next;  // 0 done, 1 sign vector, 2 unit vector e_j, 3 alternating vector
-  if (t == 0) {
-    rec->est_nsolves += 1;
-    int next = 0;
-    if (stage == 0) {
-      if (n == 1) {
-        rec->est = fabs(result[0]);
-        next = 0;
-      } else {
-        rec->est = ysum;
-        next = 1;
-        rec->est_phase = 2;
-        rec->est_stage = 1;
-      }
-    } else if (stage == 1) {
+  if (!s_last || t != 0) return;
+  // the last workgroup: combine the partials in workgroup order, then decide
+  double ysum = 0.0, b = -1.0;
+  int jmax = -1, sm = 1;
+  for (int q = 0; q < G; ++q) {
+    ysum += relaxed_load(&part[q].sum);
+    const double bq = relaxed_load(&part[q].best);
+    const int iq = relaxed_load(&part[q].bi);
+    if (iq >= 0 && (jmax < 0 || bq > b || (bq == b && iq < jmax))) { b = bq; jmax = iq; }
+    sm &= relaxed_load(&part[q].same);
+  }
+  rec->est_nsolves += 1;
+  int next = 0;
+  if (stage == 0) {
+    if (n == 1) {
+      rec->est = fabs(result[0]);
+      next = 0;
+    } else {
+      rec->est = ysum;
+      next = 1;
+      rec->est_phase = 2;
+      rec->est_stage = 1;
+    }
+  } else if (stage == 1) {
+    rec->est_j = jmax;
+    rec->est_iter = 2;
+    next = 2;
+    rec->est_phase = 1;
+    rec->est_stage = 2;
+  } else if (stage == 2) {
+    const double est_old = rec->est;
+    rec->est = ysum;
+    if (sm || ysum <= est_old) {
+      next = 3;
+      rec->est_phase = 1;
+      rec->est_stage = 4;
+    } else {
+      next = 1;
+      rec->est_phase = 2;
+      rec->est_stage = 3;
+    }
+  } else if (stage == 3) {
+    const double zl = fabs(result[rec->est_j]);  // |z| at the previous index
+    const double zmax = fabs(result[jmax]);
+    if (zl != zmax && rec->est_iter < 5) {
+      rec->est_iter += 1;
       rec->est_j = jmax;
-      rec->est_iter = 2;
       next = 2;
       rec->est_phase = 1;
       rec->est_stage = 2;
-    } else if (stage == 2) {
-      const double est_old = rec->est;
-      rec->est = ysum;
-      if (s_same || ysum <= est_old) {
-        next = 3;
-        rec->est_phase = 1;
-        rec->est_stage = 4;
-      } else {
-        next = 1;
-        rec->est_phase = 2;
-        rec->est_stage = 3;
-      }
-    } else if (stage == 3) {
-      const double zl = s_zl;             // |z| at the previous index
-      const double zmax = fabs(result[jmax]);
-      if (zl != zmax && rec->est_iter < 5) {
-        rec->est_iter += 1;
-        rec->est_j = jmax;
-        next = 2;
-        rec->est_phase = 1;
-        rec->est_stage = 2;
-      } else {
-        next = 3;
-        rec->est_phase = 1;
-        rec->est_stage = 4;
-      }
     } else {
-      const double temp = 2.0 * (ysum / (3.0 * n));
-      if (temp > rec->est) rec->est = temp;
-      next = 0;
+      next = 3;
+      rec->est_phase = 1;
+      rec->est_stage = 4;
     }
-    if (next == 0) rec->est_phase = 0;
-    s_next = next;
+  } else {
+    const double temp = 2.0 * (ysum / (3.0 * n));
+    if (temp > rec->est) rec->est = temp;
+    next = 0;
   }
-  __syncthreads();
-  const int next = s_next;
-  if (next == 1) {
-    for (int i = t; i < n; i += blockDim.x) {
+  if (next == 0) rec->est_phase = 0;
+  rec->est_next = next;
+  rec->est_next_tag = tag;
+}
+
+__global__ __launch_bounds__(EST_WG) void k_est_write(int n, int tag, const double* result, double* next_in,
+                                                      double* xi, const DevRec* rec) {
+  if (rec->est_next_tag != tag) return;
+  const int next = rec->est_next;
+  if (next == 0) return;
+  const int j = rec->est_j;
+  for (int i = blockIdx.x * EST_WG + threadIdx.x; i < n; i += gridDim.x * EST_WG) {
+    if (next == 1) {
       const double s = sgn1(result[i]);
       xi[i] = s;
-    }
-    __syncthreads();
-    for (int i = t; i < n; i += blockDim.x) next_in[i] = xi[i];
-  } else if (next == 2) {
-    const int j = rec->est_j;
-    __syncthreads();
-    for (int i = t; i < n; i += blockDim.x) next_in[i] = (i == j) ? 1.0 : 0.0;
-  } else if (next == 3) {
-    __syncthreads();
-    for (int i = t; i < n; i += blockDim.x)
+      next_in[i] = s;
+    } else if (next == 2) {
+      next_in[i] = (i == j) ? 1.0 : 0.0;
+    } else {
       next_in[i] = ((i & 1) ? -1.0 : 1.0) * (1.0 + (double)i / (double)(n - 1));
+    }
   }
 }
 
-hipError_t launch_est_step(int n, int slot_type, const double* result, double* next_in, double* xi, DevRec* rec,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_est_step, dim3(1), dim3(1024), 0, st, n, slot_type, result, next_in, xi, rec);
+size_t est_part_bytes() { return sizeof(EstPart) * EST_MAXG; }
+
+hipError_t launch_est_step(int n, int slot_type, int tag, const double* result, double* next_in, double* xi,
+                           DevRec* rec, void* part, unsigned* counter, hipStream_t st) {
+  int G = (n + 4 * EST_WG - 1) / (4 * EST_WG);
+  G = G < 1 ? 1 : (G > EST_MAXG ? EST_MAXG : G);
+  hipLaunchKernelGGL(k_est_reduce, dim3(G), dim3(EST_WG), 0, st, n, slot_type, tag, result, xi, rec,
+                     (EstPart*)part, counter);
+  int Gw = (n + EST_WG - 1) / EST_WG;
+  Gw = Gw > 1024 ? 1024 : Gw;
+  hipLaunchKernelGGL(k_est_write, dim3(Gw), dim3(EST_WG), 0, st, n, tag, result, next_in, xi, rec);
   return hipGetLastError();
 }
 

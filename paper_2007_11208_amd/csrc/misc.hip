@@ -130,15 +130,22 @@ hipError_t launch_resid_gemv(int n, int nrhs, const double* A, int lda, const do
   return hipGetLastError();
 }
 
-// one workgroup per right-hand side
-__global__ __launch_bounds__(256) void k_berr_col(int n, const double* __restrict__ R, int ldr,
-                                                  const double* __restrict__ B, int ldb,
-                                                  const double* __restrict__ X, int ldx, double* per_col,
-                                                  DevRec* rec) {
-  const int c = blockIdx.x;
+// eta_c = ||r_c||_inf / (||A||_inf ||x_c||_inf + ||b_c||_inf) per right-hand side, then the maximum.
+// The three maxima of each column are formed by a grid of workgroups with
+// atomic maxima on the bit patterns (non-negative doubles order like their bits),
+// so the result does not depend on the order.
+__global__ void k_berr_zero(int nrhs, unsigned long long* acc) {
+  for (int e = threadIdx.x; e < 4 * nrhs; e += blockDim.x) acc[e] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_berr_part(int n, const double* __restrict__ R, int ldr,
+                                                   const double* __restrict__ B, int ldb,
+                                                   const double* __restrict__ X, int ldx,
+                                                   unsigned long long* acc) {
+  const int c = blockIdx.y;
   double rn = 0.0, xn = 0.0, bn = 0.0;
   int nf = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const double r = R[(size_t)i + (size_t)c * ldr];
     const double x = X[(size_t)i + (size_t)c * ldx];
     const double b = B[(size_t)i + (size_t)c * ldb];
@@ -151,38 +158,41 @@ __global__ __launch_bounds__(256) void k_berr_col(int n, const double* __restric
   xn = wave_max(xn);
   bn = wave_max(bn);
   nf = wave_or(nf);
-  __shared__ double s[4][3];
-  __shared__ int snf[4];
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { s[w][0] = rn; s[w][1] = xn; s[w][2] = bn; snf[w] = nf; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0, b2 = 0, d = 0;
-    int f = 0;
-    for (int q = 0; q < 4; ++q) { a = fmax(a, s[q][0]); b2 = fmax(b2, s[q][1]); d = fmax(d, s[q][2]); f |= snf[q]; }
-    const double den = rec->anorm_inf * b2 + d;
-    double eta = den > 0.0 ? a / den : (a > 0.0 ? INFINITY : 0.0);
-    if (f) eta = __longlong_as_double(0x7ff8000000000000LL);
-    per_col[c] = eta;
-    if (f) atomicOr(&rec->x_nonfinite, 1);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&acc[4 * c + 0], dbits(rn));
+    atomicMax(&acc[4 * c + 1], dbits(xn));
+    atomicMax(&acc[4 * c + 2], dbits(bn));
+    if (nf) atomicOr(&acc[4 * c + 3], 1ull);
   }
 }
 
-__global__ void k_berr_max(int nrhs, const double* per_col, DevRec* rec) {
+__global__ void k_berr_max(int nrhs, const unsigned long long* acc, DevRec* rec) {
   double m = 0.0;
-  bool nan = false;
+  bool nan = false, nonfinite = false;
+  const double an = rec->anorm_inf;
   for (int c = 0; c < nrhs; ++c) {
-    const double v = per_col[c];
+    const double rn = __longlong_as_double((long long)acc[4 * c + 0]);
+    const double xn = __longlong_as_double((long long)acc[4 * c + 1]);
+    const double bn = __longlong_as_double((long long)acc[4 * c + 2]);
+    if (acc[4 * c + 3]) nonfinite = true;
+    const double den = an * xn + bn;
+    double v = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+    if (acc[4 * c + 3]) v = __longlong_as_double(0x7ff8000000000000LL);
     if (v != v) nan = true;
     else m = fmax(m, v);
   }
+  if (nonfinite) rec->x_nonfinite = 1;
   rec->berr = nan ? __longlong_as_double(0x7ff8000000000000LL) : m;
 }
 
 hipError_t launch_berr(int n, int nrhs, const double* R, int ldr, const double* B, int ldb, const double* X,
                        int ldx, double* per_col, DevRec* rec, hipStream_t st) {
-  hipLaunchKernelGGL(k_berr_col, dim3(nrhs), dim3(256), 0, st, n, R, ldr, B, ldb, X, ldx, per_col, rec);
-  hipLaunchKernelGGL(k_berr_max, dim3(1), dim3(1), 0, st, nrhs, per_col, rec);
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(per_col);  // 4 * nrhs words
+  hipLaunchKernelGGL(k_berr_zero, dim3(1), dim3(256), 0, st, nrhs, acc);
+  int gx = (n + 2047) / 2048;
+  gx = gx < 1 ? 1 : (gx > 256 ? 256 : gx);
+  hipLaunchKernelGGL(k_berr_part, dim3(gx, nrhs), dim3(256), 0, st, n, R, ldr, B, ldb, X, ldx, acc);
+  hipLaunchKernelGGL(k_berr_max, dim3(1), dim3(1), 0, st, nrhs, acc, rec);
   return hipGetLastError();
 }
 
