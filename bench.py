@@ -36,10 +36,10 @@ FAMILY_KERNEL = {
     "gemm": ("k_gemm_sub", "gemm.hip", "mfma"),
     "panel": ("k_getrf_panel", "lu.hip", "hbm"),
     "laswp": ("k_laswp_moves", "lu.hip", "hbm"),
-    "trsm_block": ("k_trsm_llnu/k_trsm_rltn", "lu.hip", "alu"),
+    "trsm_block": ("k_trsm_lines", "trsm_lines.hip", "alu"),
     "potrf": ("k_potrf_diag", "chol.hip", "alu"),
-    "trsv": ("k_trsm_dec", "trsv.hip", "hbm"),
-    "gbtrf": ("k_gbtrf", "band.hip", "hbm"),
+    "trsv": ("k_trsv1", "trsv.hip", "hbm"),
+    "gbtrf": ("k_gbtrf_k", "band.hip", "hbm"),
     "detect": ("k_detect_dense", "detect.hip", "hbm"),
 }
 PEAK = {"mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
