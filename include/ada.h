@@ -89,7 +89,7 @@ typedef struct {
   int32_t sweeps;           /* SVD route: Jacobi sweeps */
   int32_t nsolves;          /* solves spent by the condition estimate */
   int32_t refine_iters;     /* reserved (0) */
-  int32_t pad;
+  int32_t status;           /* per-system status of a batched solve (ADA_OK or ADA_ERR_*); ada_solve: ADA_OK */
   double rcond;             /* reciprocal 1-norm condition estimate of the routed factorisation; NaN if none */
   double berr;              /* max over columns of ||b-Ax||_inf / (||A||_inf ||x||_inf + ||b||_inf); NaN unless want_berr */
 } ada_result;
@@ -119,6 +119,37 @@ size_t ada_workspace_size(int n, int nrhs, const ada_opts* opts);
  * Blocking: returns after the result is known (X is complete on `stream`). */
 int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
               int ldx, void* work, size_t work_bytes, const ada_opts* opts, ada_result* result, void* stream);
+
+/* ---- batched solve: many independent small systems in one launch ----
+ * Every system goes through the whole method of Section II (detection,
+ * routed factorisation and solve, condition estimate, the rule of Section
+ * II-E with the SVD least-squares fallback, backward error) inside one
+ * workgroup on the device; workgroups take systems from a counter.
+ * Supported per system: 1 <= n <= 256, 1 <= nrhs <= 8, dense column-major
+ * input; others are reported with status ADA_ERR_ARG. A banded system is
+ * factored by partial-pivoting elimination over the full matrix, which on a
+ * band gives the band LU's pivots and factors. */
+typedef struct {
+  int32_t n, nrhs;          /* order and number of right-hand sides */
+  int32_t lda, ldb, ldx;    /* leading dimensions, >= n */
+  int32_t pad;
+  int64_t a_off, b_off, x_off; /* element offsets of this system's A, B and X in the pools */
+} ada_desc;
+
+/* Bytes of device workspace ada_solve_batched needs for `count` systems. Pure host function. */
+size_t ada_batched_workspace_size(int count);
+
+/* Solve count systems. d_desc: device array of count descriptors; A_pool,
+ * B_pool: device FP64 pools the offsets index (never modified); X_pool:
+ * device FP64 pool for the solutions; work: device, >= the size above,
+ * 256-byte aligned; opts: host pointer or NULL (layout must be dense;
+ * no_approx, rcond_threshold, force_general, want_berr apply to every
+ * system); d_results: device array of count results, filled with each
+ * system's status. Asynchronous: returns once the work is enqueued on
+ * `stream`. Returns ADA_ERR_ARG for invalid arguments (nothing enqueued). */
+int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
+                      double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
+                      void* stream);
 
 /* ---- instrumentation (not part of the method) ----
  * When enabled, the library records HIP events on the solve's stream around

@@ -37,8 +37,14 @@ class Result(ctypes.Structure):
     _fields_ = [("cls", ctypes.c_int32), ("kl", ctypes.c_int32), ("ku", ctypes.c_int32),
                 ("route", ctypes.c_int32), ("chol_failed", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("info", ctypes.c_int32), ("rank", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("nsolves", ctypes.c_int32), ("refine_iters", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("nsolves", ctypes.c_int32), ("refine_iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rcond", ctypes.c_double), ("berr", ctypes.c_double)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("lda", ctypes.c_int32), ("ldb", ctypes.c_int32),
+                ("ldx", ctypes.c_int32), ("pad", ctypes.c_int32), ("a_off", ctypes.c_int64),
+                ("b_off", ctypes.c_int64), ("x_off", ctypes.c_int64)]
 
 
 class AdaError(RuntimeError):
@@ -69,6 +75,10 @@ def lib() -> ctypes.CDLL:
         L.ada_workspace_size.restype = sz
         L.ada_solve.argtypes = [vp, i, i, vp, i, vp, i, vp, i, vp, sz, ctypes.POINTER(Opts), ctypes.POINTER(Result), vp]
         L.ada_solve.restype = i
+        L.ada_batched_workspace_size.argtypes = [i]
+        L.ada_batched_workspace_size.restype = sz
+        L.ada_solve_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(Opts), vp, vp]
+        L.ada_solve_batched.restype = i
         L.ada_profile_enable.argtypes = [vp, i]
         L.ada_profile_enable.restype = i
         L.ada_profile_reset.argtypes = [vp]
@@ -243,3 +253,71 @@ def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, w
         return None, SolveResult("", -1, -1, "none", False, 0, 0, 0, 0, 0, math.nan, math.nan, rc)
     out_x = X[:, 0] if vec else X
     return out_x, _result(res, rc)
+
+
+class Batch:
+    """Many independent small systems packed once into device pools (column-major,
+    one descriptor each), solved by one ada_solve_batched launch per run()."""
+
+    def __init__(self, As, Bs, device="cuda:0", no_approx=False, rcond_threshold=-1.0, force_general=False,
+                 want_berr=True, ctx: Context | None = None):
+        import numpy as np
+        import torch
+        if len(As) != len(Bs) or not As:
+            raise ValueError("As and Bs must be non-empty lists of equal length")
+        self.count = len(As)
+        dev = torch.device(device)
+        descs = (Desc * self.count)()
+        a_parts, b_parts = [], []
+        ao = bo = xo = 0
+        self.shapes = []
+        for k, (a, b) in enumerate(zip(As, Bs)):
+            a = np.asarray(a, dtype=np.float64)
+            b = np.asarray(b, dtype=np.float64)
+            if b.ndim == 1:
+                b = b[:, None]
+            n, nr = a.shape[0], b.shape[1]
+            descs[k] = Desc(n, nr, n, n, n, 0, ao, bo, xo)
+            a_parts.append(np.asfortranarray(a).ravel(order="F"))
+            b_parts.append(np.asfortranarray(b).ravel(order="F"))
+            self.shapes.append((n, nr, xo))
+            ao += n * n
+            bo += n * nr
+            xo += n * nr
+        self.A = torch.from_numpy(np.concatenate(a_parts)).to(dev)
+        self.B = torch.from_numpy(np.concatenate(b_parts)).to(dev)
+        self.X = torch.zeros(xo, dtype=torch.float64, device=dev)
+        raw = bytes(descs)
+        self.desc = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        self.res = torch.zeros(self.count * ctypes.sizeof(Result), dtype=torch.uint8, device=dev)
+        ws = int(lib().ada_batched_workspace_size(self.count))
+        self.work = torch.empty(ws, dtype=torch.uint8, device=dev)
+        self.opts = make_opts(no_approx, rcond_threshold, LAYOUT_DENSE, 0, 0, force_general, want_berr)
+        self.ctx = ctx or context(dev.index or 0)
+
+    def run(self):
+        import torch
+        stream = torch.cuda.current_stream(self.A.device).cuda_stream
+        rc = lib().ada_solve_batched(self.ctx.handle, self.count, self.desc.data_ptr(), self.A.data_ptr(),
+                                     self.B.data_ptr(), self.X.data_ptr(), self.work.data_ptr(), self.work.numel(),
+                                     ctypes.byref(self.opts), self.res.data_ptr(), ctypes.c_void_p(stream))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+
+    def results(self):
+        raw = bytes(self.res.cpu().numpy().tobytes())
+        arr = (Result * self.count).from_buffer_copy(raw)
+        return [_result(r, r.status) for r in arr]
+
+    def solutions(self):
+        xs = self.X.cpu().numpy()
+        return [xs[o:o + n * nr].reshape((n, nr), order="F") for (n, nr, o) in self.shapes]
+
+
+def solve_batched(As, Bs, **kw):
+    """Solve the systems A_k X_k = B_k (host arrays) with one batched launch; returns (Xs, results)."""
+    import torch
+    b = Batch(As, Bs, **kw)
+    b.run()
+    torch.cuda.synchronize()
+    return b.solutions(), b.results()

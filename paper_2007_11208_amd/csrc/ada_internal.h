@@ -1,6 +1,8 @@
 // Internal declarations of libada (HIP, gfx950). Not part of the ABI.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "ada.h"
 #include <stdint.h>
 #include <stddef.h>
 
@@ -213,6 +215,11 @@ hipError_t launch_gbtrf(int n, int kl, int ku, const double* GBin, double* GB, i
                         double* spec_scratch, size_t spec_doubles, hipStream_t st);
 hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv, bool trans,
                         double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
+// batched solve of many small systems (n <= 256, nrhs <= 8): one persistent launch
+size_t batched_workspace_bytes(int max_workgroups);
+int batched_workgroups(int count);
+hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
+                                void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st);
 // band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles
 enum { SW_L = 0, SW_U = 1, SW_UT = 2, SW_LT = 3 };
 constexpr int LC = 256;  // steps per chunk of the parallel band sweeps

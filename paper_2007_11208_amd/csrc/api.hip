@@ -572,6 +572,30 @@ size_t ada_workspace_size(int n, int nrhs, const ada_opts* opts) {
   return p.total;
 }
 
+size_t ada_batched_workspace_size(int count) {
+  if (count < 1) return 0;
+  return batched_workspace_bytes(batched_workgroups(count));
+}
+
+int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
+                      double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
+                      void* stream) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  if (count < 1) return fail(ADA_ERR_ARG, "count must be >= 1");
+  if (!d_desc || !A_pool || !B_pool || !X_pool || !work || !d_results)
+    return fail(ADA_ERR_ARG, "NULL descriptor, pool, workspace or result pointer");
+  ada_opts o;
+  if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
+  if (o.layout != ADA_LAYOUT_DENSE) return fail(ADA_ERR_ARG, "batched solves take dense input only");
+  if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(ADA_ERR_ARG, "work must be 256-byte aligned");
+  if (work_bytes < ada_batched_workspace_size(count)) return fail(ADA_ERR_ARG, "workspace too small");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(launch_solve_batched(count, d_desc, A_pool, B_pool, X_pool, work, work_bytes, o, d_results,
+                              static_cast<hipStream_t>(stream)));
+  return ADA_OK;
+}
+
 int ada_profile_enable(ada_ctx ctx, int on) {
   if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
   ctx->prof = on != 0;

@@ -1,0 +1,806 @@
+// Batched adaptive solve: many independent small systems (n <= 256,
+// nrhs <= 8) in one persistent launch. Every step of Section II runs inside
+// one workgroup per system, on the device, with no host decision:
+//   detection (band scan, 25% rule, triangular test, likely_sympd of Fig. 4),
+//   the routed factorisation (Cholesky with the LU re-route, LU with partial
+//   pivoting, triangular substitution; a banded system is factored by the
+//   same partial-pivoting elimination, which on a band makes the band LU's
+//   pivots and factors), the solve, the condition estimate, the rule of
+//   Section II-E and the Jacobi SVD least-squares fallback, and the backward
+//   error.
+// Workgroups take systems from a counter until none are left. The matrix of
+// a system lives in LDS up to order 128 and in the workgroup's slice of the
+// workspace above that. The triangular solves and the condition estimate run
+// in one wave (lane = row, four rows per lane, solved values broadcast by
+// readlane); factorisations and the Jacobi rounds use the four waves.
+#include "ada.h"
+#include "ada_internal.h"
+
+#include <climits>
+
+namespace ada {
+
+constexpr int BT = 256;       // threads per workgroup
+constexpr int BNM = 256;      // largest order
+constexpr int BRM = 8;        // most right-hand sides
+constexpr int BNL = 128;      // orders up to this keep the matrix in LDS
+constexpr int BRB = BNM / 64; // rows per lane in the one-wave solves
+
+struct BDesc {
+  int32_t n, nrhs, lda, ldb, ldx, pad;
+  int64_t a_off, b_off, x_off;
+};
+
+// per-workgroup slice of the workspace (doubles, then ints)
+constexpr size_t kBW = (size_t)BNM * BNM;  // matrix (orders > BNL) / Jacobi U
+constexpr size_t kBV = (size_t)BNM * BNM;  // Jacobi V
+constexpr size_t kBSliceD = kBW + kBV + (size_t)BNM * BRM * 2 + (size_t)BNM * 4;
+constexpr size_t kBSliceI = (size_t)BNM * 2;
+constexpr size_t kBSliceBytes = kBSliceD * 8 + kBSliceI * 4;
+
+struct BCtx {
+  int t, lane, w;
+  double* red;  // LDS scratch for reductions (8 doubles)
+  int* ired;    // 8 ints
+};
+
+__device__ __forceinline__ double b_sum(const BCtx& c, double v) {
+  v = wave_sum(v);
+  if (c.lane == 0) c.red[c.w] = v;
+  __syncthreads();
+  const double s = (c.red[0] + c.red[1]) + (c.red[2] + c.red[3]);
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ double b_max(const BCtx& c, double v) {
+  v = wave_max(v);
+  if (c.lane == 0) c.red[c.w] = v;
+  __syncthreads();
+  const double s = fmax(fmax(c.red[0], c.red[1]), fmax(c.red[2], c.red[3]));
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ int b_max_int(const BCtx& c, int v) {
+  v = wave_max_int(v);
+  if (c.lane == 0) c.ired[c.w] = v;
+  __syncthreads();
+  const int s = max(max(c.ired[0], c.ired[1]), max(c.ired[2], c.ired[3]));
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ int b_or(const BCtx& c, int v) {
+  v = wave_or(v);
+  if (c.lane == 0) c.ired[c.w] = v;
+  __syncthreads();
+  const int s = c.ired[0] | c.ired[1] | c.ired[2] | c.ired[3];
+  __syncthreads();
+  return s;
+}
+// largest |v| with the lowest index on ties (idx < 0: no candidate)
+__device__ __forceinline__ int b_argmax(const BCtx& c, double v, int idx) {
+  wave_argmax(v, idx);
+  if (c.lane == 0) { c.red[c.w] = v; c.ired[c.w] = idx; }
+  __syncthreads();
+  double bv = c.red[0];
+  int bi = c.ired[0];
+  for (int q = 1; q < 4; ++q) {
+    const int i2 = c.ired[q];
+    const double v2 = c.red[q];
+    if (i2 >= 0 && (bi < 0 || v2 > bv || (v2 == bv && i2 < bi))) { bv = v2; bi = i2; }
+  }
+  __syncthreads();
+  return bi;
+}
+
+// ---------------------------------------------------------------- factorisations (four waves)
+// LU with partial pivoting of M (ld n) in place; perm tracks the row order. Returns info (0 or 1-based column).
+__device__ int b_getrf(const BCtx& c, double* M, int n, int* perm) {
+  int info = 0;
+  for (int i = c.t; i < n; i += BT) perm[i] = i;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double v = -1.0;
+    int idx = -1;
+    for (int i = j + c.t; i < n; i += BT) {
+      const double a = fabs(M[i + j * n]);
+      if (idx < 0 || a > v) { v = a; idx = i; }
+    }
+    const int p = b_argmax(c, v, idx);
+    const double piv = M[p + j * n];
+    if (piv == 0.0) {
+      if (info == 0) info = j + 1;
+      continue;
+    }
+    if (p != j) {
+      for (int k = c.t; k < n; k += BT) {
+        const double a = M[j + k * n];
+        M[j + k * n] = M[p + k * n];
+        M[p + k * n] = a;
+      }
+      if (c.t == 0) {
+        const int q = perm[j];
+        perm[j] = perm[p];
+        perm[p] = q;
+      }
+      __syncthreads();
+    }
+    for (int i = j + 1 + c.t; i < n; i += BT) M[i + j * n] = M[i + j * n] / piv;
+    __syncthreads();
+    // rank-1 update: wave w takes columns j+1+w, j+5+w, ...; lane takes rows j+1+lane, +64, ...
+    double l[BRB];
+#pragma unroll
+    for (int b = 0; b < BRB; ++b) {
+      const int i = j + 1 + c.lane + 64 * b;
+      l[b] = i < n ? M[i + j * n] : 0.0;
+    }
+    for (int k = j + 1 + c.w; k < n; k += 4) {
+      const double u = M[j + k * n];
+#pragma unroll
+      for (int b = 0; b < BRB; ++b) {
+        const int i = j + 1 + c.lane + 64 * b;
+        if (i < n) M[i + k * n] = fma(-l[b], u, M[i + k * n]);
+      }
+    }
+    __syncthreads();
+  }
+  return info;
+}
+
+// Cholesky A = L L^T from the lower triangle of M; returns 0 or the 1-based failing column
+__device__ int b_potrf(const BCtx& c, double* M, int n) {
+  for (int j = 0; j < n; ++j) {
+    const double d = M[j + j * n];
+    if (!(d > 0.0)) return j + 1;
+    const double sd = sqrt(d);
+    __syncthreads();
+    for (int i = j + c.t; i < n; i += BT) M[i + j * n] = (i == j) ? sd : M[i + j * n] / sd;
+    __syncthreads();
+    double l[BRB];
+#pragma unroll
+    for (int b = 0; b < BRB; ++b) {
+      const int i = j + 1 + c.lane + 64 * b;
+      l[b] = i < n ? M[i + j * n] : 0.0;
+    }
+    for (int k = j + 1 + c.w; k < n; k += 4) {
+      const double u = M[k + j * n];
+#pragma unroll
+      for (int b = 0; b < BRB; ++b) {
+        const int i = j + 1 + c.lane + 64 * b;
+        if (i >= k && i < n) M[i + k * n] = fma(-l[b], u, M[i + k * n]);
+      }
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------- one-wave solves
+// Vector (or block of nr <= BRM columns) held by wave 0: x[b][r] = row lane + 64 b, column r.
+template <int NRC>
+struct WVec {
+  double x[BRB][NRC];
+};
+
+// op(T) y = y in place; T (ld ldt) lower or upper as stored, op = transpose if trans.
+// FWD: forward substitution (op(T) lower). Register blocks are visited in a
+// compile-time order so every register index is a constant.
+template <bool FWD, int NRC>
+__device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v, int nr, int lane) {
+#pragma unroll
+  for (int jbi = 0; jbi < BRB; ++jbi) {
+    const int jb = FWD ? jbi : BRB - 1 - jbi;
+    if (64 * jb >= n) continue;
+    const int cnt = min(64, n - 64 * jb);
+    for (int jj0 = 0; jj0 < cnt; ++jj0) {
+      const int jj = FWD ? jj0 : cnt - 1 - jj0;
+      const int j = 64 * jb + jj;
+      const double d = unit ? 1.0 : T[j + (size_t)j * ldt];
+      double xj[NRC];
+#pragma unroll
+      for (int r = 0; r < NRC; ++r) {
+        if (r < nr) {
+          xj[r] = read_lane(v.x[jb][r], jj) / d;
+          if (lane == jj) v.x[jb][r] = xj[r];
+        } else {
+          xj[r] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < BRB; ++b) {
+        const int i = lane + 64 * b;
+        const bool rel = FWD ? (i > j) : (i < j);
+        if (i < n && rel) {
+          const double tij = trans ? T[j + (size_t)i * ldt] : T[i + (size_t)j * ldt];
+#pragma unroll
+          for (int r = 0; r < NRC; ++r)
+            if (r < nr) v.x[b][r] = fma(-tij, xj[r], v.x[b][r]);
+        }
+      }
+    }
+  }
+}
+template <int NRC>
+__device__ __forceinline__ void w_trsv(const double* T, int ldt, int n, bool lower, bool trans, bool unit,
+                                       WVec<NRC>& v, int nr, int lane) {
+  if (lower != trans) w_trsv_dir<true, NRC>(T, ldt, n, trans, unit, v, nr, lane);
+  else w_trsv_dir<false, NRC>(T, ldt, n, trans, unit, v, nr, lane);
+}
+
+// routed factor: 0 LU (M = L\U, perm), 1 Cholesky (M = L), 2 triangular (T = A as given)
+struct BFactor {
+  int kind;
+  const double* M;
+  int ld;
+  const int* perm;
+  bool lower;  // triangular kind
+};
+
+// y = inv(A) y (trans = false) or inv(A)^T y (trans = true); wave 0 only; sbuf: LDS, BNM * BRM doubles
+template <int NRC>
+__device__ __forceinline__ void w_apply_inv(const BFactor& f, int n, bool trans, WVec<NRC>& v, int nr, int lane, double* sbuf) {
+  if (f.kind == 0) {
+    if (!trans) {
+      // P y: y_new[i] = y[perm[i]]
+#pragma unroll
+      for (int b = 0; b < BRB; ++b)
+#pragma unroll
+        for (int r = 0; r < NRC; ++r)
+          if (r < nr && lane + 64 * b < n) sbuf[(lane + 64 * b) * BRM + r] = v.x[b][r];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int b = 0; b < BRB; ++b) {
+        const int i = lane + 64 * b;
+        if (i < n) {
+          const int src = f.perm[i];
+#pragma unroll
+          for (int r = 0; r < NRC; ++r)
+            if (r < nr) v.x[b][r] = sbuf[src * BRM + r];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      w_trsv(f.M, f.ld, n, true, false, true, v, nr, lane);
+      w_trsv(f.M, f.ld, n, false, false, false, v, nr, lane);
+    } else {
+      w_trsv(f.M, f.ld, n, false, true, false, v, nr, lane);
+      w_trsv(f.M, f.ld, n, true, true, true, v, nr, lane);
+      // P^T y: y_new[perm[i]] = y[i]
+#pragma unroll
+      for (int b = 0; b < BRB; ++b) {
+        const int i = lane + 64 * b;
+        if (i < n) {
+          const int dst = f.perm[i];
+#pragma unroll
+          for (int r = 0; r < NRC; ++r)
+            if (r < nr) sbuf[dst * BRM + r] = v.x[b][r];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int b = 0; b < BRB; ++b)
+#pragma unroll
+        for (int r = 0; r < NRC; ++r)
+          if (r < nr && lane + 64 * b < n) v.x[b][r] = sbuf[(lane + 64 * b) * BRM + r];
+      __builtin_amdgcn_wave_barrier();
+    }
+  } else if (f.kind == 1) {
+    w_trsv(f.M, f.ld, n, true, false, false, v, nr, lane);
+    w_trsv(f.M, f.ld, n, true, true, false, v, nr, lane);
+  } else {
+    w_trsv(f.M, f.ld, n, f.lower, trans, false, v, nr, lane);
+  }
+}
+
+__device__ __forceinline__ double w_sum(const WVec<1>& v, int n, int lane) {
+  double s = 0.0;
+#pragma unroll
+  for (int b = 0; b < BRB; ++b)
+    if (lane + 64 * b < n) s += fabs(v.x[b][0]);
+  return wave_sum(s);
+}
+
+// ||inv(A)||_1 by Hager's method as refined by Higham (the same steps as the single-system estimator)
+__device__ __forceinline__ double w_estimate(const BFactor& f, int n, int lane, double* sbuf, int& nsolves) {
+  WVec<1> v;
+  double xi[BRB];
+#pragma unroll
+  for (int b = 0; b < BRB; ++b) {
+    xi[b] = 0.0;
+    v.x[b][0] = (lane + 64 * b < n) ? 1.0 / n : 0.0;
+  }
+  nsolves = 0;
+  w_apply_inv(f, n, false, v, 1, lane, sbuf);
+  ++nsolves;
+  if (n == 1) return fabs(read_lane(v.x[0][0], 0));
+  double est = w_sum(v, n, lane);
+#pragma unroll
+  for (int b = 0; b < BRB; ++b) {
+    xi[b] = v.x[b][0] >= 0.0 ? 1.0 : -1.0;
+    v.x[b][0] = (lane + 64 * b < n) ? xi[b] : 0.0;
+  }
+  w_apply_inv(f, n, true, v, 1, lane, sbuf);
+  ++nsolves;
+  int iter = 2;
+  int j = 0;
+  auto argmax_abs = [&](const WVec<1>& z) -> int {
+    double bv = -1.0;
+    int bi = -1;
+#pragma unroll
+    for (int b = 0; b < BRB; ++b) {
+      const int i = lane + 64 * b;
+      if (i < n) {
+        const double a = fabs(z.x[b][0]);
+        if (bi < 0 || a > bv) { bv = a; bi = i; }
+      }
+    }
+    wave_argmax(bv, bi);
+    return bi;
+  };
+  auto value_at = [&](const WVec<1>& z, int i) -> double {
+    double r = 0.0;
+#pragma unroll
+    for (int b = 0; b < BRB; ++b)
+      if (i / 64 == b) r = read_lane(z.x[b][0], i % 64);
+    return r;
+  };
+  j = argmax_abs(v);
+  bool alt = false;
+  while (true) {
+    // y = inv(A) e_j
+#pragma unroll
+    for (int b = 0; b < BRB; ++b) v.x[b][0] = (lane + 64 * b == j) ? 1.0 : 0.0;
+    w_apply_inv(f, n, false, v, 1, lane, sbuf);
+    ++nsolves;
+    const double est_old = est;
+    est = w_sum(v, n, lane);
+    int same = 1;
+#pragma unroll
+    for (int b = 0; b < BRB; ++b)
+      if (lane + 64 * b < n && (v.x[b][0] >= 0.0 ? 1.0 : -1.0) != xi[b]) same = 0;
+    same = __all(same) ? 1 : 0;
+    if (same || est <= est_old) {
+      alt = true;
+      break;
+    }
+#pragma unroll
+    for (int b = 0; b < BRB; ++b) {
+      xi[b] = v.x[b][0] >= 0.0 ? 1.0 : -1.0;
+      v.x[b][0] = (lane + 64 * b < n) ? xi[b] : 0.0;
+    }
+    w_apply_inv(f, n, true, v, 1, lane, sbuf);
+    ++nsolves;
+    const int jn = argmax_abs(v);
+    const double zl = fabs(value_at(v, j));
+    const double zmax = fabs(value_at(v, jn));
+    if (zl != zmax && iter < 5) {
+      ++iter;
+      j = jn;
+      continue;
+    }
+    alt = true;
+    break;
+  }
+  if (alt) {
+#pragma unroll
+    for (int b = 0; b < BRB; ++b) {
+      const int i = lane + 64 * b;
+      v.x[b][0] = i < n ? ((i & 1) ? -1.0 : 1.0) * (1.0 + (double)i / (double)(n - 1)) : 0.0;
+    }
+    w_apply_inv(f, n, false, v, 1, lane, sbuf);
+    ++nsolves;
+    const double temp = 2.0 * (w_sum(v, n, lane) / (3.0 * n));
+    if (temp > est) est = temp;
+  }
+  return est;
+}
+
+// ---------------------------------------------------------------- Jacobi SVD (four waves)
+__device__ __forceinline__ void b_rr_pair(int m, int r, int pi, int& a, int& b) {
+  if (pi == 0) {
+    a = r;
+    b = m - 1;
+  } else {
+    a = (r + pi) % (m - 1);
+    b = (r - pi + m - 1) % (m - 1);
+  }
+}
+
+__device__ int b_jacobi(const BCtx& c, double* U, double* V, int n, int max_sweeps) {
+  const int m = (n + 1) & ~1;
+  const double tol = (double)n * kEps;
+  __shared__ int s_rot;
+  int sweeps = 0;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    if (c.t == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      for (int pi = c.w; pi < m / 2; pi += 4) {
+        int a, b;
+        b_rr_pair(m, r, pi, a, b);
+        if (a >= n || b >= n) continue;
+        const int p = min(a, b), q = max(a, b);
+        double* up = U + (size_t)p * n;
+        double* uq = U + (size_t)q * n;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = c.lane; i < n; i += 64) {
+          const double x = up[i], y = uq[i];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int i = c.lane; i < n; i += 64) {
+          const double x = up[i], y = uq[i];
+          up[i] = cs * x - sn * y;
+          uq[i] = sn * x + cs * y;
+        }
+        double* vp = V + (size_t)p * n;
+        double* vq = V + (size_t)q * n;
+        for (int i = c.lane; i < n; i += 64) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = cs * x - sn * y;
+          vq[i] = sn * x + cs * y;
+        }
+        if (c.lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (!rot) {
+      ++sweeps;
+      break;
+    }
+  }
+  return sweeps;
+}
+
+// ---------------------------------------------------------------- the solve of one system
+__global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __restrict__ desc,
+                                                      const double* __restrict__ Apool,
+                                                      const double* __restrict__ Bpool, double* Xpool,
+                                                      char* work, ada_opts o, ada_result* results,
+                                                      unsigned* queue) {
+  extern __shared__ double lds[];  // BNL * BNL matrix, then BNM * BRM vector buffer
+  __shared__ double s_red[8];
+  __shared__ int s_ired[8];
+  __shared__ int s_idx;
+  BCtx c;
+  c.t = threadIdx.x;
+  c.lane = c.t & 63;
+  c.w = c.t >> 6;
+  c.red = s_red;
+  c.ired = s_ired;
+  double* sbuf = lds + (size_t)BNL * BNL;
+  char* slice = work + (size_t)blockIdx.x * kBSliceBytes;
+  double* gW = reinterpret_cast<double*>(slice);
+  double* gV = gW + kBW;
+  double* gX = gV + kBV;                     // BNM * BRM
+  int* perm = reinterpret_cast<int*>(gW + kBSliceD);
+  const double thr = o.rcond_threshold >= 0.0 ? o.rcond_threshold : 0.5 * kEps;
+
+  while (true) {
+    if (c.t == 0) s_idx = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int idx = s_idx;
+    __syncthreads();
+    if (idx >= count) break;
+    const BDesc d = desc[idx];
+    ada_result res;
+    res.cls = ADA_CLASS_GENERAL;
+    res.kl = -1;
+    res.ku = -1;
+    res.route = ADA_ROUTE_NONE;
+    res.chol_failed = 0;
+    res.fallback = ADA_FALLBACK_NONE;
+    res.info = 0;
+    res.rank = d.n;
+    res.sweeps = 0;
+    res.nsolves = 0;
+    res.refine_iters = 0;
+    res.status = ADA_OK;
+    res.rcond = __longlong_as_double(0x7ff8000000000000LL);
+    res.berr = __longlong_as_double(0x7ff8000000000000LL);
+    const int n = d.n, nr = d.nrhs;
+    if (n < 1 || n > BNM || nr < 1 || nr > BRM || d.lda < n || d.ldb < n || d.ldx < n) {
+      res.status = ADA_ERR_ARG;
+      if (c.t == 0) results[idx] = res;
+      continue;
+    }
+    const double* A = Apool + d.a_off;
+    const double* B = Bpool + d.b_off;
+    double* X = Xpool + d.x_off;
+    double* M = (n <= BNL) ? lds : gW;  // working matrix, ld n
+    // ---- S1/S2: copy A to the working matrix (coalesced), non-finite check, band scan, norms
+    int nf = 0;
+    for (int e = c.t; e < n * n; e += BT) {
+      const double a = A[e % n + (size_t)(e / n) * d.lda];
+      nf |= !isfinite(a);
+      M[e] = a;
+    }
+    for (int e = c.t; e < n * nr; e += BT) nf |= !isfinite(B[e % n + (size_t)(e / n) * d.ldb]);
+    nf = b_or(c, nf);  // (its barriers also publish M)
+    if (nf) {
+      res.status = ADA_ERR_NONFINITE;
+      if (c.t == 0) results[idx] = res;
+      continue;
+    }
+    int klj = 0, kuj = 0;
+    double colsum = 0.0, rowsum = 0.0;
+    for (int j = c.t; j < n; j += BT) {
+      double cs = 0.0, rs = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double a = M[i + j * n];
+        cs += fabs(a);
+        if (a != 0.0) {
+          if (i < j) kuj = max(kuj, j - i);
+          if (i > j) klj = max(klj, i - j);
+        }
+        rs += fabs(M[j + i * n]);
+      }
+      colsum = fmax(colsum, cs);
+      rowsum = fmax(rowsum, rs);
+    }
+    const int kl = b_max_int(c, klj), ku = b_max_int(c, kuj);
+    const double anorm1 = b_max(c, colsum);
+    const double anorm_inf = b_max(c, rowsum);
+    int cls = ADA_CLASS_GENERAL;
+    if (!o.force_general) {
+      res.kl = kl;
+      res.ku = ku;
+      const long long nn = n;
+      const long long nnz = nn * (kl + ku + 1) - (long long)kl * (kl + 1) / 2 - (long long)ku * (ku + 1) / 2;
+      if (4 * nnz <= nn * nn) cls = ADA_CLASS_BANDED;
+      else if (kl == 0) cls = ADA_CLASS_TRI_UPPER;
+      else if (ku == 0) cls = ADA_CLASS_TRI_LOWER;
+      else {
+        // S5: Fig. 4 (tol = 100 eps)
+        const double tol = 100.0 * kEps;
+        int bad = 0;
+        double md = 0.0;
+        for (int j = c.t; j < n; j += BT) {
+          const double dj = M[j + j * n];
+          if (dj <= 0.0) bad = 1;
+          md = fmax(md, dj);
+        }
+        bad = b_or(c, bad);
+        const double max_diag = b_max(c, md);
+        if (!bad) {
+          for (int j = c.t; j < n; j += BT) {
+            const double ajj = M[j + j * n];
+            for (int i = j + 1; i < n; ++i) {
+              const double aij = M[i + j * n], aji = M[j + i * n];
+              const double delta = fabs(aij - aji);
+              if (delta > tol && delta > tol * fmax(fabs(aij), fabs(aji))) bad = 1;
+              if (fabs(aij) >= max_diag) bad = 1;
+              if ((fabs(aij) + fabs(aji)) >= (M[i + i * n] + ajj)) bad = 1;
+            }
+          }
+          bad = b_or(c, bad);
+        }
+        cls = bad ? ADA_CLASS_GENERAL : ADA_CLASS_SYMPD;
+      }
+    }
+    res.cls = cls;
+    // ---- S6: routed factorisation
+    int info = 0;
+    BFactor f;
+    f.M = M;
+    f.ld = n;
+    f.perm = perm;
+    f.lower = false;
+    double anorm = anorm1;
+    bool routed_sym = false;
+    if (cls == ADA_CLASS_TRI_UPPER || cls == ADA_CLASS_TRI_LOWER) {
+      res.route = ADA_ROUTE_TRI;
+      f.kind = 2;
+      f.lower = cls == ADA_CLASS_TRI_LOWER;
+      int z = INT_MAX;
+      for (int j = c.t; j < n; j += BT)
+        if (M[j + j * n] == 0.0) z = min(z, j);
+      z = -b_max_int(c, z == INT_MAX ? -INT_MAX : -z);
+      info = (z == INT_MAX) ? 0 : z + 1;
+    } else {
+      bool fresh = true;  // M still holds A
+      if (cls == ADA_CLASS_SYMPD) {
+        const int ci = b_potrf(c, M, n);
+        fresh = false;
+        __syncthreads();
+        if (ci == 0) {
+          res.route = ADA_ROUTE_CHOL;
+          f.kind = 1;
+          routed_sym = true;
+        } else {
+          res.chol_failed = 1;
+        }
+      }
+      if (!routed_sym) {
+        res.route = (cls == ADA_CLASS_BANDED) ? ADA_ROUTE_BAND_LU : ADA_ROUTE_LU;
+        if (!fresh) {
+          for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
+          __syncthreads();
+        }
+        info = b_getrf(c, M, n, perm);
+        __syncthreads();
+        f.kind = 0;
+      }
+    }
+    if (routed_sym) {
+      // ||A||_1 of the symmetric matrix the lower triangle defines
+      double s = 0.0;
+      for (int j = c.t; j < n; j += BT) {
+        double q = 0.0;
+        for (int i = 0; i < j; ++i) q += fabs(A[j + (size_t)i * d.lda]);
+        for (int i = j; i < n; ++i) q += fabs(A[i + (size_t)j * d.lda]);
+        s = fmax(s, q);
+      }
+      anorm = b_max(c, s);
+    }
+    res.info = info;
+    // ---- solve, condition estimate (wave 0)
+    __shared__ int s_flag;
+    __shared__ double s_rc;
+    if (c.w == 0) {
+      double rcond = __longlong_as_double(0x7ff8000000000000LL);
+      int xnf = 0;
+      if (info == 0) {
+        for (int r0 = 0; r0 < nr; ++r0) {  // one right-hand side at a time keeps the wave's registers small
+          WVec<1> v;
+#pragma unroll
+          for (int b = 0; b < BRB; ++b) {
+            const int i = c.lane + 64 * b;
+            v.x[b][0] = i < n ? B[i + (size_t)r0 * d.ldb] : 0.0;
+          }
+          w_apply_inv(f, n, false, v, 1, c.lane, sbuf);
+#pragma unroll
+          for (int b = 0; b < BRB; ++b) {
+            const int i = c.lane + 64 * b;
+            if (i < n) {
+              X[i + (size_t)r0 * d.ldx] = v.x[b][0];
+              xnf |= !isfinite(v.x[b][0]);
+            }
+          }
+        }
+        int ns = 0;
+        const double est = w_estimate(f, n, c.lane, sbuf, ns);
+        res.nsolves = ns;
+        if (anorm == 0.0) rcond = 0.0;
+        else if (est != est) rcond = est;
+        else if (est == 0.0) rcond = 0.0;
+        else rcond = (1.0 / est) / anorm;
+        xnf = wave_or(xnf);
+      }
+      if (c.lane == 0) {
+        int fb = ADA_FALLBACK_NONE;
+        if (info || xnf) fb = ADA_FALLBACK_FAILURE;
+        else if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
+        else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
+        s_flag = fb;
+        s_rc = rcond;
+      }
+    }
+    __syncthreads();
+    res.fallback = s_flag;
+    res.rcond = info ? __longlong_as_double(0x7ff8000000000000LL) : s_rc;
+    __syncthreads();
+    bool svd = false;
+    if (res.fallback != ADA_FALLBACK_NONE) {
+      if (o.no_approx) {
+        res.status = ADA_ERR_SINGULAR;
+      } else {
+        svd = true;
+      }
+    }
+    if (svd) {
+      // ---- S8: one-sided Jacobi SVD of the original A, min-norm least squares
+      res.route = ADA_ROUTE_SVD;
+      for (int e = c.t; e < n * n; e += BT) {
+        const int i = e % n, j = e / n;
+        gW[e] = A[i + (size_t)j * d.lda];
+        gV[e] = (i == j) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      res.sweeps = b_jacobi(c, gW, gV, n, 30);
+      // sigma_j = ||u_j||, cut at eps * sigma_max
+      double* sig = sbuf;  // BNM
+      for (int j = c.t; j < n; j += BT) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s = fma(gW[i + (size_t)j * n], gW[i + (size_t)j * n], s);
+        sig[j] = sqrt(s);
+      }
+      __syncthreads();
+      double sm = 0.0;
+      for (int j = c.t; j < n; j += BT) sm = fmax(sm, sig[j]);
+      const double smax = b_max(c, sm);
+      const double cut = kEps * smax;
+      int keep = 0;
+      for (int j = c.t; j < n; j += BT) keep += sig[j] > cut ? 1 : 0;
+      keep = (int)b_sum(c, (double)keep);
+      res.rank = keep;
+      // T = diag(1/sigma^2) U^T B for kept j, then X = V T
+      double* T = gX;  // BNM x BRM
+      for (int e = c.t; e < n * nr; e += BT) {
+        const int j = e % n, r = e / n;
+        double s = 0.0;
+        if (sig[j] > cut) {
+          for (int i = 0; i < n; ++i) s = fma(gW[i + (size_t)j * n], B[i + (size_t)r * d.ldb], s);
+          s = s / (sig[j] * sig[j]);
+        }
+        T[j + (size_t)r * BNM] = s;
+      }
+      __syncthreads();
+      for (int e = c.t; e < n * nr; e += BT) {
+        const int i = e % n, r = e / n;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s = fma(gV[i + (size_t)j * n], T[j + (size_t)r * BNM], s);
+        X[i + (size_t)r * d.ldx] = s;
+      }
+      __syncthreads();
+    }
+    // ---- S9: backward error of the returned x
+    const bool have_x = res.status == ADA_OK || (res.status == ADA_ERR_SINGULAR && info == 0);
+    if (have_x && o.want_berr) {
+      double worst = 0.0;
+      int nan = 0;
+      for (int r = 0; r < nr; ++r) {
+        double rn = 0.0, xn = 0.0, bn = 0.0;
+        int xbad = 0;
+        for (int i = c.t; i < n; i += BT) {
+          double s = B[i + (size_t)r * d.ldb];
+          for (int j = 0; j < n; ++j) s = fma(-A[i + (size_t)j * d.lda], X[j + (size_t)r * d.ldx], s);
+          const double xi = X[i + (size_t)r * d.ldx];
+          xbad |= !isfinite(xi);
+          rn = fmax(rn, fabs(s));
+          xn = fmax(xn, fabs(xi));
+          bn = fmax(bn, fabs(B[i + (size_t)r * d.ldb]));
+        }
+        rn = b_max(c, rn);
+        xn = b_max(c, xn);
+        bn = b_max(c, bn);
+        xbad = b_or(c, xbad);
+        const double den = anorm_inf * xn + bn;
+        const double eta = xbad ? __longlong_as_double(0x7ff8000000000000LL)
+                                : (den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0));
+        if (eta != eta) nan = 1;
+        else worst = fmax(worst, eta);
+      }
+      res.berr = nan ? __longlong_as_double(0x7ff8000000000000LL) : worst;
+    }
+    if (c.t == 0) results[idx] = res;
+    __syncthreads();
+  }
+}
+
+__global__ void k_queue_zero(unsigned* q) { *q = 0u; }
+
+size_t batched_workspace_bytes(int max_workgroups) {
+  return 256 + (size_t)max_workgroups * kBSliceBytes;
+}
+
+int batched_workgroups(int count) {
+  int g = 256;  // one per compute unit: each holds up to 160 KB of LDS
+  return count < g ? (count < 1 ? 1 : count) : g;
+}
+
+hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
+                                void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st) {
+  const int G = batched_workgroups(count);
+  if (work_bytes < batched_workspace_bytes(G)) return hipErrorInvalidValue;
+  unsigned* queue = reinterpret_cast<unsigned*>(work);
+  char* slices = reinterpret_cast<char*>(work) + 256;
+  const size_t lds = sizeof(double) * ((size_t)BNL * BNL + (size_t)BNM * BRM);
+  static size_t done = 0;
+  hipError_t e = ensure_lds((const void*)k_solve_batched, lds, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_queue_zero, dim3(1), dim3(1), 0, st, queue);
+  hipLaunchKernelGGL(k_solve_batched, dim3(G), dim3(BT), lds, st, count, (const BDesc*)desc, A, B, X, slices, o,
+                     (ada_result*)results, queue);
+  return hipGetLastError();
+}
+
+}  // namespace ada

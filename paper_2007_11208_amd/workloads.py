@@ -218,3 +218,33 @@ def large_case(name: str, nrhs: int = 1, k: int = 0, n: int | None = None):
         raise ValueError(name)
     x = x_true(a.shape[0], nrhs, g)
     return a, rhs_for(a, x), ("dense",)
+
+
+BATCH_MIX = (("dense", 0.40), ("spd", 0.30), ("banded", 0.15), ("triangular", 0.10), ("spectrum", 0.05))
+
+
+def batched_case(count: int, k: int = 0, n_lo: int = 8, n_hi: int = 256, nrhs_hi: int = 8):
+    """Many independent small systems: n uniform in [n_lo, n_hi], nrhs uniform in [1, nrhs_hi],
+    class mix 40% dense general, 30% SPD, 15% banded (kl, ku uniform in [1, 4]), 10% triangular
+    (upper or lower, off-diagonals N(0,1)), 5% prescribed spectrum with condition 1e15.
+    Returns a list of (kind, A, B)."""
+    g = rng_for(3, k)
+    kinds = [m[0] for m in BATCH_MIX]
+    probs = np.array([m[1] for m in BATCH_MIX])
+    out = []
+    for _ in range(count):
+        n = int(g.integers(n_lo, n_hi + 1))
+        nrhs = int(g.integers(1, nrhs_hi + 1))
+        kind = kinds[int(g.choice(len(kinds), p=probs))]
+        if kind == "dense":
+            a = dense_general(n, g)
+        elif kind == "spd":
+            a = spd(n, g)
+        elif kind == "banded":
+            a = banded_dense(n, int(g.integers(1, 5)), int(g.integers(1, 5)), g)
+        elif kind == "triangular":
+            a = triangular(n, g, upper=bool(g.integers(0, 2)))
+        else:
+            a = prescribed_spectrum(n, np.logspace(0, -15, n), g)
+        out.append((kind, a, rhs_for(a, x_true(n, nrhs, g))))
+    return out

@@ -1,0 +1,113 @@
+"""GPU parity of the batched solve (many small systems in one launch) against the oracle.
+
+Same bars as the single-system parity tests: class and band widths bit-exact,
+route / Cholesky failure / fallback reason exact, rcond within a factor 2,
+backward error <= 1e-12 (or twice the oracle's for inconsistent least-squares
+systems), x within 32 n kappa eps |x| off the SVD route, SVD rank exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_11208_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+O = oracle.get()
+
+
+@pytest.fixture(scope="module")
+def ada():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_11208_amd import ada as _ada
+    _ada.lib()
+    return _ada
+
+
+def check(ada, a, b, x, r, **okw):
+    xr, rr = O.solve(a, b, **okw)
+    assert r.status == rr["status"], (r, rr)
+    if r.status not in (0, -3):
+        return
+    assert r.cls == ada.CLASS_NAMES[rr["cls"]], (r, rr)
+    assert (r.kl, r.ku) == (rr["kl"], rr["ku"])
+    assert r.route == ada.ROUTE_NAMES[rr["route"]], (r, rr)
+    assert r.chol_failed == bool(rr["chol_failed"])
+    assert r.fallback == rr["fallback"]
+    if rr["fallback"] == 0:
+        assert 0.5 * rr["rcond"] <= r.rcond <= 2.0 * rr["rcond"], (r.rcond, rr["rcond"])
+    if r.status == 0:
+        assert r.berr <= max(1e-12, 2.0 * rr["berr"]), (r.berr, rr["berr"])
+        if r.route != "svd":
+            kappa = 1.0 / max(rr["rcond"], 1e-300)
+            tol = 32 * a.shape[0] * kappa * EPS * max(1.0, np.max(np.abs(xr)))
+            assert np.max(np.abs(x.reshape(xr.shape) - xr)) <= tol
+        else:
+            assert r.rank == rr["rank"]
+
+
+def test_batched_mix(ada):
+    cases = W.batched_case(120, k=1, n_hi=192)
+    As = [c[1] for c in cases]
+    Bs = [c[2] for c in cases]
+    xs, rs = ada.solve_batched(As, Bs)
+    for (kind, a, b), x, r in zip(cases, xs, rs):
+        print(f"{kind} n={a.shape[0]} nrhs={b.shape[1]} -> {r.cls}/{r.route}", flush=True)
+        check(ada, a, b, x, r)
+
+
+def test_batched_special_systems(ada):
+    import json, os
+    fig1 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fig1.json")))
+    sys_ = [np.array(fig1[k]["matrix"], dtype=np.float64) for k in ("a", "b", "c")]
+    rng = np.random.default_rng(9)
+    sys_ += [np.array([[3.0]]), np.array([[0.0, 1.0], [1.0, 0.0]]), W.sym_indefinite(200, rng),
+             W.triangular(256, rng, upper=True), W.triangular(256, rng, upper=False, scaled=True),
+             W.spd(256, rng), W.dense_general(256, rng), W.banded_dense(256, 3, 2, rng)]
+    for name in W.SMALL_CASES:
+        a, _ = W.small_case(name)
+        if a.shape[0] <= 256:
+            sys_.append(a)
+    z = W.dense_general(40, rng)
+    z[:, 7] = 0.0  # exactly singular: zero pivot -> SVD route
+    sys_.append(z)
+    Bs = [W.rhs_for(a, W.x_true(a.shape[0], 2, rng)) for a in sys_]
+    xs, rs = ada.solve_batched(sys_, Bs)
+    for a, b, x, r in zip(sys_, Bs, xs, rs):
+        print(f"n={a.shape[0]} -> {r.cls}/{r.route} status={r.status}", flush=True)
+        check(ada, a, b, x, r)
+
+
+def test_batched_same_alone_and_in_the_mix(ada):
+    cases = W.batched_case(40, k=2, n_hi=160)
+    As = [c[1] for c in cases]
+    Bs = [c[2] for c in cases]
+    xs, rs = ada.solve_batched(As, Bs)
+    for k in (0, 7, 23):
+        x1, r1 = ada.solve_batched([As[k]], [Bs[k]])
+        assert np.array_equal(x1[0], xs[k])
+        assert (r1[0].route, r1[0].rcond, r1[0].berr) == (rs[k].route, rs[k].rcond, rs[k].berr)
+
+
+def test_batched_errors_and_options(ada):
+    rng = np.random.default_rng(4)
+    big = W.dense_general(300, rng)
+    nanm = W.dense_general(20, rng)
+    nanm[3, 4] = np.nan
+    ok = W.dense_general(30, rng)
+    ill = W.ill_conditioned(64, rng, smin=1e-18)
+    As = [big, nanm, ok, ill]
+    Bs = [np.ones((300, 1)), np.ones((20, 1)), np.ones((30, 9)), np.ones((64, 1))]
+    _, rs = ada.solve_batched(As, Bs)
+    assert rs[0].status == ada.ERR_ARG
+    assert rs[1].status == ada.ERR_NONFINITE
+    assert rs[2].status == ada.ERR_ARG  # nrhs > 8
+    assert rs[3].status == 0 and rs[3].route == "svd"
+    _, rs2 = ada.solve_batched([ill], [np.ones((64, 1))], no_approx=True)
+    assert rs2[0].status == ada.ERR_SINGULAR and rs2[0].fallback != 0
+    x3, rs3 = ada.solve_batched([ok], [np.ones((30, 1))], force_general=True)
+    assert rs3[0].route == "lu" and rs3[0].kl == -1
+    assert np.allclose(ok @ x3[0], 1.0, atol=1e-10)
