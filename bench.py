@@ -112,6 +112,77 @@ def cpu_baseline(nrhs: int, budget_s: float = 25.0):
             "per_system_s": {k: round(v, 4) for k, v in per.items()}}
 
 
+def batched_flops(kind_route, n, nrhs):
+    route = kind_route
+    if route in ("lu", "band_lu"):
+        return 2.0 * n ** 3 / 3.0 + 2.0 * n * n * nrhs
+    if route == "chol":
+        return n ** 3 / 3.0 + 2.0 * n * n * nrhs
+    if route == "tri":
+        return float(n) * n * nrhs
+    return 0.0  # the SVD route: not counted as useful work
+
+
+def bench_batched(args):
+    """Many small systems (sizes, class mix and right-hand sides of the batched configuration)
+    solved by one ada_solve_batched launch per step."""
+    import torch
+    from paper_2007_11208_amd import ada
+    n_lo, n_hi = (int(v) for v in args.n_range.split(","))
+    cases = W.batched_case(args.count, k=0, n_lo=n_lo, n_hi=n_hi)
+    As = [c[1] for c in cases]
+    Bs = [c[2] for c in cases]
+    batch = ada.Batch(As, Bs)
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        batch.run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - s0)
+    total = time.perf_counter() - t0
+    res = batch.results()
+    worst = max((r.berr for r in res), default=0.0)
+    bad = [k for k, r in enumerate(res) if r.status != 0 or not (r.berr <= BERR_BAR)]
+    if bad:
+        print(f"{len(bad)} systems failed or missed the backward-error bar (first {bad[:5]})", file=sys.stderr)
+        sys.exit(1)
+    flops = sum(batched_flops(r.route, a.shape[0], b.shape[1]) for r, a, b in zip(res, As, Bs))
+    routes = {}
+    for r in res:
+        routes[r.route] = routes.get(r.route, 0) + 1
+    value = args.count * args.steps / total
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        O = oracle.get()
+        t = time.perf_counter()
+        m = 0
+        for a, b in zip(As, Bs):
+            O.solve(a, b)
+            m += 1
+            if time.perf_counter() - t > 20.0:
+                break
+        dt = time.perf_counter() - t
+        cpu = {"value": m / dt, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"the first {m} systems of the same batch, one oracle solve each"}
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched: {args.count} systems, n uniform in [{n_lo}, {n_hi}], nrhs uniform in [1, 8], "
+                               "40% dense general, 30% SPD, 15% banded, 10% triangular, 5% condition 1e15",
+                   "count": args.count},
+        "tflops": round(flops * args.steps / total / 1e12, 4),
+        "p50_step_ms": round(pct(times, 50) * 1e3, 3), "p99_step_ms": round(pct(times, 99) * 1e3, 3),
+        "max_berr": worst, "routes": routes, "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +191,10 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--systems", default=",".join(SYSTEMS))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="single", choices=("single", "batched"),
+                    help="single: the five large systems; batched: many small systems in one launch per step")
+    ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
+    ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy this many MiB device-to-device three times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -140,6 +215,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 8, "copies": 3}), flush=True)
         return
+    if args.workload == "batched":
+        return bench_batched(args)
     names = [s for s in args.systems.split(",") if s]
     cases = []
     for name in names:
