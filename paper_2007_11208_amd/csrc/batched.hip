@@ -185,16 +185,37 @@ struct WVec {
 // FWD: forward substitution (op(T) lower). Register blocks are visited in a
 // compile-time order so every register index is a constant.
 template <bool FWD, int NRC>
-__device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v, int nr, int lane) {
+__device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v,
+                                           int nr, int lane, double* stg) {
 #pragma unroll
   for (int jbi = 0; jbi < BRB; ++jbi) {
     const int jb = FWD ? jbi : BRB - 1 - jbi;
     if (64 * jb >= n) continue;
     const int cnt = min(64, n - 64 * jb);
+    // op(T)(i, 64 jb + jj) for every row i: from LDS directly, or staged into LDS (matrix in HBM)
+    const double* P;
+    int pr, pc;  // element (i, jj) at P[i * pr + jj * pc]
+    if (stg) {
+      if (!trans) {
+        for (int jj = 0; jj < cnt; ++jj)
+          for (int i = lane; i < n; i += 64) stg[jj * BNM + i] = T[i + (size_t)(64 * jb + jj) * ldt];
+      } else {
+        for (int i = 0; i < n; ++i)
+          if (lane < cnt) stg[lane * BNM + i] = T[(64 * jb + lane) + (size_t)i * ldt];
+      }
+      __builtin_amdgcn_wave_barrier();
+      P = stg;
+      pr = 1;
+      pc = BNM;
+    } else {
+      P = trans ? T + (size_t)(64 * jb) : T + (size_t)(64 * jb) * ldt;
+      pr = trans ? ldt : 1;
+      pc = trans ? 1 : ldt;
+    }
     for (int jj0 = 0; jj0 < cnt; ++jj0) {
       const int jj = FWD ? jj0 : cnt - 1 - jj0;
       const int j = 64 * jb + jj;
-      const double d = unit ? 1.0 : T[j + (size_t)j * ldt];
+      const double d = unit ? 1.0 : P[j * pr + jj * pc];
       double xj[NRC];
 #pragma unroll
       for (int r = 0; r < NRC; ++r) {
@@ -210,20 +231,21 @@ __device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool
         const int i = lane + 64 * b;
         const bool rel = FWD ? (i > j) : (i < j);
         if (i < n && rel) {
-          const double tij = trans ? T[j + (size_t)i * ldt] : T[i + (size_t)j * ldt];
+          const double tij = P[i * pr + jj * pc];
 #pragma unroll
           for (int r = 0; r < NRC; ++r)
             if (r < nr) v.x[b][r] = fma(-tij, xj[r], v.x[b][r]);
         }
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 template <int NRC>
 __device__ __forceinline__ void w_trsv(const double* T, int ldt, int n, bool lower, bool trans, bool unit,
-                                       WVec<NRC>& v, int nr, int lane) {
-  if (lower != trans) w_trsv_dir<true, NRC>(T, ldt, n, trans, unit, v, nr, lane);
-  else w_trsv_dir<false, NRC>(T, ldt, n, trans, unit, v, nr, lane);
+                                       WVec<NRC>& v, int nr, int lane, double* stg) {
+  if (lower != trans) w_trsv_dir<true, NRC>(T, ldt, n, trans, unit, v, nr, lane, stg);
+  else w_trsv_dir<false, NRC>(T, ldt, n, trans, unit, v, nr, lane, stg);
 }
 
 // routed factor: 0 LU (M = L\U, perm), 1 Cholesky (M = L), 2 triangular (T = A as given)
@@ -232,7 +254,8 @@ struct BFactor {
   const double* M;
   int ld;
   const int* perm;
-  bool lower;  // triangular kind
+  bool lower;   // triangular kind
+  double* stg;  // LDS staging for a matrix kept in HBM (null when M is in LDS)
 };
 
 // y = inv(A) y (trans = false) or inv(A)^T y (trans = true); wave 0 only; sbuf: LDS, BNM * BRM doubles
@@ -258,11 +281,11 @@ __device__ __forceinline__ void w_apply_inv(const BFactor& f, int n, bool trans,
         }
       }
       __builtin_amdgcn_wave_barrier();
-      w_trsv(f.M, f.ld, n, true, false, true, v, nr, lane);
-      w_trsv(f.M, f.ld, n, false, false, false, v, nr, lane);
+      w_trsv(f.M, f.ld, n, true, false, true, v, nr, lane, f.stg);
+      w_trsv(f.M, f.ld, n, false, false, false, v, nr, lane, f.stg);
     } else {
-      w_trsv(f.M, f.ld, n, false, true, false, v, nr, lane);
-      w_trsv(f.M, f.ld, n, true, true, true, v, nr, lane);
+      w_trsv(f.M, f.ld, n, false, true, false, v, nr, lane, f.stg);
+      w_trsv(f.M, f.ld, n, true, true, true, v, nr, lane, f.stg);
       // P^T y: y_new[perm[i]] = y[i]
 #pragma unroll
       for (int b = 0; b < BRB; ++b) {
@@ -283,10 +306,10 @@ __device__ __forceinline__ void w_apply_inv(const BFactor& f, int n, bool trans,
       __builtin_amdgcn_wave_barrier();
     }
   } else if (f.kind == 1) {
-    w_trsv(f.M, f.ld, n, true, false, false, v, nr, lane);
-    w_trsv(f.M, f.ld, n, true, true, false, v, nr, lane);
+    w_trsv(f.M, f.ld, n, true, false, false, v, nr, lane, f.stg);
+    w_trsv(f.M, f.ld, n, true, true, false, v, nr, lane, f.stg);
   } else {
-    w_trsv(f.M, f.ld, n, f.lower, trans, false, v, nr, lane);
+    w_trsv(f.M, f.ld, n, f.lower, trans, false, v, nr, lane, f.stg);
   }
 }
 
@@ -404,55 +427,87 @@ __device__ __forceinline__ void b_rr_pair(int m, int r, int pi, int& a, int& b) 
   }
 }
 
+// Each quarter-wave (16 lanes) takes one pair, so a workgroup has 16 pairs in
+// flight; the two columns stay in registers between the dot products and the
+// rotation (up to 16 elements per lane).
+constexpr int JQ = BNM / 16;  // elements of a column per lane of a quarter-wave
 __device__ int b_jacobi(const BCtx& c, double* U, double* V, int n, int max_sweeps) {
   const int m = (n + 1) & ~1;
   const double tol = (double)n * kEps;
+  const int q = c.lane >> 4, ql = c.lane & 15;  // quarter of the wave, lane in it
+  const int slot = c.w * 4 + q;                 // 16 pair slots per workgroup
   __shared__ int s_rot;
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
     if (c.t == 0) s_rot = 0;
     __syncthreads();
+    int rot = 0;
     for (int r = 0; r < m - 1; ++r) {
-      for (int pi = c.w; pi < m / 2; pi += 4) {
-        int a, b;
-        b_rr_pair(m, r, pi, a, b);
-        if (a >= n || b >= n) continue;
-        const int p = min(a, b), q = max(a, b);
+      for (int pi0 = 0; pi0 < m / 2; pi0 += 16) {
+        const int pi = pi0 + slot;
+        int a = 0, b = 0;
+        bool live = pi < m / 2;
+        if (live) {
+          b_rr_pair(m, r, pi, a, b);
+          live = a < n && b < n;
+        }
+        const int p = min(a, b), qq = max(a, b);
         double* up = U + (size_t)p * n;
-        double* uq = U + (size_t)q * n;
+        double* uq = U + (size_t)qq * n;
+        double x[JQ], y[JQ];
+#pragma unroll
+        for (int k = 0; k < JQ; ++k) {
+          const int i = ql + 16 * k;
+          x[k] = (live && i < n) ? up[i] : 0.0;
+          y[k] = (live && i < n) ? uq[i] : 0.0;
+        }
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = c.lane; i < n; i += 64) {
-          const double x = up[i], y = uq[i];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
+#pragma unroll
+        for (int k = 0; k < JQ; ++k) {
+          al = fma(x[k], x[k], al);
+          be = fma(y[k], y[k], be);
+          ga = fma(x[k], y[k], ga);
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        for (int i = c.lane; i < n; i += 64) {
-          const double x = up[i], y = uq[i];
-          up[i] = cs * x - sn * y;
-          uq[i] = sn * x + cs * y;
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 64);
+          be += __shfl_xor(be, o, 64);
+          ga += __shfl_xor(ga, o, 64);
         }
-        double* vp = V + (size_t)p * n;
-        double* vq = V + (size_t)q * n;
-        for (int i = c.lane; i < n; i += 64) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = cs * x - sn * y;
-          vq[i] = sn * x + cs * y;
+        if (live && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+          for (int k = 0; k < JQ; ++k) {
+            const int i = ql + 16 * k;
+            if (i < n) {
+              up[i] = cs * x[k] - sn * y[k];
+              uq[i] = sn * x[k] + cs * y[k];
+            }
+          }
+          double* vp = V + (size_t)p * n;
+          double* vq = V + (size_t)qq * n;
+#pragma unroll
+          for (int k = 0; k < JQ; ++k) {
+            const int i = ql + 16 * k;
+            if (i < n) {
+              const double xv = vp[i], yv = vq[i];
+              vp[i] = cs * xv - sn * yv;
+              vq[i] = sn * xv + cs * yv;
+            }
+          }
+          rot = 1;
         }
-        if (c.lane == 0) s_rot = 1;
       }
       __syncthreads();
     }
-    const int rot = s_rot;
+    rot = wave_or(rot);
+    if (c.lane == 0 && rot) s_rot = 1;
     __syncthreads();
-    if (!rot) {
+    const int any = s_rot;
+    __syncthreads();
+    if (!any) {
       ++sweeps;
       break;
     }
@@ -594,6 +649,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     f.ld = n;
     f.perm = perm;
     f.lower = false;
+    f.stg = (n <= BNL) ? nullptr : lds;  // the LDS matrix region is free when the matrix lives in HBM
     double anorm = anorm1;
     bool routed_sym = false;
     if (cls == ADA_CLASS_TRI_UPPER || cls == ADA_CLASS_TRI_LOWER) {
