@@ -132,17 +132,22 @@ def bench_batched(args):
     cases = W.batched_case(args.count, k=0, n_lo=n_lo, n_hi=n_hi)
     As = [c[1] for c in cases]
     Bs = [c[2] for c in cases]
-    batch = ada.Batch(As, Bs)
+    batch = ada.Batch(As, Bs, precision=args.precision)
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
     times = []
+    ev = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()  # the batch runs on torch's current stream
         batch.run()
+        e1.record()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - s0)
+        ev.append(e0.elapsed_time(e1) * 1e-3)
     total = time.perf_counter() - t0
     res = batch.results()
     worst = max((r.berr for r in res), default=0.0)
@@ -154,7 +159,19 @@ def bench_batched(args):
     routes = {}
     for r in res:
         routes[r.route] = routes.get(r.route, 0) + 1
+    refine = None
+    if args.precision == "fp32_ir":
+        its = [r.refine_iters for r in res if r.route in ("lu", "chol", "band_lu") or r.refine_iters < 0]
+        conv = [i for i in its if i > 0]
+        refine = {"refined": len(conv), "to_fp64": sum(1 for i in its if i < 0),
+                  "iters_mean": round(float(np.mean(conv)), 3) if conv else None,
+                  "iters_max": max(conv) if conv else None}
     value = args.count * args.steps / total
+    kern_s = float(np.mean(ev))
+    achieved = flops / kern_s / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": 78.6, "unit": "TFLOP/s",
+            "frac": round(achieved / 78.6, 5), "traffic": None, "kernel": "k_solve_batched",
+            "avg_launch_ms": round(kern_s * 1e3, 3)}
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -172,13 +189,14 @@ def bench_batched(args):
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batched: {args.count} systems, n uniform in [{n_lo}, {n_hi}], nrhs uniform in [1, 8], "
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched ({args.precision}): {args.count} systems, n uniform in [{n_lo}, {n_hi}], nrhs uniform in [1, 8], "
                                "40% dense general, 30% SPD, 15% banded, 10% triangular, 5% condition 1e15",
                    "count": args.count},
         "tflops": round(flops * args.steps / total / 1e12, 4),
         "p50_step_ms": round(pct(times, 50) * 1e3, 3), "p99_step_ms": round(pct(times, 99) * 1e3, 3),
-        "max_berr": worst, "routes": routes, "roofline": None, "cpu_baseline": cpu,
+        "max_berr": worst, "routes": routes, "refinement": refine, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -195,6 +213,8 @@ def main():
                     help="single: the five large systems; batched: many small systems in one launch per step")
     ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
     ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32_ir"),
+                    help="batched workload: FP64 factors, or FP32 factors with FP64 iterative refinement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy this many MiB device-to-device three times (calibrates HBM byte counters)")
     args = ap.parse_args()

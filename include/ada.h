@@ -58,6 +58,9 @@ enum { ADA_CLASS_GENERAL = 0, ADA_CLASS_BANDED = 1, ADA_CLASS_TRI_UPPER = 2, ADA
 /* solver whose x is returned */
 enum { ADA_ROUTE_NONE = 0, ADA_ROUTE_BAND_LU = 1, ADA_ROUTE_TRI = 2, ADA_ROUTE_CHOL = 3, ADA_ROUTE_LU = 4,
        ADA_ROUTE_SVD = 5 };
+/* arithmetic of the factorisation (ada_solve_batched): FP64 throughout, or FP32 factors with FP64
+   residuals and iterative refinement, falling back to FP64 when the refinement does not converge */
+enum { ADA_PREC_FP64 = 0, ADA_PREC_FP32_IR = 1 };
 /* input layout */
 enum { ADA_LAYOUT_DENSE = 0, ADA_LAYOUT_BAND = 1 };
 /* why the SVD fallback ran (Section II-E): */
@@ -76,6 +79,7 @@ typedef struct {
   int32_t kl_in, ku_in;     /* stored band widths for ADA_LAYOUT_BAND */
   int32_t force_general;    /* 1: skip detection, always LU (the paper's "standard" solver, Section III) */
   int32_t want_berr;        /* 1: compute result.berr (normwise backward error) on the device */
+  int32_t precision;        /* ADA_PREC_FP64 (default) or ADA_PREC_FP32_IR (batched solves) */
 } ada_opts;
 
 typedef struct {
@@ -88,7 +92,9 @@ typedef struct {
   int32_t rank;             /* SVD route: number of singular values > eps*sigma_max; else n */
   int32_t sweeps;           /* SVD route: Jacobi sweeps */
   int32_t nsolves;          /* solves spent by the condition estimate */
-  int32_t refine_iters;     /* reserved (0) */
+  int32_t refine_iters;     /* FP32_IR: refinement steps taken; < 0: the FP32 attempt did not converge
+                               (-1: its factorisation failed, -1-k: stopped after k steps) and x comes
+                               from the FP64 route; 0 otherwise */
   int32_t status;           /* per-system status of a batched solve (ADA_OK or ADA_ERR_*); ada_solve: ADA_OK */
   double rcond;             /* reciprocal 1-norm condition estimate of the routed factorisation; NaN if none */
   double berr;              /* max over columns of ||b-Ax||_inf / (||A||_inf ||x||_inf + ||b||_inf); NaN unless want_berr */

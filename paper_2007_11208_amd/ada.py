@@ -20,6 +20,8 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_SINGULAR, ERR_NOMEM, ERR_HIP, ERR_FALLBACK_INFEA
 CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD = 0, 1, 2, 3, 4
 ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD = 0, 1, 2, 3, 4, 5
 LAYOUT_DENSE, LAYOUT_BAND = 0, 1
+PREC_FP64, PREC_FP32_IR = 0, 1
+PRECISIONS = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR}
 # kernel families of the instrumentation (ADA_KF_*)
 KERNEL_FAMILIES = ("gemm", "panel", "laswp", "trsm_block", "potrf", "trsv", "gbtrf", "gbtrs", "detect", "jacobi")
 CLASS_NAMES = {0: "general", 1: "banded", 2: "tri_upper", 3: "tri_lower", 4: "sympd"}
@@ -30,7 +32,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("no_approx", ctypes.c_int32),
                 ("rcond_threshold", ctypes.c_double), ("layout", ctypes.c_int32),
                 ("kl_in", ctypes.c_int32), ("ku_in", ctypes.c_int32), ("force_general", ctypes.c_int32),
-                ("want_berr", ctypes.c_int32)]
+                ("want_berr", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -95,7 +97,7 @@ def last_error() -> str:
 
 
 def make_opts(no_approx=False, rcond_threshold=-1.0, layout=LAYOUT_DENSE, kl_in=0, ku_in=0, force_general=False,
-              want_berr=True) -> Opts:
+              want_berr=True, precision="fp64") -> Opts:
     o = Opts()
     lib().ada_opts_default(ctypes.byref(o))
     o.no_approx = int(no_approx)
@@ -105,6 +107,9 @@ def make_opts(no_approx=False, rcond_threshold=-1.0, layout=LAYOUT_DENSE, kl_in=
     o.ku_in = int(ku_in)
     o.force_general = int(force_general)
     o.want_berr = int(want_berr)
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    o.precision = PRECISIONS[precision]
     return o
 
 
@@ -201,11 +206,13 @@ class SolveResult:
     rcond: float
     berr: float
     status: int = OK
+    refine_iters: int = 0
 
 
 def _result(r: Result, status: int) -> SolveResult:
     return SolveResult(CLASS_NAMES.get(r.cls, str(r.cls)), r.kl, r.ku, ROUTE_NAMES.get(r.route, str(r.route)),
-                       bool(r.chol_failed), r.fallback, r.info, r.rank, r.sweeps, r.nsolves, r.rcond, r.berr, status)
+                       bool(r.chol_failed), r.fallback, r.info, r.rank, r.sweeps, r.nsolves, r.rcond, r.berr, status,
+                       r.refine_iters)
 
 
 def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, want_berr=True, layout="dense",
@@ -260,7 +267,7 @@ class Batch:
     one descriptor each), solved by one ada_solve_batched launch per run()."""
 
     def __init__(self, As, Bs, device="cuda:0", no_approx=False, rcond_threshold=-1.0, force_general=False,
-                 want_berr=True, ctx: Context | None = None):
+                 want_berr=True, precision="fp64", ctx: Context | None = None):
         import numpy as np
         import torch
         if len(As) != len(Bs) or not As:
@@ -292,7 +299,7 @@ class Batch:
         self.res = torch.zeros(self.count * ctypes.sizeof(Result), dtype=torch.uint8, device=dev)
         ws = int(lib().ada_batched_workspace_size(self.count))
         self.work = torch.empty(ws, dtype=torch.uint8, device=dev)
-        self.opts = make_opts(no_approx, rcond_threshold, LAYOUT_DENSE, 0, 0, force_general, want_berr)
+        self.opts = make_opts(no_approx, rcond_threshold, LAYOUT_DENSE, 0, 0, force_general, want_berr, precision)
         self.ctx = ctx or context(dev.index or 0)
 
     def run(self):

@@ -587,6 +587,7 @@ int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const doub
   ada_opts o;
   if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
   if (o.layout != ADA_LAYOUT_DENSE) return fail(ADA_ERR_ARG, "batched solves take dense input only");
+  if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR) return fail(ADA_ERR_ARG, "unknown precision");
   if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(ADA_ERR_ARG, "work must be 256-byte aligned");
   if (work_bytes < ada_batched_workspace_size(count)) return fail(ADA_ERR_ARG, "workspace too small");
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -831,6 +832,7 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
   ada_opts o;
   if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
   if (o.layout != ADA_LAYOUT_DENSE && o.layout != ADA_LAYOUT_BAND) return fail(ADA_ERR_ARG, "unknown layout");
+  if (o.precision != ADA_PREC_FP64) return fail(ADA_ERR_ARG, "single solves take precision ADA_PREC_FP64");
   if (n < 1 || nrhs < 1) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
   if (o.layout == ADA_LAYOUT_DENSE && lda < n) return fail(ADA_ERR_ARG, "lda < n");
   if (ldb < n || ldx < n) return fail(ADA_ERR_ARG, "ldb or ldx < n");

@@ -25,6 +25,8 @@ constexpr int BNM = 256;      // largest order
 constexpr int BRM = 8;        // most right-hand sides
 constexpr int BNL = 128;      // orders up to this keep the matrix in LDS
 constexpr int BRB = BNM / 64; // rows per lane in the one-wave solves
+constexpr int BNL32 = 181;    // orders up to this keep an FP32 matrix in LDS (181^2 * 4 bytes <= 128 KB)
+constexpr int kMaxRefine = 30;  // refinement steps at most (the limit of LAPACK's mixed-precision driver)
 
 struct BDesc {
   int32_t n, nrhs, lda, ldb, ldx, pad;
@@ -94,7 +96,8 @@ __device__ __forceinline__ int b_argmax(const BCtx& c, double v, int idx) {
 
 // ---------------------------------------------------------------- factorisations (four waves)
 // LU with partial pivoting of M (ld n) in place; perm tracks the row order. Returns info (0 or 1-based column).
-__device__ int b_getrf(const BCtx& c, double* M, int n, int* perm) {
+template <class T>
+__device__ int b_getrf(const BCtx& c, T* M, int n, int* perm) {
   int info = 0;
   for (int i = c.t; i < n; i += BT) perm[i] = i;
   __syncthreads();
@@ -102,18 +105,18 @@ __device__ int b_getrf(const BCtx& c, double* M, int n, int* perm) {
     double v = -1.0;
     int idx = -1;
     for (int i = j + c.t; i < n; i += BT) {
-      const double a = fabs(M[i + j * n]);
+      const double a = fabs((double)M[i + j * n]);
       if (idx < 0 || a > v) { v = a; idx = i; }
     }
     const int p = b_argmax(c, v, idx);
-    const double piv = M[p + j * n];
+    const T piv = M[p + j * n];
     if (piv == 0.0) {
       if (info == 0) info = j + 1;
       continue;
     }
     if (p != j) {
       for (int k = c.t; k < n; k += BT) {
-        const double a = M[j + k * n];
+        const T a = M[j + k * n];
         M[j + k * n] = M[p + k * n];
         M[p + k * n] = a;
       }
@@ -127,14 +130,14 @@ __device__ int b_getrf(const BCtx& c, double* M, int n, int* perm) {
     for (int i = j + 1 + c.t; i < n; i += BT) M[i + j * n] = M[i + j * n] / piv;
     __syncthreads();
     // rank-1 update: wave w takes columns j+1+w, j+5+w, ...; lane takes rows j+1+lane, +64, ...
-    double l[BRB];
+    T l[BRB];
 #pragma unroll
     for (int b = 0; b < BRB; ++b) {
       const int i = j + 1 + c.lane + 64 * b;
-      l[b] = i < n ? M[i + j * n] : 0.0;
+      l[b] = i < n ? M[i + j * n] : T(0);
     }
     for (int k = j + 1 + c.w; k < n; k += 4) {
-      const double u = M[j + k * n];
+      const T u = M[j + k * n];
 #pragma unroll
       for (int b = 0; b < BRB; ++b) {
         const int i = j + 1 + c.lane + 64 * b;
@@ -147,22 +150,23 @@ __device__ int b_getrf(const BCtx& c, double* M, int n, int* perm) {
 }
 
 // Cholesky A = L L^T from the lower triangle of M; returns 0 or the 1-based failing column
-__device__ int b_potrf(const BCtx& c, double* M, int n) {
+template <class T>
+__device__ int b_potrf(const BCtx& c, T* M, int n) {
   for (int j = 0; j < n; ++j) {
-    const double d = M[j + j * n];
-    if (!(d > 0.0)) return j + 1;
-    const double sd = sqrt(d);
+    const T d = M[j + j * n];
+    if (!(d > T(0))) return j + 1;
+    const T sd = sqrt(d);
     __syncthreads();
     for (int i = j + c.t; i < n; i += BT) M[i + j * n] = (i == j) ? sd : M[i + j * n] / sd;
     __syncthreads();
-    double l[BRB];
+    T l[BRB];
 #pragma unroll
     for (int b = 0; b < BRB; ++b) {
       const int i = j + 1 + c.lane + 64 * b;
-      l[b] = i < n ? M[i + j * n] : 0.0;
+      l[b] = i < n ? M[i + j * n] : T(0);
     }
     for (int k = j + 1 + c.w; k < n; k += 4) {
-      const double u = M[k + j * n];
+      const T u = M[k + j * n];
 #pragma unroll
       for (int b = 0; b < BRB; ++b) {
         const int i = j + 1 + c.lane + 64 * b;
@@ -184,16 +188,16 @@ struct WVec {
 // op(T) y = y in place; T (ld ldt) lower or upper as stored, op = transpose if trans.
 // FWD: forward substitution (op(T) lower). Register blocks are visited in a
 // compile-time order so every register index is a constant.
-template <bool FWD, int NRC>
-__device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v,
-                                           int nr, int lane, double* stg) {
+template <bool FWD, int NRC, class TF>
+__device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v,
+                                           int nr, int lane, TF* stg) {
 #pragma unroll
   for (int jbi = 0; jbi < BRB; ++jbi) {
     const int jb = FWD ? jbi : BRB - 1 - jbi;
     if (64 * jb >= n) continue;
     const int cnt = min(64, n - 64 * jb);
     // op(T)(i, 64 jb + jj) for every row i: from LDS directly, or staged into LDS (matrix in HBM)
-    const double* P;
+    const TF* P;
     int pr, pc;  // element (i, jj) at P[i * pr + jj * pc]
     if (stg) {
       if (!trans) {
@@ -215,7 +219,7 @@ __device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool
     for (int jj0 = 0; jj0 < cnt; ++jj0) {
       const int jj = FWD ? jj0 : cnt - 1 - jj0;
       const int j = 64 * jb + jj;
-      const double d = unit ? 1.0 : P[j * pr + jj * pc];
+      const double d = unit ? 1.0 : (double)P[j * pr + jj * pc];
       double xj[NRC];
 #pragma unroll
       for (int r = 0; r < NRC; ++r) {
@@ -231,7 +235,7 @@ __device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool
         const int i = lane + 64 * b;
         const bool rel = FWD ? (i > j) : (i < j);
         if (i < n && rel) {
-          const double tij = P[i * pr + jj * pc];
+          const double tij = (double)P[i * pr + jj * pc];
 #pragma unroll
           for (int r = 0; r < NRC; ++r)
             if (r < nr) v.x[b][r] = fma(-tij, xj[r], v.x[b][r]);
@@ -241,26 +245,28 @@ __device__ __forceinline__ void w_trsv_dir(const double* T, int ldt, int n, bool
     __builtin_amdgcn_wave_barrier();
   }
 }
-template <int NRC>
-__device__ __forceinline__ void w_trsv(const double* T, int ldt, int n, bool lower, bool trans, bool unit,
-                                       WVec<NRC>& v, int nr, int lane, double* stg) {
-  if (lower != trans) w_trsv_dir<true, NRC>(T, ldt, n, trans, unit, v, nr, lane, stg);
-  else w_trsv_dir<false, NRC>(T, ldt, n, trans, unit, v, nr, lane, stg);
+template <int NRC, class TF>
+__device__ __forceinline__ void w_trsv(const TF* T, int ldt, int n, bool lower, bool trans, bool unit,
+                                       WVec<NRC>& v, int nr, int lane, TF* stg) {
+  if (lower != trans) w_trsv_dir<true, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg);
+  else w_trsv_dir<false, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg);
 }
 
 // routed factor: 0 LU (M = L\U, perm), 1 Cholesky (M = L), 2 triangular (T = A as given)
+template <class TF>
 struct BFactor {
   int kind;
-  const double* M;
+  const TF* M;
   int ld;
   const int* perm;
-  bool lower;   // triangular kind
-  double* stg;  // LDS staging for a matrix kept in HBM (null when M is in LDS)
+  bool lower;  // triangular kind
+  TF* stg;     // LDS staging for a matrix kept in HBM (null when M is in LDS)
 };
 
 // y = inv(A) y (trans = false) or inv(A)^T y (trans = true); wave 0 only; sbuf: LDS, BNM * BRM doubles
-template <int NRC>
-__device__ __forceinline__ void w_apply_inv(const BFactor& f, int n, bool trans, WVec<NRC>& v, int nr, int lane, double* sbuf) {
+template <int NRC, class TF>
+__device__ __forceinline__ void w_apply_inv(const BFactor<TF>& f, int n, bool trans, WVec<NRC>& v, int nr, int lane,
+                                            double* sbuf) {
   if (f.kind == 0) {
     if (!trans) {
       // P y: y_new[i] = y[perm[i]]
@@ -322,7 +328,8 @@ __device__ __forceinline__ double w_sum(const WVec<1>& v, int n, int lane) {
 }
 
 // ||inv(A)||_1 by Hager's method as refined by Higham (the same steps as the single-system estimator)
-__device__ __forceinline__ double w_estimate(const BFactor& f, int n, int lane, double* sbuf, int& nsolves) {
+template <class TF>
+__device__ __forceinline__ double w_estimate(const BFactor<TF>& f, int n, int lane, double* sbuf, int& nsolves) {
   WVec<1> v;
   double xi[BRB];
 #pragma unroll
@@ -642,51 +649,18 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       }
     }
     res.cls = cls;
-    // ---- S6: routed factorisation
-    int info = 0;
-    BFactor f;
-    f.M = M;
-    f.ld = n;
-    f.perm = perm;
-    f.lower = false;
-    f.stg = (n <= BNL) ? nullptr : lds;  // the LDS matrix region is free when the matrix lives in HBM
+    // ---- FP32 factorisation with FP64 iterative refinement (precision option): the class and the
+    // route are the FP64 decisions above; residuals, corrections and the condition estimate are FP64
+    // arithmetic on FP32 factors; a refinement that does not reach sqrt(n)*eps in backward error
+    // (stagnation, a non-finite value, or the step limit) hands the system to the FP64 route.
+    __shared__ int s_flag;
+    __shared__ double s_rc;
+    bool mixed_ok = false;
+    bool m_clobbered = false;
+    int refine = 0;
+    const bool sym_class = cls == ADA_CLASS_SYMPD;
     double anorm = anorm1;
-    bool routed_sym = false;
-    if (cls == ADA_CLASS_TRI_UPPER || cls == ADA_CLASS_TRI_LOWER) {
-      res.route = ADA_ROUTE_TRI;
-      f.kind = 2;
-      f.lower = cls == ADA_CLASS_TRI_LOWER;
-      int z = INT_MAX;
-      for (int j = c.t; j < n; j += BT)
-        if (M[j + j * n] == 0.0) z = min(z, j);
-      z = -b_max_int(c, z == INT_MAX ? -INT_MAX : -z);
-      info = (z == INT_MAX) ? 0 : z + 1;
-    } else {
-      bool fresh = true;  // M still holds A
-      if (cls == ADA_CLASS_SYMPD) {
-        const int ci = b_potrf(c, M, n);
-        fresh = false;
-        __syncthreads();
-        if (ci == 0) {
-          res.route = ADA_ROUTE_CHOL;
-          f.kind = 1;
-          routed_sym = true;
-        } else {
-          res.chol_failed = 1;
-        }
-      }
-      if (!routed_sym) {
-        res.route = (cls == ADA_CLASS_BANDED) ? ADA_ROUTE_BAND_LU : ADA_ROUTE_LU;
-        if (!fresh) {
-          for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
-          __syncthreads();
-        }
-        info = b_getrf(c, M, n, perm);
-        __syncthreads();
-        f.kind = 0;
-      }
-    }
-    if (routed_sym) {
+    if (sym_class) {
       // ||A||_1 of the symmetric matrix the lower triangle defines
       double s = 0.0;
       for (int j = c.t; j < n; j += BT) {
@@ -697,53 +671,222 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       }
       anorm = b_max(c, s);
     }
-    res.info = info;
-    // ---- solve, condition estimate (wave 0)
-    __shared__ int s_flag;
-    __shared__ double s_rc;
-    if (c.w == 0) {
-      double rcond = __longlong_as_double(0x7ff8000000000000LL);
-      int xnf = 0;
-      if (info == 0) {
-        for (int r0 = 0; r0 < nr; ++r0) {  // one right-hand side at a time keeps the wave's registers small
-          WVec<1> v;
+    if (o.precision == ADA_PREC_FP32_IR &&
+        (cls == ADA_CLASS_SYMPD || cls == ADA_CLASS_GENERAL || cls == ADA_CLASS_BANDED)) {
+      float* M32 = (n <= BNL32) ? reinterpret_cast<float*>(lds) : reinterpret_cast<float*>(gV);
+      m_clobbered = n <= BNL;  // the FP64 copy shared the LDS region
+      for (int e = c.t; e < n * n; e += BT) M32[e] = (float)A[e % n + (size_t)(e / n) * d.lda];
+      __syncthreads();
+      BFactor<float> g;
+      g.M = M32;
+      g.ld = n;
+      g.perm = perm;
+      g.lower = false;
+      g.stg = (n <= BNL32) ? nullptr : reinterpret_cast<float*>(lds);
+      int ok;
+      if (sym_class) {
+        ok = b_potrf<float>(c, M32, n) == 0;
+        g.kind = 1;
+      } else {
+        ok = b_getrf<float>(c, M32, n, perm) == 0;
+        g.kind = 0;
+      }
+      __syncthreads();
+      refine = -1;  // the FP32 factorisation failed
+      if (ok) {
+        const double tol = sqrt((double)n) * kEps;
+        double* Rv = gX;
+        int conv_all = 1;
+        refine = 0;
+        for (int r0 = 0; r0 < nr && conv_all; ++r0) {
+          if (c.w == 0) {
+            WVec<1> v;
 #pragma unroll
-          for (int b = 0; b < BRB; ++b) {
-            const int i = c.lane + 64 * b;
-            v.x[b][0] = i < n ? B[i + (size_t)r0 * d.ldb] : 0.0;
-          }
-          w_apply_inv(f, n, false, v, 1, c.lane, sbuf);
+            for (int b = 0; b < BRB; ++b) {
+              const int i = c.lane + 64 * b;
+              v.x[b][0] = i < n ? B[i + (size_t)r0 * d.ldb] : 0.0;
+            }
+            w_apply_inv(g, n, false, v, 1, c.lane, sbuf);
 #pragma unroll
-          for (int b = 0; b < BRB; ++b) {
-            const int i = c.lane + 64 * b;
-            if (i < n) {
-              X[i + (size_t)r0 * d.ldx] = v.x[b][0];
-              xnf |= !isfinite(v.x[b][0]);
+            for (int b = 0; b < BRB; ++b) {
+              const int i = c.lane + 64 * b;
+              if (i < n) X[i + (size_t)r0 * d.ldx] = v.x[b][0];
             }
           }
+          __syncthreads();
+          double eta_prev = INFINITY;
+          int it = 0, conv = 0;
+          for (;; ++it) {
+            double rn = 0.0, xn = 0.0, bn = 0.0;
+            int bad = 0;
+            for (int i = c.t; i < n; i += BT) {
+              const double bi = B[i + (size_t)r0 * d.ldb];
+              double sres = bi;
+              for (int j = 0; j < n; ++j) sres = fma(-A[i + (size_t)j * d.lda], X[j + (size_t)r0 * d.ldx], sres);
+              Rv[i] = sres;
+              const double xi = X[i + (size_t)r0 * d.ldx];
+              bad |= !isfinite(xi) || !isfinite(sres);
+              rn = fmax(rn, fabs(sres));
+              xn = fmax(xn, fabs(xi));
+              bn = fmax(bn, fabs(bi));
+            }
+            rn = b_max(c, rn);
+            xn = b_max(c, xn);
+            bn = b_max(c, bn);
+            bad = b_or(c, bad);
+            const double den = anorm_inf * xn + bn;
+            const double eta = bad ? __longlong_as_double(0x7ff8000000000000LL)
+                                   : (den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0));
+            if (eta <= tol) {
+              conv = 1;
+              break;
+            }
+            if (!(eta <= 0.5 * eta_prev) || it == kMaxRefine) break;
+            eta_prev = eta;
+            if (c.w == 0) {
+              WVec<1> v;
+#pragma unroll
+              for (int b = 0; b < BRB; ++b) {
+                const int i = c.lane + 64 * b;
+                v.x[b][0] = i < n ? Rv[i] : 0.0;
+              }
+              w_apply_inv(g, n, false, v, 1, c.lane, sbuf);
+#pragma unroll
+              for (int b = 0; b < BRB; ++b) {
+                const int i = c.lane + 64 * b;
+                if (i < n) X[i + (size_t)r0 * d.ldx] += v.x[b][0];
+              }
+            }
+            __syncthreads();
+          }
+          refine = max(refine, it);
+          if (!conv) conv_all = 0;
         }
-        int ns = 0;
-        const double est = w_estimate(f, n, c.lane, sbuf, ns);
-        res.nsolves = ns;
-        if (anorm == 0.0) rcond = 0.0;
-        else if (est != est) rcond = est;
-        else if (est == 0.0) rcond = 0.0;
-        else rcond = (1.0 / est) / anorm;
-        xnf = wave_or(xnf);
+        mixed_ok = conv_all;
+        if (!mixed_ok) refine = -1 - refine;
       }
-      if (c.lane == 0) {
-        int fb = ADA_FALLBACK_NONE;
-        if (info || xnf) fb = ADA_FALLBACK_FAILURE;
-        else if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
-        else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
-        s_flag = fb;
-        s_rc = rcond;
+      if (mixed_ok) {
+        res.route = sym_class ? ADA_ROUTE_CHOL : (cls == ADA_CLASS_BANDED ? ADA_ROUTE_BAND_LU : ADA_ROUTE_LU);
+        if (c.w == 0) {
+          int ns = 0;
+          const double est = w_estimate(g, n, c.lane, sbuf, ns);
+          res.nsolves = ns;
+          double rcond;
+          if (anorm == 0.0) rcond = 0.0;
+          else if (est != est) rcond = est;
+          else if (est == 0.0) rcond = 0.0;
+          else rcond = (1.0 / est) / anorm;
+          if (c.lane == 0) {
+            int fb = ADA_FALLBACK_NONE;
+            if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
+            else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
+            s_flag = fb;
+            s_rc = rcond;
+          }
+        }
+        __syncthreads();
+        res.fallback = s_flag;
+        res.rcond = s_rc;
+        res.info = 0;
+        __syncthreads();
       }
+      res.refine_iters = refine;
     }
-    __syncthreads();
-    res.fallback = s_flag;
-    res.rcond = info ? __longlong_as_double(0x7ff8000000000000LL) : s_rc;
-    __syncthreads();
+    int info = 0;
+    if (!mixed_ok) {
+      // ---- S6: routed factorisation
+      BFactor<double> f;
+      f.M = M;
+      f.ld = n;
+      f.perm = perm;
+      f.lower = false;
+      f.stg = (n <= BNL) ? nullptr : lds;  // the LDS matrix region is free when the matrix lives in HBM
+      bool routed_sym = false;
+      if (m_clobbered) {
+        for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
+        __syncthreads();
+      }
+      if (cls == ADA_CLASS_TRI_UPPER || cls == ADA_CLASS_TRI_LOWER) {
+        res.route = ADA_ROUTE_TRI;
+        f.kind = 2;
+        f.lower = cls == ADA_CLASS_TRI_LOWER;
+        int z = INT_MAX;
+        for (int j = c.t; j < n; j += BT)
+          if (M[j + j * n] == 0.0) z = min(z, j);
+        z = -b_max_int(c, z == INT_MAX ? -INT_MAX : -z);
+        info = (z == INT_MAX) ? 0 : z + 1;
+      } else {
+        bool fresh = true;  // M still holds A
+        if (cls == ADA_CLASS_SYMPD) {
+          const int ci = b_potrf(c, M, n);
+          fresh = false;
+          __syncthreads();
+          if (ci == 0) {
+            res.route = ADA_ROUTE_CHOL;
+            f.kind = 1;
+            routed_sym = true;
+          } else {
+            res.chol_failed = 1;
+          }
+        }
+        if (!routed_sym) {
+          res.route = (cls == ADA_CLASS_BANDED) ? ADA_ROUTE_BAND_LU : ADA_ROUTE_LU;
+          if (!fresh) {
+            for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
+            __syncthreads();
+          }
+          info = b_getrf(c, M, n, perm);
+          __syncthreads();
+          f.kind = 0;
+        }
+      }
+      const double anorm_r = routed_sym ? anorm : anorm1;  // LU after a failed Cholesky: the full matrix
+      res.info = info;
+      // ---- solve, condition estimate (wave 0)
+      if (c.w == 0) {
+        double rcond = __longlong_as_double(0x7ff8000000000000LL);
+        int xnf = 0;
+        if (info == 0) {
+          for (int r0 = 0; r0 < nr; ++r0) {  // one right-hand side at a time keeps the wave's registers small
+            WVec<1> v;
+  #pragma unroll
+            for (int b = 0; b < BRB; ++b) {
+              const int i = c.lane + 64 * b;
+              v.x[b][0] = i < n ? B[i + (size_t)r0 * d.ldb] : 0.0;
+            }
+            w_apply_inv(f, n, false, v, 1, c.lane, sbuf);
+  #pragma unroll
+            for (int b = 0; b < BRB; ++b) {
+              const int i = c.lane + 64 * b;
+              if (i < n) {
+                X[i + (size_t)r0 * d.ldx] = v.x[b][0];
+                xnf |= !isfinite(v.x[b][0]);
+              }
+            }
+          }
+          int ns = 0;
+          const double est = w_estimate(f, n, c.lane, sbuf, ns);
+          res.nsolves = ns;
+          if (anorm_r == 0.0) rcond = 0.0;
+          else if (est != est) rcond = est;
+          else if (est == 0.0) rcond = 0.0;
+          else rcond = (1.0 / est) / anorm_r;
+          xnf = wave_or(xnf);
+        }
+        if (c.lane == 0) {
+          int fb = ADA_FALLBACK_NONE;
+          if (info || xnf) fb = ADA_FALLBACK_FAILURE;
+          else if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
+          else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
+          s_flag = fb;
+          s_rc = rcond;
+        }
+      }
+      __syncthreads();
+      res.fallback = s_flag;
+      res.rcond = info ? __longlong_as_double(0x7ff8000000000000LL) : s_rc;
+      __syncthreads();
+    }
     bool svd = false;
     if (res.fallback != ADA_FALLBACK_NONE) {
       if (o.no_approx) {

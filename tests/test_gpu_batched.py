@@ -111,3 +111,58 @@ def test_batched_errors_and_options(ada):
     x3, rs3 = ada.solve_batched([ok], [np.ones((30, 1))], force_general=True)
     assert rs3[0].route == "lu" and rs3[0].kl == -1
     assert np.allclose(ok @ x3[0], 1.0, atol=1e-10)
+
+
+def test_batched_fp32_refined_mix(ada):
+    """FP32 factors + FP64 refinement: same decisions as the FP64 oracle, backward error
+    <= 1e-10 (the refined form's bar; the refinement itself stops at sqrt(n) eps)."""
+    cases = W.batched_case(120, k=1, n_hi=256)
+    As = [c[1] for c in cases]
+    Bs = [c[2] for c in cases]
+    xs, rs = ada.solve_batched(As, Bs, precision="fp32_ir")
+    refined = 0
+    for (kind, a, b), x, r in zip(cases, xs, rs):
+        xr, rr = O.solve(a, b)
+        print(f"{kind} n={a.shape[0]} nrhs={b.shape[1]} -> {r.cls}/{r.route} it={r.refine_iters}", flush=True)
+        assert r.status == rr["status"] == 0
+        assert r.cls == ada.CLASS_NAMES[rr["cls"]] and (r.kl, r.ku) == (rr["kl"], rr["ku"])
+        assert r.route == ada.ROUTE_NAMES[rr["route"]], (r, rr)
+        assert r.fallback == rr["fallback"]
+        if r.route == "tri":
+            assert r.refine_iters == 0
+        elif r.route == "svd":
+            assert r.refine_iters <= 0  # FP32 never reaches the fallback's systems; FP64 decided
+        else:
+            refined += r.refine_iters > 0
+            assert 0.5 * rr["rcond"] <= r.rcond <= 2.0 * rr["rcond"], (r.rcond, rr["rcond"])
+        if r.route != "svd":
+            assert r.berr <= 1e-10, r
+            kappa = 1.0 / max(rr["rcond"], 1e-300)
+            tol = 32 * a.shape[0] * kappa * EPS * max(1.0, np.max(np.abs(xr)))
+            assert np.max(np.abs(x.reshape(xr.shape) - xr)) <= tol
+        else:
+            assert r.rank == rr["rank"]
+    assert refined > 0
+
+
+def test_batched_fp32_refinement_falls_back_to_fp64(ada):
+    """A system FP32 cannot factor usefully (kappa 1e10, or entries beyond the FP32 range) is
+    handed to the FP64 route: x and the result equal the FP64 solve's bit for bit."""
+    rng = np.random.default_rng(12)
+    hard = W.prescribed_spectrum(96, np.logspace(0, -10, 96), rng)
+    huge = W.dense_general(50, rng) * 1e40
+    spd = W.spd(140, rng)
+    ok = W.dense_general(200, rng)
+    As = [hard, huge, spd, ok]
+    Bs = [W.rhs_for(a, W.x_true(a.shape[0], 3, rng)) for a in As]
+    x64, r64 = ada.solve_batched(As, Bs)
+    x32, r32 = ada.solve_batched(As, Bs, precision="fp32_ir")
+    for k in (0, 1):
+        assert r32[k].refine_iters < 0, r32[k]
+        assert np.array_equal(x32[k], x64[k])
+        assert (r32[k].route, r32[k].rcond, r32[k].berr) == (r64[k].route, r64[k].rcond, r64[k].berr)
+    for k in (2, 3):
+        assert r32[k].refine_iters > 0 and r32[k].route == r64[k].route
+        assert r32[k].berr <= 1e-10
+    with pytest.raises(ValueError):
+        ada.make_opts(precision="bf16")
