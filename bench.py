@@ -42,7 +42,8 @@ FAMILY_KERNEL = {
     "gbtrf": ("k_gbtrf_k", "band.hip", "hbm"),
     "detect": ("k_detect_dense", "detect.hip", "hbm"),
 }
-PEAK = {"mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
+PEAK = {"mfma": (78.6, "TFLOP/s"), "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s"), "mfma32": (157.3, "TFLOP/s"),
+        "mfma16": (2500.0, "TFLOP/s")}
 
 
 def algorithmic_flops(name: str, n: int, nrhs: int, route: str, kl: int = 0, ku: int = 0) -> float:
@@ -201,23 +202,128 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def spectrum_system_gpu(n, kappa, spd, nrhs, seed, dev):
+    """U diag(s) V^T (V = U for SPD) with Haar U, V (QR of a Gaussian, signs fixed), s log-spaced
+    from 1 to 1/kappa; b = A x_true, x_true ~ N(0,1). Generated on the device (input generation,
+    outside the timed solves)."""
+    import torch
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+
+    def haar():
+        q, r = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device=dev, generator=g))
+        return q * torch.sign(torch.diagonal(r))[None, :]
+
+    u = haar()
+    v = u if spd else haar()
+    s = torch.logspace(0.0, -math.log10(kappa), n, dtype=torch.float64, device=dev)
+    a = (u * s[None, :]) @ v.T
+    del u, v
+    x = torch.randn(n, nrhs, dtype=torch.float64, device=dev, generator=g)
+    b = a @ x
+    # column-major storage for the library
+    return a.T.contiguous().T, b.T.contiguous().T
+
+
+def bench_mixed(args):
+    """Mixed precision against plain FP64 on the same systems: dense and SPD with a prescribed
+    spectrum, nrhs right-hand sides, each solved in FP64, with FP32 and with BF16 trailing updates
+    (FP64 refinement). Reports refinement steps, final backward error and time per solve."""
+    import torch
+    from paper_2007_11208_amd import ada
+    dev = torch.device("cuda:0")
+    sizes = [int(v) for v in args.mixed_n.split(",") if v]
+    kappas = [float(v) for v in args.mixed_kappa.split(",") if v]
+    precs = ("fp64", "fp32_ir", "bf16_ir")
+    ctx = ada.context(0)
+    rows = []
+    tot = {p: 0.0 for p in precs}
+    flops = 0.0
+    worst = {p: 0.0 for p in precs}
+    k = 0
+    for kind in ("dense", "spd"):
+        for n in sizes:
+            for kappa in kappas:
+                A, B = spectrum_system_gpu(n, kappa, kind == "spd", args.nrhs, 200 + k, dev)
+                k += 1
+                X = torch.empty((args.nrhs, n), dtype=torch.float64, device=dev).t()
+                opts = ada.make_opts()
+                work = torch.empty(ada.workspace_size(n, args.nrhs, opts), dtype=torch.uint8, device=dev)
+                torch.cuda.synchronize()
+                row = {"kind": kind, "n": n, "kappa": kappa}
+                for p in precs:
+                    for _ in range(args.warmup):
+                        ada.solve(A, B, out=X, work=work, ctx=ctx, precision=p)
+                    ts = []
+                    for _ in range(args.steps):
+                        t0 = time.perf_counter()
+                        _, r = ada.solve(A, B, out=X, work=work, ctx=ctx, precision=p)
+                        ts.append(time.perf_counter() - t0)
+                    t = float(np.median(ts))
+                    tot[p] += t
+                    worst[p] = max(worst[p], r.berr)
+                    row[p] = {"ms": round(t * 1e3, 3), "route": r.route, "refine_iters": r.refine_iters,
+                              "berr": r.berr, "rcond": r.rcond}
+                    if not (r.berr <= BERR_BAR):
+                        print(f"{kind} n={n} kappa={kappa} {p}: backward error {r.berr} above {BERR_BAR}",
+                              file=sys.stderr)
+                        sys.exit(1)
+                flops += (2.0 if kind == "dense" else 1.0) * n ** 3 / 3.0 + 2.0 * n * n * args.nrhs
+                print(json.dumps({"case": row}), flush=True)
+                rows.append(row)
+                del A, B, X, work
+                torch.cuda.empty_cache()
+    # achieved rate of the low-precision trailing update (FP32 operands) on the largest dense case
+    n = sizes[-1]
+    A, B = spectrum_system_gpu(n, kappas[0], False, args.nrhs, 999, dev)
+    X = torch.empty((args.nrhs, n), dtype=torch.float64, device=dev).t()
+    work = torch.empty(ada.workspace_size(n, args.nrhs, ada.make_opts()), dtype=torch.uint8, device=dev)
+    ada.solve(A, B, out=X, work=work, ctx=ctx, precision="fp32_ir")
+    ctx.profile_reset()
+    ctx.profile(True)
+    ada.solve(A, B, out=X, work=work, ctx=ctx, precision="fp32_ir")
+    ctx.profile(False)
+    launches, ms, fl, by = ctx.profile_read("gemm")
+    achieved = fl / (ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["mfma32"][0], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK["mfma32"][0], 5), "traffic": None, "kernel": "k_gemm_sub_f32",
+            "launches": launches, "avg_us": round(ms * 1e3 / max(1, launches), 2)}
+    nsys = len(rows)
+    out = {
+        "metric": METRIC, "value": round(nsys / tot["fp32_ir"], 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot["fp32_ir"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"mixed precision: dense and SPD U diag(s) V^T, n in {sizes}, kappa in {kappas}, "
+                               f"nrhs={args.nrhs}; one step = every system once (median of {args.steps} solves each)"},
+        "solves_per_s": {p: round(nsys / tot[p], 4) for p in precs},
+        "tflops": {p: round(flops / tot[p] / 1e12, 4) for p in precs},
+        "speedup_vs_fp64": {p: round(tot["fp64"] / tot[p], 3) for p in precs},
+        "max_berr": worst, "roofline": roof, "cpu_baseline": None, "cases": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=None, help="right-hand sides (default 1; 16 for --workload mixed)")
     ap.add_argument("--systems", default=",".join(SYSTEMS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="single", choices=("single", "batched"),
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "mixed"),
                     help="single: the five large systems; batched: many small systems in one launch per step")
     ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
     ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
+    ap.add_argument("--mixed-n", default="4096,8192,16384", help="mixed workload: orders")
+    ap.add_argument("--mixed-kappa", default="1e2,1e5,1e8", help="mixed workload: condition numbers")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32_ir"),
                     help="batched workload: FP64 factors, or FP32 factors with FP64 iterative refinement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy this many MiB device-to-device three times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.nrhs is None:
+        args.nrhs = 16 if args.workload == "mixed" else 1
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs each system on a single device; "
               "run it with --gpus 1", file=sys.stderr)
@@ -237,6 +343,8 @@ def main():
         return
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "mixed":
+        return bench_mixed(args)
     names = [s for s in args.systems.split(",") if s]
     cases = []
     for name in names:

@@ -58,9 +58,14 @@ enum { ADA_CLASS_GENERAL = 0, ADA_CLASS_BANDED = 1, ADA_CLASS_TRI_UPPER = 2, ADA
 /* solver whose x is returned */
 enum { ADA_ROUTE_NONE = 0, ADA_ROUTE_BAND_LU = 1, ADA_ROUTE_TRI = 2, ADA_ROUTE_CHOL = 3, ADA_ROUTE_LU = 4,
        ADA_ROUTE_SVD = 5 };
-/* arithmetic of the factorisation (ada_solve_batched): FP64 throughout, or FP32 factors with FP64
-   residuals and iterative refinement, falling back to FP64 when the refinement does not converge */
-enum { ADA_PREC_FP64 = 0, ADA_PREC_FP32_IR = 1 };
+/* arithmetic of the LU / Cholesky factorisation. FP64: FP64 throughout. FP32_IR, BF16_IR: a
+   factorisation in lower precision (ada_solve: the trailing-matrix updates take FP32 or BF16 operands
+   with FP32 accumulation, panels and pivot search stay FP64; ada_solve_batched: FP32_IR only, the
+   whole factorisation in FP32), then FP64 iterative refinement (FP64 residuals and corrections) until
+   the backward error reaches sqrt(n)*eps; when it stalls, grows or needs more than 30 steps, the
+   system is solved again by the FP64 route (the result's refine_iters is then negative). Triangular,
+   banded and SVD routes always run in FP64. */
+enum { ADA_PREC_FP64 = 0, ADA_PREC_FP32_IR = 1, ADA_PREC_BF16_IR = 2 };
 /* input layout */
 enum { ADA_LAYOUT_DENSE = 0, ADA_LAYOUT_BAND = 1 };
 /* why the SVD fallback ran (Section II-E): */
@@ -79,7 +84,7 @@ typedef struct {
   int32_t kl_in, ku_in;     /* stored band widths for ADA_LAYOUT_BAND */
   int32_t force_general;    /* 1: skip detection, always LU (the paper's "standard" solver, Section III) */
   int32_t want_berr;        /* 1: compute result.berr (normwise backward error) on the device */
-  int32_t precision;        /* ADA_PREC_FP64 (default) or ADA_PREC_FP32_IR (batched solves) */
+  int32_t precision;        /* ADA_PREC_* (default FP64) */
 } ada_opts;
 
 typedef struct {

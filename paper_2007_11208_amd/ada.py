@@ -20,8 +20,8 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_SINGULAR, ERR_NOMEM, ERR_HIP, ERR_FALLBACK_INFEA
 CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD = 0, 1, 2, 3, 4
 ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD = 0, 1, 2, 3, 4, 5
 LAYOUT_DENSE, LAYOUT_BAND = 0, 1
-PREC_FP64, PREC_FP32_IR = 0, 1
-PRECISIONS = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR}
+PREC_FP64, PREC_FP32_IR, PREC_BF16_IR = 0, 1, 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR, "bf16_ir": PREC_BF16_IR}
 # kernel families of the instrumentation (ADA_KF_*)
 KERNEL_FAMILIES = ("gemm", "panel", "laswp", "trsm_block", "potrf", "trsv", "gbtrf", "gbtrs", "detect", "jacobi")
 CLASS_NAMES = {0: "general", 1: "banded", 2: "tri_upper", 3: "tri_lower", 4: "sympd"}
@@ -216,7 +216,7 @@ def _result(r: Result, status: int) -> SolveResult:
 
 
 def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, want_berr=True, layout="dense",
-          kl_in=0, ku_in=0, out=None, work=None, ctx: Context | None = None, raise_on_error=True):
+          kl_in=0, ku_in=0, out=None, work=None, ctx: Context | None = None, raise_on_error=True, precision="fp64"):
     """Adaptive solve of A X = B on the GPU.
 
     A: (n, n) float64 CUDA tensor, or for layout="band" the (kl_in+ku_in+1, n)
@@ -238,7 +238,7 @@ def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, w
         raise ValueError("A must be n x n and match B")
     if lay == LAYOUT_BAND and Ac.shape[1] != n:
         raise ValueError("band storage must have n columns")
-    opts = make_opts(no_approx, rcond_threshold, lay, kl_in, ku_in, force_general, want_berr)
+    opts = make_opts(no_approx, rcond_threshold, lay, kl_in, ku_in, force_general, want_berr, precision)
     ws = workspace_size(n, nrhs, opts)
     if ws == 0:
         raise ValueError("invalid shape for the workspace query")

@@ -167,6 +167,10 @@ hipError_t launch_scatter_rows(int n, int nrhs, const int* perm, const double* S
                                const int* pred, int pred_val, hipStream_t st);
 
 // FP64 MFMA GEMM: C -= A * op(B); op(B) = B (k x n) or B^T (B is n x k); lower: only tiles meeting i >= j
+// C -= A * op(B) with FP32 (prec = ADA_PREC_FP32_IR) or BF16 (ADA_PREC_BF16_IR) operands, FP32 accumulation
+hipError_t launch_gemm_sub_lp(int prec, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
+                              bool transB, double* C, int ldc, bool lower, const int* skip_if_nonzero,
+                              hipStream_t st);
 hipError_t launch_gemm_sub(int m, int n, int k, const double* A, int lda, const double* B, int ldb, bool transB,
                            double* C, int ldc, bool lower, const int* skip_if_nonzero, hipStream_t st,
                            hipEvent_t ev0, hipEvent_t ev1);
@@ -258,6 +262,8 @@ size_t est_part_bytes();
 hipError_t launch_finalize_rcond(DevRec* rec, hipStream_t st);
 
 // residual and backward error
+// X += D (n x nrhs)
+hipError_t launch_add_to(int n, int nrhs, const double* D, int ldd, double* X, int ldx, hipStream_t st);
 hipError_t launch_resid_gemv(int n, int nrhs, const double* A, int lda, const double* B, int ldb, const double* X,
                              int ldx, double* R, int ldr, double* P, hipStream_t st);
 hipError_t launch_x_finite(int n, int nrhs, const double* X, int ldx, DevRec* rec, hipStream_t st);

@@ -201,6 +201,7 @@ struct Solve {
   int n, nrhs;
   int counter_idx = 0;
   int epoch = 0;
+  int lowp = ADA_PREC_FP64;  // operand precision of the trailing-matrix updates
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -237,6 +238,8 @@ struct Solve {
     const double fl = lower ? 2.0 * (double)k * ((double)m * (m + 1) / 2.0) : 2.0 * (double)m * nn * k;
     const double by = 8.0 * ((double)m * k + (double)nn * k + 2.0 * (lower ? (double)m * (m + 1) / 2.0 : (double)m * nn));
     HIPCHK(timed(ADA_KF_GEMM, fl, by, [&] {
+      if (lowp != ADA_PREC_FP64)
+        return launch_gemm_sub_lp(lowp, m, nn, k, A, lda, B, ldb, transB, C, ldc, lower, &rec->stop, on);
       return launch_gemm_sub(m, nn, k, A, lda, B, ldb, transB, C, ldc, lower, &rec->stop, on, nullptr, nullptr);
     }, on));
     return ADA_OK;
@@ -505,6 +508,46 @@ int backward_error_dense(Solve& s, const double* A, int lda, const double* B, in
   return ADA_OK;
 }
 
+constexpr int kMaxRefine = 30;  // refinement steps at most (as LAPACK's mixed-precision drivers)
+
+// FP64 iterative refinement of X with the factors in W (chol: L of the Cholesky route; else the LU
+// route's LU and row permutation): r = B - A X, stop when the backward error of every column is at
+// most sqrt(n) eps (converged) or has not halved since the last step, or after kMaxRefine steps;
+// otherwise X += solve(r). On return rec->berr is the backward error of X.
+int refine(Solve& s, bool chol, const double* A, int lda, const double* B, int ldb, double* X, int ldx, bool& conv,
+           int& steps) {
+  const int n = s.n, nrhs = s.nrhs, ldw = s.p.ldw;
+  const double tol = std::sqrt((double)n) * DBL_EPSILON;
+  double* R = s.at<double>(s.p.R);
+  double* T = s.at<double>(s.p.T);
+  const double* W = s.at<double>(s.p.W);
+  const int* perm = s.at<int>(s.p.perm);
+  int* stop = &s.rec->stop;
+  double prev = INFINITY;
+  conv = false;
+  for (steps = 0;; ++steps) {
+    TRY(backward_error_dense(s, A, lda, B, ldb, X, ldx));
+    TRY(s.sync_read());
+    const double eta = s.ctx->host_rec->berr;
+    if (eta <= tol) {
+      conv = true;
+      return ADA_OK;
+    }
+    if (!(eta <= 0.5 * prev) || steps == kMaxRefine) return ADA_OK;
+    prev = eta;
+    if (chol) {
+      TRY(s.trsm(W, ldw, true, false, false, R, n, nrhs, stop, 0));
+      TRY(s.trsm(W, ldw, true, true, false, R, n, nrhs, stop, 0));
+      HIPCHK(launch_add_to(n, nrhs, R, n, X, ldx, s.st));
+    } else {
+      HIPCHK(launch_gather_rows(n, nrhs, perm, R, n, T, n, stop, 0, s.st));
+      TRY(s.trsm(W, ldw, true, false, true, T, n, nrhs, stop, 0));
+      TRY(s.trsm(W, ldw, false, false, false, T, n, nrhs, stop, 0));
+      HIPCHK(launch_add_to(n, nrhs, T, n, X, ldx, s.st));
+    }
+  }
+}
+
 void fill_result(ada_result* r, const DevRec& h, int cls, int kl, int ku, int route, int chol_failed, int fallback,
                  int n) {
   memset(r, 0, sizeof(*r));
@@ -587,7 +630,8 @@ int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const doub
   ada_opts o;
   if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
   if (o.layout != ADA_LAYOUT_DENSE) return fail(ADA_ERR_ARG, "batched solves take dense input only");
-  if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR) return fail(ADA_ERR_ARG, "unknown precision");
+  if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR)
+    return fail(ADA_ERR_ARG, "batched solves take precision ADA_PREC_FP64 or ADA_PREC_FP32_IR");
   if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(ADA_ERR_ARG, "work must be 256-byte aligned");
   if (work_bytes < ada_batched_workspace_size(count)) return fail(ADA_ERR_ARG, "workspace too small");
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -729,7 +773,34 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   const int norm_mode = (cls == ADA_CLASS_SYMPD) ? 1 : 0;
   if (!band_route_from_band_layout)
     HIPCHK(launch_anorm(n, s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot), norm_mode, s.rec, st));
-  if (cls == ADA_CLASS_GENERAL) {
+  // mixed precision (LU and Cholesky routes): low-precision trailing updates, FP64 refinement; the
+  // FP64 route below runs when the factorisation fails or the refinement does not converge
+  bool mixed_done = false;
+  int refine_iters = 0;
+  if (o.precision != ADA_PREC_FP64 && (cls == ADA_CLASS_GENERAL || cls == ADA_CLASS_SYMPD)) {
+    const bool chol = cls == ADA_CLASS_SYMPD;
+    s.lowp = o.precision;
+    TRY(chol ? route_chol(s, Ad, ldad, B, ldb, X, ldx) : route_lu(s, Ad, ldad, B, ldb, X, ldx));
+    s.lowp = ADA_PREC_FP64;
+    TRY(s.sync_read());
+    if (h.timeout) return fail(ADA_ERR_HIP, "a bounded device wait timed out");
+    const bool fact_ok = chol ? h.chol_info == INT_MAX : h.info == INT_MAX;
+    bool conv = false;
+    int steps = 0;
+    if (fact_ok) TRY(refine(s, chol, Ad, ldad, B, ldb, X, ldx, conv, steps));
+    if (conv) {
+      mixed_done = true;
+      route = chol ? ADA_ROUTE_CHOL : ADA_ROUTE_LU;
+      refine_iters = steps;
+    } else {
+      refine_iters = fact_ok ? -1 - steps : -1;
+      HIPCHK(launch_init_rec(s.rec, st));
+      HIPCHK(launch_anorm(n, s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot), norm_mode, s.rec, st));
+    }
+  }
+  if (mixed_done) {
+    // x, rcond (of the low-precision factors) and the backward error come from the refinement
+  } else if (cls == ADA_CLASS_GENERAL) {
     route = ADA_ROUTE_LU;
     TRY(route_lu(s, Ad, ldad, B, ldb, X, ldx));
   } else if (cls == ADA_CLASS_SYMPD) {
@@ -769,7 +840,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
     TRY(route_band(s, G0, W, bkl, bku, B, ldb, X, ldx));
   }
   // backward error of the routed x (also flags a non-finite x)
-  if (info == 0) {
+  if (info == 0 && !mixed_done) {
     if (band_route_from_band_layout) {
       HIPCHK(launch_band_resid(n, o.kl_in, o.ku_in, nrhs, A, lda, o.ku_in, B, ldb, X, ldx, s.at<double>(p.R), n, st));
       HIPCHK(launch_berr(n, nrhs, s.at<double>(p.R), n, B, ldb, X, ldx, s.at<double>(p.percol), s.rec, st));
@@ -790,9 +861,10 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   collect_profile(ctx);
 
   fill_result(result, h, cls, kl, ku, route, chol_failed, fallback, n);
+  result->refine_iters = refine_iters;
   result->info = info;
   result->rcond = rcond;
-  result->berr = (o.want_berr || band_route_from_band_layout) && info == 0 ? h.berr : NAN;
+  result->berr = (o.want_berr || band_route_from_band_layout || mixed_done) && info == 0 ? h.berr : NAN;
   if (!fallback) return ADA_OK;
   if (o.no_approx) return fail(ADA_ERR_SINGULAR, "the fallback is due (solver failure or rcond below threshold) "
                                                  "but no_approx is set");
@@ -832,7 +904,8 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
   ada_opts o;
   if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
   if (o.layout != ADA_LAYOUT_DENSE && o.layout != ADA_LAYOUT_BAND) return fail(ADA_ERR_ARG, "unknown layout");
-  if (o.precision != ADA_PREC_FP64) return fail(ADA_ERR_ARG, "single solves take precision ADA_PREC_FP64");
+  if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR && o.precision != ADA_PREC_BF16_IR)
+    return fail(ADA_ERR_ARG, "unknown precision");
   if (n < 1 || nrhs < 1) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
   if (o.layout == ADA_LAYOUT_DENSE && lda < n) return fail(ADA_ERR_ARG, "lda < n");
   if (ldb < n || ldx < n) return fail(ADA_ERR_ARG, "ldb or ldx < n");

@@ -196,6 +196,23 @@ hipError_t launch_berr(int n, int nrhs, const double* R, int ldr, const double* 
   return hipGetLastError();
 }
 
+// X += D (n x nrhs), the correction step of iterative refinement
+__global__ void k_add_to(int n, int nrhs, const double* __restrict__ D, int ldd, double* __restrict__ X, int ldx) {
+  const size_t total = (size_t)n * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e % n, c = e / n;
+    X[i + c * ldx] += D[i + c * ldd];
+  }
+}
+
+hipError_t launch_add_to(int n, int nrhs, const double* D, int ldd, double* X, int ldx, hipStream_t st) {
+  const size_t total = (size_t)n * nrhs;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_add_to, dim3(blocks), dim3(256), 0, st, n, nrhs, D, ldd, X, ldx);
+  return hipGetLastError();
+}
+
 // x finiteness only (used when the backward error is not requested)
 __global__ void k_x_finite(int n, int nrhs, const double* __restrict__ X, int ldx, DevRec* rec) {
   const size_t total = (size_t)n * nrhs;
