@@ -44,10 +44,11 @@ extern "C" {
 /* return codes */
 enum {
   ADA_OK = 0,
+  ADA_PENDING = 1,                   /* ada_poll: the request has not completed yet */
   ADA_ERR_ARG = -1,                  /* bad n/nrhs/ld/layout/workspace, NULL pointer */
   ADA_ERR_NONFINITE = -2,            /* A or B holds NaN or Inf (rejected before any solve) */
   ADA_ERR_SINGULAR = -3,             /* fallback needed but opts.no_approx = 1; X holds the routed x */
-  ADA_ERR_NOMEM = -4,                /* host allocation failed */
+  ADA_ERR_NOMEM = -4,                /* host allocation failed, or a server request larger than its arena */
   ADA_ERR_HIP = -5,                  /* a HIP runtime call failed, or a device wait timed out */
   ADA_ERR_FALLBACK_INFEASIBLE = -6   /* SVD fallback of a band-layout system too large to expand */
 };
@@ -161,6 +162,56 @@ size_t ada_batched_workspace_size(int count);
 int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
                       double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
                       void* stream);
+
+/* ---- solve server: continuous batching over a caller-provided HBM arena ----
+ * Requests are independent systems (each solved by the method of Section II, as ada_solve or, for
+ * n <= 256 and nrhs <= 8, as ada_solve_batched). A request is admitted when its footprint fits in the
+ * arena's free space and a worker is free, while earlier requests are still running: waiting small
+ * systems are solved together by one batched launch, larger ones by solve workers that each have their
+ * own context and stream, so that their kernels overlap on the device. Fresh large requests start in
+ * arrival order; a request whose footprint cannot fit beside the server's fixed buffers is refused at
+ * submission (ADA_ERR_NOMEM). A request may keep its factors resident (keep_factor = 1); later
+ * requests that name the returned ada_factor (reuse) solve new right-hand sides with those factors
+ * only, FP64-refined when the factors were mixed precision, until ada_factor_release.
+ * Ownership: the arena, A, B and X are the caller's device memory; A and B must stay unchanged and X
+ * untouched until the request's ada_poll returns a completion. The server copies A into the arena when
+ * it keeps factors. Each server has one batch worker and `solve_workers` solve workers (host threads);
+ * its calls are thread-safe. */
+typedef struct ada_server_s* ada_server;
+typedef uint64_t ada_ticket;
+typedef uint64_t ada_factor;  /* 0 = none */
+typedef struct {
+  int32_t n, nrhs;           /* reuse: n = 0 or the factor's n; nrhs <= 8 */
+  int32_t lda, ldb, ldx;     /* column-major leading dimensions (lda unused for reuse) */
+  int32_t keep_factor;       /* 1: keep the factors resident and return them from ada_poll */
+  const double* A;           /* device, n x n (NULL for reuse) */
+  ada_factor reuse;          /* nonzero: solve with these kept factors (A unused) */
+  const double* B;           /* device, n x nrhs */
+  double* X;                 /* device, n x nrhs */
+  ada_opts opts;             /* struct_size 0 = defaults; dense layout only; reuse takes the factor's */
+} ada_request;
+
+/* arena: device memory of arena_bytes (256-byte aligned), e.g. a torch allocation; solve_workers 1..8 */
+int ada_server_create(ada_ctx ctx, void* arena, size_t arena_bytes, int solve_workers, ada_server* out);
+/* Stops the workers after the requests they are running; queued requests are dropped. */
+void ada_server_destroy(ada_server s);
+/* Arena bytes the request holds while it runs (and, with keep_factor, until released); 0 for requests
+ * the batch worker's fixed buffers serve and for reuse requests. Pure host function. */
+size_t ada_request_footprint(const ada_request* r);
+/* Queues the request and returns at once with its ticket (never waits for the device). */
+int ada_submit(ada_server s, const ada_request* r, ada_ticket* out);
+/* Waits up to timeout_us (< 0: without limit, 0: not at all) for the request. Returns ADA_PENDING if it
+ * has not completed; otherwise its status (ADA_OK or ADA_ERR_*), fills *out (and *kept with the kept
+ * factor, or 0) and retires the ticket. */
+int ada_poll(ada_server s, ada_ticket t, ada_result* out, ada_factor* kept, int64_t timeout_us);
+/* ada_poll that also reports the request's wait before it started and its latency from submission to
+ * completion, in microseconds (either pointer may be NULL). */
+int ada_poll_timed(ada_server s, ada_ticket t, ada_result* out, ada_factor* kept, int64_t timeout_us,
+                   double* queue_us, double* total_us);
+/* Frees the kept factors (after the requests that name them complete). */
+int ada_factor_release(ada_server s, ada_factor f);
+/* Arena bytes in use, requests waiting to start, factors kept. Any pointer may be NULL. */
+int ada_server_usage(ada_server s, size_t* arena_used, int* queued, int* kept_factors);
 
 /* ---- instrumentation (not part of the method) ----
  * When enabled, the library records HIP events on the solve's stream around

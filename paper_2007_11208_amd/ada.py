@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libada.so")
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_SINGULAR, ERR_NOMEM, ERR_HIP, ERR_FALLBACK_INFEASIBLE = 0, -1, -2, -3, -4, -5, -6
+PENDING = 1
 CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD = 0, 1, 2, 3, 4
 ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD = 0, 1, 2, 3, 4, 5
 LAYOUT_DENSE, LAYOUT_BAND = 0, 1
@@ -47,6 +48,12 @@ class Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("lda", ctypes.c_int32), ("ldb", ctypes.c_int32),
                 ("ldx", ctypes.c_int32), ("pad", ctypes.c_int32), ("a_off", ctypes.c_int64),
                 ("b_off", ctypes.c_int64), ("x_off", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("lda", ctypes.c_int32), ("ldb", ctypes.c_int32),
+                ("ldx", ctypes.c_int32), ("keep_factor", ctypes.c_int32), ("A", ctypes.c_void_p),
+                ("reuse", ctypes.c_uint64), ("B", ctypes.c_void_p), ("X", ctypes.c_void_p), ("opts", Opts)]
 
 
 class AdaError(RuntimeError):
@@ -88,6 +95,23 @@ def lib() -> ctypes.CDLL:
         L.ada_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.ada_profile_read.restype = i
+        u64, dp = ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)
+        L.ada_server_create.argtypes = [vp, vp, sz, i, ctypes.POINTER(vp)]
+        L.ada_server_create.restype = i
+        L.ada_server_destroy.argtypes = [vp]
+        L.ada_server_destroy.restype = None
+        L.ada_request_footprint.argtypes = [ctypes.POINTER(Request)]
+        L.ada_request_footprint.restype = sz
+        L.ada_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]
+        L.ada_submit.restype = i
+        L.ada_poll.argtypes = [vp, u64, ctypes.POINTER(Result), ctypes.POINTER(u64), ctypes.c_int64]
+        L.ada_poll.restype = i
+        L.ada_poll_timed.argtypes = [vp, u64, ctypes.POINTER(Result), ctypes.POINTER(u64), ctypes.c_int64, dp, dp]
+        L.ada_poll_timed.restype = i
+        L.ada_factor_release.argtypes = [vp, u64]
+        L.ada_factor_release.restype = i
+        L.ada_server_usage.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.ada_server_usage.restype = i
         _lib = L
     return _lib
 
@@ -328,3 +352,93 @@ def solve_batched(As, Bs, **kw):
     b.run()
     torch.cuda.synchronize()
     return b.solutions(), b.results()
+
+
+class Server:
+    """Continuous-batching solve server over a device arena (ada_server_*).
+
+    submit() queues a request and returns its ticket at once; poll() waits for it.
+    The tensors of a request are held until it has been polled to completion."""
+
+    def __init__(self, arena_bytes: int, device="cuda:0", solve_workers: int = 3, ctx: Context | None = None):
+        import torch
+        dev = torch.device(device)
+        self.device = dev
+        self.ctx = ctx or context(dev.index or 0)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        rc = lib().ada_server_create(self.ctx.handle, self.arena.data_ptr(), self.arena.numel(), int(solve_workers),
+                                     ctypes.byref(h))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+        self.handle = h
+        self._held = {}
+
+    def submit(self, A=None, B=None, X=None, *, keep=False, reuse=0, **opt_kw) -> int:
+        """A: (n, n) float64 CUDA tensor (None with reuse), B: (n,) or (n, nrhs); X: output
+        (allocated when None). Returns the ticket."""
+        import torch
+        Bc = _colmajor(B if B.dim() == 2 else B[:, None])
+        n, nrhs = Bc.shape
+        if X is None:
+            X = torch.empty((nrhs, n), dtype=torch.float64, device=Bc.device).t()
+        r = Request()
+        r.n = 0 if reuse else n
+        r.nrhs = nrhs
+        r.ldb = Bc.stride(1) if nrhs > 1 else n
+        r.ldx = X.stride(1) if nrhs > 1 else n
+        r.keep_factor = int(keep)
+        r.reuse = int(reuse)
+        r.B = Bc.data_ptr()
+        r.X = X.data_ptr()
+        Ac = None
+        if not reuse:
+            Ac = _colmajor(A)
+            r.A = Ac.data_ptr()
+            r.lda = Ac.stride(1) if n > 1 else n
+        r.opts = make_opts(**opt_kw) if opt_kw else Opts()
+        t = ctypes.c_uint64()
+        rc = lib().ada_submit(self.handle, ctypes.byref(r), ctypes.byref(t))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+        self._held[t.value] = (Ac, Bc, X)
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = -1):
+        """Returns None while pending, else (status, SolveResult, X, kept_factor, queue_us, total_us)."""
+        res = Result()
+        kept = ctypes.c_uint64()
+        q = ctypes.c_double()
+        tot = ctypes.c_double()
+        rc = lib().ada_poll_timed(self.handle, ctypes.c_uint64(ticket), ctypes.byref(res), ctypes.byref(kept),
+                                  int(timeout_us), ctypes.byref(q), ctypes.byref(tot))
+        if rc == PENDING:
+            return None
+        if ticket not in self._held:
+            raise AdaError(rc, last_error())
+        _, _, X = self._held.pop(ticket)
+        return rc, _result(res, rc), X, kept.value, q.value, tot.value
+
+    def release(self, factor: int):
+        rc = lib().ada_factor_release(self.handle, ctypes.c_uint64(factor))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+
+    def usage(self):
+        used = ctypes.c_size_t()
+        queued = ctypes.c_int()
+        kept = ctypes.c_int()
+        lib().ada_server_usage(self.handle, ctypes.byref(used), ctypes.byref(queued), ctypes.byref(kept))
+        return used.value, queued.value, kept.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ada_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

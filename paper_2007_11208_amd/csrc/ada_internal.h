@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include "ada.h"
 #include <stdint.h>
 #include <stddef.h>
@@ -219,11 +221,13 @@ hipError_t launch_gbtrf(int n, int kl, int ku, const double* GBin, double* GB, i
                         double* spec_scratch, size_t spec_doubles, hipStream_t st);
 hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv, bool trans,
                         double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
-// batched solve of many small systems (n <= 256, nrhs <= 8): one persistent launch
+// batched solve of many small systems (n <= 256, nrhs <= 8): one persistent launch of at most max_wg
+// workgroups (one per compute unit)
 size_t batched_workspace_bytes(int max_workgroups);
-int batched_workgroups(int count);
+int batched_workgroups(int count, int max_wg = 256);
 hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
-                                void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st);
+                                void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st,
+                                int max_wg = 256);
 // band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles
 enum { SW_L = 0, SW_U = 1, SW_UT = 2, SW_LT = 3 };
 constexpr int LC = 256;  // steps per chunk of the parallel band sweeps
@@ -280,5 +284,22 @@ hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, doub
 hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st);
 hipError_t launch_svd_apply(int n, int nrhs, const double* U, int ldu, const double* V, int ldv, const double* B,
                             int ldb, double* X, int ldx, double* sigma, double* T, DevRec* rec, hipStream_t st);
+
+// ---- host entry points shared by the C ABI and the solve server
+// ada_solve with the workspace planned for up to plan_nrhs right-hand sides (plan_nrhs >= nrhs), so that the
+// factors it leaves in `work` can serve later solves of up to plan_nrhs columns (solve_factored)
+int solve_internal(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,
+                   double* X, int ldx, void* work, size_t work_bytes, const ada_opts& o, ada_result* result,
+                   hipStream_t st);
+// X = A^{-1} B with the factors a completed solve_internal (same n, plan_nrhs, opts) left in `work`; A is the
+// matrix it solved (for the triangular route and the backward error); `orig` its result
+int solve_factored(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,
+                   double* X, int ldx, void* work, size_t work_bytes, const ada_opts& o, const ada_result& orig,
+                   ada_result* result, hipStream_t st);
+// the device a context is bound to
+int context_device(ada_ctx ctx);
+// the calling thread's ada_last_error() message
+void set_last_error(const std::string& msg);
+std::string last_error_string();
 
 }  // namespace ada

@@ -682,9 +682,10 @@ static void collect_profile(ada_ctx ctx) {
 
 static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
                       int ldx, void* work, size_t work_bytes, const ada_opts& o, ada_result* result,
-                      hipStream_t st) {
+                      hipStream_t st, int plan_nrhs) {
   Plan p;
-  if (!make_plan(n, nrhs, o, p)) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
+  if (plan_nrhs < nrhs) return fail(ADA_ERR_ARG, "plan_nrhs < nrhs");
+  if (!make_plan(n, plan_nrhs, o, p)) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
   if (!work || work_bytes < p.total)
     return fail(ADA_ERR_ARG, "workspace too small: need " + std::to_string(p.total) + " bytes");
   if (((uintptr_t)work & 255) != 0) return fail(ADA_ERR_ARG, "workspace must be 256-byte aligned");
@@ -912,7 +913,101 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
   std::lock_guard<std::mutex> lock(ctx->mu);
   HIPCHK(hipSetDevice(ctx->device));
   return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, o, result,
-                    static_cast<hipStream_t>(stream));
+                    static_cast<hipStream_t>(stream), nrhs);
 }
 
 }  // extern "C"
+
+namespace ada {
+
+void set_last_error(const std::string& msg) { g_err = msg; }
+int context_device(ada_ctx ctx) { return ctx ? ctx->device : -1; }
+std::string last_error_string() { return g_err; }
+
+int solve_internal(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,
+                   double* X, int ldx, void* work, size_t work_bytes, const ada_opts& o, ada_result* result,
+                   hipStream_t st) {
+  if (!ctx || !A || !B || !X || !result) return fail(ADA_ERR_ARG, "NULL context, matrix or result pointer");
+  if (n < 1 || nrhs < 1 || lda < n || ldb < n || ldx < n) return fail(ADA_ERR_ARG, "bad n, nrhs or leading dimension");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  HIPCHK(hipSetDevice(ctx->device));
+  return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, o, result, st, plan_nrhs);
+}
+
+int solve_factored(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,
+                   double* X, int ldx, void* work, size_t work_bytes, const ada_opts& o, const ada_result& orig,
+                   ada_result* result, hipStream_t st) {
+  if (!ctx || !A || !B || !X || !result) return fail(ADA_ERR_ARG, "NULL context, matrix or result pointer");
+  if (n < 1 || nrhs < 1 || nrhs > plan_nrhs || lda < n || ldb < n || ldx < n)
+    return fail(ADA_ERR_ARG, "bad n, nrhs or leading dimension for the kept factors");
+  if (o.layout != ADA_LAYOUT_DENSE) return fail(ADA_ERR_ARG, "kept factors of dense input only");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  HIPCHK(hipSetDevice(ctx->device));
+  Plan p;
+  if (!make_plan(n, plan_nrhs, o, p) || work_bytes < p.total) return fail(ADA_ERR_ARG, "workspace of the kept factors");
+  Solve s;
+  s.ctx = ctx;
+  s.st = st;
+  s.p = p;
+  s.base = static_cast<char*>(work);
+  s.rec = s.at<DevRec>(p.rec);
+  s.n = n;
+  s.nrhs = nrhs;
+  DevRec& h = *ctx->host_rec;
+  ctx->ev_used = 0;
+  ctx->pending.clear();
+  // fresh record (counters, flags, stop), then the norms from the column/row totals detection left
+  HIPCHK(launch_init_rec(s.rec, st));
+  HIPCHK(launch_fill_int(s.at<int>(p.flags), 0, (size_t)p.nflags, st));
+  const int norm_mode = orig.route == ADA_ROUTE_CHOL ? 1 : 0;
+  HIPCHK(launch_anorm(n, s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot), norm_mode, s.rec, st));
+  double* W = s.at<double>(p.W);
+  int* stop = &s.rec->stop;
+  switch (orig.route) {
+    case ADA_ROUTE_LU:
+      HIPCHK(launch_gather_rows(n, nrhs, s.at<int>(p.perm), B, ldb, X, ldx, stop, 0, st));
+      TRY(s.trsm(W, p.ldw, true, false, true, X, ldx, nrhs, stop, 0));
+      TRY(s.trsm(W, p.ldw, false, false, false, X, ldx, nrhs, stop, 0));
+      break;
+    case ADA_ROUTE_CHOL:
+      HIPCHK(launch_copy(n, nrhs, B, ldb, X, ldx, st));
+      TRY(s.trsm(W, p.ldw, true, false, false, X, ldx, nrhs, stop, 0));
+      TRY(s.trsm(W, p.ldw, true, true, false, X, ldx, nrhs, stop, 0));
+      break;
+    case ADA_ROUTE_TRI:
+      HIPCHK(launch_copy(n, nrhs, B, ldb, X, ldx, st));
+      TRY(s.trsm(A, lda, orig.cls == ADA_CLASS_TRI_LOWER, false, false, X, ldx, nrhs, stop, 0));
+      break;
+    case ADA_ROUTE_BAND_LU:
+      HIPCHK(launch_copy(n, nrhs, B, ldb, X, ldx, st));
+      TRY(band_solve(s, W, orig.kl, orig.ku, false, X, ldx, nrhs, s.at<double>(p.T), n, stop, 0));
+      break;
+    case ADA_ROUTE_SVD:
+      HIPCHK(launch_svd_apply(n, nrhs, W, n, s.at<double>(p.V), n, B, ldb, X, ldx, s.at<double>(p.sigma),
+                              s.at<double>(p.T), s.rec, st));
+      break;
+    default:
+      return fail(ADA_ERR_ARG, "no kept factors (the solve did not route)");
+  }
+  int refine_iters = 0;
+  if (orig.refine_iters > 0 && (orig.route == ADA_ROUTE_LU || orig.route == ADA_ROUTE_CHOL)) {
+    bool conv = false;
+    int steps = 0;
+    TRY(refine(s, orig.route == ADA_ROUTE_CHOL, A, lda, B, ldb, X, ldx, conv, steps));
+    refine_iters = conv ? steps : -1 - steps;
+  } else if (o.want_berr) {
+    TRY(backward_error_dense(s, A, lda, B, ldb, X, ldx));
+  } else {
+    HIPCHK(launch_x_finite(n, nrhs, X, ldx, s.rec, st));
+  }
+  TRY(s.sync_read());
+  if (h.timeout) return fail(ADA_ERR_HIP, "a bounded device wait timed out");
+  *result = orig;
+  result->refine_iters = refine_iters;
+  result->berr = (o.want_berr || orig.refine_iters > 0) ? h.berr : NAN;
+  result->status = ADA_OK;
+  if (h.x_nonfinite) return fail(ADA_ERR_NONFINITE, "the solve with the kept factors produced a non-finite x");
+  return ADA_OK;
+}
+
+}  // namespace ada

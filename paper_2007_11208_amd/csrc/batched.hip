@@ -981,14 +981,15 @@ size_t batched_workspace_bytes(int max_workgroups) {
   return 256 + (size_t)max_workgroups * kBSliceBytes;
 }
 
-int batched_workgroups(int count) {
-  int g = 256;  // one per compute unit: each holds up to 160 KB of LDS
+int batched_workgroups(int count, int max_wg) {
+  int g = max_wg < 1 ? 1 : (max_wg > 256 ? 256 : max_wg);  // one per compute unit: each holds up to 160 KB of LDS
   return count < g ? (count < 1 ? 1 : count) : g;
 }
 
 hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
-                                void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st) {
-  const int G = batched_workgroups(count);
+                                void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st,
+                                int max_wg) {
+  const int G = batched_workgroups(count, max_wg);
   if (work_bytes < batched_workspace_bytes(G)) return hipErrorInvalidValue;
   unsigned* queue = reinterpret_cast<unsigned*>(work);
   char* slices = reinterpret_cast<char*>(work) + 256;

@@ -11,6 +11,8 @@ descriptions at the sizes of the benchmark configurations.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -248,3 +250,36 @@ def batched_case(count: int, k: int = 0, n_lo: int = 8, n_hi: int = 256, nrhs_hi
             a = prescribed_spectrum(n, np.logspace(0, -15, n), g)
         out.append((kind, a, rhs_for(a, x_true(n, nrhs, g))))
     return out
+
+
+def serving_system(k: int, n_lo: int = 16, n_hi: int = 4096, nrhs_hi: int = 8):
+    """One request system of the serving configuration: n log-uniform in [n_lo, n_hi],
+    nrhs uniform in [1, nrhs_hi], the batched class mix. Returns (kind, A, B)."""
+    g = rng_for(4, k)
+    n = int(round(math.exp(g.uniform(math.log(n_lo), math.log(n_hi)))))
+    nrhs = int(g.integers(1, nrhs_hi + 1))
+    kinds = [m[0] for m in BATCH_MIX]
+    probs = np.array([m[1] for m in BATCH_MIX])
+    kind = kinds[int(g.choice(len(kinds), p=probs))]
+    if kind == "dense":
+        a = dense_general(n, g)
+    elif kind == "spd":
+        a = spd(n, g)
+    elif kind == "banded":
+        a = banded_dense(n, int(g.integers(1, 5)), int(g.integers(1, 5)), g)
+    elif kind == "triangular":
+        a = triangular(n, g, upper=bool(g.integers(0, 2)))
+    else:
+        a = prescribed_spectrum(n, np.logspace(0, -15, n), g)
+    return kind, a, rhs_for(a, x_true(n, nrhs, g))
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int = 0) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of the given rate over [0, duration)."""
+    g = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t >= duration:
+            return np.array(out)
+        out.append(t)
