@@ -303,6 +303,136 @@ def bench_mixed(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args):
+    """Poisson request stream into the solve server: requests draw a system from a seeded pool
+    (sizes log-uniform in [16, 4096], the batched class mix); a fraction reuse one of the
+    resident factorisations with a new right-hand side. Latency is submission to completion as
+    the server records it; throughput is completed requests over the span from the first
+    submission to the last completion."""
+    import threading
+    import torch
+    from paper_2007_11208_amd import ada
+    dev = torch.device("cuda:0")
+    pool = [W.serving_system(k) for k in range(args.pool)]
+    dA = [torch.from_numpy(np.asfortranarray(a)).to(dev) for _, a, _ in pool]
+    dB = [torch.from_numpy(np.asfortranarray(b)).to(dev) for _, _, b in pool]
+    free, total = torch.cuda.mem_get_info(dev)
+    arena = int(min(args.arena_gb * (1 << 30), free - (8 << 30)))
+    srv = ada.Server(arena, solve_workers=args.workers)
+    # resident factors: the first systems of the pool, kept before the stream starts
+    resident = []
+    for k in range(min(args.resident, len(pool))):
+        rc, r, _, f, _, _ = srv.poll(srv.submit(dA[k], dB[k], keep=True))
+        if rc != 0:
+            print(f"keeping factors of pool system {k} failed: {rc} {ada.last_error()}", file=sys.stderr)
+            sys.exit(1)
+        g = torch.Generator(device=dev)
+        g.manual_seed(500 + k)
+        bn = torch.randn(dB[k].shape[1], dB[k].shape[0], dtype=torch.float64, device=dev, generator=g).t()
+        resident.append((k, f, bn))
+    arrivals = W.poisson_arrivals(args.rate, args.duration, seed=4)
+    g = np.random.default_rng(44)
+    reuse = g.random(len(arrivals)) < args.reuse
+    pick_pool = g.integers(0, len(pool), len(arrivals))
+    pick_res = g.integers(0, max(1, len(resident)), len(arrivals))
+    tickets = []
+    meta = []
+    lock = threading.Lock()
+    done = []
+    sub_done = threading.Event()
+
+    def drain():
+        i = 0
+        while True:
+            with lock:
+                have = i < len(tickets)
+                t = tickets[i] if have else None
+            if not have:
+                if sub_done.is_set():
+                    with lock:
+                        if i >= len(tickets):
+                            return
+                    continue
+                time.sleep(0.0005)
+                continue
+            out = srv.poll(t, timeout_us=100000)
+            if out is None:
+                if time.perf_counter() - t0 > args.max_wait:
+                    return  # stop waiting: the rest is reported as unfinished
+                continue
+            done.append((i, out[0], out[1], out[4], out[5], time.perf_counter()))
+            i += 1
+            if i % 1000 == 0:
+                print(f"served {i} of {len(arrivals)} at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+
+    th = threading.Thread(target=drain)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th.start()
+    late = 0.0
+    for i, ta in enumerate(arrivals):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        else:
+            late = max(late, now - ta)
+        if reuse[i] and resident:
+            k, f, bn = resident[pick_res[i]]
+            t = srv.submit(None, bn, reuse=f)
+            kind = "reuse"
+            n = dA[k].shape[0]
+        else:
+            k = int(pick_pool[i])
+            t = srv.submit(dA[k], dB[k])
+            n = dA[k].shape[0]
+            kind = "batched" if n <= 256 and dB[k].shape[1] <= 8 else "single"
+        with lock:
+            tickets.append(t)
+            meta.append((kind, n, pool[k][0]))
+    sub_done.set()
+    th.join()
+    if not done:
+        print("no request completed", file=sys.stderr)
+        sys.exit(1)
+    t_end = max(d[5] for d in done)
+    span = t_end - t0
+    lat = np.array([d[4] for d in done]) * 1e-3  # ms
+    statuses = {}
+    worst = 0.0
+    by_kind = {}
+    by_class = {}
+    for (i, rc, r, q_us, tot_us, _) in done:
+        statuses[rc] = statuses.get(rc, 0) + 1
+        if rc == 0 and r.berr == r.berr:
+            worst = max(worst, r.berr)
+        kind, n, cls = meta[i]
+        by_kind.setdefault(kind, []).append(tot_us * 1e-3)
+        by_class.setdefault(r.route, []).append(tot_us * 1e-3)
+    ok_bar = sum(1 for (i, rc, r, _, _, _) in done if rc == 0 and r.berr <= BERR_BAR)
+
+    def summ(v):
+        return {"count": len(v), "p50_ms": round(pct(v, 50), 3), "p99_ms": round(pct(v, 99), 3)}
+
+    unfinished = len(arrivals) - len(done)
+    srv.close()  # drops what never started; waits for what runs
+    out = {
+        "metric": METRIC, "value": round(len(done) / span, 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(span * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson {args.rate:g} req/s for {args.duration:g} s, n log-uniform in "
+                               f"[16, 4096] (pool of {len(pool)} seeded systems), 40% dense / 30% SPD / 15% banded / "
+                               f"10% triangular / 5% condition 1e15, {args.reuse:.0%} reuse of {len(resident)} resident "
+                               f"factorisations, arena {arena / (1 << 30):.1f} GiB, {args.workers} solve workers"},
+        "offered_rate": args.rate, "requests": len(done), "unfinished": unfinished, "p50_ms": round(float(np.median(lat)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3), "by_kind": {k: summ(v) for k, v in by_kind.items()},
+        "by_route": {k: summ(v) for k, v in by_class.items()}, "status_counts": statuses,
+        "met_berr_bar": ok_bar, "max_berr": worst, "submit_lag_ms": round(late * 1e3, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,11 +441,20 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None, help="right-hand sides (default 1; 16 for --workload mixed)")
     ap.add_argument("--systems", default=",".join(SYSTEMS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="single", choices=("single", "batched", "mixed"),
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "mixed", "serving"),
                     help="single: the five large systems; batched: many small systems in one launch per step")
     ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
     ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
     ap.add_argument("--mixed-n", default="4096,8192,16384", help="mixed workload: orders")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: offered requests per second")
+    ap.add_argument("--duration", type=float, default=1.0, help="serving: seconds of arrivals")
+    ap.add_argument("--max-wait", type=float, default=120.0,
+                    help="serving: stop waiting for completions this many seconds after the first arrival")
+    ap.add_argument("--pool", type=int, default=64, help="serving: distinct seeded systems")
+    ap.add_argument("--resident", type=int, default=16, help="serving: resident factorisations")
+    ap.add_argument("--reuse", type=float, default=0.3, help="serving: fraction of requests that reuse one")
+    ap.add_argument("--workers", type=int, default=3, help="serving: solve workers")
+    ap.add_argument("--arena-gb", type=float, default=200.0, help="serving: admission cap (GiB)")
     ap.add_argument("--mixed-kappa", default="1e2,1e5,1e8", help="mixed workload: condition numbers")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32_ir"),
                     help="batched workload: FP64 factors, or FP32 factors with FP64 iterative refinement")
@@ -345,6 +484,8 @@ def main():
         return bench_batched(args)
     if args.workload == "mixed":
         return bench_mixed(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     names = [s for s in args.systems.split(",") if s]
     cases = []
     for name in names:

@@ -282,8 +282,23 @@ hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, in
 hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, DevRec* rec,
                                hipStream_t st);
 hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st);
-hipError_t launch_svd_apply(int n, int nrhs, const double* U, int ldu, const double* V, int ldv, const double* B,
-                            int ldb, double* X, int ldx, double* sigma, double* T, DevRec* rec, hipStream_t st);
+// x = P sum over kept j of Ut_j (W_j^T C) / sigma_j^2, sigma_j = ||Ut_j|| (after the Jacobi on R^T: Ut = R^T W, W
+// the accumulated rotations, C = Q^T B, P the column order, row i of the sum goes to row perm[i] of X; perm NULL:
+// identity); also sets rec->sigma_max and rec->rank
+hipError_t launch_svd_apply(int n, int nrhs, const double* Ut, int ldu, const double* W, int ldw, const double* C,
+                            int ldc, double* X, int ldx, const int* perm, double* sigma, double* T, DevRec* rec,
+                            hipStream_t st);
+// Q = A P with the columns of A in order of decreasing 2-norm (ties to the lower index): perm[k] = source column
+// of Q's column k; norm: n doubles of scratch
+hipError_t launch_order_columns(int n, const double* A, int lda, double* norm, int* perm, double* Q, int ldq,
+                                hipStream_t st);
+// Householder QR of Q in place (reflectors below the diagonal, tau[n]), applying Q^T to the ncol columns of C
+hipError_t launch_house_qr(int n, double* Q, int ldq, double* tau, double* C, int ldc, int ncol, hipStream_t st);
+// C = Q^T C with the reflectors launch_house_qr left
+hipError_t launch_house_qt(int n, const double* Q, int ldq, const double* tau, double* C, int ldc, int ncol,
+                           hipStream_t st);
+// X = R^T from the upper triangle of Q
+hipError_t launch_rt(int n, const double* Q, int ldq, double* X, int ldx, hipStream_t st);
 
 // ---- host entry points shared by the C ABI and the solve server
 // ada_solve with the workspace planned for up to plan_nrhs right-hand sides (plan_nrhs >= nrhs), so that the

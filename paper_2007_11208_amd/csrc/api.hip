@@ -44,7 +44,7 @@ struct Plan {
   size_t total = 0;
   // offsets (bytes)
   size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, slot_val, slot_row,
-      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec, estpart;
+      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec, estpart, Q, tau;
   size_t bsc_doubles, gbspec_doubles;
   int n, nrhs, ldw, T64, nflags;
   bool dense, band, band_dense;
@@ -123,6 +123,8 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     p.V = take(cur, (N > 64 ? N : 64) * N * 8);
     if (!(p.band && !p.dense)) p.gb0 = p.V;  // the Jacobi V is not in use on the band route
     p.sigma = take(cur, N * 8);
+    p.Q = take(cur, N * N * 8);  // Householder reflectors of the SVD route's QR preconditioner
+    p.tau = take(cur, N * 8);
     p.slot_val = take(cur, 2 * 64 * 8);
     p.slot_row = take(cur, 2 * 64 * 4);
     p.slot_rows = take(cur, 2 * 64 * 128 * 8);
@@ -475,7 +477,16 @@ int route_band(Solve& s, const double* GB0, double* GB, int kl, int ku, const do
 int route_svd(Solve& s, const double* A, int lda, const double* B, int ldb, double* X, int ldx, double* Wbuf,
               double* Vbuf, double* Tbuf) {
   const int n = s.n;
-  HIPCHK(launch_copy(n, n, A, lda, Wbuf, n, s.st));
+  // A P = Q R (columns by decreasing norm); C = Q^T B (in R's slot: the residual is formed after the solve);
+  // Jacobi on R^T with V = I
+  double* Q = s.at<double>(s.p.Q);
+  double* tau = s.at<double>(s.p.tau);
+  double* C = s.at<double>(s.p.R);
+  int* perm = s.at<int>(s.p.perm);
+  HIPCHK(launch_order_columns(n, A, lda, s.at<double>(s.p.sigma), perm, Q, n, s.st));
+  HIPCHK(launch_copy(n, s.nrhs, B, ldb, C, n, s.st));
+  HIPCHK(launch_house_qr(n, Q, n, tau, C, n, s.nrhs, s.st));
+  HIPCHK(launch_rt(n, Q, n, Wbuf, n, s.st));
   HIPCHK(launch_set_identity(n, Vbuf, n, s.st));
   if (n <= kJacobiSmall) {
     HIPCHK(launch_jacobi_small(n, Wbuf, n, Vbuf, n, 30, s.rec, s.st));
@@ -491,7 +502,8 @@ int route_svd(Solve& s, const double* A, int lda, const double* B, int ldb, doub
     s.ctx->host_rec->sweeps = sweeps;
     HIPCHK(hipMemcpyAsync(&s.rec->sweeps, &s.ctx->host_rec->sweeps, sizeof(int), hipMemcpyHostToDevice, s.st));
   }
-  HIPCHK(launch_svd_apply(n, s.nrhs, Wbuf, n, Vbuf, n, B, ldb, X, ldx, s.at<double>(s.p.sigma), Tbuf, s.rec, s.st));
+  HIPCHK(launch_svd_apply(n, s.nrhs, Wbuf, n, Vbuf, n, C, n, X, ldx, perm, s.at<double>(s.p.sigma), Tbuf, s.rec,
+                          s.st));
   return ADA_OK;
 }
 
@@ -982,10 +994,14 @@ int solve_factored(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A,
       HIPCHK(launch_copy(n, nrhs, B, ldb, X, ldx, st));
       TRY(band_solve(s, W, orig.kl, orig.ku, false, X, ldx, nrhs, s.at<double>(p.T), n, stop, 0));
       break;
-    case ADA_ROUTE_SVD:
-      HIPCHK(launch_svd_apply(n, nrhs, W, n, s.at<double>(p.V), n, B, ldb, X, ldx, s.at<double>(p.sigma),
-                              s.at<double>(p.T), s.rec, st));
+    case ADA_ROUTE_SVD: {
+      double* C = s.at<double>(p.R);
+      HIPCHK(launch_copy(n, nrhs, B, ldb, C, n, st));
+      HIPCHK(launch_house_qt(n, s.at<double>(p.Q), n, s.at<double>(p.tau), C, n, nrhs, st));
+      HIPCHK(launch_svd_apply(n, nrhs, W, n, s.at<double>(p.V), n, C, n, X, ldx, s.at<int>(p.perm),
+                              s.at<double>(p.sigma), s.at<double>(p.T), s.rec, st));
       break;
+    }
     default:
       return fail(ADA_ERR_ARG, "no kept factors (the solve did not route)");
   }

@@ -523,6 +523,45 @@ __device__ int b_jacobi(const BCtx& c, double* U, double* V, int n, int max_swee
 }
 
 // ---------------------------------------------------------------- the solve of one system
+// Householder QR of M (n x n, ld n) in place, reflectors below the diagonal, tau[n] (LDS); the same
+// reflectors applied to the ncol columns of C (ld ldc). Reflector k maps M[k.., k] to (beta, 0, ...):
+// beta = -sign(alpha) ||M[k.., k]||, tau_k = (beta - alpha) / beta, v = (1, M[k+1.., k] / (alpha - beta));
+// tau_k = 0 when the part below the diagonal is zero. Columns are updated one per wave.
+__device__ void b_house_qr(const BCtx& c, double* M, int n, double* tau, double* C, int ldc, int ncol) {
+  for (int k = 0; k < n; ++k) {
+    double* col = M + (size_t)k * n;
+    double s = 0.0;
+    for (int i = k + 1 + c.t; i < n; i += BT) s = fma(col[i], col[i], s);
+    const double sig2 = b_sum(c, s);
+    const double alpha = col[k];
+    double tk = 0.0, sc = 1.0, beta = alpha;
+    if (sig2 != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+      tk = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    __syncthreads();  // every thread has read alpha
+    for (int i = k + 1 + c.t; i < n; i += BT) col[i] *= sc;
+    if (c.t == 0) {
+      col[k] = beta;
+      tau[k] = tk;
+    }
+    __syncthreads();
+    if (tk != 0.0) {
+      const int ncols = (n - k - 1) + ncol;
+      for (int q = c.w; q < ncols; q += BT / 64) {
+        double* a = q < n - k - 1 ? M + (size_t)(k + 1 + q) * n : C + (size_t)(q - (n - k - 1)) * ldc;
+        double dd = 0.0;
+        for (int i = k + 1 + c.lane; i < n; i += 64) dd = fma(col[i], a[i], dd);
+        dd = (wave_sum(dd) + a[k]) * tk;
+        if (c.lane == 0) a[k] -= dd;
+        for (int i = k + 1 + c.lane; i < n; i += 64) a[i] = fma(-dd, col[i], a[i]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __restrict__ desc,
                                                       const double* __restrict__ Apool,
                                                       const double* __restrict__ Bpool, double* Xpool,
@@ -896,13 +935,36 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       }
     }
     if (svd) {
-      // ---- S8: one-sided Jacobi SVD of the original A, min-norm least squares
+      // ---- S8: SVD of the original A, min-norm least squares. A P = Q R (columns by decreasing norm,
+      // Householder, reflectors in gV), C = Q^T B (gX), then one-sided Jacobi on R^T (gW) with V = I:
+      // R^T W = U~, sigma_j = ||u~_j||, x = P sum over kept j of u~_j (w_j^T C) / sigma_j^2
       res.route = ADA_ROUTE_SVD;
+      double* C = gX;              // BNM x BRM
+      double* tau = lds;           // n (the LDS matrix region is free here)
+      // columns by decreasing norm: perm[k] = source column of position k (ties to the lower index)
+      double* cn = sbuf;  // n
+      for (int j = c.t; j < n; j += BT) {
+        double q = 0.0;
+        for (int i = 0; i < n; ++i) q = fma(A[i + (size_t)j * d.lda], A[i + (size_t)j * d.lda], q);
+        cn[j] = sqrt(q);
+      }
+      __syncthreads();
+      for (int j = c.t; j < n; j += BT) {
+        int r = 0;
+        for (int k = 0; k < n; ++k) r += (cn[k] > cn[j] || (cn[k] == cn[j] && k < j)) ? 1 : 0;
+        perm[r] = j;
+      }
+      __syncthreads();
+      for (int e = c.t; e < n * n; e += BT) gV[e] = A[e % n + (size_t)perm[e / n] * d.lda];
+      for (int e = c.t; e < n * nr; e += BT) C[e % n + (size_t)(e / n) * BNM] = B[e % n + (size_t)(e / n) * d.ldb];
+      __syncthreads();
+      b_house_qr(c, gV, n, tau, C, BNM, nr);
       for (int e = c.t; e < n * n; e += BT) {
         const int i = e % n, j = e / n;
-        gW[e] = A[i + (size_t)j * d.lda];
-        gV[e] = (i == j) ? 1.0 : 0.0;
+        gW[e] = i >= j ? gV[j + (size_t)i * n] : 0.0;
       }
+      __syncthreads();
+      for (int e = c.t; e < n * n; e += BT) gV[e] = (e % n == e / n) ? 1.0 : 0.0;
       __syncthreads();
       res.sweeps = b_jacobi(c, gW, gV, n, 30);
       // sigma_j = ||u_j||, cut at eps * sigma_max
@@ -921,13 +983,13 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       for (int j = c.t; j < n; j += BT) keep += sig[j] > cut ? 1 : 0;
       keep = (int)b_sum(c, (double)keep);
       res.rank = keep;
-      // T = diag(1/sigma^2) U^T B for kept j, then X = V T
-      double* T = gX;  // BNM x BRM
+      // T = diag(1/sigma^2) W^T C for kept j, then X = U~ T
+      double* T = gX + (size_t)BNM * BRM;  // BNM x BRM
       for (int e = c.t; e < n * nr; e += BT) {
         const int j = e % n, r = e / n;
         double s = 0.0;
         if (sig[j] > cut) {
-          for (int i = 0; i < n; ++i) s = fma(gW[i + (size_t)j * n], B[i + (size_t)r * d.ldb], s);
+          for (int i = 0; i < n; ++i) s = fma(gV[i + (size_t)j * n], C[i + (size_t)r * BNM], s);
           s = s / (sig[j] * sig[j]);
         }
         T[j + (size_t)r * BNM] = s;
@@ -936,8 +998,8 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       for (int e = c.t; e < n * nr; e += BT) {
         const int i = e % n, r = e / n;
         double s = 0.0;
-        for (int j = 0; j < n; ++j) s = fma(gV[i + (size_t)j * n], T[j + (size_t)r * BNM], s);
-        X[i + (size_t)r * d.ldx] = s;
+        for (int j = 0; j < n; ++j) s = fma(gW[i + (size_t)j * n], T[j + (size_t)r * BNM], s);
+        X[perm[i] + (size_t)r * d.ldx] = s;
       }
       __syncthreads();
     }

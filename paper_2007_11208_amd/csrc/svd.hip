@@ -1,10 +1,16 @@
 // SVD-based minimum-norm least-squares fallback (Section II-E) by one-sided
-// (Hestenes) Jacobi on the columns of U (a copy of A), with V accumulating the
-// rotations. Pairs are visited in round-robin (tournament) order, so the
-// n/2 pairs of a round are disjoint and are rotated in parallel. A pair is
-// rotated when |u_p^T u_q| > n*eps*||u_p|| ||u_q||, with Rutishauser's
-// formulas. After convergence sigma_j = ||u_j||, and
-// x = sum_{sigma_j > eps*sigma_max} v_j (u_j^T b) / sigma_j^2.
+// (Hestenes) Jacobi with V accumulating the rotations. Pairs are visited in
+// round-robin (tournament) order, so the n/2 pairs of a round are disjoint and
+// are rotated in parallel. A pair is rotated when
+// |u_p^T u_q| > n*eps*||u_p|| ||u_q||, with Rutishauser's formulas.
+//
+// Preconditioning (Drmac and Veselic's QR-preconditioned one-sided Jacobi):
+// the columns of A are ordered by decreasing norm (A P), A P = Q R by
+// Householder reflectors, and the Jacobi runs on R^T, whose columns are graded:
+// the sweeps drop from the cap of 30 (dense log-spaced spectra, triangular
+// matrices with N(0,1) entries) to about 10. With R^T W = U~ (columns of norm
+// sigma_j): A P = (Q W) Sigma (U~ Sigma^{-1})^T, so
+// x = P sum_{sigma_j > eps*sigma_max} u~_j (w_j^T Q^T b) / sigma_j^2.
 #include "ada_internal.h"
 
 namespace ada {
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(256) void k_utb(int n, int nrhs, const double* U, i
 
 // X = V T, eight right-hand sides per pass
 __global__ __launch_bounds__(256) void k_vt(int n, int nrhs, int c0, const double* V, int ldv, const double* T,
-                                            double* X, int ldx) {
+                                            double* X, int ldx, const int* perm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   __shared__ double st[64][8];
   double acc[8];
@@ -231,17 +237,140 @@ __global__ __launch_bounds__(256) void k_vt(int n, int nrhs, int c0, const doubl
       }
     }
   }
-  if (i < n)
-    for (int c = 0; c < nc; ++c) X[(size_t)i + (size_t)(c0 + c) * ldx] = acc[c];
+  if (i < n) {
+    const int row = perm ? perm[i] : i;
+    for (int c = 0; c < nc; ++c) X[(size_t)row + (size_t)(c0 + c) * ldx] = acc[c];
+  }
 }
 
-hipError_t launch_svd_apply(int n, int nrhs, const double* U, int ldu, const double* V, int ldv, const double* B,
-                            int ldb, double* X, int ldx, double* sigma, double* T, DevRec* rec, hipStream_t st) {
-  hipLaunchKernelGGL(k_colnorms, dim3(n), dim3(256), 0, st, n, U, ldu, sigma);
+hipError_t launch_svd_apply(int n, int nrhs, const double* Ut, int ldu, const double* W, int ldw, const double* C,
+                            int ldc, double* X, int ldx, const int* perm, double* sigma, double* T, DevRec* rec,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorms, dim3(n), dim3(256), 0, st, n, Ut, ldu, sigma);
   hipLaunchKernelGGL(k_sigma_stats, dim3(1), dim3(1024), 0, st, n, sigma, rec);
-  hipLaunchKernelGGL(k_utb, dim3(n), dim3(256), 0, st, n, nrhs, U, ldu, B, ldb, sigma, rec, T);
+  hipLaunchKernelGGL(k_utb, dim3(n), dim3(256), 0, st, n, nrhs, W, ldw, C, ldc, sigma, rec, T);
   for (int c0 = 0; c0 < nrhs; c0 += 8)
-    hipLaunchKernelGGL(k_vt, dim3((n + 255) / 256), dim3(256), 0, st, n, nrhs, c0, V, ldv, T, X, ldx);
+    hipLaunchKernelGGL(k_vt, dim3((n + 255) / 256), dim3(256), 0, st, n, nrhs, c0, Ut, ldu, T, X, ldx, perm);
+  return hipGetLastError();
+}
+
+// ---- column order by decreasing norm: perm[k] = the column of A that goes to position k (ties to the
+// lower index), then Q = A P
+__global__ void k_norm_rank(int n, const double* norm, int* perm) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double s = norm[j];
+  int r = 0;
+  for (int k = 0; k < n; ++k) {
+    const double t = norm[k];
+    r += (t > s || (t == s && k < j)) ? 1 : 0;
+  }
+  perm[r] = j;
+}
+
+__global__ void k_gather_cols(int n, const double* A, int lda, const int* perm, double* Q, int ldq) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), k = (int)(e / n);
+    Q[(size_t)i + (size_t)k * ldq] = A[(size_t)i + (size_t)perm[k] * lda];
+  }
+}
+
+hipError_t launch_order_columns(int n, const double* A, int lda, double* norm, int* perm, double* Q, int ldq,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorms, dim3(n), dim3(256), 0, st, n, A, lda, norm);
+  hipLaunchKernelGGL(k_norm_rank, dim3((n + 255) / 256), dim3(256), 0, st, n, norm, perm);
+  size_t total = (size_t)n * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_gather_cols, dim3(blocks), dim3(256), 0, st, n, A, lda, perm, Q, ldq);
+  return hipGetLastError();
+}
+
+// ---- Householder QR (the preconditioner)
+// Reflector k: H_k = I - tau_k v v^T with v = (1, v_{k+1..n-1}) stored below the diagonal of column k,
+// chosen so that H_k maps Q[k..n-1, k] to (beta, 0, ..., 0); beta = -sign(alpha) ||Q[k..n-1, k]||,
+// tau_k = (beta - alpha) / beta, v_i = Q[i, k] / (alpha - beta); tau_k = 0 (H_k = I) when the part
+// below the diagonal is zero.
+__global__ __launch_bounds__(256) void k_house_gen(int n, int k, double* Q, int ldq, double* tau) {
+  double* col = Q + (size_t)k * ldq;
+  double s = 0.0;
+  for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) s = fma(col[i], col[i], s);
+  s = wave_sum(s);
+  __shared__ double sh[4];
+  __shared__ double s_scale;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double sig2 = sh[0] + sh[1] + sh[2] + sh[3];
+    const double alpha = col[k];
+    if (sig2 == 0.0) {
+      tau[k] = 0.0;
+      s_scale = 1.0;
+    } else {
+      const double beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+      tau[k] = (beta - alpha) / beta;
+      s_scale = 1.0 / (alpha - beta);
+      col[k] = beta;
+    }
+  }
+  __syncthreads();
+  const double sc = s_scale;
+  for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) col[i] *= sc;
+}
+
+// apply H_k to columns k+1..n-1 of Q (when with_q) and to the ncol columns of C; one wave per column
+__global__ __launch_bounds__(256) void k_house_apply(int n, int k, const double* Q, int ldq, double* Qw, int with_q,
+                                                     const double* tau, double* C, int ldc, int ncol) {
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nq = with_q ? n - k - 1 : 0;
+  if (col >= nq + ncol) return;
+  const double t = tau[k];
+  if (t == 0.0) return;
+  double* a = col < nq ? Qw + (size_t)(k + 1 + col) * ldq : C + (size_t)(col - nq) * ldc;
+  const double* v = Q + (size_t)k * ldq;
+  double d = 0.0;
+  for (int i = k + 1 + lane; i < n; i += 64) d = fma(v[i], a[i], d);
+  d = wave_sum(d) + a[k];
+  d *= t;
+  if (lane == 0) a[k] -= d;
+  for (int i = k + 1 + lane; i < n; i += 64) a[i] = fma(-d, v[i], a[i]);
+}
+
+// X = R^T (R: upper triangle of Q), zero above the diagonal
+__global__ void k_rt(int n, const double* Q, int ldq, double* X, int ldx) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    X[(size_t)i + (size_t)j * ldx] = i >= j ? Q[(size_t)j + (size_t)i * ldq] : 0.0;
+  }
+}
+
+hipError_t launch_house_qr(int n, double* Q, int ldq, double* tau, double* C, int ldc, int ncol, hipStream_t st) {
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_house_gen, dim3(1), dim3(256), 0, st, n, k, Q, ldq, tau);
+    const int cols = (n - k - 1) + ncol;
+    if (cols > 0)
+      hipLaunchKernelGGL(k_house_apply, dim3((cols + 3) / 4), dim3(256), 0, st, n, k, Q, ldq, Q, 1, tau, C, ldc,
+                         ncol);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_house_qt(int n, const double* Q, int ldq, const double* tau, double* C, int ldc, int ncol,
+                           hipStream_t st) {
+  for (int k = 0; k < n; ++k)
+    hipLaunchKernelGGL(k_house_apply, dim3((ncol + 3) / 4), dim3(256), 0, st, n, k, Q, ldq, nullptr, 0, tau, C, ldc,
+                       ncol);
+  return hipGetLastError();
+}
+
+hipError_t launch_rt(int n, const double* Q, int ldq, double* X, int ldx, hipStream_t st) {
+  size_t total = (size_t)n * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_rt, dim3(blocks), dim3(256), 0, st, n, Q, ldq, X, ldx);
   return hipGetLastError();
 }
 
