@@ -168,8 +168,10 @@ int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const doub
  * n <= 256 and nrhs <= 8, as ada_solve_batched). A request is admitted when its footprint fits in the
  * arena's free space and a worker is free, while earlier requests are still running: waiting small
  * systems are solved together by one batched launch, larger ones by solve workers that each have their
- * own context and stream, so that their kernels overlap on the device. Fresh large requests start in
- * arrival order; a request whose footprint cannot fit beside the server's fixed buffers is refused at
+ * own context and stream, so that their kernels overlap on the device. Requests that reuse kept factors
+ * start first; other requests start in arrival order, except that with two or more solve workers the
+ * first of them takes only requests of order <= 1024 (a fast lane beside long factorisations and SVD
+ * fallbacks). A request whose footprint cannot fit beside the server's fixed buffers is refused at
  * submission (ADA_ERR_NOMEM). A request may keep its factors resident (keep_factor = 1); later
  * requests that name the returned ada_factor (reuse) solve new right-hand sides with those factors
  * only, FP64-refined when the factors were mixed precision, until ada_factor_release.

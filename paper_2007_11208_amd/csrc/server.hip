@@ -40,6 +40,7 @@ constexpr int kSmallRhs = 8;       // and nrhs <= 8
 constexpr int kPlanRhs = 8;        // kept factors serve up to this many right-hand sides per request
 constexpr int kMaxBatch = 16384;   // systems per batched launch
 constexpr int kBatchWg = 128;      // batched launches use half the compute units; single solves get the rest
+constexpr int kFastN = 1024;       // the fast-lane solve worker takes fresh solves up to this order
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -220,31 +221,36 @@ void batch_worker(ada_server s, int w) {
   }
 }
 
-// first queued large request that can start: a fresh solve whose workspace fits, or a reuse whose
-// factors are idle; requests are taken in arrival order, and a fresh solve that does not fit holds
-// back the fresh solves behind it (no starvation of large requests)
-Job* take_large(ada_server s) {
-  bool fresh_blocked = false;
+// next request for a solve worker: first a reuse whose factors are idle (only triangular solves: it
+// never waits behind factorisations), then the first fresh solve in arrival order whose workspace fits;
+// a fresh solve that does not fit holds back the fresh solves behind it (no starvation of large
+// requests). The fast-lane worker takes fresh solves of order <= kFastN only, so that small and medium
+// requests keep moving while the other workers run long factorisations or SVD fallbacks.
+Job* take_large(ada_server s, bool fast_lane) {
   for (auto it = s->large_q.begin(); it != s->large_q.end(); ++it) {
     Job* j = *it;
-    if (j->kind == JOB_REUSE) {
-      Factor* f = s->factors.at(j->req.reuse);
-      if (f->busy) continue;
-      f->busy = true;
-      s->large_q.erase(it);
-      return j;
-    }
-    if (fresh_blocked) continue;
+    if (j->kind != JOB_REUSE) continue;
+    Factor* f = s->factors.at(j->req.reuse);
+    if (f->busy) continue;
+    f->busy = true;
+    s->large_q.erase(it);
+    return j;
+  }
+  for (auto it = s->large_q.begin(); it != s->large_q.end(); ++it) {
+    Job* j = *it;
+    if (j->kind == JOB_REUSE) continue;
+    if (fast_lane && j->req.n > kFastN) continue;
     if (s->arena.alloc(j->bytes, j->off)) {
       s->large_q.erase(it);
       return j;
     }
-    fresh_blocked = true;
+    return nullptr;
   }
   return nullptr;
 }
 
 void solve_worker(ada_server s, int w) {
+  const bool fast_lane = w == 1 && s->ctxs.size() > 2;  // with two or more solve workers, the first is the fast lane
   ada_ctx ctx = s->ctxs[w];
   hipStream_t st = s->streams[w];
   hipSetDevice(s->device);
@@ -252,7 +258,7 @@ void solve_worker(ada_server s, int w) {
     Job* j = nullptr;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || (j = take_large(s)) != nullptr; });
+      s->cv_work.wait(lk, [&] { return s->stop || (j = take_large(s, fast_lane)) != nullptr; });
       if (s->stop && !j) return;
       j->state = RUNNING;
       j->t_start = Clock::now();
