@@ -158,7 +158,11 @@ size_t ada_batched_workspace_size(int count);
  * no_approx, rcond_threshold, force_general, want_berr apply to every
  * system); d_results: device array of count results, filled with each
  * system's status. Asynchronous: returns once the work is enqueued on
- * `stream`. Returns ADA_ERR_ARG for invalid arguments (nothing enqueued). */
+ * `stream`; it enqueues kernels only (no host synchronisation, no memset,
+ * no allocation), so it may be captured into a HIP graph and replayed.
+ * Systems are taken largest first (a device-side ordering by n); each
+ * system's result does not depend on the others in the batch.
+ * Returns ADA_ERR_ARG for invalid arguments (nothing enqueued). */
 int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
                       double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
                       void* stream);

@@ -223,7 +223,7 @@ hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int l
                         double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
 // batched solve of many small systems (n <= 256, nrhs <= 8): one persistent launch of at most max_wg
 // workgroups (one per compute unit)
-size_t batched_workspace_bytes(int max_workgroups);
+size_t batched_workspace_bytes(int count, int max_workgroups);
 int batched_workgroups(int count, int max_wg = 256);
 hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
                                 void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st,

@@ -629,7 +629,7 @@ size_t ada_workspace_size(int n, int nrhs, const ada_opts* opts) {
 
 size_t ada_batched_workspace_size(int count) {
   if (count < 1) return 0;
-  return batched_workspace_bytes(batched_workgroups(count));
+  return batched_workspace_bytes(count, batched_workgroups(count));
 }
 
 int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,

@@ -566,7 +566,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
                                                       const double* __restrict__ Apool,
                                                       const double* __restrict__ Bpool, double* Xpool,
                                                       char* work, ada_opts o, ada_result* results,
-                                                      unsigned* queue) {
+                                                      unsigned* queue, const int* __restrict__ order) {
   extern __shared__ double lds[];  // BNL * BNL matrix, then BNM * BRM vector buffer
   __shared__ double s_red[8];
   __shared__ int s_ired[8];
@@ -591,7 +591,8 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     const int idx = s_idx;
     __syncthreads();
     if (idx >= count) break;
-    const BDesc d = desc[idx];
+    const int sys = order[idx];  // largest systems first
+    const BDesc d = desc[sys];
     ada_result res;
     res.cls = ADA_CLASS_GENERAL;
     res.kl = -1;
@@ -610,7 +611,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     const int n = d.n, nr = d.nrhs;
     if (n < 1 || n > BNM || nr < 1 || nr > BRM || d.lda < n || d.ldb < n || d.ldx < n) {
       res.status = ADA_ERR_ARG;
-      if (c.t == 0) results[idx] = res;
+      if (c.t == 0) results[sys] = res;
       continue;
     }
     const double* A = Apool + d.a_off;
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     nf = b_or(c, nf);  // (its barriers also publish M)
     if (nf) {
       res.status = ADA_ERR_NONFINITE;
-      if (c.t == 0) results[idx] = res;
+      if (c.t == 0) results[sys] = res;
       continue;
     }
     int klj = 0, kuj = 0;
@@ -1032,15 +1033,42 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       }
       res.berr = nan ? __longlong_as_double(0x7ff8000000000000LL) : worst;
     }
-    if (c.t == 0) results[idx] = res;
+    if (c.t == 0) results[sys] = res;
     __syncthreads();
   }
 }
 
-__global__ void k_queue_zero(unsigned* q) { *q = 0u; }
+// order[] = the systems by decreasing n (a counting sort; systems outside the kernel's limits last), so
+// that the persistent workgroups take the longest systems first and the launch does not end on a tail of
+// large systems picked up late. The order among systems of equal n is arbitrary: each system's result does
+// not depend on when or where it runs. Also zeroes the queue counter. One workgroup.
+__global__ __launch_bounds__(1024) void k_batch_order(int count, const BDesc* __restrict__ desc, int* order,
+                                                      unsigned* queue) {
+  __shared__ int cnt[BNM + 1];
+  for (int b = threadIdx.x; b <= BNM; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  auto bin_of = [&](int i) {
+    const int n = desc[i].n;
+    return (n >= 1 && n <= BNM) ? BNM - n : BNM;
+  };
+  for (int i = threadIdx.x; i < count; i += blockDim.x) atomicAdd(&cnt[bin_of(i)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int b = 0; b <= BNM; ++b) {
+      const int c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+    *queue = 0u;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) order[atomicAdd(&cnt[bin_of(i)], 1)] = i;
+}
 
-size_t batched_workspace_bytes(int max_workgroups) {
-  return 256 + (size_t)max_workgroups * kBSliceBytes;
+size_t batched_workspace_bytes(int count, int max_workgroups) {
+  const size_t order = ((size_t)count * 4 + 255) / 256 * 256;
+  return 256 + order + (size_t)max_workgroups * kBSliceBytes;
 }
 
 int batched_workgroups(int count, int max_wg) {
@@ -1052,16 +1080,17 @@ hipError_t launch_solve_batched(int count, const void* desc, const double* A, co
                                 void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st,
                                 int max_wg) {
   const int G = batched_workgroups(count, max_wg);
-  if (work_bytes < batched_workspace_bytes(G)) return hipErrorInvalidValue;
+  if (count < 1 || work_bytes < batched_workspace_bytes(count, G)) return hipErrorInvalidValue;
   unsigned* queue = reinterpret_cast<unsigned*>(work);
-  char* slices = reinterpret_cast<char*>(work) + 256;
+  int* order = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + 256);
+  char* slices = reinterpret_cast<char*>(work) + 256 + ((size_t)count * 4 + 255) / 256 * 256;
   const size_t lds = sizeof(double) * ((size_t)BNL * BNL + (size_t)BNM * BRM);
   static size_t done = 0;
   hipError_t e = ensure_lds((const void*)k_solve_batched, lds, done);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_queue_zero, dim3(1), dim3(1), 0, st, queue);
+  hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, count, (const BDesc*)desc, order, queue);
   hipLaunchKernelGGL(k_solve_batched, dim3(G), dim3(BT), lds, st, count, (const BDesc*)desc, A, B, X, slices, o,
-                     (ada_result*)results, queue);
+                     (ada_result*)results, queue, (const int*)order);
   return hipGetLastError();
 }
 

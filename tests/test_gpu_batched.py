@@ -166,3 +166,33 @@ def test_batched_fp32_refinement_falls_back_to_fp64(ada):
         assert r32[k].berr <= 1e-10
     with pytest.raises(ValueError):
         ada.make_opts(precision="bf16")
+
+
+def test_batched_launch_in_a_hip_graph(ada):
+    """The batched launch captured into a HIP graph and replayed: every replay, with eager
+    work and synchronisations between them, gives the eager run's x and results bit for bit."""
+    cases = W.batched_case(64, k=5, n_hi=200)
+    batch = ada.Batch([c[1] for c in cases], [c[2] for c in cases])
+    batch.run()
+    torch.cuda.synchronize()
+    x_ref = batch.X.clone()
+    r_ref = batch.res.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        batch.run()
+    for rep in range(3):
+        batch.X.zero_()
+        batch.res.zero_()
+        junk = torch.randn(1 << 20, device="cuda:0").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(batch.X, x_ref), f"replay {rep}: x differs"
+        assert torch.equal(batch.res, r_ref), f"replay {rep}: results differ"
+        del junk
