@@ -16,11 +16,18 @@ namespace ada {
 
 constexpr int TB = 64;
 
-__global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double* __restrict__ T, int ldt, int lower,
+// Several right-hand sides (2..64). The tiles of earlier blocks stream through two LDS buffers (the next
+// tile's loads are in flight while the current one is applied to all columns); the diagonal block is solved
+// by the four waves, each taking every fourth column, lane = row, the lane's row of the diagonal tile and
+// the reciprocal of its diagonal entry in registers, the solved values broadcast by readlane; a wave runs
+// two of its columns at a time, interleaved step by step, so their broadcasts overlap.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_trsm_dec(
+    int n, int nrhs, const double* __restrict__ T, int ldt, int lower,
                                                   int trans, int unit, double* X, int ldx, int* flags, int epoch,
                                                   unsigned* ticket, DevRec* rec, const int* pred, int pred_val) {
   if (pred && *pred != pred_val) return;
-  const int t = threadIdx.x;
+  constexpr int LD = TB + 1;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int nblk = (n + TB - 1) / TB;
   __shared__ int s_tk;
   if (t == 0) s_tk = (int)atomicAdd(ticket, 1u);
@@ -28,39 +35,57 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
   const int tk = s_tk;
   if (tk >= nblk) return;
   const bool eff_lower = (lower != 0) != (trans != 0);
-  const int bi = eff_lower ? tk : (nblk - 1 - tk);
+  auto blk = [&](int q) { return eff_lower ? q : (nblk - 1 - q); };
+  const int bi = blk(tk);
   const int r0 = bi * TB;
   const int rows = min(TB, n - r0);
 
   extern __shared__ double sm[];
-  double* acc = sm;                    // acc[c * TB + r]
-  double* tile = acc + TB * nrhs;      // tile[k * (TB + 1) + r] = op(T)(r0 + r, c0 + k)
-  double* xj = tile + TB * (TB + 1);   // xj[c * TB + k]
+  double* acc = sm;                  // acc[c * TB + r]
+  double* xj = acc + TB * nrhs;      // xj[c * TB + k]
+  double* tb0 = xj + TB * nrhs;      // tb[k * LD + r] = op(T)(r0 + r, c0 + k)
+  double* tb1 = tb0 + TB * LD;
 
   for (int e = t; e < TB * nrhs; e += blockDim.x) {
     const int r = e % TB, c = e / TB;
     acc[e] = (r < rows) ? X[(size_t)(r0 + r) + (size_t)c * ldx] : 0.0;
   }
-
-  auto stage_tile = [&](int c0, int cols) {
-    if (!trans) {
-      for (int e = t; e < TB * TB; e += blockDim.x) {
-        const int r = e % TB, k = e / TB;
-        tile[k * (TB + 1) + r] = (r < rows && k < cols) ? T[(size_t)(r0 + r) + (size_t)(c0 + k) * ldt] : 0.0;
-      }
-    } else {
-      for (int e = t; e < TB * TB; e += blockDim.x) {
-        const int k = e % TB, r = e / TB;
-        tile[k * (TB + 1) + r] = (r < rows && k < cols) ? T[(size_t)(c0 + k) + (size_t)(r0 + r) * ldt] : 0.0;
-      }
+  // thread t stages 16 elements of a 64x64 tile (coalesced in memory)
+  double st[16];
+  auto load_tile = [&](int c0, int cols) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u;
+      const int a = e % TB, b = e / TB;  // a runs along memory
+      const int r = trans ? b : a, k = trans ? a : b;
+      st[u] = (r < rows && k < cols) ? (trans ? T[(size_t)(c0 + k) + (size_t)(r0 + r) * ldt]
+                                               : T[(size_t)(r0 + r) + (size_t)(c0 + k) * ldt])
+                                     : 0.0;
     }
   };
-
+  auto store_tile = [&](double* dst) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u;
+      const int a = e % TB, b = e / TB;
+      const int r = trans ? b : a, k = trans ? a : b;
+      dst[k * LD + r] = st[u];
+    }
+  };
+  if (tk > 0) {
+    const int c0 = blk(0) * TB;
+    load_tile(c0, min(TB, n - c0));
+    store_tile(tb0);
+  }
+  __syncthreads();
   for (int q = 0; q < tk; ++q) {
-    const int bj = eff_lower ? q : (nblk - 1 - q);
-    const int c0 = bj * TB;
-    const int cols = min(TB, n - c0);
-    stage_tile(c0, cols);
+    double* cur = (q & 1) ? tb1 : tb0;
+    double* nxt = (q & 1) ? tb0 : tb1;
+    if (q + 1 < tk) {
+      const int c1 = blk(q + 1) * TB;
+      load_tile(c1, min(TB, n - c1));
+    }
+    const int bj = blk(q), c0 = bj * TB, cols = min(TB, n - c0);
     if (t == 0) {
       long spins = 0;
       while (relaxed_load(&flags[bj]) != epoch) {
@@ -68,7 +93,7 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
           atomicOr(&rec->timeout, 1);
           break;
         }
-        __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_s_sleep(0);
       }
     }
     __syncthreads();
@@ -77,67 +102,58 @@ __global__ __launch_bounds__(256) void k_trsm_dec(int n, int nrhs, const double*
       xj[e] = (k < cols) ? relaxed_load(X + (size_t)(c0 + k) + (size_t)c * ldx) : 0.0;
     }
     __syncthreads();
-    {
-      const int r = t & 63;
-      for (int c = t >> 6; c < nrhs; c += 4) {
-        double s = 0.0;
-        const double* xc = xj + c * TB;
+    for (int c = w; c < nrhs; c += 4) {
+      double sacc = 0.0;
+      const double* xc = xj + c * TB;
 #pragma unroll 16
-        for (int k = 0; k < TB; ++k) s = fma(tile[k * (TB + 1) + r], xc[k], s);
-        acc[c * TB + r] -= s;
-      }
+      for (int k = 0; k < TB; ++k) sacc = fma(cur[k * LD + lane], xc[k], sacc);
+      acc[c * TB + lane] -= sacc;
     }
+    if (q + 1 < tk) store_tile(nxt);
     __syncthreads();
   }
 
-  // diagonal block: substitution
-  stage_tile(r0, rows);
+  // diagonal block
+  double* td = (tk & 1) ? tb1 : tb0;
+  load_tile(r0, rows);
+  store_tile(td);
   __syncthreads();
-  if (nrhs <= 4) {
-    // wave w solves column w; lane = row
-    const int w = t >> 6, lane = t & 63;
-    if (w < nrhs) {
-      double a = acc[w * TB + lane];
+  {
+    double trow[TB];
+#pragma unroll
+    for (int i = 0; i < TB; ++i) trow[i] = td[i * LD + lane];
+    const double rd = (lane < rows && !unit) ? 1.0 / td[lane * LD + lane] : 1.0;
+    // the wave's columns c = w, w + 4, ..., two per pass (their steps interleave)
+    for (int c = w; c < nrhs; c += 8) {
+      const bool two = c + 4 < nrhs;  // wave-uniform
+      double a0 = acc[c * TB + lane];
+      double a1 = two ? acc[(c + 4) * TB + lane] : 0.0;
       if (eff_lower) {
-        for (int i = 0; i < rows; ++i) {
-          double xi = unit ? a : a / tile[i * (TB + 1) + i];
-          xi = __shfl(xi, i, 64);
-          if (lane == i) a = xi;
-          if (lane > i) a = fma(-tile[i * (TB + 1) + lane], xi, a);
+#pragma unroll
+        for (int i = 0; i < TB; ++i) {
+          const double x0 = read_lane(a0 * rd, i);
+          const double x1 = read_lane(a1 * rd, i);
+          a0 = (lane == i) ? x0 : a0;
+          a1 = (lane == i) ? x1 : a1;
+          a0 = (lane > i) ? fma(-trow[i], x0, a0) : a0;
+          a1 = (lane > i) ? fma(-trow[i], x1, a1) : a1;
         }
       } else {
-        for (int i = rows - 1; i >= 0; --i) {
-          double xi = unit ? a : a / tile[i * (TB + 1) + i];
-          xi = __shfl(xi, i, 64);
-          if (lane == i) a = xi;
-          if (lane < i) a = fma(-tile[i * (TB + 1) + lane], xi, a);
+#pragma unroll
+        for (int i = TB - 1; i >= 0; --i) {
+          const double x0 = read_lane(a0 * rd, i);
+          const double x1 = read_lane(a1 * rd, i);
+          a0 = (lane == i) ? x0 : a0;
+          a1 = (lane == i) ? x1 : a1;
+          a0 = (lane < i) ? fma(-trow[i], x0, a0) : a0;
+          a1 = (lane < i) ? fma(-trow[i], x1, a1) : a1;
         }
       }
-      acc[w * TB + lane] = a;
-    }
-  } else {
-    // thread c solves column c
-    for (int c = t; c < nrhs; c += blockDim.x) {
-      double* a = acc + c * TB;
-      if (eff_lower) {
-        for (int i = 0; i < rows; ++i) {
-          const double xi = unit ? a[i] : a[i] / tile[i * (TB + 1) + i];
-          a[i] = xi;
-          for (int r = i + 1; r < rows; ++r) a[r] = fma(-tile[i * (TB + 1) + r], xi, a[r]);
-        }
-      } else {
-        for (int i = rows - 1; i >= 0; --i) {
-          const double xi = unit ? a[i] : a[i] / tile[i * (TB + 1) + i];
-          a[i] = xi;
-          for (int r = 0; r < i; ++r) a[r] = fma(-tile[i * (TB + 1) + r], xi, a[r]);
-        }
+      if (lane < rows) {
+        relaxed_store(X + (size_t)(r0 + lane) + (size_t)c * ldx, a0);
+        if (two) relaxed_store(X + (size_t)(r0 + lane) + (size_t)(c + 4) * ldx, a1);
       }
     }
-  }
-  __syncthreads();
-  for (int e = t; e < TB * nrhs; e += blockDim.x) {
-    const int r = e % TB, c = e / TB;
-    if (r < rows) relaxed_store(X + (size_t)(r0 + r) + (size_t)c * ldx, acc[e]);
   }
   wait_stores_done();
   __syncthreads();
@@ -316,7 +332,7 @@ hipError_t launch_trsm_dec(int n, int nrhs, const double* T, int ldt, bool lower
                        flags, epoch, ticket, rec, pred, pred_val);
     return hipGetLastError();
   }
-  const size_t lds = sizeof(double) * ((size_t)TB * nrhs * 2 + (size_t)TB * (TB + 1));
+  const size_t lds = sizeof(double) * ((size_t)TB * nrhs * 2 + (size_t)2 * TB * (TB + 1));
   static size_t done = 0;
   hipError_t e = ensure_lds((const void*)k_trsm_dec, lds, done);
   if (e != hipSuccess) return e;
