@@ -302,3 +302,21 @@ def test_band_row_parallel_solve(ada, n, kl, ku, nrhs, shift):
     assert r.berr <= max(1e-13, 4 * rr["berr"]), (r.berr, rr["berr"])
     tol = 32 * n * EPS / rr["rcond"] * max(1.0, np.max(np.abs(xr)))
     assert np.max(np.abs(xs.cpu().numpy().reshape(xr.shape) - xr)) <= tol
+
+
+@pytest.mark.parametrize("n", [3000, 6000])
+def test_lu_many_panel_workgroups(ada, n):
+    """LU whose panels span up to 24 workgroups (one cross-workgroup exchange per column): properties
+    that hold at any size: backward error, error against the known solution within kappa eps, route."""
+    rng = np.random.default_rng(n)
+    a = W.dense_general(n, rng)
+    xt = W.x_true(n, 2, rng)
+    b = W.rhs_for(a, xt)
+    x, r = ada.solve(T(a), T(b))
+    torch.cuda.synchronize()
+    print(f"n={n} route={r.route} rcond={r.rcond:.2e} berr={r.berr:.2e}", flush=True)
+    assert r.status == 0 and r.route == "lu" and r.cls == "general"
+    assert r.berr <= 1e-14
+    xg = x.cpu().numpy()
+    kappa = 1.0 / r.rcond
+    assert np.max(np.abs(xg - xt)) <= 32 * n * kappa * EPS * max(1.0, np.max(np.abs(xt)))
