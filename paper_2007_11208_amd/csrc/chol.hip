@@ -17,7 +17,7 @@ namespace ada {
 //      row in registers (the column-j values of other rows come by readlane,
 //      so the 32 steps need no barrier);
 //   2. the rows below solve x L_kk^T = a (one thread per row, L_kk from LDS);
-//   3. the trailing lower triangle takes the symmetric rank-32 update.
+//   3. the trailing lower triangle takes the symmetric rank-32 update (4x4 register tiles).
 // A pivot that is not positive (or NaN) ends the factorisation: the matrix is
 // then not taken to be sympd and the system is re-solved by LU on the
 // original A (Section II-C).
@@ -105,17 +105,45 @@ __global__ __launch_bounds__(256) void k_potrf_diag(int k0, int nbw, double* __r
         if (j < cb) sA[(kb + j) * ld + r] = x[j];
     }
     __syncthreads();
-    // 3. trailing lower triangle: A(r, c) -= sum_j L(r, j) L(c, j), r >= c >= r0
-    for (int e = t; e < rest * 2; e += blockDim.x) {
-      const int r = r0 + e / 2, par = e % 2;
-      double lr[PB];
+    // 3. trailing lower triangle: A(r, c) -= sum_j L(r, j) L(c, j), r >= c >= r0, in 4x4 register tiles
+    //    (tile rows ti >= tile columns tj, dealt evenly over the threads; 8 LDS reads per 16 FMAs)
+    {
+      const int nt = (rest + 3) / 4;
+      const int ntiles = nt * (nt + 1) / 2;
+      for (int tile = t; tile < ntiles; tile += blockDim.x) {
+        int ti = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+        while (ti * (ti + 1) / 2 > tile) --ti;
+        while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+        const int tj = tile - ti * (ti + 1) / 2;
+        const int rb = r0 + 4 * ti, cb0 = r0 + 4 * tj;
+        double acc[4][4];
 #pragma unroll
-      for (int j = 0; j < PB; ++j) lr[j] = j < cb ? sA[(kb + j) * ld + r] : 0.0;
-      for (int c = r0 + par; c <= r; c += 2) {
-        double a = sA[c * ld + r];
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int j = 0; j < PB; ++j) a = fma(-lr[j], sA[(kb + j) * ld + c], a);
-        sA[c * ld + r] = a;
+          for (int b = 0; b < 4; ++b) {
+            const int r = rb + a, c = cb0 + b;
+            acc[a][b] = (r < nbw && c <= r) ? sA[c * ld + r] : 0.0;
+          }
+        for (int j = 0; j < cb; ++j) {
+          const double* lj = sA + (kb + j) * ld;
+          double lr[4], lc[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            lr[a] = rb + a < nbw ? lj[rb + a] : 0.0;
+            lc[a] = cb0 + a < nbw ? lj[cb0 + a] : 0.0;
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = fma(-lr[a], lc[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int r = rb + a, c = cb0 + b;
+            if (r < nbw && c <= r) sA[c * ld + r] = acc[a][b];
+          }
       }
     }
     __syncthreads();
