@@ -149,6 +149,240 @@ __device__ int b_getrf(const BCtx& c, T* M, int n, int* perm) {
   return info;
 }
 
+// ---- blocked forms for matrices in HBM (orders above what LDS holds): 32-column panels are factored in
+// LDS, and the trailing matrix takes one rank-32 update per panel in 4x4 register tiles, so each of its
+// elements is read and written once per panel rather than once per column. S: LDS scratch of at least
+// 2 * PW * BNM elements of T (the LDS matrix region).
+constexpr int PW = 32;
+constexpr int LDP = BNM;  // P and U together fill the BNL x BNL LDS region exactly
+static_assert(2 * PW * BNM <= BNL * BNL, "the blocked factorisations' LDS scratch must fit the matrix region");
+
+// LU with partial pivoting (ties to the lowest row, as b_getrf), same result up to rounding order
+template <class T>
+__device__ int b_getrf_blk(const BCtx& c, T* M, int n, int* perm, T* S) {
+  T* P = S;               // panel: P[r + cc * LDP] = M(k0 + r, k0 + cc)
+  T* U = S + PW * LDP;    // U12: U[kk * BNM + q] = M(k0 + kk, k0 + nbw + q)
+  __shared__ int s_piv[PW];       // panel row that column jj's pivot came from (jj: no interchange)
+  __shared__ int s_rows[2 * PW];  // rows touched by the panel's interchanges (offsets from k0)
+  __shared__ int s_from[2 * PW];  // ... and which of them each one takes its value from (index into s_rows)
+  __shared__ int s_nrows;
+  int info = 0;
+  for (int i = c.t; i < n; i += BT) perm[i] = i;
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += PW) {
+    const int nbw = min(PW, n - k0), m = n - k0, rest = m - nbw;
+    for (int e = c.t; e < m * nbw; e += BT) {
+      const int r = e % m, cc = e / m;
+      P[r + cc * LDP] = M[(k0 + r) + (size_t)(k0 + cc) * n];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nbw; ++jj) {
+      double v = -1.0;
+      int idx = -1;
+      for (int r = jj + c.t; r < m; r += BT) {
+        const double a = fabs((double)P[r + jj * LDP]);
+        if (idx < 0 || a > v) { v = a; idx = r; }
+      }
+      const int p = b_argmax(c, v, idx);
+      const T piv = P[p + jj * LDP];
+      if (piv == T(0)) {
+        if (info == 0) info = k0 + jj + 1;
+        if (c.t == 0) s_piv[jj] = jj;
+        __syncthreads();
+        continue;
+      }
+      if (c.t == 0) s_piv[jj] = p;
+      if (p != jj) {
+        for (int cc = c.t; cc < nbw; cc += BT) {
+          const T a = P[jj + cc * LDP];
+          P[jj + cc * LDP] = P[p + cc * LDP];
+          P[p + cc * LDP] = a;
+        }
+        if (c.t == 0) {
+          const int q = perm[k0 + jj];
+          perm[k0 + jj] = perm[k0 + p];
+          perm[k0 + p] = q;
+        }
+      }
+      __syncthreads();
+      for (int r = jj + 1 + c.t; r < m; r += BT) P[r + jj * LDP] = P[r + jj * LDP] / piv;
+      __syncthreads();
+      for (int r = jj + 1 + c.t; r < m; r += BT) {
+        const T l = P[r + jj * LDP];
+        for (int cc = jj + 1; cc < nbw; ++cc) P[r + cc * LDP] = fma(-l, P[jj + cc * LDP], P[r + cc * LDP]);
+      }
+      __syncthreads();
+    }
+    // the panel back; the interchanges as one gather per column: s_rows lists the touched rows, row
+    // s_rows[i] takes the value row s_rows[s_from[i]] had
+    for (int e = c.t; e < m * nbw; e += BT) {
+      const int r = e % m, cc = e / m;
+      M[(k0 + r) + (size_t)(k0 + cc) * n] = P[r + cc * LDP];
+    }
+    if (c.t == 0) {
+      int nr = 0;
+      for (int jj = 0; jj < nbw; ++jj) s_rows[nr++] = jj;
+      for (int jj = 0; jj < nbw; ++jj) {
+        const int p = s_piv[jj];
+        bool seen = false;
+        for (int i = 0; i < nr; ++i) seen |= s_rows[i] == p;
+        if (!seen) s_rows[nr++] = p;
+      }
+      for (int i = 0; i < nr; ++i) s_from[i] = i;
+      for (int jj = 0; jj < nbw; ++jj) {
+        const int p = s_piv[jj];
+        if (p == jj) continue;
+        int ia = 0, ib = 0;
+        for (int i = 0; i < nr; ++i) {
+          if (s_rows[i] == jj) ia = i;
+          if (s_rows[i] == p) ib = i;
+        }
+        const int tmp = s_from[ia];
+        s_from[ia] = s_from[ib];
+        s_from[ib] = tmp;
+      }
+      s_nrows = nr;
+    }
+    __syncthreads();
+    // each of 128 threads gathers one column through its own slots of U's region (free until U12 is formed)
+    const int nr = s_nrows;
+    for (int b0 = 0; b0 < n - nbw; b0 += 128) {
+      const int qi = b0 + c.t;
+      if (c.t < 128 && qi < n - nbw) {
+        const int q = qi < k0 ? qi : qi + nbw;  // the columns left and right of the panel
+        T* col = M + (size_t)q * n + k0;
+#pragma unroll 16
+        for (int i = 0; i < nr; ++i) U[i * 128 + c.t] = col[s_rows[i]];
+#pragma unroll 16
+        for (int i = 0; i < nr; ++i) col[s_rows[i]] = U[s_from[i] * 128 + c.t];
+      }
+    }
+    __syncthreads();
+    if (rest <= 0) break;
+    // U12 = L11^{-1} A12 (unit lower L11), one thread per column
+    for (int q = c.t; q < rest; q += BT) {
+      T* col = M + (size_t)(k0 + nbw + q) * n + k0;
+      T x[PW];
+#pragma unroll
+      for (int kk = 0; kk < PW; ++kk) x[kk] = kk < nbw ? col[kk] : T(0);
+#pragma unroll
+      for (int kk = 1; kk < PW; ++kk)
+#pragma unroll
+        for (int ii = 0; ii < kk; ++ii)
+          if (kk < nbw) x[kk] = fma(-P[kk + ii * LDP], x[ii], x[kk]);
+#pragma unroll
+      for (int kk = 0; kk < PW; ++kk)
+        if (kk < nbw) {
+          U[kk * BNM + q] = x[kk];
+          col[kk] = x[kk];
+        }
+    }
+    __syncthreads();
+    // A22 -= L21 U12 in 4x4 tiles
+    const int nt = (rest + 3) / 4;
+    for (int tile = c.t; tile < nt * nt; tile += BT) {
+      const int r4 = 4 * (tile % nt), q4 = 4 * (tile / nt);
+      T acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = (r4 + a < rest && q4 + b < rest)
+                          ? M[(k0 + nbw + r4 + a) + (size_t)(k0 + nbw + q4 + b) * n] : T(0);
+      for (int kk = 0; kk < nbw; ++kk) {
+        T l[4], u[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          l[a] = r4 + a < rest ? P[(nbw + r4 + a) + kk * LDP] : T(0);
+          u[a] = q4 + a < rest ? U[kk * BNM + q4 + a] : T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(-l[a], u[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (r4 + a < rest && q4 + b < rest) M[(k0 + nbw + r4 + a) + (size_t)(k0 + nbw + q4 + b) * n] = acc[a][b];
+    }
+    __syncthreads();
+  }
+  return info;
+}
+
+// Cholesky A = L L^T from the lower triangle (as b_potrf): 0 or the 1-based failing column
+template <class T>
+__device__ int b_potrf_blk(const BCtx& c, T* M, int n, T* S) {
+  T* P = S;  // panel: P[r + cc * LDP] = M(k0 + r, k0 + cc), r >= cc
+  for (int k0 = 0; k0 < n; k0 += PW) {
+    const int nbw = min(PW, n - k0), m = n - k0, rest = m - nbw;
+    for (int e = c.t; e < m * nbw; e += BT) {
+      const int r = e % m, cc = e / m;
+      P[r + cc * LDP] = r >= cc ? M[(k0 + r) + (size_t)(k0 + cc) * n] : T(0);
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nbw; ++jj) {
+      const T d = P[jj + jj * LDP];
+      if (!(d > T(0))) return k0 + jj + 1;
+      const T sd = sqrt(d);
+      __syncthreads();
+      for (int r = jj + c.t; r < m; r += BT) P[r + jj * LDP] = (r == jj) ? sd : P[r + jj * LDP] / sd;
+      __syncthreads();
+      for (int r = jj + 1 + c.t; r < m; r += BT) {
+        const T l = P[r + jj * LDP];
+        for (int cc = jj + 1; cc < nbw && cc <= r; ++cc) P[r + cc * LDP] = fma(-l, P[cc + jj * LDP], P[r + cc * LDP]);
+      }
+      __syncthreads();
+    }
+    for (int e = c.t; e < m * nbw; e += BT) {
+      const int r = e % m, cc = e / m;
+      if (r >= cc) M[(k0 + r) + (size_t)(k0 + cc) * n] = P[r + cc * LDP];
+    }
+    if (rest <= 0) break;
+    // trailing lower triangle: A22 -= L21 L21^T in 4x4 tiles (tile rows ti >= tile columns tj)
+    const int nt = (rest + 3) / 4;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int tile = c.t; tile < ntiles; tile += BT) {
+      int ti = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+      while (ti * (ti + 1) / 2 > tile) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+      const int tj = tile - ti * (ti + 1) / 2;
+      const int r4 = 4 * ti, q4 = 4 * tj;
+      T acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int r = r4 + a, q = q4 + b;
+          acc[a][b] = (r < rest && q <= r) ? M[(k0 + nbw + r) + (size_t)(k0 + nbw + q) * n] : T(0);
+        }
+      for (int kk = 0; kk < nbw; ++kk) {
+        T l[4], u[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          l[a] = r4 + a < rest ? P[(nbw + r4 + a) + kk * LDP] : T(0);
+          u[a] = q4 + a < rest ? P[(nbw + q4 + a) + kk * LDP] : T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(-l[a], u[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int r = r4 + a, q = q4 + b;
+          if (r < rest && q <= r) M[(k0 + nbw + r) + (size_t)(k0 + nbw + q) * n] = acc[a][b];
+        }
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
 // Cholesky A = L L^T from the lower triangle of M; returns 0 or the 1-based failing column
 template <class T>
 __device__ int b_potrf(const BCtx& c, T* M, int n) {
@@ -434,11 +668,12 @@ __device__ __forceinline__ void b_rr_pair(int m, int r, int pi, int& a, int& b) 
   }
 }
 
-// Each quarter-wave (16 lanes) takes one pair, so a workgroup has 16 pairs in
-// flight; the two columns stay in registers between the dot products and the
-// rotation (up to 16 elements per lane).
+// One-sided Jacobi on the n columns of U (ld n), round-robin pairs, the rotation rule and Rutishauser's
+// formulas of the single-system route. Each quarter-wave (16 lanes) takes one pair, so a workgroup has 16
+// pairs in flight; the two columns stay in registers between the dot products and the rotation (up to 16
+// elements per lane). Y (n x BRM, row j = the nr projections w_j^T c) takes every rotation as well.
 constexpr int JQ = BNM / 16;  // elements of a column per lane of a quarter-wave
-__device__ int b_jacobi(const BCtx& c, double* U, double* V, int n, int max_sweeps) {
+__device__ int b_jacobi(const BCtx& c, double* U, double* Y, int nr, int n, int max_sweeps) {
   const int m = (n + 1) & ~1;
   const double tol = (double)n * kEps;
   const int q = c.lane >> 4, ql = c.lane & 15;  // quarter of the wave, lane in it
@@ -493,16 +728,13 @@ __device__ int b_jacobi(const BCtx& c, double* U, double* V, int n, int max_swee
               uq[i] = sn * x[k] + cs * y[k];
             }
           }
-          double* vp = V + (size_t)p * n;
-          double* vq = V + (size_t)qq * n;
-#pragma unroll
-          for (int k = 0; k < JQ; ++k) {
-            const int i = ql + 16 * k;
-            if (i < n) {
-              const double xv = vp[i], yv = vq[i];
-              vp[i] = cs * xv - sn * yv;
-              vq[i] = sn * xv + cs * yv;
-            }
+          // the same rotation on the projections y_j = w_j^T c (the accumulated rotations W are not needed)
+          if (ql < nr) {
+            double* yp = Y + (size_t)p * BRM + ql;
+            double* yq = Y + (size_t)qq * BRM + ql;
+            const double xv = *yp, yv = *yq;
+            *yp = cs * xv - sn * yv;
+            *yq = sn * xv + cs * yv;
           }
           rot = 1;
         }
@@ -636,6 +868,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     double colsum = 0.0, rowsum = 0.0;
     for (int j = c.t; j < n; j += BT) {
       double cs = 0.0, rs = 0.0;
+#pragma unroll 8
       for (int i = 0; i < n; ++i) {
         const double a = M[i + j * n];
         cs += fabs(a);
@@ -675,6 +908,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
         if (!bad) {
           for (int j = c.t; j < n; j += BT) {
             const double ajj = M[j + j * n];
+#pragma unroll 8
             for (int i = j + 1; i < n; ++i) {
               const double aij = M[i + j * n], aji = M[j + i * n];
               const double delta = fabs(aij - aji);
@@ -706,6 +940,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       for (int j = c.t; j < n; j += BT) {
         double q = 0.0;
         for (int i = 0; i < j; ++i) q += fabs(A[j + (size_t)i * d.lda]);
+#pragma unroll 8
         for (int i = j; i < n; ++i) q += fabs(A[i + (size_t)j * d.lda]);
         s = fmax(s, q);
       }
@@ -725,10 +960,11 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       g.stg = (n <= BNL32) ? nullptr : reinterpret_cast<float*>(lds);
       int ok;
       if (sym_class) {
-        ok = b_potrf<float>(c, M32, n) == 0;
+        ok = (n <= BNL32 ? b_potrf<float>(c, M32, n) : b_potrf_blk<float>(c, M32, n, reinterpret_cast<float*>(lds))) == 0;
         g.kind = 1;
       } else {
-        ok = b_getrf<float>(c, M32, n, perm) == 0;
+        ok = (n <= BNL32 ? b_getrf<float>(c, M32, n, perm)
+                         : b_getrf_blk<float>(c, M32, n, perm, reinterpret_cast<float*>(lds))) == 0;
         g.kind = 0;
       }
       __syncthreads();
@@ -762,6 +998,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
             for (int i = c.t; i < n; i += BT) {
               const double bi = B[i + (size_t)r0 * d.ldb];
               double sres = bi;
+#pragma unroll 8
               for (int j = 0; j < n; ++j) sres = fma(-A[i + (size_t)j * d.lda], X[j + (size_t)r0 * d.ldx], sres);
               Rv[i] = sres;
               const double xi = X[i + (size_t)r0 * d.ldx];
@@ -858,7 +1095,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       } else {
         bool fresh = true;  // M still holds A
         if (cls == ADA_CLASS_SYMPD) {
-          const int ci = b_potrf(c, M, n);
+          const int ci = n <= BNL ? b_potrf(c, M, n) : b_potrf_blk(c, M, n, lds);
           fresh = false;
           __syncthreads();
           if (ci == 0) {
@@ -875,7 +1112,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
             for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
             __syncthreads();
           }
-          info = b_getrf(c, M, n, perm);
+          info = n <= BNL ? b_getrf(c, M, n, perm) : b_getrf_blk(c, M, n, perm, lds);
           __syncthreads();
           f.kind = 0;
         }
@@ -937,8 +1174,9 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     }
     if (svd) {
       // ---- S8: SVD of the original A, min-norm least squares. A P = Q R (columns by decreasing norm,
-      // Householder, reflectors in gV), C = Q^T B (gX), then one-sided Jacobi on R^T (gW) with V = I:
-      // R^T W = U~, sigma_j = ||u~_j||, x = P sum over kept j of u~_j (w_j^T C) / sigma_j^2
+      // Householder, reflectors in gV), C = Q^T B (gX), then one-sided Jacobi on R^T (gW): R^T W = U~,
+      // sigma_j = ||u~_j||, x = P sum over kept j of u~_j (w_j^T C) / sigma_j^2, where the projections
+      // w_j^T C are rotated along with the columns instead of accumulating W
       res.route = ADA_ROUTE_SVD;
       double* C = gX;              // BNM x BRM
       double* tau = lds;           // n (the LDS matrix region is free here)
@@ -946,6 +1184,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       double* cn = sbuf;  // n
       for (int j = c.t; j < n; j += BT) {
         double q = 0.0;
+#pragma unroll 8
         for (int i = 0; i < n; ++i) q = fma(A[i + (size_t)j * d.lda], A[i + (size_t)j * d.lda], q);
         cn[j] = sqrt(q);
       }
@@ -965,13 +1204,16 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
         gW[e] = i >= j ? gV[j + (size_t)i * n] : 0.0;
       }
       __syncthreads();
-      for (int e = c.t; e < n * n; e += BT) gV[e] = (e % n == e / n) ? 1.0 : 0.0;
+      // projections y_j = w_j^T C, rotated with the columns (W = I at the start: y_j = C[j, :])
+      double* Y = gV;  // n x BRM (the reflectors are no longer needed)
+      for (int e = c.t; e < n * nr; e += BT) Y[(size_t)(e % n) * BRM + e / n] = C[e % n + (size_t)(e / n) * BNM];
       __syncthreads();
-      res.sweeps = b_jacobi(c, gW, gV, n, 30);
+      res.sweeps = b_jacobi(c, gW, Y, nr, n, 30);
       // sigma_j = ||u_j||, cut at eps * sigma_max
       double* sig = sbuf;  // BNM
       for (int j = c.t; j < n; j += BT) {
         double s = 0.0;
+#pragma unroll 8
         for (int i = 0; i < n; ++i) s = fma(gW[i + (size_t)j * n], gW[i + (size_t)j * n], s);
         sig[j] = sqrt(s);
       }
@@ -984,21 +1226,17 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       for (int j = c.t; j < n; j += BT) keep += sig[j] > cut ? 1 : 0;
       keep = (int)b_sum(c, (double)keep);
       res.rank = keep;
-      // T = diag(1/sigma^2) W^T C for kept j, then X = U~ T
+      // T = diag(1/sigma^2) (W^T C) for kept j, then X = U~ T
       double* T = gX + (size_t)BNM * BRM;  // BNM x BRM
       for (int e = c.t; e < n * nr; e += BT) {
         const int j = e % n, r = e / n;
-        double s = 0.0;
-        if (sig[j] > cut) {
-          for (int i = 0; i < n; ++i) s = fma(gV[i + (size_t)j * n], C[i + (size_t)r * BNM], s);
-          s = s / (sig[j] * sig[j]);
-        }
-        T[j + (size_t)r * BNM] = s;
+        T[j + (size_t)r * BNM] = sig[j] > cut ? Y[(size_t)j * BRM + r] / (sig[j] * sig[j]) : 0.0;
       }
       __syncthreads();
       for (int e = c.t; e < n * nr; e += BT) {
         const int i = e % n, r = e / n;
         double s = 0.0;
+#pragma unroll 8
         for (int j = 0; j < n; ++j) s = fma(gW[i + (size_t)j * n], T[j + (size_t)r * BNM], s);
         X[perm[i] + (size_t)r * d.ldx] = s;
       }
@@ -1014,6 +1252,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
         int xbad = 0;
         for (int i = c.t; i < n; i += BT) {
           double s = B[i + (size_t)r * d.ldb];
+#pragma unroll 8
           for (int j = 0; j < n; ++j) s = fma(-A[i + (size_t)j * d.lda], X[j + (size_t)r * d.ldx], s);
           const double xi = X[i + (size_t)r * d.ldx];
           xbad |= !isfinite(xi);
