@@ -434,10 +434,17 @@ __device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool tra
     const TF* P;
     int pr, pc;  // element (i, jj) at P[i * pr + jj * pc]
     if (stg) {
+      // unrolled so that 16 loads are in flight per lane (the copy is bound by HBM latency otherwise)
       if (!trans) {
+#pragma unroll 4
         for (int jj = 0; jj < cnt; ++jj)
-          for (int i = lane; i < n; i += 64) stg[jj * BNM + i] = T[i + (size_t)(64 * jb + jj) * ldt];
+#pragma unroll
+          for (int b = 0; b < BRB; ++b) {
+            const int i = lane + 64 * b;
+            if (i < n) stg[jj * BNM + i] = T[i + (size_t)(64 * jb + jj) * ldt];
+          }
       } else {
+#pragma unroll 16
         for (int i = 0; i < n; ++i)
           if (lane < cnt) stg[lane * BNM + i] = T[(64 * jb + lane) + (size_t)i * ldt];
       }
