@@ -445,6 +445,9 @@ def main():
                     help="single: the five large systems; batched: many small systems in one launch per step")
     ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
     ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
+    ap.add_argument("--concurrent-steps", type=int, default=3,
+                    help="single workload: also time this many steps with the systems solved concurrently "
+                         "(one stream each; reported beside the sequential value); 0: skip")
     ap.add_argument("--mixed-n", default="4096,8192,16384", help="mixed workload: orders")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: offered requests per second")
     ap.add_argument("--duration", type=float, default=1.0, help="serving: seconds of arrivals")
@@ -565,6 +568,43 @@ def main():
                 "per_launch": {"flops": fl / max(1, launches), "bytes": by / max(1, launches)}}
     families = {f: {"launches": v[0], "ms": round(v[1], 3)} for f, v in prof.items() if v[0]}
 
+    # the same systems solved concurrently: one host thread, context and HIP stream each, so that the
+    # latency-bound chains of different systems share the device (reported beside the sequential value)
+    concurrent = None
+    if args.concurrent_steps > 0:
+        import threading
+        ctxs = [ada.Context(0) for _ in cases]
+        streams = [torch.cuda.Stream(device=dev) for _ in cases]
+        cres = [None] * len(cases)
+
+        def solve_one(k):
+            name, A, B, kw, work, X, n = cases[k]
+            with torch.cuda.stream(streams[k]):
+                _, cres[k] = ada.solve(A, B, out=X, work=work, ctx=ctxs[k], **kw)
+
+        def conc_step():
+            ths = [threading.Thread(target=solve_one, args=(k,)) for k in range(len(cases))]
+            for th in ths:
+                th.start()
+            for th in ths:
+                th.join()
+
+        conc_step()
+        torch.cuda.synchronize()
+        ct = []
+        for _ in range(args.concurrent_steps):
+            c0 = time.perf_counter()
+            conc_step()
+            ct.append(time.perf_counter() - c0)
+        torch.cuda.synchronize()
+        cworst = max(r.berr for r in cres)
+        if not (cworst <= BERR_BAR) or any(r.route != info[c[0]].route for r, c in zip(cres, cases)):
+            print(f"concurrent solves disagree with the sequential ones (max berr {cworst})", file=sys.stderr)
+            sys.exit(1)
+        concurrent = {"solves_per_s": round(len(cases) * len(ct) / sum(ct), 4),
+                      "ms_per_step": round(sum(ct) / len(ct) * 1e3, 3),
+                      "p50_step_ms": round(pct(ct, 50) * 1e3, 3), "max_berr": cworst, "streams": len(cases)}
+
     cpu = None
     if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(args.nrhs)
@@ -579,7 +619,7 @@ def main():
         "tflops": round(flops_step * args.steps / total / 1e12, 4),
         "p50_step_ms": round(pct(step_times, 50) * 1e3, 3), "p99_step_ms": round(pct(step_times, 99) * 1e3, 3),
         "max_berr": worst_berr, "per_system": per_sys, "kernel_families": families,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "concurrent": concurrent,
     }
     print(json.dumps(out), flush=True)
 
