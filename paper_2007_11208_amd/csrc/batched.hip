@@ -25,6 +25,7 @@ constexpr int BNM = 256;      // largest order
 constexpr int BRM = 8;        // most right-hand sides
 constexpr int BNL = 128;      // orders up to this keep the matrix in LDS
 constexpr int BRB = BNM / 64; // rows per lane in the one-wave solves
+constexpr int SCOL = 16;      // columns of a triangle a wave stages into LDS at a time (matrix in HBM)
 constexpr int BNL32 = 181;    // orders up to this keep an FP32 matrix in LDS (181^2 * 4 bytes <= 128 KB)
 constexpr int kMaxRefine = 30;  // refinement steps at most (the limit of LAPACK's mixed-precision driver)
 
@@ -421,76 +422,85 @@ struct WVec {
 
 // op(T) y = y in place; T (ld ldt) lower or upper as stored, op = transpose if trans.
 // FWD: forward substitution (op(T) lower). Register blocks are visited in a
-// compile-time order so every register index is a constant.
+// compile-time order so every register index is a constant. stg: this wave's LDS staging area of
+// scol * BNM elements (matrix in HBM; scol divides 64), or null (matrix in LDS; scol = 64).
 template <bool FWD, int NRC, class TF>
 __device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v,
-                                           int nr, int lane, TF* stg) {
+                                           int nr, int lane, TF* stg, int scol) {
 #pragma unroll
   for (int jbi = 0; jbi < BRB; ++jbi) {
     const int jb = FWD ? jbi : BRB - 1 - jbi;
     if (64 * jb >= n) continue;
     const int cnt = min(64, n - 64 * jb);
-    // op(T)(i, 64 jb + jj) for every row i: from LDS directly, or staged into LDS (matrix in HBM)
-    const TF* P;
-    int pr, pc;  // element (i, jj) at P[i * pr + jj * pc]
-    if (stg) {
-      // unrolled so that 16 loads are in flight per lane (the copy is bound by HBM latency otherwise)
-      if (!trans) {
+    // columns of the block in groups of scol, in solve order
+    const int ngr = (cnt + scol - 1) / scol;
+    for (int sgi = 0; sgi < ngr; ++sgi) {
+      const int s0 = scol * (FWD ? sgi : ngr - 1 - sgi);
+      const int scnt = min(scol, cnt - s0);
+      const int c0 = 64 * jb + s0;  // first column of the group
+      // op(T)(i, c0 + k) for every row i: from LDS directly, or staged into this wave's LDS quarter (matrix
+      // in HBM), with the loads unrolled so that many are in flight
+      const TF* P;
+      int pr, pc;  // element (i, k) at P[i * pr + k * pc]
+      if (stg) {
+        if (!trans) {
 #pragma unroll 4
-        for (int jj = 0; jj < cnt; ++jj)
+          for (int k = 0; k < scnt; ++k)
 #pragma unroll
-          for (int b = 0; b < BRB; ++b) {
-            const int i = lane + 64 * b;
-            if (i < n) stg[jj * BNM + i] = T[i + (size_t)(64 * jb + jj) * ldt];
-          }
-      } else {
+            for (int b = 0; b < BRB; ++b) {
+              const int i = lane + 64 * b;
+              if (i < n) stg[k * BNM + i] = T[i + (size_t)(c0 + k) * ldt];
+            }
+        } else {
 #pragma unroll 16
-        for (int i = 0; i < n; ++i)
-          if (lane < cnt) stg[lane * BNM + i] = T[(64 * jb + lane) + (size_t)i * ldt];
+          for (int i = 0; i < n; ++i)
+            if (lane < scnt) stg[lane * BNM + i] = T[(c0 + lane) + (size_t)i * ldt];
+        }
+        __builtin_amdgcn_wave_barrier();
+        P = stg;
+        pr = 1;
+        pc = BNM;
+      } else {
+        P = trans ? T + (size_t)c0 : T + (size_t)c0 * ldt;
+        pr = trans ? ldt : 1;
+        pc = trans ? 1 : ldt;
+      }
+      for (int k0 = 0; k0 < scnt; ++k0) {
+        const int k = FWD ? k0 : scnt - 1 - k0;
+        const int jj = s0 + k;  // column within the block
+        const int j = 64 * jb + jj;
+        const double d = unit ? 1.0 : (double)P[j * pr + k * pc];
+        double xj[NRC];
+#pragma unroll
+        for (int r = 0; r < NRC; ++r) {
+          if (r < nr) {
+            xj[r] = read_lane(v.x[jb][r], jj) / d;
+            if (lane == jj) v.x[jb][r] = xj[r];
+          } else {
+            xj[r] = 0.0;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < BRB; ++b) {
+          const int i = lane + 64 * b;
+          const bool rel = FWD ? (i > j) : (i < j);
+          if (i < n && rel) {
+            const double tij = (double)P[i * pr + k * pc];
+#pragma unroll
+            for (int r = 0; r < NRC; ++r)
+              if (r < nr) v.x[b][r] = fma(-tij, xj[r], v.x[b][r]);
+          }
+        }
       }
       __builtin_amdgcn_wave_barrier();
-      P = stg;
-      pr = 1;
-      pc = BNM;
-    } else {
-      P = trans ? T + (size_t)(64 * jb) : T + (size_t)(64 * jb) * ldt;
-      pr = trans ? ldt : 1;
-      pc = trans ? 1 : ldt;
     }
-    for (int jj0 = 0; jj0 < cnt; ++jj0) {
-      const int jj = FWD ? jj0 : cnt - 1 - jj0;
-      const int j = 64 * jb + jj;
-      const double d = unit ? 1.0 : (double)P[j * pr + jj * pc];
-      double xj[NRC];
-#pragma unroll
-      for (int r = 0; r < NRC; ++r) {
-        if (r < nr) {
-          xj[r] = read_lane(v.x[jb][r], jj) / d;
-          if (lane == jj) v.x[jb][r] = xj[r];
-        } else {
-          xj[r] = 0.0;
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < BRB; ++b) {
-        const int i = lane + 64 * b;
-        const bool rel = FWD ? (i > j) : (i < j);
-        if (i < n && rel) {
-          const double tij = (double)P[i * pr + jj * pc];
-#pragma unroll
-          for (int r = 0; r < NRC; ++r)
-            if (r < nr) v.x[b][r] = fma(-tij, xj[r], v.x[b][r]);
-        }
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 template <int NRC, class TF>
 __device__ __forceinline__ void w_trsv(const TF* T, int ldt, int n, bool lower, bool trans, bool unit,
-                                       WVec<NRC>& v, int nr, int lane, TF* stg) {
-  if (lower != trans) w_trsv_dir<true, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg);
-  else w_trsv_dir<false, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg);
+                                       WVec<NRC>& v, int nr, int lane, TF* stg, int scol) {
+  if (lower != trans) w_trsv_dir<true, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
+  else w_trsv_dir<false, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
 }
 
 // routed factor: 0 LU (M = L\U, perm), 1 Cholesky (M = L), 2 triangular (T = A as given)
@@ -502,6 +512,7 @@ struct BFactor {
   const int* perm;
   bool lower;  // triangular kind
   TF* stg;     // LDS staging for a matrix kept in HBM (null when M is in LDS)
+  int scol;    // columns staged at a time (64 when one wave has the whole staging region)
 };
 
 // y = inv(A) y (trans = false) or inv(A)^T y (trans = true); wave 0 only; sbuf: LDS, BNM * BRM doubles
@@ -528,11 +539,11 @@ __device__ __forceinline__ void w_apply_inv(const BFactor<TF>& f, int n, bool tr
         }
       }
       __builtin_amdgcn_wave_barrier();
-      w_trsv(f.M, f.ld, n, true, false, true, v, nr, lane, f.stg);
-      w_trsv(f.M, f.ld, n, false, false, false, v, nr, lane, f.stg);
+      w_trsv(f.M, f.ld, n, true, false, true, v, nr, lane, f.stg, f.scol);
+      w_trsv(f.M, f.ld, n, false, false, false, v, nr, lane, f.stg, f.scol);
     } else {
-      w_trsv(f.M, f.ld, n, false, true, false, v, nr, lane, f.stg);
-      w_trsv(f.M, f.ld, n, true, true, true, v, nr, lane, f.stg);
+      w_trsv(f.M, f.ld, n, false, true, false, v, nr, lane, f.stg, f.scol);
+      w_trsv(f.M, f.ld, n, true, true, true, v, nr, lane, f.stg, f.scol);
       // P^T y: y_new[perm[i]] = y[i]
 #pragma unroll
       for (int b = 0; b < BRB; ++b) {
@@ -553,10 +564,10 @@ __device__ __forceinline__ void w_apply_inv(const BFactor<TF>& f, int n, bool tr
       __builtin_amdgcn_wave_barrier();
     }
   } else if (f.kind == 1) {
-    w_trsv(f.M, f.ld, n, true, false, false, v, nr, lane, f.stg);
-    w_trsv(f.M, f.ld, n, true, true, false, v, nr, lane, f.stg);
+    w_trsv(f.M, f.ld, n, true, false, false, v, nr, lane, f.stg, f.scol);
+    w_trsv(f.M, f.ld, n, true, true, false, v, nr, lane, f.stg, f.scol);
   } else {
-    w_trsv(f.M, f.ld, n, f.lower, trans, false, v, nr, lane, f.stg);
+    w_trsv(f.M, f.ld, n, f.lower, trans, false, v, nr, lane, f.stg, f.scol);
   }
 }
 
@@ -965,6 +976,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       g.perm = perm;
       g.lower = false;
       g.stg = (n <= BNL32) ? nullptr : reinterpret_cast<float*>(lds);
+      g.scol = 64;  // wave 0 alone solves on this route: the whole staging region
       int ok;
       if (sym_class) {
         ok = (n <= BNL32 ? b_potrf<float>(c, M32, n) : b_potrf_blk<float>(c, M32, n, reinterpret_cast<float*>(lds))) == 0;
@@ -1085,6 +1097,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       f.perm = perm;
       f.lower = false;
       f.stg = (n <= BNL) ? nullptr : lds;  // the LDS matrix region is free when the matrix lives in HBM
+      f.scol = 64;
       bool routed_sym = false;
       if (m_clobbered) {
         for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
@@ -1126,20 +1139,38 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       }
       const double anorm_r = routed_sym ? anorm : anorm1;  // LU after a failed Cholesky: the full matrix
       res.info = info;
-      // ---- solve, condition estimate (wave 0)
-      if (c.w == 0) {
-        double rcond = __longlong_as_double(0x7ff8000000000000LL);
-        int xnf = 0;
-        if (info == 0) {
-          for (int r0 = 0; r0 < nr; ++r0) {  // one right-hand side at a time keeps the wave's registers small
+      // ---- condition estimate (wave 0) beside the solves of the right-hand sides (waves 1-3, one right-hand
+      // side each in turn): each wave has its own staging quarter and its own slot of sbuf's rows
+      __shared__ int s_xnf;
+      if (c.t == 0) s_xnf = 0;
+      __syncthreads();
+      BFactor<double> fw = f;
+      if (f.stg) {
+        fw.stg = f.stg + (size_t)c.w * SCOL * BNM;
+        fw.scol = SCOL;
+      }
+      double* sbw = sbuf + c.w;
+      double rcond = __longlong_as_double(0x7ff8000000000000LL);
+      if (info == 0) {
+        if (c.w == 0) {
+          int ns = 0;
+          const double est = w_estimate(fw, n, c.lane, sbw, ns);
+          res.nsolves = ns;
+          if (anorm_r == 0.0) rcond = 0.0;
+          else if (est != est) rcond = est;
+          else if (est == 0.0) rcond = 0.0;
+          else rcond = (1.0 / est) / anorm_r;
+        } else {
+          int xnf = 0;
+          for (int r0 = c.w - 1; r0 < nr; r0 += BT / 64 - 1) {  // one right-hand side at a time per wave
             WVec<1> v;
-  #pragma unroll
+#pragma unroll
             for (int b = 0; b < BRB; ++b) {
               const int i = c.lane + 64 * b;
               v.x[b][0] = i < n ? B[i + (size_t)r0 * d.ldb] : 0.0;
             }
-            w_apply_inv(f, n, false, v, 1, c.lane, sbuf);
-  #pragma unroll
+            w_apply_inv(fw, n, false, v, 1, c.lane, sbw);
+#pragma unroll
             for (int b = 0; b < BRB; ++b) {
               const int i = c.lane + 64 * b;
               if (i < n) {
@@ -1148,23 +1179,18 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
               }
             }
           }
-          int ns = 0;
-          const double est = w_estimate(f, n, c.lane, sbuf, ns);
-          res.nsolves = ns;
-          if (anorm_r == 0.0) rcond = 0.0;
-          else if (est != est) rcond = est;
-          else if (est == 0.0) rcond = 0.0;
-          else rcond = (1.0 / est) / anorm_r;
           xnf = wave_or(xnf);
+          if (c.lane == 0 && xnf) atomicOr(&s_xnf, 1);
         }
-        if (c.lane == 0) {
-          int fb = ADA_FALLBACK_NONE;
-          if (info || xnf) fb = ADA_FALLBACK_FAILURE;
-          else if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
-          else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
-          s_flag = fb;
-          s_rc = rcond;
-        }
+      }
+      __syncthreads();
+      if (c.t == 0) {
+        int fb = ADA_FALLBACK_NONE;
+        if (info || s_xnf) fb = ADA_FALLBACK_FAILURE;
+        else if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
+        else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
+        s_flag = fb;
+        s_rc = rcond;
       }
       __syncthreads();
       res.fallback = s_flag;
