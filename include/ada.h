@@ -63,7 +63,8 @@ enum { ADA_ROUTE_NONE = 0, ADA_ROUTE_BAND_LU = 1, ADA_ROUTE_TRI = 2, ADA_ROUTE_C
    factorisation in lower precision (ada_solve: the trailing-matrix updates take FP32 or BF16 operands
    with FP32 accumulation, panels and pivot search stay FP64; ada_solve_batched: FP32_IR only, the
    whole factorisation in FP32), then FP64 iterative refinement (FP64 residuals and corrections) until
-   the backward error reaches sqrt(n)*eps; when it stalls, grows or needs more than 30 steps, the
+   the backward error reaches sqrt(n)*eps; when it stalls, grows or needs more than 30 steps, or when
+   the condition estimate of the low-precision factors is below 1e-9 (FP32) or 1e-4 (BF16), the
    system is solved again by the FP64 route (the result's refine_iters is then negative). Triangular,
    banded and SVD routes always run in FP64. */
 enum { ADA_PREC_FP64 = 0, ADA_PREC_FP32_IR = 1, ADA_PREC_BF16_IR = 2 };

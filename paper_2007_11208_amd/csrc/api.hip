@@ -521,6 +521,8 @@ int backward_error_dense(Solve& s, const double* A, int lda, const double* B, in
 }
 
 constexpr int kMaxRefine = 30;  // refinement steps at most (as LAPACK's mixed-precision drivers)
+// low-precision factors with a smaller rcond estimate are not refined (kappa_1 * u > 50; BF16: u = 2^-8)
+constexpr double kRcondRefine32 = 1e-9, kRcondRefine16 = 1e-4;
 
 // FP64 iterative refinement of X with the factors in W (chol: L of the Cholesky route; else the LU
 // route's LU and row permutation): r = B - A X, stop when the backward error of every column is at
@@ -798,15 +800,17 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
     TRY(s.sync_read());
     if (h.timeout) return fail(ADA_ERR_HIP, "a bounded device wait timed out");
     const bool fact_ok = chol ? h.chol_info == INT_MAX : h.info == INT_MAX;
+    const bool refinable =
+        fact_ok && h.rcond >= (o.precision == ADA_PREC_BF16_IR ? kRcondRefine16 : kRcondRefine32);
     bool conv = false;
     int steps = 0;
-    if (fact_ok) TRY(refine(s, chol, Ad, ldad, B, ldb, X, ldx, conv, steps));
+    if (refinable) TRY(refine(s, chol, Ad, ldad, B, ldb, X, ldx, conv, steps));
     if (conv) {
       mixed_done = true;
       route = chol ? ADA_ROUTE_CHOL : ADA_ROUTE_LU;
       refine_iters = steps;
     } else {
-      refine_iters = fact_ok ? -1 - steps : -1;
+      refine_iters = refinable ? -1 - steps : -1;
       HIPCHK(launch_init_rec(s.rec, st));
       HIPCHK(launch_anorm(n, s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot), norm_mode, s.rec, st));
     }

@@ -28,6 +28,7 @@ constexpr int BRB = BNM / 64; // rows per lane in the one-wave solves
 constexpr int SCOL = 16;      // columns of a triangle a wave stages into LDS at a time (matrix in HBM)
 constexpr int BNL32 = 181;    // orders up to this keep an FP32 matrix in LDS (181^2 * 4 bytes <= 128 KB)
 constexpr int kMaxRefine = 30;  // refinement steps at most (the limit of LAPACK's mixed-precision driver)
+constexpr double kRcondRefine = 1e-9;  // FP32 factors with a smaller rcond estimate are not refined
 
 struct BDesc {
   int32_t n, nrhs, lda, ldb, ldx, pad;
@@ -947,6 +948,8 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     // (stagnation, a non-finite value, or the step limit) hands the system to the FP64 route.
     __shared__ int s_flag;
     __shared__ double s_rc;
+    __shared__ double s_est;  // condition estimate of the FP32 factors
+    __shared__ int s_ns;
     bool mixed_ok = false;
     bool m_clobbered = false;
     int refine = 0;
@@ -990,101 +993,154 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       refine = -1;  // the FP32 factorisation failed
       if (ok) {
         const double tol = sqrt((double)n) * kEps;
-        double* Rv = gX;
-        int conv_all = 1;
-        refine = 0;
-        for (int r0 = 0; r0 < nr && conv_all; ++r0) {
-          if (c.w == 0) {
+        double* Rv = gX;  // residuals, BNM x BRM
+        BFactor<float> gw = g;
+        if (g.stg) {
+          gw.stg = g.stg + (size_t)c.w * SCOL * BNM;
+          gw.scol = SCOL;
+        }
+        double* sbw = sbuf + c.w;
+        // the condition estimate (wave 0) beside x0 = solve(b) for every right-hand side (waves 1-3)
+        if (c.w == 0) {
+          int ns = 0;
+          const double est = w_estimate(gw, n, c.lane, sbw, ns);
+          if (c.lane == 0) {
+            s_est = est;
+            s_ns = ns;
+          }
+        } else {
+          for (int r0 = c.w - 1; r0 < nr; r0 += BT / 64 - 1) {
             WVec<1> v;
 #pragma unroll
             for (int b = 0; b < BRB; ++b) {
-              const int i = c.lane + 64 * b;
-              v.x[b][0] = i < n ? B[i + (size_t)r0 * d.ldb] : 0.0;
+              const int ii = c.lane + 64 * b;
+              v.x[b][0] = ii < n ? B[ii + (size_t)r0 * d.ldb] : 0.0;
             }
-            w_apply_inv(g, n, false, v, 1, c.lane, sbuf);
+            w_apply_inv(gw, n, false, v, 1, c.lane, sbw);
 #pragma unroll
             for (int b = 0; b < BRB; ++b) {
-              const int i = c.lane + 64 * b;
-              if (i < n) X[i + (size_t)r0 * d.ldx] = v.x[b][0];
+              const int ii = c.lane + 64 * b;
+              if (ii < n) X[ii + (size_t)r0 * d.ldx] = v.x[b][0];
+            }
+          }
+        }
+        __syncthreads();
+        // refinement of all right-hand sides together: residuals by every thread, corrections shared by the
+        // waves; each column keeps its own stopping test (every thread holds the same per-column state)
+        // factors whose condition estimate puts kappa_1 beyond 1e9 (kappa_1 * u32 > 50) are not refined:
+        // such systems go to the FP64 route at once
+        const double rc32 = (anorm > 0.0 && s_est > 0.0) ? (1.0 / s_est) / anorm : 0.0;
+        const bool hopeless = !(rc32 >= kRcondRefine);
+        double prev[BRM];
+        int act[BRM], conv[BRM], its[BRM];
+#pragma unroll
+        for (int r = 0; r < BRM; ++r) {
+          prev[r] = INFINITY;
+          act[r] = r < nr && !hopeless;
+          conv[r] = 0;
+          its[r] = 0;
+        }
+        for (;;) {
+          int any = 0;
+#pragma unroll
+          for (int r = 0; r < BRM; ++r) any |= act[r];
+          if (!any) break;
+          double rn[BRM], xn[BRM], bn[BRM];
+          int bad[BRM];
+#pragma unroll
+          for (int r = 0; r < BRM; ++r) {
+            rn[r] = xn[r] = bn[r] = 0.0;
+            bad[r] = 0;
+          }
+          for (int ii = c.t; ii < n; ii += BT) {
+#pragma unroll
+            for (int r = 0; r < BRM; ++r) {
+              if (act[r]) {
+                const double bi = B[ii + (size_t)r * d.ldb];
+                double sres = bi;
+#pragma unroll 8
+                for (int j = 0; j < n; ++j) sres = fma(-A[ii + (size_t)j * d.lda], X[j + (size_t)r * d.ldx], sres);
+                Rv[ii + (size_t)r * BNM] = sres;
+                const double xi = X[ii + (size_t)r * d.ldx];
+                bad[r] |= !isfinite(xi) || !isfinite(sres);
+                rn[r] = fmax(rn[r], fabs(sres));
+                xn[r] = fmax(xn[r], fabs(xi));
+                bn[r] = fmax(bn[r], fabs(bi));
+              }
+            }
+          }
+          unsigned cmask = 0;  // columns that take a correction this step
+#pragma unroll
+          for (int r = 0; r < BRM; ++r) {
+            if (act[r]) {
+              const double rr = b_max(c, rn[r]), xx = b_max(c, xn[r]), bb = b_max(c, bn[r]);
+              const int bd = b_or(c, bad[r]);
+              const double den = anorm_inf * xx + bb;
+              const double eta = bd ? __longlong_as_double(0x7ff8000000000000LL)
+                                    : (den > 0.0 ? rr / den : (rr > 0.0 ? INFINITY : 0.0));
+              if (eta <= tol) {
+                act[r] = 0;
+                conv[r] = 1;
+              } else if (!(eta <= 0.5 * prev[r]) || its[r] == kMaxRefine) {
+                act[r] = 0;  // stalled: the system goes to the FP64 route
+              } else {
+                prev[r] = eta;
+                ++its[r];
+                cmask |= 1u << r;
+              }
+            }
+          }
+          // corrections x += solve(r), the k-th column to correct on wave k mod 4
+          int k = 0;
+#pragma unroll
+          for (int r = 0; r < BRM; ++r) {
+            if ((cmask >> r) & 1u) {
+              if ((k & 3) == c.w) {
+                WVec<1> v;
+#pragma unroll
+                for (int b = 0; b < BRB; ++b) {
+                  const int ii = c.lane + 64 * b;
+                  v.x[b][0] = ii < n ? Rv[ii + (size_t)r * BNM] : 0.0;
+                }
+                w_apply_inv(gw, n, false, v, 1, c.lane, sbw);
+#pragma unroll
+                for (int b = 0; b < BRB; ++b) {
+                  const int ii = c.lane + 64 * b;
+                  if (ii < n) X[ii + (size_t)r * d.ldx] += v.x[b][0];
+                }
+              }
+              ++k;
             }
           }
           __syncthreads();
-          double eta_prev = INFINITY;
-          int it = 0, conv = 0;
-          for (;; ++it) {
-            double rn = 0.0, xn = 0.0, bn = 0.0;
-            int bad = 0;
-            for (int i = c.t; i < n; i += BT) {
-              const double bi = B[i + (size_t)r0 * d.ldb];
-              double sres = bi;
-#pragma unroll 8
-              for (int j = 0; j < n; ++j) sres = fma(-A[i + (size_t)j * d.lda], X[j + (size_t)r0 * d.ldx], sres);
-              Rv[i] = sres;
-              const double xi = X[i + (size_t)r0 * d.ldx];
-              bad |= !isfinite(xi) || !isfinite(sres);
-              rn = fmax(rn, fabs(sres));
-              xn = fmax(xn, fabs(xi));
-              bn = fmax(bn, fabs(bi));
-            }
-            rn = b_max(c, rn);
-            xn = b_max(c, xn);
-            bn = b_max(c, bn);
-            bad = b_or(c, bad);
-            const double den = anorm_inf * xn + bn;
-            const double eta = bad ? __longlong_as_double(0x7ff8000000000000LL)
-                                   : (den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0));
-            if (eta <= tol) {
-              conv = 1;
-              break;
-            }
-            if (!(eta <= 0.5 * eta_prev) || it == kMaxRefine) break;
-            eta_prev = eta;
-            if (c.w == 0) {
-              WVec<1> v;
-#pragma unroll
-              for (int b = 0; b < BRB; ++b) {
-                const int i = c.lane + 64 * b;
-                v.x[b][0] = i < n ? Rv[i] : 0.0;
-              }
-              w_apply_inv(g, n, false, v, 1, c.lane, sbuf);
-#pragma unroll
-              for (int b = 0; b < BRB; ++b) {
-                const int i = c.lane + 64 * b;
-                if (i < n) X[i + (size_t)r0 * d.ldx] += v.x[b][0];
-              }
-            }
-            __syncthreads();
-          }
-          refine = max(refine, it);
-          if (!conv) conv_all = 0;
         }
-        mixed_ok = conv_all;
+        int conv_all = 1;
+        refine = 0;
+#pragma unroll
+        for (int r = 0; r < BRM; ++r) {
+          if (r < nr) {
+            conv_all &= conv[r];
+            refine = max(refine, its[r]);
+          }
+        }
+        mixed_ok = conv_all && !hopeless;
         if (!mixed_ok) refine = -1 - refine;
       }
       if (mixed_ok) {
         res.route = sym_class ? ADA_ROUTE_CHOL : (cls == ADA_CLASS_BANDED ? ADA_ROUTE_BAND_LU : ADA_ROUTE_LU);
-        if (c.w == 0) {
-          int ns = 0;
-          const double est = w_estimate(g, n, c.lane, sbuf, ns);
-          res.nsolves = ns;
-          double rcond;
-          if (anorm == 0.0) rcond = 0.0;
-          else if (est != est) rcond = est;
-          else if (est == 0.0) rcond = 0.0;
-          else rcond = (1.0 / est) / anorm;
-          if (c.lane == 0) {
-            int fb = ADA_FALLBACK_NONE;
-            if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
-            else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
-            s_flag = fb;
-            s_rc = rcond;
-          }
-        }
-        __syncthreads();
-        res.fallback = s_flag;
-        res.rcond = s_rc;
+        res.nsolves = s_ns;
+        const double est = s_est;
+        double rcond;
+        if (anorm == 0.0) rcond = 0.0;
+        else if (est != est) rcond = est;
+        else if (est == 0.0) rcond = 0.0;
+        else rcond = (1.0 / est) / anorm;
+        int fb = ADA_FALLBACK_NONE;
+        if (rcond != rcond) fb = ADA_FALLBACK_RCOND_NAN;
+        else if (rcond < thr) fb = ADA_FALLBACK_RCOND;
+        res.fallback = fb;
+        res.rcond = rcond;
         res.info = 0;
-        __syncthreads();
       }
       res.refine_iters = refine;
     }
