@@ -277,14 +277,18 @@ hipError_t launch_berr(int n, int nrhs, const double* R, int ldr, const double* 
 
 // Jacobi SVD least squares
 hipError_t launch_set_identity(int n, double* V, int ldv, hipStream_t st);
-hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, int max_sweeps, DevRec* rec,
-                               hipStream_t st);
-hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, DevRec* rec,
-                               hipStream_t st);
+// One-sided Jacobi on U's columns (n <= 256: all sweeps in one workgroup; otherwise one launch per round of the
+// round-robin order). Each rotation is applied to V's columns when V is not null (the accumulated rotations) and
+// to rows p and q of the ny columns of Y (ld ldy) when ny > 0 (projections w_j^T c, carried instead of V).
+hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, double* Y, int ldy, int ny,
+                               int max_sweeps, DevRec* rec, hipStream_t st);
+hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, double* Y, int ldy,
+                               int ny, DevRec* rec, hipStream_t st);
 hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st);
 // x = P sum over kept j of Ut_j (W_j^T C) / sigma_j^2, sigma_j = ||Ut_j|| (after the Jacobi on R^T: Ut = R^T W, W
 // the accumulated rotations, C = Q^T B, P the column order, row i of the sum goes to row perm[i] of X; perm NULL:
-// identity); also sets rec->sigma_max and rec->rank
+// identity); W NULL: C already holds the projections W^T Q^T B (rotated along with the columns); also sets
+// rec->sigma_max and rec->rank
 hipError_t launch_svd_apply(int n, int nrhs, const double* Ut, int ldu, const double* W, int ldw, const double* C,
                             int ldc, double* X, int ldx, const int* perm, double* sigma, double* T, DevRec* rec,
                             hipStream_t st);
@@ -303,9 +307,10 @@ hipError_t launch_rt(int n, const double* Q, int ldq, double* X, int ldx, hipStr
 // ---- host entry points shared by the C ABI and the solve server
 // ada_solve with the workspace planned for up to plan_nrhs right-hand sides (plan_nrhs >= nrhs), so that the
 // factors it leaves in `work` can serve later solves of up to plan_nrhs columns (solve_factored)
+// (keep_factors: the SVD route also keeps its accumulated rotations, which solve_factored needs)
 int solve_internal(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,
                    double* X, int ldx, void* work, size_t work_bytes, const ada_opts& o, ada_result* result,
-                   hipStream_t st);
+                   hipStream_t st, bool keep_factors);
 // X = A^{-1} B with the factors a completed solve_internal (same n, plan_nrhs, opts) left in `work`; A is the
 // matrix it solved (for the triangular route and the backward error); `orig` its result
 int solve_factored(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,

@@ -204,6 +204,7 @@ struct Solve {
   int counter_idx = 0;
   int epoch = 0;
   int lowp = ADA_PREC_FP64;  // operand precision of the trailing-matrix updates
+  bool keep_factors = false; // the factors left in the workspace serve later right-hand sides
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -476,9 +477,12 @@ int route_band(Solve& s, const double* GB0, double* GB, int kl, int ku, const do
 
 int route_svd(Solve& s, const double* A, int lda, const double* B, int ldb, double* X, int ldx, double* Wbuf,
               double* Vbuf, double* Tbuf) {
+  // W (the accumulated rotations) is kept only when the factors serve later right-hand sides; otherwise the
+  // rotations go to the projections C = Q^T B directly (half the Jacobi's memory traffic)
+  const bool keep_w = s.keep_factors;
   const int n = s.n;
   // A P = Q R (columns by decreasing norm); C = Q^T B (in R's slot: the residual is formed after the solve);
-  // Jacobi on R^T with V = I
+  // one-sided Jacobi on R^T, each rotation applied to W (started at I) or to the rows of C
   double* Q = s.at<double>(s.p.Q);
   double* tau = s.at<double>(s.p.tau);
   double* C = s.at<double>(s.p.R);
@@ -487,22 +491,25 @@ int route_svd(Solve& s, const double* A, int lda, const double* B, int ldb, doub
   HIPCHK(launch_copy(n, s.nrhs, B, ldb, C, n, s.st));
   HIPCHK(launch_house_qr(n, Q, n, tau, C, n, s.nrhs, s.st));
   HIPCHK(launch_rt(n, Q, n, Wbuf, n, s.st));
-  HIPCHK(launch_set_identity(n, Vbuf, n, s.st));
+  if (keep_w) HIPCHK(launch_set_identity(n, Vbuf, n, s.st));
+  double* V = keep_w ? Vbuf : nullptr;
+  double* Y = keep_w ? nullptr : C;
+  const int ny = keep_w ? 0 : s.nrhs;
   if (n <= kJacobiSmall) {
-    HIPCHK(launch_jacobi_small(n, Wbuf, n, Vbuf, n, 30, s.rec, s.st));
+    HIPCHK(launch_jacobi_small(n, Wbuf, n, V, n, Y, n, ny, 30, s.rec, s.st));
   } else {
     const int m = (n + 1) & ~1;
     int sweeps = 0;
     for (; sweeps < 30; ++sweeps) {
       HIPCHK(launch_clear_rotated(s.rec, s.st));
-      for (int r = 0; r < m - 1; ++r) HIPCHK(launch_jacobi_round(n, m, r, Wbuf, n, Vbuf, n, s.rec, s.st));
+      for (int r = 0; r < m - 1; ++r) HIPCHK(launch_jacobi_round(n, m, r, Wbuf, n, V, n, Y, n, ny, s.rec, s.st));
       TRY(s.sync_read());
       if (!s.ctx->host_rec->jacobi_rotated) { ++sweeps; break; }
     }
     s.ctx->host_rec->sweeps = sweeps;
     HIPCHK(hipMemcpyAsync(&s.rec->sweeps, &s.ctx->host_rec->sweeps, sizeof(int), hipMemcpyHostToDevice, s.st));
   }
-  HIPCHK(launch_svd_apply(n, s.nrhs, Wbuf, n, Vbuf, n, C, n, X, ldx, perm, s.at<double>(s.p.sigma), Tbuf, s.rec,
+  HIPCHK(launch_svd_apply(n, s.nrhs, Wbuf, n, V, n, C, n, X, ldx, perm, s.at<double>(s.p.sigma), Tbuf, s.rec,
                           s.st));
   return ADA_OK;
 }
@@ -696,7 +703,7 @@ static void collect_profile(ada_ctx ctx) {
 
 static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
                       int ldx, void* work, size_t work_bytes, const ada_opts& o, ada_result* result,
-                      hipStream_t st, int plan_nrhs) {
+                      hipStream_t st, int plan_nrhs, bool keep_factors) {
   Plan p;
   if (plan_nrhs < nrhs) return fail(ADA_ERR_ARG, "plan_nrhs < nrhs");
   if (!make_plan(n, plan_nrhs, o, p)) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
@@ -711,6 +718,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   s.rec = s.at<DevRec>(p.rec);
   s.n = n;
   s.nrhs = nrhs;
+  s.keep_factors = keep_factors;
   DevRec& h = *ctx->host_rec;
   ctx->ev_used = 0;
   ctx->pending.clear();
@@ -929,7 +937,7 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
   std::lock_guard<std::mutex> lock(ctx->mu);
   HIPCHK(hipSetDevice(ctx->device));
   return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, o, result,
-                    static_cast<hipStream_t>(stream), nrhs);
+                    static_cast<hipStream_t>(stream), nrhs, false);
 }
 
 }  // extern "C"
@@ -942,12 +950,12 @@ std::string last_error_string() { return g_err; }
 
 int solve_internal(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,
                    double* X, int ldx, void* work, size_t work_bytes, const ada_opts& o, ada_result* result,
-                   hipStream_t st) {
+                   hipStream_t st, bool keep_factors) {
   if (!ctx || !A || !B || !X || !result) return fail(ADA_ERR_ARG, "NULL context, matrix or result pointer");
   if (n < 1 || nrhs < 1 || lda < n || ldb < n || ldx < n) return fail(ADA_ERR_ARG, "bad n, nrhs or leading dimension");
   std::lock_guard<std::mutex> lock(ctx->mu);
   HIPCHK(hipSetDevice(ctx->device));
-  return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, o, result, st, plan_nrhs);
+  return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, o, result, st, plan_nrhs, keep_factors);
 }
 
 int solve_factored(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A, int lda, const double* B, int ldb,

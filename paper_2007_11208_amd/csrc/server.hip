@@ -295,7 +295,8 @@ void solve_worker(ada_server s, int w) {
     const int plan = keep ? kPlanRhs : r.nrhs;
     const size_t ws = ada_workspace_size(r.n, plan, &r.opts);
     char* work = s->base + j->off;
-    rc = ada::solve_internal(ctx, r.n, r.nrhs, plan, r.A, r.lda, r.B, r.ldb, r.X, r.ldx, work, ws, r.opts, &res, st);
+    rc = ada::solve_internal(ctx, r.n, r.nrhs, plan, r.A, r.lda, r.B, r.ldb, r.X, r.ldx, work, ws, r.opts, &res, st,
+                             keep);
     if (rc != ADA_OK) err = ada::last_error_string();
     bool kept = false;
     if (keep && rc == ADA_OK && res.route != ADA_ROUTE_NONE) {

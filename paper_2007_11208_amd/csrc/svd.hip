@@ -33,8 +33,8 @@ __device__ __forceinline__ void rotation(double alpha, double beta, double gamma
 }
 
 // whole algorithm in one workgroup (small n); U, V stay in L2
-__global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* U, int ldu, double* V, int ldv, int max_sweeps,
-                                                       DevRec* rec) {
+__global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* U, int ldu, double* V, int ldv, double* Y,
+                                                       int ldy, int ny, int max_sweeps, DevRec* rec) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
   const int m = (n + 1) & ~1;
   const double tol = (double)n * kEps;
@@ -69,12 +69,19 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* U, int ldu
           up[i] = c * x - s * y;
           uq[i] = s * x + c * y;
         }
-        double* vp = V + (size_t)p * ldv;
-        double* vq = V + (size_t)q * ldv;
-        for (int i = lane; i < n; i += 64) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = c * x - s * y;
-          vq[i] = s * x + c * y;
+        if (V) {
+          double* vp = V + (size_t)p * ldv;
+          double* vq = V + (size_t)q * ldv;
+          for (int i = lane; i < n; i += 64) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = c * x - s * y;
+            vq[i] = s * x + c * y;
+          }
+        }
+        for (int k = lane; k < ny; k += 64) {
+          const double x = Y[p + (size_t)k * ldy], y = Y[q + (size_t)k * ldy];
+          Y[p + (size_t)k * ldy] = c * x - s * y;
+          Y[q + (size_t)k * ldy] = s * x + c * y;
         }
         if (lane == 0) s_rot = 1;
       }
@@ -87,15 +94,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(int n, double* U, int ldu
   if (t == 0) rec->sweeps = sweeps;
 }
 
-hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, int max_sweeps, DevRec* rec,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), 0, st, n, U, ldu, V, ldv, max_sweeps, rec);
+hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, double* Y, int ldy, int ny,
+                               int max_sweeps, DevRec* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), 0, st, n, U, ldu, V, ldv, Y, ldy, ny, max_sweeps, rec);
   return hipGetLastError();
 }
 
 // one round of the tournament, one pair per workgroup
 __global__ __launch_bounds__(256) void k_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv,
-                                                      DevRec* rec) {
+                                                      double* Y, int ldy, int ny, DevRec* rec) {
   int a, b;
   rr_pair(m, round, blockIdx.x, a, b);
   if (a >= n || b >= n) return;
@@ -129,19 +136,26 @@ __global__ __launch_bounds__(256) void k_jacobi_round(int n, int m, int round, d
     up[i] = c * x - sn * y;
     uq[i] = sn * x + c * y;
   }
-  double* vp = V + (size_t)p * ldv;
-  double* vq = V + (size_t)q * ldv;
-  for (int i = t; i < n; i += blockDim.x) {
-    const double x = vp[i], y = vq[i];
-    vp[i] = c * x - sn * y;
-    vq[i] = sn * x + c * y;
+  if (V) {
+    double* vp = V + (size_t)p * ldv;
+    double* vq = V + (size_t)q * ldv;
+    for (int i = t; i < n; i += blockDim.x) {
+      const double x = vp[i], y = vq[i];
+      vp[i] = c * x - sn * y;
+      vq[i] = sn * x + c * y;
+    }
+  }
+  for (int r = t; r < ny; r += blockDim.x) {
+    const double x = Y[p + (size_t)r * ldy], y = Y[q + (size_t)r * ldy];
+    Y[p + (size_t)r * ldy] = c * x - sn * y;
+    Y[q + (size_t)r * ldy] = sn * x + c * y;
   }
   if (t == 0) atomicOr(&rec->jacobi_rotated, 1);
 }
 
-hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, DevRec* rec,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_round, dim3(m / 2), dim3(256), 0, st, n, m, round, U, ldu, V, ldv, rec);
+hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, double* Y, int ldy,
+                               int ny, DevRec* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_round, dim3(m / 2), dim3(256), 0, st, n, m, round, U, ldu, V, ldv, Y, ldy, ny, rec);
   return hipGetLastError();
 }
 
@@ -201,9 +215,14 @@ __global__ __launch_bounds__(256) void k_utb(int n, int nrhs, const double* U, i
   __shared__ double sh[4];
   for (int c = 0; c < nrhs; ++c) {
     double s = 0.0;
-    if (keep)
-      for (int i = threadIdx.x; i < n; i += blockDim.x)
-        s = fma(U[(size_t)i + (size_t)k * ldu], B[(size_t)i + (size_t)c * ldb], s);
+    if (keep) {
+      if (U) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+          s = fma(U[(size_t)i + (size_t)k * ldu], B[(size_t)i + (size_t)c * ldb], s);
+      } else if (threadIdx.x == 0) {
+        s = B[(size_t)k + (size_t)c * ldb];  // identity: the projection is the entry itself
+      }
+    }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
