@@ -15,9 +15,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libada_oracle.so")
 SRC_PATH = os.path.join(_HERE, "ada_oracle.c")
 
-GENERAL, BANDED, TRI_UPPER, TRI_LOWER, SYMPD = 0, 1, 2, 3, 4
-CLASS_NAMES = {GENERAL: "general", BANDED: "banded", TRI_UPPER: "tri_upper", TRI_LOWER: "tri_lower", SYMPD: "sympd"}
-ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd"}
+GENERAL, BANDED, TRI_UPPER, TRI_LOWER, SYMPD, SYM = 0, 1, 2, 3, 4, 5
+CLASS_NAMES = {GENERAL: "general", BANDED: "banded", TRI_UPPER: "tri_upper", TRI_LOWER: "tri_lower", SYMPD: "sympd",
+               SYM: "sym"}
+ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd", 6: "ldlt", 7: "tridiag"}
+# Section V extensions (future work of the paper), off by default
+EXT_SYM, EXT_TRIDIAG = 1, 2
 EPS = np.finfo(np.float64).eps
 
 
@@ -101,6 +104,19 @@ class Oracle:
         L.orc_berr_band.restype = d
         L.orc_solve.argtypes = [i, i, _P, i, _P, i, _P, i, i, d, i, ctypes.POINTER(_Result)]
         L.orc_solve_band.argtypes = [i, i, i, i, _P, i, _P, i, _P, i, i, d, ctypes.c_int64, ctypes.POINTER(_Result)]
+        L.orc_solve_ext.argtypes = [i, i, _P, i, _P, i, _P, i, i, d, i, i, ctypes.POINTER(_Result)]
+        L.orc_solve_band_ext.argtypes = [i, i, i, i, _P, i, _P, i, _P, i, i, d, ctypes.c_int64, i,
+                                         ctypes.POINTER(_Result)]
+        L.orc_sytrf_bk.argtypes = [i, _P, i, _P, _P, _PI]
+        L.orc_sytrf_bk.restype = i
+        L.orc_sytrs_bk.argtypes = [i, i, _P, i, _P, _P, _PI, _P, i]
+        L.orc_rcond_sym_bk.argtypes = [i, _P, i, _P, _P, _PI, d, _PI]
+        L.orc_rcond_sym_bk.restype = d
+        L.orc_gttrf.argtypes = [i, _P, _P, _P, _P, _PI]
+        L.orc_gttrf.restype = i
+        L.orc_gttrs.argtypes = [i, i, i, _P, _P, _P, _P, _PI, _P, i]
+        L.orc_rcond_gt.argtypes = [i, _P, _P, _P, _P, _PI, d, _PI]
+        L.orc_rcond_gt.restype = d
         L.orc_num_threads.restype = i
 
     # ---- helpers ----
@@ -251,26 +267,92 @@ class Oracle:
         w = self.lib.orc_berr(n, b2.shape[1], _dp(a), n, _dp(b2), n, _dp(x2), n, _dp(per))
         return w, per
 
-    def solve(self, a, b, no_approx=False, rcond_threshold=-1.0, force_general=False):
+    def sytrf_bk(self, a):
+        """Bunch-Kaufman LDL^T of the lower triangle: returns L (unit lower, as a full matrix), d, e
+        (the sub-diagonal of the 2x2 blocks), perm (P A P^T = L D L^T, row i of P A is row perm[i])
+        and info."""
+        f = self._mat(a).copy(order="F")
+        n = f.shape[0]
+        d, e = np.zeros(n), np.zeros(n)
+        perm = np.zeros(n, dtype=np.intc)
+        info = self.lib.orc_sytrf_bk(n, _dp(f), n, _dp(d), _dp(e), _ip(perm))
+        return np.tril(f, -1) + np.eye(n), d, e, perm, info
+
+    def sytrs_bk(self, l, d, e, perm, b):
+        x = self._mat(b).copy(order="F")
+        x2 = x.reshape(x.shape[0], -1, order="F")
+        l = self._mat(l)
+        n = l.shape[0]
+        self.lib.orc_sytrs_bk(n, x2.shape[1], _dp(l), n, _dp(d), _dp(e), _ip(perm), _dp(x2), n)
+        return x2.reshape(x.shape, order="F")
+
+    def rcond_sym_bk(self, a):
+        l, d, e, perm, info = self.sytrf_bk(a)
+        assert info == 0
+        l = self._mat(l)
+        ns = ctypes.c_int()
+        r = self.lib.orc_rcond_sym_bk(l.shape[0], _dp(l), l.shape[0], _dp(d), _dp(e), _ip(perm),
+                                      self.norm1_sym_lower(a), ctypes.byref(ns))
+        return r, ns.value
+
+    def gttrf(self, dl, dm, du):
+        """Tridiagonal LU with partial pivoting: returns dl (multipliers), dm, du, du2, ipiv, info."""
+        dl, dm, du = (np.array(v, dtype=np.float64, copy=True) for v in (dl, dm, du))
+        n = dm.shape[0]
+        dl2, du_2 = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        dl2[: n - 1] = dl
+        du_2[: n - 1] = du
+        du2 = np.zeros(max(n, 1))
+        ipiv = np.zeros(n, dtype=np.intc)
+        info = self.lib.orc_gttrf(n, _dp(dl2), _dp(dm), _dp(du_2), _dp(du2), _ip(ipiv))
+        return dl2[: n - 1], dm, du_2[: n - 1], du2[: max(n - 2, 0)], ipiv, info
+
+    def gttrs(self, dl, dm, du, du2, ipiv, b, trans=False):
+        x = self._mat(b).copy(order="F")
+        x2 = x.reshape(x.shape[0], -1, order="F")
+        n = dm.shape[0]
+        pad = lambda v: np.concatenate([np.asarray(v, dtype=np.float64), np.zeros(2)])
+        self.lib.orc_gttrs(int(trans), n, x2.shape[1], _dp(pad(dl)), _dp(np.asarray(dm, dtype=np.float64)),
+                           _dp(pad(du)), _dp(pad(du2)), _ip(np.asarray(ipiv, dtype=np.intc)), _dp(x2), n)
+        return x2.reshape(x.shape, order="F")
+
+    def rcond_gt(self, dl, dm, du):
+        """Condition estimate from the tridiagonal LU of the matrix with diagonals dl, dm, du."""
+        dm = np.asarray(dm, dtype=np.float64)
+        n = dm.shape[0]
+        anorm = np.abs(dm).copy()
+        anorm[1:] += np.abs(np.asarray(du, dtype=np.float64))
+        anorm[:-1] += np.abs(np.asarray(dl, dtype=np.float64))
+        f = self.gttrf(dl, dm, du)
+        assert f[5] == 0
+        pad = lambda v: np.concatenate([np.asarray(v, dtype=np.float64), np.zeros(2)])
+        fl, fd, fu, fu2 = pad(f[0]), np.ascontiguousarray(f[1]), pad(f[2]), pad(f[3])
+        ns = ctypes.c_int()
+        r = self.lib.orc_rcond_gt(n, _dp(fl), _dp(fd), _dp(fu), _dp(fu2), _ip(f[4]), float(anorm.max()),
+                                  ctypes.byref(ns))
+        return r, ns.value
+
+    def solve(self, a, b, no_approx=False, rcond_threshold=-1.0, force_general=False, ext=0):
         a = self._mat(a)
         b = self._mat(b)
         b2 = b.reshape(b.shape[0], -1, order="F")
         n = a.shape[0]
         x = np.zeros_like(b2, order="F")
         r = _Result()
-        self.lib.orc_solve(n, b2.shape[1], _dp(a), a.shape[0], _dp(b2), b2.shape[0], _dp(x), n,
-                           int(no_approx), float(rcond_threshold), int(force_general), ctypes.byref(r))
+        self.lib.orc_solve_ext(n, b2.shape[1], _dp(a), a.shape[0], _dp(b2), b2.shape[0], _dp(x), n,
+                               int(no_approx), float(rcond_threshold), int(force_general), int(ext), ctypes.byref(r))
         return x.reshape(b.shape, order="F"), _res_dict(r)
 
-    def solve_band(self, ab, kl, ku, b, no_approx=False, rcond_threshold=-1.0, dense_limit=1 << 26):
+    def solve_band(self, ab, kl, ku, b, no_approx=False, rcond_threshold=-1.0, dense_limit=1 << 26, ext=0):
         ab = self._mat(ab)
         b = self._mat(b)
         b2 = b.reshape(b.shape[0], -1, order="F")
         n = ab.shape[1]
         x = np.zeros_like(b2, order="F")
         r = _Result()
-        self.lib.orc_solve_band(n, kl, ku, b2.shape[1], _dp(ab), ab.shape[0], _dp(b2), b2.shape[0], _dp(x), n,
-                                int(no_approx), float(rcond_threshold), int(dense_limit), ctypes.byref(r))
+        self.lib.orc_solve_band_ext(n, kl, ku, b2.shape[1], _dp(ab), ab.shape[0], _dp(b2), b2.shape[0], _dp(x), n,
+                                    int(no_approx), float(rcond_threshold), int(dense_limit), int(ext),
+                                    ctypes.byref(r))
         return x.reshape(b.shape, order="F"), _res_dict(r)
 
 

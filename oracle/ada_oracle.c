@@ -486,6 +486,249 @@ double orc_rcond_band(int n, int kl, int ku, const double* AB, int ldab, const i
 }
 
 /* ======================================================================
+ * Section V (the future work it names): plain symmetric matrices.
+ * Reading: symmetric-indefinite LDL^T with Bunch-Kaufman partial pivoting
+ * (Bunch & Kaufman, Math. Comp. 31(137), 1977), P A P^T = L D L^T with L unit
+ * lower triangular and D block diagonal with 1x1 and 2x2 blocks.
+ * Written on a full symmetric copy S of the current Schur complement so that
+ * every step can be checked by eye. At column j (alpha = (1 + sqrt 17)/8):
+ *   colmax = largest |S(i,j)|, i > j, first such row r;
+ *   both |S(j,j)| and colmax zero: D(j) = 0, info = j+1 (first), nothing moves;
+ *   |S(j,j)| >= alpha colmax: 1x1 pivot, no interchange;
+ *   otherwise rowmax = largest off-diagonal |S(r,i)|, i >= j, i != r, and
+ *     |S(j,j)| rowmax >= alpha colmax^2: 1x1, no interchange;
+ *     |S(r,r)| >= alpha rowmax: 1x1, interchange j <-> r;
+ *     else: 2x2 pivot on (j, j+1), interchange j+1 <-> r.
+ * An interchange swaps rows and columns of S, rows of the L columns already
+ * formed and the entries of perm (so that P is one permutation at the end).
+ * Output: L strictly below the diagonal of A (L(j+1,j) = 0 at a 2x2 block),
+ * d[j] = D(j,j), e[j] = D(j+1,j) at the first column of a 2x2 block (else 0),
+ * perm[i] = the row of A that goes to position i. Returns info.
+ * ==================================================================== */
+static const double BK_ALPHA = 0.64038820320220756872767623199676; /* (1 + sqrt(17)) / 8 */
+
+static void sym_swap(int n, double* S, int a, int b) {
+  for (int c = 0; c < n; ++c) { const double t = EL(S, n, a, c); EL(S, n, a, c) = EL(S, n, b, c); EL(S, n, b, c) = t; }
+  for (int c = 0; c < n; ++c) { const double t = EL(S, n, c, a); EL(S, n, c, a) = EL(S, n, c, b); EL(S, n, c, b) = t; }
+}
+
+int orc_sytrf_bk(int n, double* A, int lda, double* d, double* e, int* perm) {
+  double* S = (double*)malloc(sizeof(double) * (size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) EL(S, n, i, j) = i >= j ? EL(A, lda, i, j) : EL(A, lda, j, i);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) EL(A, lda, i, j) = 0.0; /* becomes L (strict lower part) */
+  for (int i = 0; i < n; ++i) { perm[i] = i; d[i] = 0.0; e[i] = 0.0; }
+  int info = 0;
+  int j = 0;
+  while (j < n) {
+    int r = j;
+    double colmax = 0.0;
+    for (int i = j + 1; i < n; ++i)
+      if (fabs(EL(S, n, i, j)) > colmax) { colmax = fabs(EL(S, n, i, j)); r = i; }
+    const double absjj = fabs(EL(S, n, j, j));
+    int size = 1, swap_from = -1, swap_to = -1;
+    if (absjj == 0.0 && colmax == 0.0) {
+      if (info == 0) info = j + 1;
+      d[j] = 0.0;
+      ++j;
+      continue;
+    }
+    if (absjj < BK_ALPHA * colmax) {
+      double rowmax = 0.0;
+      for (int i = j; i < n; ++i)
+        if (i != r && fabs(EL(S, n, r, i)) > rowmax) rowmax = fabs(EL(S, n, r, i));
+      if (absjj * rowmax >= BK_ALPHA * colmax * colmax) {
+        /* 1x1, no interchange */
+      } else if (fabs(EL(S, n, r, r)) >= BK_ALPHA * rowmax) {
+        swap_from = j;
+        swap_to = r;
+      } else {
+        size = 2;
+        swap_from = j + 1;
+        swap_to = r;
+      }
+    }
+    if (swap_to >= 0 && swap_to != swap_from) {
+      sym_swap(n, S, swap_from, swap_to);
+      for (int c = 0; c < j; ++c) {
+        const double t = EL(A, lda, swap_from, c);
+        EL(A, lda, swap_from, c) = EL(A, lda, swap_to, c);
+        EL(A, lda, swap_to, c) = t;
+      }
+      const int t = perm[swap_from];
+      perm[swap_from] = perm[swap_to];
+      perm[swap_to] = t;
+    }
+    if (size == 1) {
+      const double dj = EL(S, n, j, j);
+      d[j] = dj;
+      for (int i = j + 1; i < n; ++i) EL(A, lda, i, j) = EL(S, n, i, j) / dj;
+#pragma omp parallel for schedule(static) if (n - j > 256)
+      for (int c = j + 1; c < n; ++c)
+        for (int i = j + 1; i < n; ++i) EL(S, n, i, c) -= EL(A, lda, i, j) * dj * EL(A, lda, c, j);
+      j += 1;
+    } else {
+      const double a = EL(S, n, j, j), b = EL(S, n, j + 1, j), c2 = EL(S, n, j + 1, j + 1);
+      const double det = a * c2 - b * b;
+      d[j] = a;
+      d[j + 1] = c2;
+      e[j] = b;
+      /* [l_i0 l_i1] = [s_i0 s_i1] D^{-1}, D^{-1} = [c2 -b; -b a] / det */
+      for (int i = j + 2; i < n; ++i) {
+        const double s0 = EL(S, n, i, j), s1 = EL(S, n, i, j + 1);
+        EL(A, lda, i, j) = (s0 * c2 - s1 * b) / det;
+        EL(A, lda, i, j + 1) = (s1 * a - s0 * b) / det;
+      }
+#pragma omp parallel for schedule(static) if (n - j > 256)
+      for (int c = j + 2; c < n; ++c)
+        for (int i = j + 2; i < n; ++i)
+          EL(S, n, i, c) -= EL(A, lda, i, j) * EL(S, n, c, j) + EL(A, lda, i, j + 1) * EL(S, n, c, j + 1);
+      j += 2;
+    }
+  }
+  free(S);
+  return info;
+}
+
+/* x = P^T L^{-T} D^{-1} L^{-1} P b for every right-hand side */
+void orc_sytrs_bk(int n, int nrhs, const double* L, int lda, const double* d, const double* e, const int* perm,
+                  double* B, int ldb) {
+#pragma omp parallel for schedule(static) if (nrhs > 1)
+  for (int r = 0; r < nrhs; ++r) {
+    double* b = B + (size_t)r * ldb;
+    double* y = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; ++i) y[i] = b[perm[i]];
+    orc_trsv(0, 0, 1, n, L, lda, y);
+    for (int j = 0; j < n;) {
+      if (j + 1 < n && e[j] != 0.0) {
+        const double a = d[j], bb = e[j], c2 = d[j + 1], det = a * c2 - bb * bb;
+        const double y0 = y[j], y1 = y[j + 1];
+        y[j] = (c2 * y0 - bb * y1) / det;
+        y[j + 1] = (a * y1 - bb * y0) / det;
+        j += 2;
+      } else {
+        y[j] /= d[j];
+        j += 1;
+      }
+    }
+    orc_trsv(0, 1, 1, n, L, lda, y);
+    for (int i = 0; i < n; ++i) b[perm[i]] = y[i];
+    free(y);
+  }
+}
+
+typedef struct { int n; const double* L; int lda; const double *d, *e; const int* perm; } sy_ctx;
+static void sy_apply(void* c, int kase, double* x) {
+  (void)kase; /* inv(A) is symmetric */
+  sy_ctx* q = (sy_ctx*)c;
+  orc_sytrs_bk(q->n, 1, q->L, q->lda, q->d, q->e, q->perm, x, q->n);
+}
+double orc_rcond_sym_bk(int n, const double* L, int lda, const double* d, const double* e, const int* perm,
+                        double anorm, int* nsolves) {
+  sy_ctx q = {n, L, lda, d, e, perm};
+  if (anorm == 0.0) { if (nsolves) *nsolves = 0; return 0.0; }
+  return rcond_from(anorm, orc_inv_norm1_est(n, sy_apply, &q, nsolves));
+}
+
+/* ======================================================================
+ * Section V (future work): tridiagonal matrices, the banded case kl = ku = 1.
+ * Reading: Gaussian elimination with partial pivoting in tridiagonal storage
+ * (dl: sub-, dm: main, du: super-diagonal). At row i the pivot is row i unless
+ * |dl_i| > |dm_i| (ties keep row i); an interchange brings a second
+ * super-diagonal du2 into U. L is unit lower bidiagonal (multipliers in dl),
+ * U upper triangular with the diagonals dm, du, du2. ipiv[i] = i or i+1.
+ * ==================================================================== */
+int orc_gttrf(int n, double* dl, double* dm, double* du, double* du2, int* ipiv) {
+  int info = 0;
+  for (int i = 0; i < n; ++i) ipiv[i] = i;
+  for (int i = 0; i < n - 2; ++i) du2[i] = 0.0;
+  for (int i = 0; i < n - 1; ++i) {
+    if (fabs(dm[i]) >= fabs(dl[i])) {
+      /* no interchange: eliminate dl[i] */
+      if (dm[i] != 0.0) {
+        const double f = dl[i] / dm[i];
+        dl[i] = f;
+        dm[i + 1] -= f * du[i];
+      }
+    } else {
+      /* interchange rows i and i+1 */
+      const double f = dm[i] / dl[i];
+      dm[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = dm[i + 1];
+      dm[i + 1] = t - f * dm[i + 1];
+      if (i < n - 2) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+      ipiv[i] = i + 1;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (dm[i] == 0.0) { info = i + 1; break; }
+  return info;
+}
+
+/* trans = 0: A x = b ; trans = 1: A^T x = b, with the factors of orc_gttrf */
+void orc_gttrs(int trans, int n, int nrhs, const double* dl, const double* dm, const double* du, const double* du2,
+               const int* ipiv, double* B, int ldb) {
+  for (int r = 0; r < nrhs; ++r) {
+    double* b = B + (size_t)r * ldb;
+    if (!trans) {
+      /* L y = P b, applied row by row */
+      for (int i = 0; i < n - 1; ++i) {
+        if (ipiv[i] == i) {
+          b[i + 1] -= dl[i] * b[i];
+        } else {
+          const double t = b[i];
+          b[i] = b[i + 1];
+          b[i + 1] = t - dl[i] * b[i];
+        }
+      }
+      /* U x = y */
+      for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        if (i + 1 < n) s -= du[i] * b[i + 1];
+        if (i + 2 < n) s -= du2[i] * b[i + 2];
+        b[i] = s / dm[i];
+      }
+    } else {
+      /* U^T z = b */
+      for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        if (i >= 1) s -= du[i - 1] * b[i - 1];
+        if (i >= 2) s -= du2[i - 2] * b[i - 2];
+        b[i] = s / dm[i];
+      }
+      /* L^T then P^T, from the last row up */
+      for (int i = n - 2; i >= 0; --i) {
+        if (ipiv[i] == i) {
+          b[i] -= dl[i] * b[i + 1];
+        } else {
+          const double t = b[i + 1];
+          b[i + 1] = b[i] - dl[i] * t;
+          b[i] = t;
+        }
+      }
+    }
+  }
+}
+
+typedef struct { int n; const double *dl, *dm, *du, *du2; const int* ipiv; } gt_ctx;
+static void gt_apply(void* c, int kase, double* x) {
+  gt_ctx* g = (gt_ctx*)c;
+  orc_gttrs(kase == 2, g->n, 1, g->dl, g->dm, g->du, g->du2, g->ipiv, x, g->n);
+}
+double orc_rcond_gt(int n, const double* dl, const double* dm, const double* du, const double* du2, const int* ipiv,
+                    double anorm, int* nsolves) {
+  gt_ctx g = {n, dl, dm, du, du2, ipiv};
+  if (anorm == 0.0) { if (nsolves) *nsolves = 0; return 0.0; }
+  return rcond_from(anorm, orc_inv_norm1_est(n, gt_apply, &g, nsolves));
+}
+
+/* ======================================================================
  * Section II-E: SVD-based minimum-norm least-squares fallback.
  * One-sided (Hestenes) Jacobi on the columns of U (initially A), cyclic by
  * rows over the pairs p<q. A pair is rotated when its inner product exceeds
@@ -662,13 +905,90 @@ static void copy_mat(int rows, int cols, const double* S, int lds, double* D, in
 }
 
 /* routes the system and fills X, info, rcond; returns 1 if the solver failed */
+static int exactly_symmetric(int n, const double* A, int lda) {
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 1; i < n; ++i)
+      if (!(EL(A, lda, i, j) == EL(A, lda, j, i))) return 0;
+  return 1;
+}
+
+/* LDL^T route (Section V future work, Bunch-Kaufman reading); returns 1 on failure */
+static int route_ldlt(int n, int nrhs, const double* A, int lda, double* X, int ldx, orc_result_t* res) {
+  double* F = (double*)malloc(sizeof(double) * (size_t)n * n);
+  double* d = (double*)malloc(sizeof(double) * (size_t)n);
+  double* e = (double*)malloc(sizeof(double) * (size_t)n);
+  int* perm = (int*)malloc(sizeof(int) * (size_t)n);
+  copy_mat(n, n, A, lda, F, n);
+  res->route = ORC_ROUTE_LDLT;
+  res->info = orc_sytrf_bk(n, F, n, d, e, perm);
+  int failed = res->info != 0;
+  if (!failed) {
+    orc_sytrs_bk(n, nrhs, F, n, d, e, perm, X, ldx);
+    res->rcond = orc_rcond_sym_bk(n, F, n, d, e, perm, orc_norm1_sym_lower(n, A, lda), NULL);
+  }
+  free(F);
+  free(d);
+  free(e);
+  free(perm);
+  return failed;
+}
+
+/* tridiagonal route (Section V future work): the three diagonals of A(i,j) = get(i,j) */
+static int route_gt(int n, int nrhs, const double* dl0, const double* dm0, const double* du0, double* X, int ldx,
+                    orc_result_t* res) {
+  double* dl = (double*)calloc((size_t)n + 1, sizeof(double));
+  double* dm = (double*)calloc((size_t)n + 1, sizeof(double));
+  double* du = (double*)calloc((size_t)n + 1, sizeof(double));
+  double* du2 = (double*)calloc((size_t)n + 1, sizeof(double));
+  int* ipiv = (int*)malloc(sizeof(int) * (size_t)n);
+  memcpy(dm, dm0, sizeof(double) * (size_t)n);
+  if (n > 1) {
+    memcpy(dl, dl0, sizeof(double) * (size_t)(n - 1));
+    memcpy(du, du0, sizeof(double) * (size_t)(n - 1));
+  }
+  /* ||A||_1: column j holds du(j-1), dm(j), dl(j) */
+  double anorm = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double c = fabs(dm0[j]);
+    if (j > 0) c += fabs(du0[j - 1]);
+    if (j < n - 1) c += fabs(dl0[j]);
+    if (c > anorm || c != c) anorm = c;
+  }
+  res->route = ORC_ROUTE_GT;
+  res->info = orc_gttrf(n, dl, dm, du, du2, ipiv);
+  const int failed = res->info != 0;
+  if (!failed) {
+    orc_gttrs(0, n, nrhs, dl, dm, du, du2, ipiv, X, ldx);
+    res->rcond = orc_rcond_gt(n, dl, dm, du, du2, ipiv, anorm, NULL);
+  }
+  free(dl);
+  free(dm);
+  free(du);
+  free(du2);
+  free(ipiv);
+  return failed;
+}
+
 static int run_route(int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
-                     orc_result_t* res) {
+                     int ext, orc_result_t* res) {
   copy_mat(n, nrhs, B, ldb, X, ldx);
   int failed = 0;
   res->info = 0;
   res->rcond = NAN;
-  if (res->cls == ORC_BANDED) {
+  if (res->cls == ORC_BANDED && (ext & ORC_EXT_TRIDIAG) && res->kl == 1 && res->ku == 1) {
+    double* dg = (double*)calloc(3 * (size_t)n, sizeof(double));
+    for (int i = 0; i < n; ++i) {
+      dg[n + i] = EL(A, lda, i, i);
+      if (i + 1 < n) {
+        dg[i] = EL(A, lda, i + 1, i);
+        dg[2 * n + i] = EL(A, lda, i, i + 1);
+      }
+    }
+    failed = route_gt(n, nrhs, dg, dg + n, dg + 2 * n, X, ldx, res);
+    free(dg);
+  } else if (res->cls == ORC_SYM) {
+    failed = route_ldlt(n, nrhs, A, lda, X, ldx, res);
+  } else if (res->cls == ORC_BANDED) {
     const int kl = res->kl, ku = res->ku, ldab = 2 * kl + ku + 1;
     double* AB = (double*)calloc((size_t)ldab * n, sizeof(double));
     int* ipiv = (int*)malloc(sizeof(int) * (size_t)n);
@@ -705,6 +1025,11 @@ static int run_route(int n, int nrhs, const double* A, int lda, const double* B,
         res->chol_failed = 1;
         res->info = info; /* replaced below by the LU's own info */
         general = 1;
+        if ((ext & ORC_EXT_SYM) && exactly_symmetric(n, A, lda)) {
+          /* with the symmetric-indefinite extension, LDL^T instead of LU */
+          general = 0;
+          failed = route_ldlt(n, nrhs, A, lda, X, ldx, res);
+        }
       } else {
         res->route = ORC_ROUTE_CHOL;
         orc_potrs_lower(n, nrhs, F, n, X, ldx);
@@ -731,6 +1056,11 @@ static int run_route(int n, int nrhs, const double* A, int lda, const double* B,
 
 void orc_solve(int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
                int no_approx, double rcond_threshold, int force_general, orc_result_t* res) {
+  orc_solve_ext(n, nrhs, A, lda, B, ldb, X, ldx, no_approx, rcond_threshold, force_general, 0, res);
+}
+
+void orc_solve_ext(int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
+                   int no_approx, double rcond_threshold, int force_general, int ext, orc_result_t* res) {
   memset(res, 0, sizeof(*res));
   res->rcond = NAN;
   res->berr = NAN;
@@ -746,9 +1076,11 @@ void orc_solve(int n, int nrhs, const double* A, int lda, const double* B, int l
     res->cls = d.cls;
     res->kl = d.kl;
     res->ku = d.ku;
+    /* extension: a plain symmetric matrix (equal to its transpose, not judged sympd) */
+    if (res->cls == ORC_GENERAL && (ext & ORC_EXT_SYM) && exactly_symmetric(n, A, lda)) res->cls = ORC_SYM;
   }
   res->rank = n;
-  const int failed = run_route(n, nrhs, A, lda, B, ldb, X, ldx, res);
+  const int failed = run_route(n, nrhs, A, lda, B, ldb, X, ldx, ext, res);
   if (failed) res->fallback = 1;
   else if (res->rcond != res->rcond) res->fallback = 3;
   else if (res->rcond < thr) res->fallback = 2;
@@ -773,6 +1105,13 @@ void orc_solve(int n, int nrhs, const double* A, int lda, const double* B, int l
 void orc_solve_band(int n, int kl_in, int ku_in, int nrhs, const double* ABin, int ldab_in, const double* B,
                     int ldb, double* X, int ldx, int no_approx, double rcond_threshold, int64_t dense_limit,
                     orc_result_t* res) {
+  orc_solve_band_ext(n, kl_in, ku_in, nrhs, ABin, ldab_in, B, ldb, X, ldx, no_approx, rcond_threshold, dense_limit, 0,
+                     res);
+}
+
+void orc_solve_band_ext(int n, int kl_in, int ku_in, int nrhs, const double* ABin, int ldab_in, const double* B,
+                        int ldb, double* X, int ldx, int no_approx, double rcond_threshold, int64_t dense_limit,
+                        int ext, orc_result_t* res) {
   memset(res, 0, sizeof(*res));
   res->rcond = NAN;
   res->berr = NAN;
@@ -806,31 +1145,44 @@ void orc_solve_band(int n, int kl_in, int ku_in, int nrhs, const double* ABin, i
     for (int j = 0; j < n; ++j)
       for (int i = imax(0, j - ku_in); i <= imin(n - 1, j + kl_in); ++i)
         A[(size_t)i + (size_t)j * n] = ABin[(size_t)(ku_in + i - j) + (size_t)j * ldab_in];
-    orc_solve(n, nrhs, A, n, B, ldb, X, ldx, no_approx, rcond_threshold, 0, res);
+    orc_solve_ext(n, nrhs, A, n, B, ldb, X, ldx, no_approx, rcond_threshold, 0, ext, res);
     free(A);
     return;
   }
   res->cls = ORC_BANDED;
   res->route = ORC_ROUTE_BAND_LU;
   res->rank = n;
-  const int ldab = 2 * kl + ku + 1;
-  double* AB = (double*)calloc((size_t)ldab * n, sizeof(double));
-  int* ipiv = (int*)malloc(sizeof(int) * (size_t)n);
-  for (int j = 0; j < n; ++j)
-    for (int i = imax(0, j - ku); i <= imin(n - 1, j + kl); ++i)
-      AB[(size_t)(kl + ku + i - j) + (size_t)j * ldab] = ABin[(size_t)(ku_in + i - j) + (size_t)j * ldab_in];
-  const double anorm = orc_norm1_band(n, kl, ku, AB, ldab, kl + ku);
-  copy_mat(n, nrhs, B, ldb, X, ldx);
   int failed = 0;
-  res->info = orc_gbtrf(n, kl, ku, AB, ldab, ipiv);
-  if (res->info) failed = 1;
-  else {
-    orc_gbtrs(0, n, kl, ku, nrhs, AB, ldab, ipiv, X, ldx);
-    res->rcond = orc_rcond_band(n, kl, ku, AB, ldab, ipiv, anorm, NULL);
-    if (!all_finite(n, nrhs, X, ldx)) failed = 1;
+  copy_mat(n, nrhs, B, ldb, X, ldx);
+  if ((ext & ORC_EXT_TRIDIAG) && kl == 1 && ku == 1) {
+    double* dg = (double*)calloc(3 * (size_t)n, sizeof(double));
+    for (int i = 0; i < n; ++i) {
+      dg[n + i] = ABin[(size_t)ku_in + (size_t)i * ldab_in];
+      if (i + 1 < n) {
+        dg[i] = ABin[(size_t)(ku_in + 1) + (size_t)i * ldab_in];
+        dg[2 * n + i] = ABin[(size_t)(ku_in - 1) + (size_t)(i + 1) * ldab_in];
+      }
+    }
+    failed = route_gt(n, nrhs, dg, dg + n, dg + 2 * n, X, ldx, res);
+    free(dg);
+  } else {
+    const int ldab = 2 * kl + ku + 1;
+    double* AB = (double*)calloc((size_t)ldab * n, sizeof(double));
+    int* ipiv = (int*)malloc(sizeof(int) * (size_t)n);
+    for (int j = 0; j < n; ++j)
+      for (int i = imax(0, j - ku); i <= imin(n - 1, j + kl); ++i)
+        AB[(size_t)(kl + ku + i - j) + (size_t)j * ldab] = ABin[(size_t)(ku_in + i - j) + (size_t)j * ldab_in];
+    const double anorm = orc_norm1_band(n, kl, ku, AB, ldab, kl + ku);
+    res->info = orc_gbtrf(n, kl, ku, AB, ldab, ipiv);
+    if (res->info) failed = 1;
+    else {
+      orc_gbtrs(0, n, kl, ku, nrhs, AB, ldab, ipiv, X, ldx);
+      res->rcond = orc_rcond_band(n, kl, ku, AB, ldab, ipiv, anorm, NULL);
+    }
+    free(AB);
+    free(ipiv);
   }
-  free(AB);
-  free(ipiv);
+  if (!failed && !all_finite(n, nrhs, X, ldx)) failed = 1;
   if (failed) res->fallback = 1;
   else if (res->rcond != res->rcond) res->fallback = 3;
   else if (res->rcond < thr) res->fallback = 2;

@@ -22,10 +22,16 @@ extern "C" {
 #endif
 
 /* structure classes (Section II, detection order banded -> triangular -> sympd) */
-enum { ORC_GENERAL = 0, ORC_BANDED = 1, ORC_TRI_UPPER = 2, ORC_TRI_LOWER = 3, ORC_SYMPD = 4 };
+enum { ORC_GENERAL = 0, ORC_BANDED = 1, ORC_TRI_UPPER = 2, ORC_TRI_LOWER = 3, ORC_SYMPD = 4,
+       ORC_SYM = 5 /* extension only: plain symmetric */ };
 /* solver whose x is returned */
 enum { ORC_ROUTE_NONE = 0, ORC_ROUTE_BAND_LU = 1, ORC_ROUTE_TRI = 2, ORC_ROUTE_CHOL = 3,
-       ORC_ROUTE_LU = 4, ORC_ROUTE_SVD = 5 };
+       ORC_ROUTE_LU = 4, ORC_ROUTE_SVD = 5, ORC_ROUTE_LDLT = 6, ORC_ROUTE_GT = 7 };
+/* extensions named as future work in Section V (off by default: the paper's classes and routes):
+   ORC_EXT_SYM: a matrix equal to its transpose that is not judged sympd (or whose Cholesky fails)
+   is solved by LDL^T with Bunch-Kaufman pivoting; ORC_EXT_TRIDIAG: a banded matrix with
+   kl = ku = 1 is solved by tridiagonal LU with partial pivoting. */
+enum { ORC_EXT_SYM = 1, ORC_EXT_TRIDIAG = 2 };
 /* status codes */
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONFINITE = -2, ORC_ERR_SINGULAR = -3,
        ORC_ERR_FALLBACK_INFEASIBLE = -6 };
@@ -76,6 +82,18 @@ double orc_rcond_chol(int n, const double* L, int lda, double anorm, int* nsolve
 double orc_rcond_tri(int upper, int n, const double* T, int ldt, double anorm, int* nsolves);
 double orc_rcond_band(int n, int kl, int ku, const double* AB, int ldab, const int* ipiv, double anorm, int* nsolves);
 
+/* ---- Section V extensions: symmetric indefinite (Bunch-Kaufman) and tridiagonal ---- */
+int orc_sytrf_bk(int n, double* A, int lda, double* d, double* e, int* perm);   /* returns info */
+void orc_sytrs_bk(int n, int nrhs, const double* L, int lda, const double* d, const double* e, const int* perm,
+                  double* B, int ldb);
+double orc_rcond_sym_bk(int n, const double* L, int lda, const double* d, const double* e, const int* perm,
+                        double anorm, int* nsolves);
+int orc_gttrf(int n, double* dl, double* dm, double* du, double* du2, int* ipiv); /* returns info */
+void orc_gttrs(int trans, int n, int nrhs, const double* dl, const double* dm, const double* du, const double* du2,
+               const int* ipiv, double* B, int ldb);
+double orc_rcond_gt(int n, const double* dl, const double* dm, const double* du, const double* du2, const int* ipiv,
+                    double anorm, int* nsolves);
+
 /* ---- SVD fallback (Section II-E) ---- */
 int orc_jacobi_svd(int n, double* U, int ldu, double* V, int ldv, double* sigma, int max_sweeps);
 int orc_svd_lstsq(int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
@@ -94,6 +112,13 @@ void orc_solve(int n, int nrhs, const double* A, int lda, const double* B, int l
 void orc_solve_band(int n, int kl_in, int ku_in, int nrhs, const double* AB, int ldab, const double* B, int ldb,
                     double* X, int ldx, int no_approx, double rcond_threshold, int64_t dense_limit,
                     orc_result_t* res);
+
+/* the same with the Section V extensions ORC_EXT_* switched on */
+void orc_solve_ext(int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
+                   int no_approx, double rcond_threshold, int force_general, int ext, orc_result_t* res);
+void orc_solve_band_ext(int n, int kl_in, int ku_in, int nrhs, const double* AB, int ldab, const double* B, int ldb,
+                        double* X, int ldx, int no_approx, double rcond_threshold, int64_t dense_limit, int ext,
+                        orc_result_t* res);
 
 int orc_num_threads(void);
 

@@ -587,3 +587,205 @@ def test_band_layout_driver(o=O):
     ab3[:, 10] = 0.0  # an all-zero column stays zero under elimination -> exact zero pivot
     _, r3 = o.solve_band(ab3, kl, ku, b, dense_limit=1000)
     assert r3["status"] == -6
+
+
+# ---------------------------------------------------------------- Section V extensions
+# Plain symmetric matrices by LDL^T with Bunch-Kaufman pivoting, tridiagonal matrices by
+# tridiagonal LU with partial pivoting (the future work the paper names; off by default).
+
+BK_ALPHA = (1.0 + np.sqrt(17.0)) / 8.0
+
+
+def _d_matrix(d, e):
+    n = d.shape[0]
+    return np.diag(d) + np.diag(e[: n - 1], -1) + np.diag(e[: n - 1], 1)
+
+
+def test_sytrf_bk_matches_lapack_ldl(o=O):
+    """LAPACK's dsytrf (through scipy.linalg.ldl) takes the same Bunch-Kaufman decisions:
+    the block diagonal D and the permuted unit lower factor agree."""
+    rng = np.random.default_rng(41)
+    for n in (1, 2, 3, 5, 17, 40, 90):
+        for t in range(3):
+            a = rng.standard_normal((n, n))
+            if t == 1:
+                a[np.diag_indices(n)] *= 1e-3  # small diagonal: many 2x2 pivots
+            a = F(a + a.T)
+            l, d, e, perm, info = o.sytrf_bk(a)
+            assert info == 0
+            lu2, d2, p2 = sla.ldl(a, lower=True)
+            np.testing.assert_allclose(_d_matrix(d, e), d2, rtol=1e-10, atol=1e-12 * np.abs(d2).max())
+            pt = np.eye(n)[perm].T
+            np.testing.assert_allclose(pt @ l, lu2, rtol=1e-9, atol=1e-11)
+
+
+def test_sytrf_bk_factorisation_identities(o=O):
+    """P A P^T = L D L^T, unit lower L, D of 1x1 and 2x2 blocks, perm a permutation, the
+    multipliers of 1x1 columns bounded by 1/(1-alpha), inertia of D = inertia of A."""
+    rng = np.random.default_rng(42)
+    for n in (4, 33, 120):
+        a = rng.standard_normal((n, n))
+        a[np.diag_indices(n)] *= 0.05
+        a = F(a + a.T)
+        l, d, e, perm, info = o.sytrf_bk(a)
+        assert info == 0 and sorted(perm) == list(range(n))
+        assert np.all(np.diag(l) == 1.0) and np.all(np.triu(l, 1) == 0.0)
+        dm = _d_matrix(d, e)
+        p = np.eye(n)[perm]
+        np.testing.assert_allclose(p @ a @ p.T, l @ dm @ l.T, atol=1e-12 * n * np.abs(a).max())
+        blocks = np.flatnonzero(e[: n - 1])
+        assert np.all(np.diff(blocks) >= 2), "2x2 blocks do not overlap"
+        assert np.all(l[blocks + 1, blocks] == 0.0), "no multiplier inside a 2x2 block"
+        assert len(blocks) > 0, "this matrix needs 2x2 pivots"
+        one = np.setdiff1d(np.arange(n), np.concatenate([blocks, blocks + 1]))
+        if one.size:
+            assert np.abs(l[:, one] - np.eye(n)[:, one]).max() <= 1.0 / (1.0 - BK_ALPHA) + 1e-12
+        ev_a = np.linalg.eigvalsh(a)
+        ev_d = np.linalg.eigvalsh(dm)
+        assert (np.sum(ev_a > 0), np.sum(ev_a < 0)) == (np.sum(ev_d > 0), np.sum(ev_d < 0))
+
+
+def test_sytrf_bk_pivot_rules_by_hand(o=O):
+    """The three Bunch-Kaufman cases on 3x3 matrices worked out by hand."""
+    # |a00| >= alpha*colmax: 1x1, no interchange
+    a = F([[4.0, 1.0, 2.0], [1.0, 3.0, 0.5], [2.0, 0.5, 5.0]])
+    l, d, e, perm, info = o.sytrf_bk(a)
+    assert list(perm)[0] == 0 and e[0] == 0.0 and d[0] == 4.0
+    # |a00| small, a_rr large against its row: 1x1 with interchange 0 <-> r (r = 2)
+    a = F([[0.0, 1.0, 2.0], [1.0, 0.0, 0.5], [2.0, 0.5, 10.0]])
+    l, d, e, perm, info = o.sytrf_bk(a)
+    assert perm[0] == 2 and d[0] == 10.0 and e[0] == 0.0
+    # |a00| small and a_rr small: 2x2 pivot on (0, r) with r moved to position 1
+    a = F([[0.0, 1.0, 3.0], [1.0, 0.0, 0.5], [3.0, 0.5, 0.0]])
+    l, d, e, perm, info = o.sytrf_bk(a)
+    assert list(perm[:2]) == [0, 2] and e[0] == 3.0 and d[0] == 0.0 and d[1] == 0.0
+    # |a00| * rowmax >= alpha * colmax^2: 1x1 with no interchange although |a00| < alpha*colmax
+    a = F([[1.0, 2.0, 0.0], [2.0, 0.0, 8.0], [0.0, 8.0, 0.0]])
+    l, d, e, perm, info = o.sytrf_bk(a)
+    assert perm[0] == 0 and d[0] == 1.0 and e[0] == 0.0
+
+
+def test_sytrf_bk_zero_column_info(o=O):
+    a = F(np.diag([2.0, 0.0, 3.0, 0.0]))
+    _, d, e, perm, info = o.sytrf_bk(a)
+    assert info == 2 and d[1] == 0.0
+    assert lapack.dsytrf(a, lower=1)[2] == 2
+
+
+def test_sytrs_and_rcond_sym_against_lapack(o=O):
+    rng = np.random.default_rng(43)
+    close = total = 0
+    for t in range(15):
+        n = int(rng.integers(3, 120))
+        a = rng.standard_normal((n, n))
+        a = F(a + a.T + (0.0 if t % 2 else 0.5) * np.eye(n))
+        l, d, e, perm, info = o.sytrf_bk(a)
+        assert info == 0
+        b = F(rng.standard_normal((n, 3)))
+        x = o.sytrs_bk(l, d, e, perm, b)
+        ref = np.linalg.solve(a, b)
+        np.testing.assert_allclose(x, ref, rtol=0, atol=10 * n * np.linalg.cond(a) * EPS * np.abs(ref).max())
+        lu2, ipiv2, info2 = lapack.dsytrf(a, lower=1)
+        r2, _ = lapack.dsycon(lu2, ipiv2, np.linalg.norm(a, 1), lower=1)
+        r1, _ = o.rcond_sym_bk(a)
+        exact = 1.0 / (np.linalg.norm(a, 1) * np.linalg.norm(np.linalg.inv(a), 1))
+        assert r1 >= exact * (1 - 1e-10) and r1 <= 3 * n * exact  # estimate of ||inv(A)||_1 is a lower bound
+        total += 1
+        close += abs(r1 - r2) <= 1e-8 * abs(r2)
+    assert close >= 0.9 * total
+
+
+def _tridiag(n, rng, dominant=False):
+    dl, dm, du = rng.standard_normal(n - 1), rng.standard_normal(n), rng.standard_normal(n - 1)
+    if dominant:
+        dm = dm + 4.0 * np.sign(dm)
+    return dl, dm, du
+
+
+def test_gttrf_matches_lapack_bitwise(o=O):
+    """dgttrf runs the same eliminations in the same order: identical factors and pivots."""
+    rng = np.random.default_rng(44)
+    for n in (3, 4, 7, 50, 301):  # (scipy's wrapper takes n >= 3)
+        for dom in (False, True):
+            dl, dm, du = _tridiag(n, rng, dom)
+            got = o.gttrf(dl, dm, du)
+            ref = lapack.dgttrf(dl.copy(), dm.copy(), du.copy())
+            for k in range(4):
+                assert np.array_equal(got[k], ref[k][: got[k].shape[0]]), (n, k)
+            assert np.array_equal(got[4], ref[4] - 1) and got[5] == ref[5]
+
+
+def test_gttrs_both_directions_and_rcond(o=O):
+    rng = np.random.default_rng(45)
+    close = total = 0
+    for n in (2, 5, 64, 257):
+        dl, dm, du = _tridiag(n, rng)
+        a = np.diag(dm) + np.diag(dl, -1) + np.diag(du, 1)
+        f = o.gttrf(dl, dm, du)
+        assert f[5] == 0
+        b = F(rng.standard_normal((n, 2)))
+        for trans in (False, True):
+            x = o.gttrs(*f[:5], b, trans=trans)
+            ref = np.linalg.solve(a.T if trans else a, b)
+            np.testing.assert_allclose(x, ref, rtol=0, atol=1e3 * np.linalg.cond(a) * EPS * np.abs(ref).max())
+        ab = np.zeros((3, n))
+        ab[0, 1:], ab[1], ab[2, :-1] = du, dm, dl
+        r_band, _ = o.rcond_band(F(ab), 1, 1)
+        r_gt, _ = o.rcond_gt(dl, dm, du)
+        if n >= 3:  # (scipy's wrapper takes n >= 3)
+            lf = lapack.dgttrf(dl.copy(), dm.copy(), du.copy())
+            r2, _ = lapack.dgtcon(*lf[:5], np.linalg.norm(a, 1))
+            total += 1
+            close += abs(r_gt - r2) <= 1e-8 * abs(r2)
+        # the banded route with kl = ku = 1 forms the same factors: the same estimate
+        assert abs(r_gt - r_band) <= 1e-12 * r_band
+    assert close >= 0.75 * total
+
+
+def test_gttrf_zero_pivot_info(o=O):
+    dl, dm, du = np.zeros(3), np.array([1.0, 0.0, 2.0, 3.0]), np.array([0.0, 0.0, 1.0])
+    f = o.gttrf(dl, dm, du)
+    assert f[5] == 2 and f[5] == lapack.dgttrf(dl.copy(), dm.copy(), du.copy())[5]
+
+
+def test_extension_routes_in_the_driver(o=O):
+    rng = np.random.default_rng(46)
+    # plain symmetric (fails Fig. 4): class sym, LDL^T; the paper's driver keeps LU
+    n = 150
+    a = rng.standard_normal((n, n))
+    a = F(a + a.T)
+    b = F(rng.standard_normal((n, 2)))
+    x0, r0 = o.solve(a, b)
+    x1, r1 = o.solve(a, b, ext=oracle.EXT_SYM)
+    assert r0["cls"] == oracle.GENERAL and r0["route"] == 4
+    assert r1["cls"] == oracle.SYM and r1["route"] == 6 and r1["fallback"] == 0 and r1["berr"] < 1e-14
+    np.testing.assert_allclose(x1, x0, rtol=0, atol=1e-8 * np.abs(x0).max())
+    assert 0.2 * r0["rcond"] <= r1["rcond"] <= 5 * r0["rcond"]
+    # a not exactly symmetric matrix stays general
+    a2 = a.copy(order="F")
+    a2[3, 7] += 1e-15
+    _, r2 = o.solve(a2, b, ext=oracle.EXT_SYM)
+    assert r2["cls"] == oracle.GENERAL and r2["route"] == 4
+    # sympd by Fig. 4 but Cholesky fails: LDL^T instead of LU
+    s = W.sym_indefinite(300, np.random.default_rng(0))
+    bs = F(rng.standard_normal((300, 1)))
+    _, rs = o.solve(s, bs, ext=oracle.EXT_SYM)
+    assert rs["cls"] == oracle.SYMPD and rs["chol_failed"] == 1 and rs["route"] == 6 and rs["berr"] < 1e-14
+    # singular symmetric: zero pivot -> solver failure -> SVD fallback
+    z = F([[1.0, 0.0, 1.0], [0.0, 0.0, 0.0], [1.0, 0.0, 2.0]])
+    _, rz = o.solve(z, F(np.ones((3, 1))), ext=oracle.EXT_SYM)
+    assert rz["route"] == 5 and rz["fallback"] == 1 and rz["info"] == 2
+    # tridiagonal: the tridiagonal route, same x as the band LU
+    n = 2000
+    dl, dm, du = _tridiag(n, rng)
+    ab = np.zeros((3, n))
+    ab[0, 1:], ab[1], ab[2, :-1] = du, dm, dl
+    bt = F(rng.standard_normal((n, 3)))
+    xb, rb = o.solve_band(F(ab), 1, 1, bt)
+    xt, rt = o.solve_band(F(ab), 1, 1, bt, ext=oracle.EXT_TRIDIAG)
+    assert rb["route"] == 1 and rt["route"] == 7 and rt["cls"] == oracle.BANDED and rt["fallback"] == 0
+    np.testing.assert_allclose(xt, xb, rtol=1e-12, atol=1e-12 * np.abs(xb).max())
+    assert abs(rt["rcond"] - rb["rcond"]) <= 1e-12 * rb["rcond"]
+    dense = np.diag(dm) + np.diag(dl, -1) + np.diag(du, 1)
+    xd, rd = o.solve(F(dense), bt, ext=oracle.EXT_TRIDIAG)
+    assert rd["route"] == 7 and np.array_equal(xd, xt)

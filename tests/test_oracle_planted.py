@@ -80,6 +80,32 @@ MUTATIONS = [
      "    const double den = anorm_inf * xn + bn;\n    const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);\n    if (per_rhs)",
      "    const double den = anorm_inf * xn;\n    const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);\n    if (per_rhs)",
      [P.test_berr_definition]),
+    ("bunch-kaufman alpha", "BK_ALPHA = 0.64038820320220756872767623199676;", "BK_ALPHA = 0.5;",
+     [P.test_sytrf_bk_matches_lapack_ldl, P.test_sytrf_bk_pivot_rules_by_hand]),
+    ("bunch-kaufman rowmax takes the diagonal",
+     "if (i != r && fabs(EL(S, n, r, i)) > rowmax)",
+     "if (fabs(EL(S, n, r, i)) > rowmax)",
+     [P.test_sytrf_bk_matches_lapack_ldl, P.test_sytrf_bk_pivot_rules_by_hand]),
+    ("bunch-kaufman interchange leaves the formed L rows",
+     "      for (int c = 0; c < j; ++c) {\n        const double t = EL(A, lda, swap_from, c);",
+     "      for (int c = 0; c < 0; ++c) {\n        const double t = EL(A, lda, swap_from, c);",
+     [P.test_sytrf_bk_factorisation_identities]),
+    ("bunch-kaufman 2x2 inverse sign",
+     "EL(A, lda, i, j) = (s0 * c2 - s1 * b) / det;",
+     "EL(A, lda, i, j) = (s0 * c2 + s1 * b) / det;",
+     [P.test_sytrf_bk_factorisation_identities]),
+    ("sytrs skips the 2x2 coupling",
+     "y[j] = (c2 * y0 - bb * y1) / det;",
+     "y[j] = (c2 * y0) / det;",
+     [P.test_sytrs_and_rcond_sym_against_lapack]),
+    ("gttrf drops the second super-diagonal",
+     "du2[i] = du[i + 1];",
+     "du2[i] = 0.0;",
+     [P.test_gttrf_matches_lapack_bitwise]),
+    ("gttrs transposed L step",
+     "          b[i + 1] = b[i] - dl[i] * t;",
+     "          b[i + 1] = b[i] + dl[i] * t;",
+     [P.test_gttrs_both_directions_and_rcond]),
 ]
 
 
