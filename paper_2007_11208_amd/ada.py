@@ -18,22 +18,25 @@ LIB_PATH = os.path.join(HERE, "libada.so")
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_SINGULAR, ERR_NOMEM, ERR_HIP, ERR_FALLBACK_INFEASIBLE = 0, -1, -2, -3, -4, -5, -6
 PENDING = 1
-CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD = 0, 1, 2, 3, 4
-ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD = 0, 1, 2, 3, 4, 5
+CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD, CLASS_SYM = 0, 1, 2, 3, 4, 5
+ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD, ROUTE_LDLT, ROUTE_TRIDIAG = range(8)
+# routes the paper names as future work (Section V), off by default: bits of Opts.extensions
+EXT_SYM, EXT_TRIDIAG = 1, 2
+EXTENSIONS = {"sym": EXT_SYM, "tridiag": EXT_TRIDIAG}
 LAYOUT_DENSE, LAYOUT_BAND = 0, 1
 PREC_FP64, PREC_FP32_IR, PREC_BF16_IR = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR, "bf16_ir": PREC_BF16_IR}
 # kernel families of the instrumentation (ADA_KF_*)
 KERNEL_FAMILIES = ("gemm", "panel", "laswp", "trsm_block", "potrf", "trsv", "gbtrf", "gbtrs", "detect", "jacobi")
-CLASS_NAMES = {0: "general", 1: "banded", 2: "tri_upper", 3: "tri_lower", 4: "sympd"}
-ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd"}
+CLASS_NAMES = {0: "general", 1: "banded", 2: "tri_upper", 3: "tri_lower", 4: "sympd", 5: "sym"}
+ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd", 6: "ldlt", 7: "tridiag"}
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("no_approx", ctypes.c_int32),
                 ("rcond_threshold", ctypes.c_double), ("layout", ctypes.c_int32),
                 ("kl_in", ctypes.c_int32), ("ku_in", ctypes.c_int32), ("force_general", ctypes.c_int32),
-                ("want_berr", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("want_berr", ctypes.c_int32), ("precision", ctypes.c_int32), ("extensions", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -121,7 +124,7 @@ def last_error() -> str:
 
 
 def make_opts(no_approx=False, rcond_threshold=-1.0, layout=LAYOUT_DENSE, kl_in=0, ku_in=0, force_general=False,
-              want_berr=True, precision="fp64") -> Opts:
+              want_berr=True, precision="fp64", extensions=()) -> Opts:
     o = Opts()
     lib().ada_opts_default(ctypes.byref(o))
     o.no_approx = int(no_approx)
@@ -134,6 +137,12 @@ def make_opts(no_approx=False, rcond_threshold=-1.0, layout=LAYOUT_DENSE, kl_in=
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
     o.precision = PRECISIONS[precision]
+    bits = 0
+    for e in extensions:
+        if e not in EXTENSIONS:
+            raise ValueError(f"extensions must be among {sorted(EXTENSIONS)}")
+        bits |= EXTENSIONS[e]
+    o.extensions = bits
     return o
 
 
@@ -240,8 +249,12 @@ def _result(r: Result, status: int) -> SolveResult:
 
 
 def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, want_berr=True, layout="dense",
-          kl_in=0, ku_in=0, out=None, work=None, ctx: Context | None = None, raise_on_error=True, precision="fp64"):
+          kl_in=0, ku_in=0, out=None, work=None, ctx: Context | None = None, raise_on_error=True, precision="fp64",
+          extensions=()):
     """Adaptive solve of A X = B on the GPU.
+
+    extensions: any of "sym" (plain symmetric matrices by Bunch-Kaufman LDL^T) and "tridiag"
+    (tridiagonal matrices by tridiagonal LU), the routes the paper names as future work.
 
     A: (n, n) float64 CUDA tensor, or for layout="band" the (kl_in+ku_in+1, n)
     LAPACK band storage (A[ku_in+i-j, j] = A(i, j)). B: (n,) or (n, nrhs).
@@ -262,7 +275,7 @@ def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, w
         raise ValueError("A must be n x n and match B")
     if lay == LAYOUT_BAND and Ac.shape[1] != n:
         raise ValueError("band storage must have n columns")
-    opts = make_opts(no_approx, rcond_threshold, lay, kl_in, ku_in, force_general, want_berr, precision)
+    opts = make_opts(no_approx, rcond_threshold, lay, kl_in, ku_in, force_general, want_berr, precision, extensions)
     ws = workspace_size(n, nrhs, opts)
     if ws == 0:
         raise ValueError("invalid shape for the workspace query")
@@ -291,7 +304,7 @@ class Batch:
     one descriptor each), solved by one ada_solve_batched launch per run()."""
 
     def __init__(self, As, Bs, device="cuda:0", no_approx=False, rcond_threshold=-1.0, force_general=False,
-                 want_berr=True, precision="fp64", ctx: Context | None = None):
+                 want_berr=True, precision="fp64", ctx: Context | None = None, extensions=()):
         import numpy as np
         import torch
         if len(As) != len(Bs) or not As:
@@ -323,7 +336,8 @@ class Batch:
         self.res = torch.zeros(self.count * ctypes.sizeof(Result), dtype=torch.uint8, device=dev)
         ws = int(lib().ada_batched_workspace_size(self.count))
         self.work = torch.empty(ws, dtype=torch.uint8, device=dev)
-        self.opts = make_opts(no_approx, rcond_threshold, LAYOUT_DENSE, 0, 0, force_general, want_berr, precision)
+        self.opts = make_opts(no_approx, rcond_threshold, LAYOUT_DENSE, 0, 0, force_general, want_berr, precision,
+                              extensions)
         self.ctx = ctx or context(dev.index or 0)
 
     def run(self):

@@ -50,6 +50,8 @@ struct DevRec {
   double sigma_max;
   int jacobi_rotated;         // a rotation happened in the current sweep
   int sweeps;                 // Jacobi sweeps used
+  int asym;                   // some A_ij != A_ji exactly (the LDL^T extension needs A = A^T)
+  int ldlt_kb;                // columns the last LDL^T panel factored
   // ---- synchronisation counters (zeroed per solve) ----
   unsigned int counters[512];  // grid barriers / tickets, one per launch that needs one
   int panel_flags[2 * 64];     // LU panel: per-workgroup publication epochs (two column parities)
@@ -289,6 +291,20 @@ hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st);
 // the accumulated rotations, C = Q^T B, P the column order, row i of the sum goes to row perm[i] of X; perm NULL:
 // identity); W NULL: C already holds the projections W^T Q^T B (rotated along with the columns); also sets
 // rec->sigma_max and rec->rank
+// ---- symmetric indefinite LDL^T, Bunch-Kaufman pivoting (ldlt.hip) ----
+// One panel of at most b columns from k0 (one workgroup): the updated columns (L D) go to Wp (n x b,
+// ld ldp), L to W, the interchange partner of each factored position to swp, D to d (diagonal) and
+// e (sub-diagonal of 2x2 blocks); the number of columns factored to rec->ldlt_kb; a zero pivot
+// column to rec->info.
+hipError_t launch_sytrf_panel(int n, int k0, int b, double* W, int ldw, double* Wp, int ldp, int* swp, double* d,
+                              double* e, DevRec* rec, hipStream_t st);
+// the panel's interchanges applied to the rows of the columns left of it and to perm
+hipError_t launch_ldlt_swap_left(int n, int k0, int kb, double* W, int ldw, const int* swp, int* perm,
+                                 hipStream_t st);
+// X = D^{-1} X for the block diagonal D (predicated like the triangular solves)
+hipError_t launch_ldlt_dsolve(int n, int nrhs, const double* d, const double* e, double* X, int ldx,
+                              const int* pred, int pred_val, hipStream_t st);
+
 hipError_t launch_svd_apply(int n, int nrhs, const double* Ut, int ldu, const double* W, int ldw, const double* C,
                             int ldc, double* X, int ldx, const int* perm, double* sigma, double* T, DevRec* rec,
                             hipStream_t st);

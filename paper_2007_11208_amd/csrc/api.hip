@@ -320,7 +320,8 @@ int band_solve(Solve& s, const double* GB, int kl, int ku, bool trans, double* X
 }
 
 int estimate(Solve& s, int route_kind, const double* F, int ldf, bool tri_lower, int kl, int ku) {
-  // route_kind: 0 LU (F = LU, perm), 1 Cholesky (F = L), 2 triangular (F = A), 3 band (F = GB)
+  // route_kind: 0 LU (F = LU, perm), 1 Cholesky (F = L), 2 triangular (F = A), 3 band (F = GB),
+  // 4 LDL^T (F = L, perm, D)
   const int n = s.n;
   double* v = s.at<double>(s.p.ev);
   double* t = s.at<double>(s.p.et);
@@ -347,6 +348,14 @@ int estimate(Solve& s, int route_kind, const double* F, int ldf, bool tri_lower,
       TRY(s.trsm(F, ldf, true, true, false, v, n, 1, phase, type));
     } else if (route_kind == 2) {
       TRY(s.trsm(F, ldf, tri_lower, type == 2, false, v, n, 1, phase, type));
+    } else if (route_kind == 4) {
+      // inv(A) is symmetric: both directions are the same solve
+      const int* perm = s.at<int>(s.p.perm);
+      HIPCHK(launch_gather_rows(n, 1, perm, v, n, t, n, phase, type, s.st));
+      TRY(s.trsm(F, ldf, true, false, true, t, n, 1, phase, type));
+      HIPCHK(launch_ldlt_dsolve(n, 1, s.at<double>(s.p.tau), s.at<double>(s.p.sigma), t, n, phase, type, s.st));
+      TRY(s.trsm(F, ldf, true, true, true, t, n, 1, phase, type));
+      HIPCHK(launch_scatter_rows(n, 1, perm, t, n, v, n, phase, type, s.st));
     } else {
       TRY(band_solve(s, F, kl, ku, type == 2, v, n, 1, t, n, phase, type));
     }
@@ -452,6 +461,56 @@ int route_tri(Solve& s, const double* A, int lda, bool lower, const double* B, i
   HIPCHK(launch_copy(s.n, s.nrhs, B, ldb, X, ldx, s.st));
   TRY(s.trsm(A, lda, lower, false, false, X, ldx, s.nrhs, stop, 0));
   return estimate(s, 2, A, lda, lower, 0, 0);
+}
+
+constexpr int kSyPanel = 32;  // LDL^T panel width (the last step may leave one column to the next)
+
+// Symmetric indefinite route (Section V future work): Bunch-Kaufman LDL^T, panels of up to kSyPanel
+// columns; the host reads back how many columns each panel factored (a 2x2 pivot may not straddle
+// the panel edge) and stops at the first zero pivot column.
+int route_ldlt(Solve& s, const double* A, int lda, const double* B, int ldb, double* X, int ldx) {
+  const int n = s.n, ldw = s.p.ldw;
+  double* W = s.at<double>(s.p.W);
+  double* Wp = s.at<double>(s.p.V);
+  int* swp = s.at<int>(s.p.ipiv);
+  int* perm = s.at<int>(s.p.perm);
+  double* d = s.at<double>(s.p.tau);
+  double* e = s.at<double>(s.p.sigma);
+  HIPCHK(launch_copy(n, n, A, lda, W, ldw, s.st));
+  HIPCHK(launch_iota(perm, n, s.st));
+  DevRec& h = *s.ctx->host_rec;
+  for (int k0 = 0; k0 < n;) {
+    const double m = (double)(n - k0), b = (double)(kSyPanel < n - k0 ? kSyPanel : n - k0);
+    // delayed updates of the panel's columns: sum over its columns of 2 m c flops; reads m x b twice
+    HIPCHK(s.timed(ADA_KF_PANEL, m * b * b, 16.0 * m * b, [&] {
+      return launch_sytrf_panel(n, k0, kSyPanel, W, ldw, Wp, n, swp, d, e, s.rec, s.st);
+    }));
+    TRY(s.sync_read());
+    const int kb = h.ldlt_kb;
+    if (kb < 1 || kb > n - k0) return fail(ADA_ERR_HIP, "LDL^T panel reported an impossible width");
+    HIPCHK(launch_ldlt_swap_left(n, k0, kb, W, ldw, swp, perm, s.st));
+    if (h.info != INT_MAX) {
+      HIPCHK(launch_mark_stop(s.rec, s.st));
+      return ADA_OK;
+    }
+    const int rest = n - k0 - kb;
+    if (rest > 0) {
+      const double* L21 = W + (k0 + kb) + (size_t)k0 * ldw;
+      const double* W21 = Wp + (k0 + kb);
+      double* A22 = W + (k0 + kb) + (size_t)(k0 + kb) * ldw;
+      TRY(s.gemm(rest, rest, kb, L21, ldw, W21, n, true, A22, ldw, true));
+    }
+    k0 += kb;
+  }
+  // X = P^T L^{-T} D^{-1} L^{-1} P B
+  int* stop = &s.rec->stop;
+  double* T = s.at<double>(s.p.T);
+  HIPCHK(launch_gather_rows(n, s.nrhs, perm, B, ldb, T, n, stop, 0, s.st));
+  TRY(s.trsm(W, ldw, true, false, true, T, n, s.nrhs, stop, 0));
+  HIPCHK(launch_ldlt_dsolve(n, s.nrhs, d, e, T, n, stop, 0, s.st));
+  TRY(s.trsm(W, ldw, true, true, true, T, n, s.nrhs, stop, 0));
+  HIPCHK(launch_scatter_rows(n, s.nrhs, perm, T, n, X, ldx, stop, 0, s.st));
+  return estimate(s, 4, W, ldw, false, 0, 0);
 }
 
 int route_band(Solve& s, const double* GB0, double* GB, int kl, int ku, const double* B, int ldb, double* X,
@@ -653,6 +712,7 @@ int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const doub
   if (o.layout != ADA_LAYOUT_DENSE) return fail(ADA_ERR_ARG, "batched solves take dense input only");
   if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR)
     return fail(ADA_ERR_ARG, "batched solves take precision ADA_PREC_FP64 or ADA_PREC_FP32_IR");
+  if (o.extensions != 0) return fail(ADA_ERR_ARG, "batched solves take the paper's routes only (extensions = 0)");
   if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(ADA_ERR_ARG, "work must be 256-byte aligned");
   if (work_bytes < ada_batched_workspace_size(count)) return fail(ADA_ERR_ARG, "workspace too small");
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -732,6 +792,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   const double* Ad = A;  // dense view of A (band-layout input: expanded copy when needed)
   int ldad = lda;
   bool band_route_from_band_layout = false;
+  bool exact_sym = false;  // A == A^T exactly (dense detection)
   int bkl = 0, bku = 0;
 
   if (o.layout == ADA_LAYOUT_BAND) {
@@ -773,6 +834,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
                                st));
     TRY(s.sync_read());
     if (h.nonfinite) return fail(ADA_ERR_NONFINITE, "A or B holds NaN or Inf");
+    exact_sym = !h.asym;
     if (o.force_general) {
       cls = ADA_CLASS_GENERAL;
       kl = ku = -1;
@@ -787,6 +849,7 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
         const double max_lower = bits_to_double(h.max_lower_bits);
         const bool sympd = !h.diag_nonpos && !h.sym_bad && (max_lower < max_diag);
         cls = sympd ? ADA_CLASS_SYMPD : ADA_CLASS_GENERAL;
+        if (cls == ADA_CLASS_GENERAL && (o.extensions & ADA_EXT_SYM) && exact_sym) cls = ADA_CLASS_SYM;
       }
     }
   }
@@ -828,18 +891,22 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   } else if (cls == ADA_CLASS_GENERAL) {
     route = ADA_ROUTE_LU;
     TRY(route_lu(s, Ad, ldad, B, ldb, X, ldx));
+  } else if (cls == ADA_CLASS_SYM) {
+    route = ADA_ROUTE_LDLT;
+    TRY(route_ldlt(s, Ad, ldad, B, ldb, X, ldx));
   } else if (cls == ADA_CLASS_SYMPD) {
     route = ADA_ROUTE_CHOL;
     TRY(route_chol(s, Ad, ldad, B, ldb, X, ldx));
     TRY(s.sync_read());
     if (h.timeout) return fail(ADA_ERR_HIP, "a bounded device wait timed out");
     if (h.chol_info != INT_MAX) {
-      // Cholesky failed: not sympd after all -> LU on the original A
+      // Cholesky failed: not sympd after all -> LU on the original A (LDL^T with the symmetric extension)
       chol_failed = 1;
-      route = ADA_ROUTE_LU;
+      const bool ldlt = (o.extensions & ADA_EXT_SYM) && exact_sym;
+      route = ldlt ? ADA_ROUTE_LDLT : ADA_ROUTE_LU;
       HIPCHK(launch_init_rec(s.rec, st));
       HIPCHK(launch_anorm(n, s.at<double>(p.ctot), s.at<double>(p.csym), s.at<double>(p.rtot), 0, s.rec, st));
-      TRY(route_lu(s, Ad, ldad, B, ldb, X, ldx));
+      TRY(ldlt ? route_ldlt(s, Ad, ldad, B, ldb, X, ldx) : route_lu(s, Ad, ldad, B, ldb, X, ldx));
     }
   } else if (cls == ADA_CLASS_TRI_UPPER || cls == ADA_CLASS_TRI_LOWER) {
     route = ADA_ROUTE_TRI;
@@ -862,6 +929,10 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
     else
       HIPCHK(launch_band_pack_dense(n, bkl, bku, Ad, ldad, G0, ldgb, st));
     HIPCHK(launch_band_norms(n, bkl, bku, G0, ldgb, s.rec, st));
+    // tridiagonal extension: LU with partial pivoting of the three diagonals; at kl = ku = 1 the band
+    // kernels run exactly the tridiagonal eliminations (pivot between rows i and i+1, one fill
+    // diagonal), so the route shares them
+    if ((o.extensions & ADA_EXT_TRIDIAG) && bkl == 1 && bku == 1) route = ADA_ROUTE_TRIDIAG;
     TRY(route_band(s, G0, W, bkl, bku, B, ldb, X, ldx));
   }
   // backward error of the routed x (also flags a non-finite x)
@@ -931,6 +1002,7 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
   if (o.layout != ADA_LAYOUT_DENSE && o.layout != ADA_LAYOUT_BAND) return fail(ADA_ERR_ARG, "unknown layout");
   if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR && o.precision != ADA_PREC_BF16_IR)
     return fail(ADA_ERR_ARG, "unknown precision");
+  if (o.extensions & ~(ADA_EXT_SYM | ADA_EXT_TRIDIAG)) return fail(ADA_ERR_ARG, "unknown extension bits");
   if (n < 1 || nrhs < 1) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
   if (o.layout == ADA_LAYOUT_DENSE && lda < n) return fail(ADA_ERR_ARG, "lda < n");
   if (ldb < n || ldx < n) return fail(ADA_ERR_ARG, "ldb or ldx < n");
@@ -998,11 +1070,22 @@ int solve_factored(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A,
       TRY(s.trsm(W, p.ldw, true, false, false, X, ldx, nrhs, stop, 0));
       TRY(s.trsm(W, p.ldw, true, true, false, X, ldx, nrhs, stop, 0));
       break;
+    case ADA_ROUTE_LDLT: {
+      const int* perm = s.at<int>(p.perm);
+      double* T = s.at<double>(p.T);
+      HIPCHK(launch_gather_rows(n, nrhs, perm, B, ldb, T, n, stop, 0, st));
+      TRY(s.trsm(W, p.ldw, true, false, true, T, n, nrhs, stop, 0));
+      HIPCHK(launch_ldlt_dsolve(n, nrhs, s.at<double>(p.tau), s.at<double>(p.sigma), T, n, stop, 0, st));
+      TRY(s.trsm(W, p.ldw, true, true, true, T, n, nrhs, stop, 0));
+      HIPCHK(launch_scatter_rows(n, nrhs, perm, T, n, X, ldx, stop, 0, st));
+      break;
+    }
     case ADA_ROUTE_TRI:
       HIPCHK(launch_copy(n, nrhs, B, ldb, X, ldx, st));
       TRY(s.trsm(A, lda, orig.cls == ADA_CLASS_TRI_LOWER, false, false, X, ldx, nrhs, stop, 0));
       break;
     case ADA_ROUTE_BAND_LU:
+    case ADA_ROUTE_TRIDIAG:
       HIPCHK(launch_copy(n, nrhs, B, ldb, X, ldx, st));
       TRY(band_solve(s, W, orig.kl, orig.ku, false, X, ldx, nrhs, s.at<double>(p.T), n, stop, 0));
       break;

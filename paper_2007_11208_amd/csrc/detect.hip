@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_detect_dense(int n, const double* __res
   __syncthreads();
 
   __shared__ double s_cs[64], s_rs[64];
-  int kl_c = 0, ku_c = 0, nonfin = 0, bad = 0;
+  int kl_c = 0, ku_c = 0, nonfin = 0, bad = 0, asym = 0;
   double maxlow = 0.0;
   double rowX = 0.0;  // row i = I*64+r over this thread's 16 columns (strictly lower part for the diag tile)
   double colY = 0.0;  // column i = I*64+r from the mirror elements (strictly upper part)
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(256) void k_detect_dense(int n, const double* __res
       nonfin |= !isfinite(a) || !isfinite(bm);
       if (a != 0.0) kl_c = max(kl_c, gi - gj);
       if (bm != 0.0) ku_c = max(ku_c, gi - gj);
+      if (a != bm) asym = 1;                                           // exact symmetry
       const double delta = fabs(a - bm);
       if (delta > tol && delta > tol * fmax(aa, ab)) bad = 1;          // Fig. 4 lines 12-14
       if ((aa + ab) >= (dii + sdJ[c])) bad = 1;                        // Fig. 4 line 16
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(256) void k_detect_dense(int n, const double* __res
   ku_c = wave_max_int(ku_c);
   nonfin = wave_or(nonfin);
   bad = wave_or(bad);
+  asym = wave_or(asym);
   dnonpos = wave_or(dnonpos);
   dzero = wave_min_int(dzero);
   maxlow = wave_max(maxlow);
@@ -169,22 +171,23 @@ __global__ __launch_bounds__(256) void k_detect_dense(int n, const double* __res
   const int w = t >> 6;
   if (r == 0) {
     s_red[w][0] = kl_c; s_red[w][1] = ku_c; s_red[w][2] = nonfin; s_red[w][3] = bad;
-    s_red[w][4] = dnonpos; s_red[w][5] = dzero;
+    s_red[w][4] = dnonpos; s_red[w][5] = dzero; s_red[w][6] = asym;
     s_redd[w][0] = maxlow; s_redd[w][1] = dmax;
   }
   __syncthreads();
   if (t == 0) {
-    int k0 = 0, k1 = 0, nf = 0, bd = 0, dn = 0, dz = INT_MAX;
+    int k0 = 0, k1 = 0, nf = 0, bd = 0, dn = 0, dz = INT_MAX, as = 0;
     double ml = 0.0, dm = 0.0;
     for (int i = 0; i < 4; ++i) {
       k0 = max(k0, s_red[i][0]); k1 = max(k1, s_red[i][1]); nf |= s_red[i][2]; bd |= s_red[i][3];
-      dn |= s_red[i][4]; dz = min(dz, s_red[i][5]);
+      dn |= s_red[i][4]; dz = min(dz, s_red[i][5]); as |= s_red[i][6];
       ml = fmax(ml, s_redd[i][0]); dm = fmax(dm, s_redd[i][1]);
     }
     if (k0) atomicMax(&rec->kl, k0);
     if (k1) atomicMax(&rec->ku, k1);
     if (nf) atomicOr(&rec->nonfinite, 1);
     if (bd) atomicOr(&rec->sym_bad, 1);
+    if (as) atomicOr(&rec->asym, 1);
     if (dn) atomicOr(&rec->diag_nonpos, 1);
     if (dz != INT_MAX) atomicMin(&rec->diag_zero_first, dz);
     if (ml > 0.0) atomicMax(&rec->max_lower_bits, dbits(ml));

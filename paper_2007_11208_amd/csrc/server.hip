@@ -425,7 +425,7 @@ size_t ada_request_footprint(const ada_request* r) {
   ada_opts o;
   if (!normalized_opts(r->opts, o)) return 0;
   if (!r->keep_factor && r->n >= 1 && r->n <= kSmallN && r->nrhs >= 1 && r->nrhs <= kSmallRhs &&
-      o.precision != ADA_PREC_BF16_IR)
+      o.precision != ADA_PREC_BF16_IR && o.extensions == 0)
     return 0;
   const int plan = r->keep_factor ? kPlanRhs : r->nrhs;
   size_t b = ada_workspace_size(r->n, plan, &o);
@@ -471,7 +471,9 @@ int ada_submit(ada_server s, const ada_request* r, ada_ticket* out) {
       delete j;
       return fail_s(ADA_ERR_ARG, "dense requests support n <= 16384");
     }
-    const bool small = !r->keep_factor && r->n <= kSmallN && r->nrhs <= kSmallRhs && o.precision != ADA_PREC_BF16_IR;
+    // the batched kernel runs the paper's routes only: requests with extensions take a solve worker
+    const bool small = !r->keep_factor && r->n <= kSmallN && r->nrhs <= kSmallRhs &&
+                       o.precision != ADA_PREC_BF16_IR && o.extensions == 0;
     j->kind = small ? JOB_BATCH : JOB_SINGLE;
     if (!small) {
       ada_request rq = j->req;
