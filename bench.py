@@ -433,6 +433,62 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_extensions(args, cases, ctx, dev):
+    """The routes the paper names as future work, beside the paper's routes on the same systems:
+    the symmetric-indefinite system (Cholesky fails; LU vs LDL^T), a plain symmetric n=4096 system
+    (LU vs LDL^T) and a tridiagonal n=1e6 band-layout system (band LU vs the tridiagonal route)."""
+    import torch
+    from paper_2007_11208_amd import ada
+    out = {}
+
+    def timed(label, A, B, X, work, exts, **kw):
+        ts, r = [], None
+        ctx.profile_reset()
+        for k in range(args.ext_steps + 1):
+            if k == 1:
+                ctx.profile(True)
+            t0 = time.perf_counter()
+            _, r = ada.solve(A, B, out=X, work=work, ctx=ctx, extensions=exts, **kw)
+            if k:
+                ts.append(time.perf_counter() - t0)
+        ctx.profile(False)
+        pr = ctx.profile_all()
+        if not (r.berr <= BERR_BAR):
+            print(f"backward error {r.berr} of {label} above {BERR_BAR}", file=sys.stderr)
+            sys.exit(1)
+        pl = pr["panel"]
+        out[label] = {"route": r.route, "chol_failed": r.chol_failed, "berr": r.berr, "rcond": r.rcond,
+                      "p50_ms": round(pct(ts, 50) * 1e3, 3),
+                      "panel_avg_us": round(pl[1] * 1e3 / pl[0], 2) if pl[0] else None,
+                      "panel_ms_per_solve": round(pl[1] / len(ts), 3)}
+
+    sym = [c for c in cases if c[0] == "symindef"]
+    if sym:
+        name, A, B, kw, work, X, n = sym[0]
+        for label, exts in (("symindef_paper", ()), ("symindef_ldlt", ("sym",))):
+            timed(label, A, B, X, work, exts)
+        g = torch.Generator(device=dev).manual_seed(4242)
+        M = torch.randn((n, n), generator=g, dtype=torch.float64, device=dev)
+        M = (M + M.t()).contiguous().t()  # column-major storage of the symmetric matrix
+        for label, exts in (("plain_sym_n4096_paper", ()), ("plain_sym_n4096_ldlt", ("sym",))):
+            timed(label, M, B, X, work, exts)
+        del M
+    nt = 1_000_000
+    g = torch.Generator(device=dev).manual_seed(4343)
+    ab = torch.randn((nt, 3), generator=g, dtype=torch.float64, device=dev).t()  # (3, n) column-major
+    ab[1] += 3.0 * torch.sign(ab[1])  # well conditioned; interchanges still occur where |dl| > |d|
+    ab[0, 0] = 0.0
+    ab[2, nt - 1] = 0.0
+    bt = torch.randn((args.nrhs, nt), generator=g, dtype=torch.float64, device=dev).t()
+    xt = torch.empty_like(bt)
+    o = ada.make_opts(layout=ada.LAYOUT_BAND, kl_in=1, ku_in=1)
+    wt = torch.empty(ada.workspace_size(nt, args.nrhs, o), dtype=torch.uint8, device=dev)
+    for label, exts in (("tridiag_n1e6_paper", ()), ("tridiag_n1e6_ext", ("tridiag",))):
+        timed(label, ab, bt, xt, wt, exts, layout="band", kl_in=1, ku_in=1)
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,6 +501,9 @@ def main():
                     help="single: the five large systems; batched: many small systems in one launch per step")
     ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
     ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
+    ap.add_argument("--ext-steps", type=int, default=3,
+                    help="single workload: also time the Section V extension routes (LDL^T, tridiagonal) "
+                         "against the paper's routes on systems of the same shapes")
     ap.add_argument("--concurrent-steps", type=int, default=3,
                     help="single workload: also time this many steps with the systems solved concurrently "
                          "(one stream each; reported beside the sequential value); 0: skip")
@@ -605,6 +664,8 @@ def main():
                       "ms_per_step": round(sum(ct) / len(ct) * 1e3, 3),
                       "p50_step_ms": round(pct(ct, 50) * 1e3, 3), "max_berr": cworst, "streams": len(cases)}
 
+    extensions = bench_extensions(args, cases, ctx, dev) if args.ext_steps > 0 else None
+
     cpu = None
     if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(args.nrhs)
@@ -619,7 +680,7 @@ def main():
         "tflops": round(flops_step * args.steps / total / 1e12, 4),
         "p50_step_ms": round(pct(step_times, 50) * 1e3, 3), "p99_step_ms": round(pct(step_times, 99) * 1e3, 3),
         "max_berr": worst_berr, "per_system": per_sys, "kernel_families": families,
-        "roofline": roofline, "cpu_baseline": cpu, "concurrent": concurrent,
+        "roofline": roofline, "cpu_baseline": cpu, "concurrent": concurrent, "extensions": extensions,
     }
     print(json.dumps(out), flush=True)
 

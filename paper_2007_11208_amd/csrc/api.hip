@@ -463,7 +463,7 @@ int route_tri(Solve& s, const double* A, int lda, bool lower, const double* B, i
   return estimate(s, 2, A, lda, lower, 0, 0);
 }
 
-constexpr int kSyPanel = 32;  // LDL^T panel width (the last step may leave one column to the next)
+constexpr int kSyPanel = 16;  // LDL^T panel width (the last step may leave one column to the next)
 
 // Symmetric indefinite route (Section V future work): Bunch-Kaufman LDL^T, panels of up to kSyPanel
 // columns; the host reads back how many columns each panel factored (a 2x2 pivot may not straddle

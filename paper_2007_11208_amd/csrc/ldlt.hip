@@ -33,6 +33,42 @@ __device__ void block_argmax(double& v, int& idx, double* sv, int* si) {
     if (si[q] >= 0 && (idx < 0 || sv[q] > v || (sv[q] == v && si[q] < idx))) { v = sv[q]; idx = si[q]; }
 }
 
+// Rows i = i0 + q*SP_T (q < 4) of "raw column minus the panel's contribution": v_q = raw(i) -
+// sum_{c < jj} L(i, k0+c) s[c], with raw(i) = W(i, col) below the diagonal position `mirror` and
+// W(mirror, i) above it (mirror < 0: always W(i, col)). Four rows and four panel columns per step
+// keep sixteen loads in flight per thread (the panel's L columns stream from L2). Rows past the
+// end are clamped to n-1 (valid addresses, results unused).
+__device__ __forceinline__ void panel_rows(int n, int i0, int col, int mirror, int k0, int jj,
+                                           const double* __restrict__ W, int ldw, const double* s, double v[4]) {
+  int ir[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ir[q] = min(i0 + q * SP_T, n - 1);
+    v[q] = (mirror >= 0 && ir[q] < mirror) ? W[mirror + (size_t)ir[q] * ldw] : W[ir[q] + (size_t)col * ldw];
+  }
+  // 32-bit offsets from the uniform panel base (n <= 16384: the panel spans < 2^31 elements)
+  const double* L = W + (size_t)k0 * ldw;
+  int c = 0;
+  for (; c + 4 <= jj; c += 4) {
+    double l[4][4];
+    const int cb = c * ldw;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) l[u][q] = L[ir[q] + cb + u * ldw];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = fma(-l[u][q], s[c + u], v[q]);
+  }
+  for (; c < jj; ++c) {
+    const double sc = s[c];
+    const int cb = c * ldw;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = fma(-L[ir[q] + cb], sc, v[q]);
+  }
+}
+
 // kind of pivot: 0 zero column, 1 1x1 in place, 2 1x1 with j <-> r, 3 2x2 with j+1 <-> r
 __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, double* __restrict__ W, int ldw,
                                                       double* __restrict__ Wp, int ldp, int* __restrict__ swp,
@@ -53,12 +89,17 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
     __syncthreads();
     double best = -1.0;
     int bi = -1;
-    for (int i = j + t; i < n; i += SP_T) {
-      double v = W[i + (size_t)j * ldw];
-      for (int c = 0; c < jj; ++c) v = fma(-W[i + (size_t)(k0 + c) * ldw], s_wj[c], v);
-      Wp[i + (size_t)jj * ldp] = v;
-      if (i == j) s_val[0] = v;
-      else if (fabs(v) > best) { best = fabs(v); bi = i; }
+    for (int i0 = j + t; i0 < n; i0 += 4 * SP_T) {
+      double v[4];
+      panel_rows(n, i0, j, -1, k0, jj, W, ldw, s_wj, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q * SP_T;
+        if (i >= n) break;
+        Wp[i + (size_t)jj * ldp] = v[q];
+        if (i == j) s_val[0] = v[q];
+        else if (fabs(v[q]) > best) { best = fabs(v[q]); bi = i; }
+      }
     }
     block_argmax(best, bi, s_rv, s_ri);
     const double colmax = bi >= 0 ? best : 0.0;
@@ -75,12 +116,17 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
       __syncthreads();
       double rb = -1.0;
       int ri = -1;
-      for (int i = j + t; i < n; i += SP_T) {
-        double v = i < r ? W[r + (size_t)i * ldw] : W[i + (size_t)r * ldw];
-        for (int c = 0; c < jj; ++c) v = fma(-W[i + (size_t)(k0 + c) * ldw], s_wr[c], v);
-        Wp[i + (size_t)(jj + 1) * ldp] = v;
-        if (i == r) s_val[1] = v;
-        else if (fabs(v) > rb) { rb = fabs(v); ri = i; }
+      for (int i0 = j + t; i0 < n; i0 += 4 * SP_T) {
+        double v[4];
+        panel_rows(n, i0, r, r, k0, jj, W, ldw, s_wr, v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + q * SP_T;
+          if (i >= n) break;
+          Wp[i + (size_t)(jj + 1) * ldp] = v[q];
+          if (i == r) s_val[1] = v[q];
+          else if (fabs(v[q]) > rb) { rb = fabs(v[q]); ri = i; }
+        }
       }
       block_argmax(rb, ri, s_rv, s_ri);
       const double rowmax = rb;
@@ -113,6 +159,7 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
       // the raw column p moves to position r (the raw column and row r were consumed into w2)
       if (p != r) {
         if (t == 0) W[r + (size_t)r * ldw] = W[p + (size_t)p * ldw];
+#pragma unroll 4
         for (int i = p + 1 + t; i < n; i += SP_T) {
           if (i < r) W[r + (size_t)i * ldw] = W[i + (size_t)p * ldw];
           else if (i > r) W[i + (size_t)r * ldw] = W[i + (size_t)p * ldw];
@@ -121,6 +168,7 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
       __syncthreads();
       if (kind == 2) {
         // new column j = w2 with entries j and r exchanged
+#pragma unroll 4
         for (int i = j + t; i < n; i += SP_T) {
           const double v = i == j ? s_val[5] : (i == r ? s_val[4] : Wp[i + (size_t)(jj + 1) * ldp]);
           Wp[i + (size_t)jj * ldp] = v;
@@ -146,6 +194,7 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
     // ---- L columns and D
     if (kind <= 2) {
       const double dj = kind == 2 ? s_val[5] : wjj;
+#pragma unroll 4
       for (int i = j + 1 + t; i < n; i += SP_T)
         W[i + (size_t)j * ldw] = kind == 0 ? 0.0 : Wp[i + (size_t)jj * ldp] / dj;
       if (t == 0) {
@@ -157,6 +206,7 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
     } else {
       const double a = wjj, bb = s_val[3], c2 = s_val[5];
       const double det = a * c2 - bb * bb;
+#pragma unroll 4
       for (int i = j + 2 + t; i < n; i += SP_T) {
         const double s0 = Wp[i + (size_t)jj * ldp], s1 = Wp[i + (size_t)(jj + 1) * ldp];
         W[i + (size_t)j * ldw] = (s0 * c2 - s1 * bb) / det;
