@@ -287,6 +287,12 @@ hipError_t launch_jacobi_small(int n, double* U, int ldu, double* V, int ldv, do
 hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, double* V, int ldv, double* Y, int ldy,
                                int ny, DevRec* rec, hipStream_t st);
 hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st);
+// blocked sweep step (blocks of four columns, two blocks per workgroup): intra = the pairs inside
+// each block, else round `round` of the round-robin over block pairs; Y (ny <= 64 columns) turns
+// with U; no V. jacobi_blocked_fits says whether (n, ny) can take it.
+bool jacobi_blocked_fits(int n, int ny);
+hipError_t launch_jacobi_blk(int n, int round, bool intra, double* U, int ldu, double* Y, int ldy, int ny,
+                             DevRec* rec, hipStream_t st);
 // x = P sum over kept j of Ut_j (W_j^T C) / sigma_j^2, sigma_j = ||Ut_j|| (after the Jacobi on R^T: Ut = R^T W, W
 // the accumulated rotations, C = Q^T B, P the column order, row i of the sum goes to row perm[i] of X; perm NULL:
 // identity); W NULL: C already holds the projections W^T Q^T B (rotated along with the columns); also sets

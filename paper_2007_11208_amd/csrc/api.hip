@@ -556,6 +556,19 @@ int route_svd(Solve& s, const double* A, int lda, const double* B, int ldb, doub
   const int ny = keep_w ? 0 : s.nrhs;
   if (n <= kJacobiSmall) {
     HIPCHK(launch_jacobi_small(n, Wbuf, n, V, n, Y, n, ny, 30, s.rec, s.st));
+  } else if (!keep_w && jacobi_blocked_fits(n, ny)) {
+    // blocks of four columns: one intra-block step and a round-robin over block pairs per sweep
+    const int nblk = (n + 3) / 4, nbm = (nblk + 1) & ~1;
+    int sweeps = 0;
+    for (; sweeps < 30; ++sweeps) {
+      HIPCHK(launch_clear_rotated(s.rec, s.st));
+      HIPCHK(launch_jacobi_blk(n, 0, true, Wbuf, n, Y, n, ny, s.rec, s.st));
+      for (int r = 0; r < nbm - 1; ++r) HIPCHK(launch_jacobi_blk(n, r, false, Wbuf, n, Y, n, ny, s.rec, s.st));
+      TRY(s.sync_read());
+      if (!s.ctx->host_rec->jacobi_rotated) { ++sweeps; break; }
+    }
+    s.ctx->host_rec->sweeps = sweeps;
+    HIPCHK(hipMemcpyAsync(&s.rec->sweeps, &s.ctx->host_rec->sweeps, sizeof(int), hipMemcpyHostToDevice, s.st));
   } else {
     const int m = (n + 1) & ~1;
     int sweeps = 0;

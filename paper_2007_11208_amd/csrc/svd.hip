@@ -159,6 +159,161 @@ hipError_t launch_jacobi_round(int n, int m, int round, double* U, int ldu, doub
   return hipGetLastError();
 }
 
+// Blocked form of the same cyclic one-sided Jacobi for 1024 < n <= 4096: the columns form blocks of
+// four; one workgroup holds two blocks (eight columns, rows spread over 1024 threads, four rows per
+// thread) in registers and applies the ordinary two-column rotations to every pair that crosses the
+// two blocks (four rounds of four disjoint pairs), or, in the intra step, to the six pairs inside
+// one block. A sweep is one intra step and a round-robin over block pairs, so every column pair is
+// visited once per sweep as in the per-pair form, while U streams through HBM about n/4 times per
+// sweep instead of n. The right-hand sides' projections (rows of Y) turn with their columns.
+constexpr int JB_T = 1024;
+constexpr int JB_R = 4;       // rows per thread (n <= 4096)
+constexpr int JB_YMAX = 64;   // projections held in LDS (columns of Y)
+
+// slots of the pairs of round rd: intra {(0,1),(2,3)}, {(0,2),(1,3)}, {(0,3),(1,2)}; cross (k, 4+(k+rd)%4)
+template <bool INTRA>
+__device__ __forceinline__ constexpr int blk_pa(int rd, int k) {
+  return INTRA ? (k == 0 ? 0 : (rd == 0 ? 2 : 1)) : k;
+}
+template <bool INTRA>
+__device__ __forceinline__ constexpr int blk_pb(int rd, int k) {
+  return INTRA ? (k == 0 ? rd + 1 : (rd == 2 ? 2 : 3)) : 4 + ((k + rd) & 3);
+}
+
+template <bool INTRA>
+__global__ __launch_bounds__(JB_T) void k_jacobi_blk(int n, int nbm, int round, double* __restrict__ U, int ldu,
+                                                     double* __restrict__ Y, int ldy, int ny, DevRec* rec) {
+  const bool intra = INTRA;
+  const int nblk = (n + 3) / 4;
+  int ba, bb;
+  if (intra) {
+    ba = blockIdx.x;
+    bb = -1;
+  } else {
+    rr_pair(nbm, round, blockIdx.x, ba, bb);
+    if (ba >= nblk || bb >= nblk) return;
+  }
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nslot = intra ? 4 : 8;
+  __shared__ double sy[8][JB_YMAX];
+  __shared__ double sred[JB_T / 64][12];
+  __shared__ double stot[12];
+  __shared__ int s_any;
+  int col[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) col[k] = k < 4 ? ba * 4 + k : (bb >= 0 ? bb * 4 + (k - 4) : n);
+  double u[8][JB_R];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int q = 0; q < JB_R; ++q) {
+      const int row = t + q * JB_T;
+      u[k][q] = (k < nslot && col[k] < n && row < n) ? U[row + (size_t)col[k] * ldu] : 0.0;
+    }
+  for (int e = t; e < nslot * ny; e += JB_T) {
+    const int k = e / ny, c = e % ny;
+    sy[k][c] = col[k] < n ? Y[col[k] + (size_t)c * ldy] : 0.0;
+  }
+  if (t == 0) s_any = 0;
+  __syncthreads();
+  const double tol = (double)n * kEps;
+  constexpr int nrounds = INTRA ? 3 : 4;
+  constexpr int np = INTRA ? 2 : 4;
+#pragma unroll
+  for (int rd = 0; rd < nrounds; ++rd) {
+    double part[12];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double al = 0.0, be = 0.0, ga = 0.0;
+      if (k < np) {
+#pragma unroll
+        for (int q = 0; q < JB_R; ++q) {
+          const double x = u[blk_pa<INTRA>(rd, k)][q], y = u[blk_pb<INTRA>(rd, k)][q];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+      }
+      part[3 * k] = wave_sum(al);
+      part[3 * k + 1] = wave_sum(be);
+      part[3 * k + 2] = wave_sum(ga);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) sred[w][k] = part[k];
+    __syncthreads();
+    if (t < 12) {
+      double sum = 0.0;
+      for (int q = 0; q < JB_T / 64; ++q) sum += sred[q][t];
+      stot[t] = sum;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k >= np) continue;
+      const int sa = blk_pa<INTRA>(rd, k), sb = blk_pb<INTRA>(rd, k);
+      if (col[sa] >= n || col[sb] >= n) continue;
+      // the first column of the pair is the lower index (the per-pair form's convention)
+      const bool swap = col[sa] > col[sb];
+      const double al = swap ? stot[3 * k + 1] : stot[3 * k], be = swap ? stot[3 * k] : stot[3 * k + 1];
+      const double ga = stot[3 * k + 2];
+      if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+      double c, sn;
+      rotation(al, be, ga, c, sn);
+      const int sp = swap ? sb : sa, sq = swap ? sa : sb;
+      if (!swap) {
+#pragma unroll
+        for (int q = 0; q < JB_R; ++q) {
+          const double x = u[sa][q], y = u[sb][q];
+          u[sa][q] = c * x - sn * y;
+          u[sb][q] = sn * x + c * y;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < JB_R; ++q) {
+          const double x = u[sb][q], y = u[sa][q];
+          u[sb][q] = c * x - sn * y;
+          u[sa][q] = sn * x + c * y;
+        }
+      }
+      for (int cc = t; cc < ny; cc += JB_T) {
+        const double x = sy[sp][cc], y = sy[sq][cc];
+        sy[sp][cc] = c * x - sn * y;
+        sy[sq][cc] = sn * x + c * y;
+      }
+      if (t == 0) s_any = 1;
+    }
+    __syncthreads();
+  }
+  if (!s_any) return;  // nothing turned: U and Y unchanged
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int q = 0; q < JB_R; ++q) {
+      const int row = t + q * JB_T;
+      if (k < nslot && col[k] < n && row < n) U[row + (size_t)col[k] * ldu] = u[k][q];
+    }
+  for (int e = t; e < nslot * ny; e += JB_T) {
+    const int k = e / ny, c = e % ny;
+    if (col[k] < n) Y[col[k] + (size_t)c * ldy] = sy[k][c];
+  }
+  if (t == 0) atomicOr(&rec->jacobi_rotated, 1);
+}
+
+// below about a thousand columns the per-pair rounds are cheaper (U sits in L2; measured on the MI355X)
+bool jacobi_blocked_fits(int n, int ny) { return n > 1024 && n <= JB_T * JB_R && ny <= JB_YMAX; }
+
+hipError_t launch_jacobi_blk(int n, int round, bool intra, double* U, int ldu, double* Y, int ldy, int ny,
+                             DevRec* rec, hipStream_t st) {
+  if (!jacobi_blocked_fits(n, ny)) return hipErrorInvalidValue;
+  const int nblk = (n + 3) / 4, nbm = (nblk + 1) & ~1;
+  if (intra)
+    hipLaunchKernelGGL(k_jacobi_blk<true>, dim3(nblk), dim3(JB_T), 0, st, n, nbm, round, U, ldu, Y, ldy, ny, rec);
+  else
+    hipLaunchKernelGGL(k_jacobi_blk<false>, dim3(nbm / 2), dim3(JB_T), 0, st, n, nbm, round, U, ldu, Y, ldy, ny, rec);
+  return hipGetLastError();
+}
+
 __global__ void k_clear_rotated(DevRec* rec) { rec->jacobi_rotated = 0; }
 
 hipError_t launch_clear_rotated(DevRec* rec, hipStream_t st) {

@@ -209,6 +209,40 @@ def test_fallback_routes(ada):
     assert np.max(np.abs(x.cpu().numpy() - xr)) <= 10 * n * 1e4 * EPS * np.max(np.abs(xr))
 
 
+@pytest.mark.parametrize("n,nrhs", [(257, 3), (520, 8), (1030, 2), (1100, 5), (1100, 65)])
+def test_svd_fallback_blocked_jacobi_sizes(ada, n, nrhs):
+    """Sizes past the one-workgroup Jacobi: per-pair rounds up to n = 1024, blocks of four columns
+    beyond (up to 64 right-hand sides; a ragged last block at n = 1030), per-pair rounds again for
+    more right-hand sides. Exactly rank deficient (rank n-20, kept spectrum 1..1e-4): the
+    minimum-norm solution is unique and matches the oracle's."""
+    g = np.random.default_rng(n + nrhs)
+    k = n - 20
+    a = np.zeros((n, n))
+    a[:k, :k] = W.prescribed_spectrum(k, np.logspace(0, -4, k), g)
+    a = np.asfortranarray(a[np.ix_(g.permutation(n), g.permutation(n))])
+    b = np.asfortranarray(a @ g.standard_normal((n, nrhs)))
+    x, r, rr = check_against_oracle(ada, a, b)
+    assert r.route == "svd" and r.rank == k and r.sweeps <= 30
+    xr, _ = O.solve(a, b)
+    assert np.max(np.abs(x.cpu().numpy().reshape(xr.shape) - xr)) <= 10 * n * 1e4 * EPS * np.max(np.abs(xr))
+
+
+def test_svd_fallback_ill_conditioned_blocked(ada):
+    """rcond below the threshold (fallback 2) with a clear gap at the truncation level: a 10 x 10
+    block scaled by 1e-20 beside a block with spectrum [1e-8, 1], rows and columns permuted (all
+    exact, so the ten tiny singular values are not buried in rounding of the large ones: a
+    spectrum that reaches eps*sigma_max through rounding noise has no well-defined rank)."""
+    n = 600
+    g = np.random.default_rng(5)
+    a = np.zeros((n, n))
+    a[:n - 10, :n - 10] = W.prescribed_spectrum(n - 10, np.logspace(0, -8, n - 10), g)
+    a[n - 10:, n - 10:] = 1e-20 * W.prescribed_spectrum(10, np.logspace(0, -1, 10), g)
+    a = np.asfortranarray(a[np.ix_(g.permutation(n), g.permutation(n))])
+    b = W.rhs_for(a, W.x_true(n, 2, np.random.default_rng(6)))
+    x, r, rr = check_against_oracle(ada, a, b)
+    assert r.route == "svd" and r.fallback == 2 and r.rank == n - 10
+
+
 def test_solver_failures(ada):
     n = 70
     a = W.dense_general(n, np.random.default_rng(1))
