@@ -230,7 +230,10 @@ int batched_workgroups(int count, int max_wg = 256);
 hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
                                 void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st,
                                 int max_wg = 256);
-// band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles
+// band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles.
+// The chunk maps of a sweep kind (bit 1<<kind of *maps_ready) are computed at its first use after the
+// factorisation, predicated on map_pred == map_pred_val only (not on the solve's own predicate), and
+// reused while the bit stays set; the caller clears *maps_ready when the factor changes.
 enum { SW_L = 0, SW_U = 1, SW_UT = 2, SW_LT = 3 };
 constexpr int LC = 256;  // steps per chunk of the parallel band sweeps
 struct BandSweep {
@@ -241,17 +244,21 @@ struct BandSweep {
   int piece;  // steps staged in LDS at a time
 };
 struct BandScratch {
-  double* Phi;    // chunk maps (homogeneous part), nchunks x S x S
+  // the homogeneous parts depend on the factor only: one set per sweep kind, kept across the solves
+  // of one factorisation (first the four Phi sets, then the four Msup sets, whatever nrhs is)
+  double* Phi;    // chunk maps (homogeneous part), nchunks x S x S, kind k at Phi + k * map_stride
+  double* Msup;   // composed maps of the scan groups, kind k at Msup + k * sup_stride
+  size_t map_stride, sup_stride;
   double* phi;    // chunk maps (particular part), nchunks x nrhs x S
   double* entry;  // entry state of every chunk, nchunks x nrhs x S
-  double* Msup;   // composed maps of the scan groups
   double* msup;
   double* esup;   // entry state of every scan group
 };
 BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs);
 hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv,
                                 bool trans, double* X, int ldx, double* T, int ldt, BandScratch sc, const int* pred,
-                                int pred_val, hipStream_t st);
+                                int pred_val, const int* map_pred, int map_pred_val, unsigned* maps_ready,
+                                hipStream_t st);
 size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs);
 hipError_t launch_band_resid(int n, int kl, int ku, int nrhs, const double* AB, int ldab, int ku_in,
                              const double* B, int ldb, const double* X, int ldx, double* R, int ldr,

@@ -205,6 +205,7 @@ struct Solve {
   int epoch = 0;
   int lowp = ADA_PREC_FP64;  // operand precision of the trailing-matrix updates
   bool keep_factors = false; // the factors left in the workspace serve later right-hand sides
+  unsigned band_maps = 0;     // sweep kinds whose chunk maps the current band factor already has
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -309,7 +310,8 @@ int band_solve(Solve& s, const double* GB, int kl, int ku, bool trans, double* X
       return fail(ADA_ERR_ARG, "band scratch smaller than the band width needs");
     BandScratch sc = band_chunked_scratch(s.at<double>(s.p.bsc), n, kl, ku, nrhs);
     HIPCHK(s.timed(kind, fl, by, [&] {
-      return launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, T, ldt, sc, pred, pred_val, s.st);
+      return launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, T, ldt, sc, pred, pred_val,
+                                  &s.rec->stop, 0, &s.band_maps, s.st);
     }));
   } else {
     HIPCHK(s.timed(kind, fl, by, [&] {
@@ -517,6 +519,7 @@ int route_band(Solve& s, const double* GB0, double* GB, int kl, int ku, const do
                int ldx) {
   // GB0: the packed band (its norms already recorded); the factor goes to GB
   const int n = s.n, ldgb = 2 * kl + ku + 1;
+  s.band_maps = 0;  // a new factor: its chunk maps are formed at the first solve of each kind
   {
     // algorithmic: per column kl multipliers and a kl x (kl + ku) update; reads the kl+ku+1 band rows,
     // writes the 2kl+ku+1 factor rows and the pivots

@@ -241,14 +241,16 @@ __global__ __launch_bounds__(256) void k_band_phase1(BandSweep B, int nchunks, i
 //   2c  every group replays its chunk maps from its entry and writes every
 //       chunk's entry state.
 template <int KIND, int SM>
-__global__ __launch_bounds__(64) void k_band_compose(BandSweep B, int nchunks, int G, const double* Phi,
+// part: 1 the maps M (depend on the factor only), 2 the particular parts m (per right-hand side), 3 both
+__global__ __launch_bounds__(64) void k_band_compose(BandSweep B, int nchunks, int G, int part, const double* Phi,
                                                      const double* phi, double* Msup, double* msup,
                                                      const int* pred, int pred_val) {
   if (pred && *pred != pred_val) return;
   const int S = sweep_state(KIND, B.kl, B.ku);
   const int sg = blockIdx.x, t = threadIdx.x;
-  const int c = blockIdx.y * 64 + t;  // right-hand side of this lane
   const int nr = B.nrhs_all;
+  const int c = (part & 2) ? blockIdx.y * 64 + t : nr;  // right-hand side of this lane (none for part 1)
+  const bool mats = (part & 1) && blockIdx.y == 0;
   const int q0 = sg * G, q1 = min(nchunks, q0 + G);
   __shared__ double sP[SM * SM], sM[2][SM * SM];
   for (int e = t; e < S * S; e += 64) sM[0][e] = (e / S == e % S) ? 1.0 : 0.0;
@@ -275,7 +277,7 @@ __global__ __launch_bounds__(64) void k_band_compose(BandSweep B, int nchunks, i
       pre[u] = (q + 1 < q1 && e < S * S) ? Phi[(size_t)(q + 1) * S * S + e] : 0.0;
     }
     __syncthreads();
-    if (blockIdx.y == 0) {
+    if (mats) {
 #pragma unroll
       for (int u = 0; u < PE; ++u) {
         const int e = t + 64 * u;
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(64) void k_band_compose(BandSweep B, int nchunks, i
     }
   }
   __syncthreads();
-  if (blockIdx.y == 0)
+  if (mats)
     for (int e = t; e < S * S; e += 64) Msup[(size_t)sg * S * S + e] = sM[cur][e];
   if (c < nr) {
 #pragma unroll
@@ -435,7 +437,8 @@ static int scan_group(int nchunks) {
 
 template <int KIND, int SM>
 static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* Xout, int ldo, BandScratch sc,
-                        const int* pred, int pred_val, hipStream_t st) {
+                        const int* pred, int pred_val, const int* map_pred, int map_pred_val, bool maps_ready,
+                        hipStream_t st) {
   const int nchunks = (B.n + LC - 1) / LC;
   const int S = sweep_state(KIND, B.kl, B.ku);
   const size_t lds13 = chunk_lds(B.piece, B.kl + B.ku, B.ldgb);
@@ -446,21 +449,28 @@ static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* 
   if (e != hipSuccess) return e;
   const int grid = (nchunks + CPW - 1) / CPW;
   if (S > 0) {
-    hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 0, 0, 0, Xin, ldi,
-                       sc.Phi, sc.phi, pred, pred_val);
+    double* Phi = sc.Phi + (size_t)KIND * sc.map_stride;
+    double* Msup = sc.Msup + (size_t)KIND * sc.sup_stride;
+    const int G = scan_group(nchunks);
+    const int nsup = (nchunks + G - 1) / G;
+    if (!maps_ready) {
+      // the factor's own maps: Phi per chunk, then their products per scan group
+      hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 0, 0, 0, Xin, ldi,
+                         Phi, sc.phi, map_pred, map_pred_val);
+      hipLaunchKernelGGL((k_band_compose<KIND, SM>), dim3(nsup, 1), dim3(64), 0, st, B, nchunks, G, 1, Phi, sc.phi,
+                         Msup, sc.msup, map_pred, map_pred_val);
+    }
     for (int c0 = 0; c0 < B.nrhs_all; c0 += NCB) {
       const int nc = B.nrhs_all - c0 < NCB ? B.nrhs_all - c0 : NCB;
       hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 1, c0, nc, Xin,
-                         ldi, sc.Phi, sc.phi, pred, pred_val);
+                         ldi, Phi, sc.phi, pred, pred_val);
     }
-    const int G = scan_group(nchunks);
-    const int nsup = (nchunks + G - 1) / G;
     hipLaunchKernelGGL((k_band_compose<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B,
-                       nchunks, G, sc.Phi, sc.phi, sc.Msup, sc.msup, pred, pred_val);
-    hipLaunchKernelGGL((k_band_chain<KIND, SM>), dim3(B.nrhs_all), dim3(64), 0, st, B, nsup, Xin, ldi, sc.Msup,
+                       nchunks, G, 2, Phi, sc.phi, Msup, sc.msup, pred, pred_val);
+    hipLaunchKernelGGL((k_band_chain<KIND, SM>), dim3(B.nrhs_all), dim3(64), 0, st, B, nsup, Xin, ldi, Msup,
                        sc.msup, sc.esup, pred, pred_val);
     hipLaunchKernelGGL((k_band_fill<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B, nchunks,
-                       G, sc.Phi, sc.phi, sc.esup, sc.entry, pred, pred_val);
+                       G, Phi, sc.phi, sc.esup, sc.entry, pred, pred_val);
   } else {
     // no state (kl = 0 for the L sweeps): every chunk starts from the empty state
   }
@@ -474,37 +484,45 @@ static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* 
 
 template <int KIND>
 static hipError_t sweep_any(const BandSweep& B, const double* Xin, int ldi, double* Xout, int ldo, BandScratch sc,
-                            const int* pred, int pred_val, hipStream_t st) {
+                            const int* pred, int pred_val, const int* map_pred, int map_pred_val,
+                            unsigned* maps_ready, hipStream_t st) {
   const int S = sweep_state(KIND, B.kl, B.ku);
-  if (S <= 8) return sweep<KIND, 8>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, st);
-  if (S <= 16) return sweep<KIND, 16>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, st);
-  return sweep<KIND, 32>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, st);
+  const bool ready = maps_ready && ((*maps_ready >> KIND) & 1u);
+  hipError_t e;
+  if (S <= 8) e = sweep<KIND, 8>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, map_pred, map_pred_val, ready, st);
+  else if (S <= 16) e = sweep<KIND, 16>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, map_pred, map_pred_val, ready, st);
+  else e = sweep<KIND, 32>(B, Xin, ldi, Xout, ldo, sc, pred, pred_val, map_pred, map_pred_val, ready, st);
+  if (e == hipSuccess && maps_ready) *maps_ready |= 1u << KIND;
+  return e;
 }
 
 hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv,
                                 bool trans, double* X, int ldx, double* T, int ldt, BandScratch sc, const int* pred,
-                                int pred_val, hipStream_t st) {
+                                int pred_val, const int* map_pred, int map_pred_val, unsigned* maps_ready,
+                                hipStream_t st) {
   if (kl + ku > 31 || nrhs < 1) return hipErrorInvalidValue;
-  int piece = 64;
+  // rows staged through LDS per step of a chunk: short pieces keep the LDS of a workgroup small, so
+  // that more chunks run side by side (measured: 16 beats 8, 32 and 64 at kl + ku = 10)
+  int piece = 16;
   while (piece > 8 && chunk_lds(piece, kl + ku, ldgb) > kLdsMax) piece /= 2;
   if (chunk_lds(piece, kl + ku, ldgb) > kLdsMax) return hipErrorInvalidValue;
   BandSweep B{GB, ldgb, kl, ku, n, ipiv, nrhs, piece};
   hipError_t e;
   if (!trans) {
-    e = sweep_any<SW_L>(B, X, ldx, T, ldt, sc, pred, pred_val, st);
+    e = sweep_any<SW_L>(B, X, ldx, T, ldt, sc, pred, pred_val, map_pred, map_pred_val, maps_ready, st);
     if (e != hipSuccess) return e;
-    return sweep_any<SW_U>(B, T, ldt, X, ldx, sc, pred, pred_val, st);
+    return sweep_any<SW_U>(B, T, ldt, X, ldx, sc, pred, pred_val, map_pred, map_pred_val, maps_ready, st);
   }
-  e = sweep_any<SW_UT>(B, X, ldx, T, ldt, sc, pred, pred_val, st);
+  e = sweep_any<SW_UT>(B, X, ldx, T, ldt, sc, pred, pred_val, map_pred, map_pred_val, maps_ready, st);
   if (e != hipSuccess) return e;
-  return sweep_any<SW_LT>(B, T, ldt, X, ldx, sc, pred, pred_val, st);
+  return sweep_any<SW_LT>(B, T, ldt, X, ldx, sc, pred, pred_val, map_pred, map_pred_val, maps_ready, st);
 }
 
 size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs) {
   const size_t nchunks = (size_t)(n + LC - 1) / LC;
   const size_t S = (size_t)(kl + ku) > 1 ? (size_t)(kl + ku) : 1;
   const size_t G = (size_t)scan_group((int)nchunks), nsup = (nchunks + G - 1) / G;
-  return nchunks * S * S + 2 * nchunks * (size_t)nrhs * S + nsup * S * S + 2 * nsup * (size_t)nrhs * S + 64;
+  return 4 * nchunks * S * S + 4 * nsup * S * S + 2 * nchunks * (size_t)nrhs * S + 2 * nsup * (size_t)nrhs * S + 64;
 }
 
 BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs) {
@@ -512,11 +530,13 @@ BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs) 
   const size_t S = (size_t)(kl + ku) > 1 ? (size_t)(kl + ku) : 1;
   const size_t G = (size_t)scan_group((int)nchunks), nsup = (nchunks + G - 1) / G;
   BandScratch sc;
+  sc.map_stride = nchunks * S * S;
+  sc.sup_stride = nsup * S * S;
   sc.Phi = base;
-  sc.phi = sc.Phi + nchunks * S * S;
+  sc.Msup = sc.Phi + 4 * sc.map_stride;
+  sc.phi = sc.Msup + 4 * sc.sup_stride;
   sc.entry = sc.phi + nchunks * (size_t)nrhs * S;
-  sc.Msup = sc.entry + nchunks * (size_t)nrhs * S;
-  sc.msup = sc.Msup + nsup * S * S;
+  sc.msup = sc.entry + nchunks * (size_t)nrhs * S;
   sc.esup = sc.msup + nsup * (size_t)nrhs * S;
   return sc;
 }
