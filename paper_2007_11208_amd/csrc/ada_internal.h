@@ -245,10 +245,11 @@ struct BandSweep {
 };
 struct BandScratch {
   // the homogeneous parts depend on the factor only: one set per sweep kind, kept across the solves
-  // of one factorisation (first the four Phi sets, then the four Msup sets, whatever nrhs is)
+  // of one factorisation (the four Phi sets, the four Msup sets, the four H sets, whatever nrhs is)
   double* Phi;    // chunk maps (homogeneous part), nchunks x S x S, kind k at Phi + k * map_stride
   double* Msup;   // composed maps of the scan groups, kind k at Msup + k * sup_stride
-  size_t map_stride, sup_stride;
+  double* H;      // response of every output position to the chunk's entry state, n x S, kind k at H + k * h_stride
+  size_t map_stride, sup_stride, h_stride;
   double* phi;    // chunk maps (particular part), nchunks x nrhs x S
   double* entry;  // entry state of every chunk, nchunks x nrhs x S
   double* msup;

@@ -130,7 +130,7 @@ __device__ __forceinline__ int phys_chunk(int kind, int nchunks, int scan_idx) {
 // columns, pivots and inputs of each piece are staged through LDS together.
 template <int KIND, int SM>
 __device__ void run_chunk(const BandSweep& B, int nchunks, bool live, int S, double (&st)[SM], int mode,
-                          const double* X, int ldx, int c0, int nc, double* xout, double* lds) {
+                          const double* X, int ldx, int c0, int nc, double* xout, int xstride, double* lds) {
   const int n = B.n, kl = B.kl, kd = B.kl + B.ku, ldgb = B.ldgb;
   const bool fwd = sweep_fwd(KIND);
   const int halo = kd + 1;
@@ -194,22 +194,24 @@ __device__ void run_chunk(const BandSweep& B, int nchunks, bool live, int S, dou
       double out;
       int outpos;
       band_step<KIND, SM>(st, S, in, j, n, kl, kd, ldgb, sg, out, outpos);
-      if (mode == 2 && outpos >= 0) xout[outpos] = out;
+      if (xout && outpos >= 0) xout[(size_t)outpos * xstride] = out;
     }
   }
   // the L^T sweep ends with positions 0 .. kl-1 in the state of the chunk holding row 0
   if (KIND == SW_LT && mode == 2 && live && ph == 0)
 #pragma unroll
     for (int r = 0; r < SM; ++r)
-      if (r < S && r < n) xout[r] = st[r];
+      if (r < S && r < n) xout[(size_t)r * xstride] = st[r];
 }
 
-// phase 1: mode 0 -> Phi (thread v of a group propagates unit vector e_v, v < S);
-//          mode 1 -> phi for right-hand sides c0 .. c0+nc-1 (thread v handles c0+v).
+// phase 1: mode 0 -> Phi (thread v of a group propagates unit vector e_v, v < S) and, when H is given,
+//          the response of every output position to e_v: H[pos * S + v];
+//          mode 1 -> phi for right-hand sides c0 .. c0+nc-1 (thread v handles c0+v) and, when Xout is
+//          given, the outputs of the chunk from a zero entry state (the particular part).
 template <int KIND, int SM>
 __global__ __launch_bounds__(256) void k_band_phase1(BandSweep B, int nchunks, int mode, int c0, int nc,
-                                                     const double* X, int ldx, double* Phi, double* phi,
-                                                     const int* pred, int pred_val) {
+                                                     const double* X, int ldx, double* Phi, double* phi, double* H,
+                                                     double* Xout, int ldo, const int* pred, int pred_val) {
   if (pred && *pred != pred_val) return;
   extern __shared__ double lds[];
   const int S = sweep_state(KIND, B.kl, B.ku);
@@ -219,7 +221,15 @@ __global__ __launch_bounds__(256) void k_band_phase1(BandSweep B, int nchunks, i
   double st[SM];
 #pragma unroll
   for (int r = 0; r < SM; ++r) st[r] = (mode == 0 && r == v) ? 1.0 : 0.0;
-  run_chunk<KIND, SM>(B, nchunks, live, S, st, mode, X, ldx, c0, nc, nullptr, lds);
+  double* xo = nullptr;
+  int xs = 1;
+  if (mode == 0 && H) {
+    xo = H + (v < S ? v : 0);
+    xs = S;
+  } else if (mode == 1 && Xout) {
+    xo = Xout + (size_t)(c0 + (v < nc ? v : 0)) * ldo;
+  }
+  run_chunk<KIND, SM>(B, nchunks, live, S, st, mode, X, ldx, c0, nc, xo, xs, lds);
   if (!live) return;
   if (mode == 0) {
 #pragma unroll
@@ -229,6 +239,43 @@ __global__ __launch_bounds__(256) void k_band_phase1(BandSweep B, int nchunks, i
 #pragma unroll
     for (int r = 0; r < SM; ++r)
       if (r < S) phi[((size_t)sc * B.nrhs_all + c0 + v) * S + r] = st[r];
+  }
+}
+
+// The outputs are affine in the chunk's entry state e: x(pos) = particular(pos) + H(pos, :) e.
+// One thread per (position, right-hand side) adds the homogeneous part to the particular outputs
+// phase 1 wrote; the L^T sweep's first kl positions are the exit state of the chunk holding row 0,
+// Phi e + phi of that chunk.
+template <int KIND, int SM>
+__global__ __launch_bounds__(256) void k_band_combine(BandSweep B, int nchunks, const double* H, const double* Phi,
+                                                      const double* phi, const double* entry, double* Xout, int ldo,
+                                                      const int* pred, int pred_val) {
+  if (pred && *pred != pred_val) return;
+  const int S = sweep_state(KIND, B.kl, B.ku);
+  const int n = B.n, nr = B.nrhs_all;
+  const size_t total = (size_t)n * nr;
+  for (size_t gi = blockIdx.x * (size_t)blockDim.x + threadIdx.x; gi < total; gi += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(gi % n), c = (int)(gi / n);
+    if (KIND == SW_LT && p < B.kl) {
+      const int sc0 = nchunks - 1;  // the chunk holding row 0 comes last in the backward scan
+      const double* e = entry + ((size_t)sc0 * nr + c) * S;
+      double x = phi[((size_t)sc0 * nr + c) * S + p];
+#pragma unroll
+      for (int v = 0; v < SM; ++v)
+        if (v < S) x = fma(Phi[((size_t)sc0 * S + p) * S + v], e[v], x);
+      Xout[(size_t)p + (size_t)c * ldo] = x;
+      continue;
+    }
+    const int step = (KIND == SW_LT) ? p - B.kl : p;
+    const int ph = step / LC;
+    const int sc = sweep_fwd(KIND) ? ph : nchunks - 1 - ph;
+    const double* e = entry + ((size_t)sc * nr + c) * S;
+    const double* h = H + (size_t)p * S;
+    double x = Xout[(size_t)p + (size_t)c * ldo];
+#pragma unroll
+    for (int v = 0; v < SM; ++v)
+      if (v < S) x = fma(h[v], e[v], x);
+    Xout[(size_t)p + (size_t)c * ldo] = x;
   }
 }
 
@@ -418,7 +465,7 @@ __global__ __launch_bounds__(256) void k_band_phase3(BandSweep B, int nchunks, i
 #pragma unroll
   for (int r = 0; r < SM; ++r) st[r] = (live && r < S) ? entry[((size_t)sc * B.nrhs_all + c0 + v) * S + r] : 0.0;
   const int c = c0 + (v < nc ? v : 0);
-  run_chunk<KIND, SM>(B, nchunks, live, S, st, 2, Xin, ldi, c0, nc, Xout + (size_t)c * ldo, lds);
+  run_chunk<KIND, SM>(B, nchunks, live, S, st, 2, Xin, ldi, c0, nc, Xout + (size_t)c * ldo, 1, lds);
 }
 
 // LDS of the phase 1 / phase 3 kernels for a given piece length
@@ -453,17 +500,19 @@ static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* 
     double* Msup = sc.Msup + (size_t)KIND * sc.sup_stride;
     const int G = scan_group(nchunks);
     const int nsup = (nchunks + G - 1) / G;
+    double* H = sc.H + (size_t)KIND * sc.h_stride;
     if (!maps_ready) {
-      // the factor's own maps: Phi per chunk, then their products per scan group
+      // the factor's own maps: Phi per chunk with the outputs' responses H, then the maps' products
+      // per scan group
       hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 0, 0, 0, Xin, ldi,
-                         Phi, sc.phi, map_pred, map_pred_val);
+                         Phi, sc.phi, H, (double*)nullptr, 0, map_pred, map_pred_val);
       hipLaunchKernelGGL((k_band_compose<KIND, SM>), dim3(nsup, 1), dim3(64), 0, st, B, nchunks, G, 1, Phi, sc.phi,
                          Msup, sc.msup, map_pred, map_pred_val);
     }
     for (int c0 = 0; c0 < B.nrhs_all; c0 += NCB) {
       const int nc = B.nrhs_all - c0 < NCB ? B.nrhs_all - c0 : NCB;
       hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 1, c0, nc, Xin,
-                         ldi, Phi, sc.phi, pred, pred_val);
+                         ldi, Phi, sc.phi, (double*)nullptr, Xout, ldo, pred, pred_val);
     }
     hipLaunchKernelGGL((k_band_compose<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B,
                        nchunks, G, 2, Phi, sc.phi, Msup, sc.msup, pred, pred_val);
@@ -471,9 +520,14 @@ static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* 
                        sc.msup, sc.esup, pred, pred_val);
     hipLaunchKernelGGL((k_band_fill<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B, nchunks,
                        G, Phi, sc.phi, sc.esup, sc.entry, pred, pred_val);
-  } else {
-    // no state (kl = 0 for the L sweeps): every chunk starts from the empty state
+    // outputs = the particular part phase 1 wrote + H times the chunk's entry state
+    const size_t total = (size_t)B.n * B.nrhs_all;
+    const int cblocks = (int)((total + 255) / 256 < 8192 ? (total + 255) / 256 : 8192);
+    hipLaunchKernelGGL((k_band_combine<KIND, SM>), dim3(cblocks), dim3(256), 0, st, B, nchunks, H, Phi, sc.phi,
+                       sc.entry, Xout, ldo, pred, pred_val);
+    return hipGetLastError();
   }
+  // no state (kl = 0 for the L sweeps): every chunk starts from the empty state and replays its rows
   for (int c0 = 0; c0 < B.nrhs_all; c0 += NCB) {
     const int nc = B.nrhs_all - c0 < NCB ? B.nrhs_all - c0 : NCB;
     hipLaunchKernelGGL((k_band_phase3<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, c0, nc, Xin, ldi,
@@ -522,7 +576,8 @@ size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs) {
   const size_t nchunks = (size_t)(n + LC - 1) / LC;
   const size_t S = (size_t)(kl + ku) > 1 ? (size_t)(kl + ku) : 1;
   const size_t G = (size_t)scan_group((int)nchunks), nsup = (nchunks + G - 1) / G;
-  return 4 * nchunks * S * S + 4 * nsup * S * S + 2 * nchunks * (size_t)nrhs * S + 2 * nsup * (size_t)nrhs * S + 64;
+  return 4 * nchunks * S * S + 4 * nsup * S * S + 4 * (size_t)n * S + 2 * nchunks * (size_t)nrhs * S +
+         2 * nsup * (size_t)nrhs * S + 64;
 }
 
 BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs) {
@@ -532,9 +587,11 @@ BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs) 
   BandScratch sc;
   sc.map_stride = nchunks * S * S;
   sc.sup_stride = nsup * S * S;
+  sc.h_stride = (size_t)n * S;
   sc.Phi = base;
   sc.Msup = sc.Phi + 4 * sc.map_stride;
-  sc.phi = sc.Msup + 4 * sc.sup_stride;
+  sc.H = sc.Msup + 4 * sc.sup_stride;
+  sc.phi = sc.H + 4 * sc.h_stride;
   sc.entry = sc.phi + nchunks * (size_t)nrhs * S;
   sc.msup = sc.entry + nchunks * (size_t)nrhs * S;
   sc.esup = sc.msup + nsup * (size_t)nrhs * S;
