@@ -281,12 +281,13 @@ __global__ __launch_bounds__(256) void k_band_combine(BandSweep B, int nchunks, 
 
 // phase 2: entry state of every chunk, in three short launches over groups of
 // G consecutive chunks (scan order):
-//   2a  every group composes its chunk maps: M = Phi_last ... Phi_first, and
-//       m_c = the group's exit state from a zero entry, per right-hand side;
+//   2a  every group composes its chunk maps: M = Phi_last ... Phi_first (once per
+//       factor, k_band_compose), and m_c = the group's exit state from a zero
+//       entry, per right-hand side (k_band_vec_chain);
 //   2b  one wave per right-hand side chains the groups (lane r holds component
 //       r of the state);
 //   2c  every group replays its chunk maps from its entry and writes every
-//       chunk's entry state.
+//       chunk's entry state (k_band_vec_chain).
 template <int KIND, int SM>
 // part: 1 the maps M (depend on the factor only), 2 the particular parts m (per right-hand side), 3 both
 __global__ __launch_bounds__(64) void k_band_compose(BandSweep B, int nchunks, int G, int part, const double* Phi,
@@ -395,59 +396,42 @@ __global__ __launch_bounds__(64) void k_band_chain(BandSweep B, int nsup, const 
   }
 }
 
+// The per-right-hand-side chains of phase 2 over the chunks of one scan group: e <- Phi_q e + phi_q.
+// One wave per (group, right-hand side); lane r holds component r of the state, the next chunk's row r
+// of Phi and phi are loaded one step ahead, and the other components come by readlane, so a step
+// costs S fused multiply-adds and no barrier. mode 0 (composition): start from zero, write the
+// group's exit state to msup; mode 1 (fill): start from the group's entry state esup and write every
+// chunk's entry state. The sums run in the same order as the matrix form (phi first, then u = 0..S-1).
 template <int KIND, int SM>
-__global__ __launch_bounds__(64) void k_band_fill(BandSweep B, int nchunks, int G, const double* Phi,
-                                                  const double* phi, const double* esup, double* entry,
-                                                  const int* pred, int pred_val) {
+__global__ __launch_bounds__(64) void k_band_vec_chain(BandSweep B, int nchunks, int G, int mode, const double* Phi,
+                                                       const double* phi, const double* esup, double* msup,
+                                                       double* entry, const int* pred, int pred_val) {
   if (pred && *pred != pred_val) return;
   const int S = sweep_state(KIND, B.kl, B.ku);
-  const int sg = blockIdx.x, t = threadIdx.x;
-  const int c = blockIdx.y * 64 + t;
+  const int sg = blockIdx.x, c = blockIdx.y, r = threadIdx.x;
   const int nr = B.nrhs_all;
   const int q0 = sg * G, q1 = min(nchunks, q0 + G);
-  __shared__ double sP[SM * SM];
-  double e[SM], pf[SM];
+  const bool act = r < S;
+  const int rr = act ? r : 0;
+  double e = (mode == 1 && act) ? esup[((size_t)sg * nr + c) * S + r] : 0.0;
+  double prow[SM], pf = 0.0;
 #pragma unroll
-  for (int r = 0; r < SM; ++r) {
-    e[r] = (c < nr && r < S) ? esup[((size_t)sg * nr + c) * S + r] : 0.0;
-    pf[r] = (c < nr && r < S && q0 < q1) ? phi[((size_t)q0 * nr + c) * S + r] : 0.0;
-  }
-  constexpr int PE = (SM * SM + 63) / 64;
-  double pre[PE];
-#pragma unroll
-  for (int u = 0; u < PE; ++u) {
-    const int e = t + 64 * u;
-    pre[u] = (q0 < q1 && e < S * S) ? Phi[(size_t)q0 * S * S + e] : 0.0;
-  }
+  for (int u = 0; u < SM; ++u) prow[u] = (u < S && q0 < q1) ? Phi[((size_t)q0 * S + rr) * S + u] : 0.0;
+  if (q0 < q1) pf = phi[((size_t)q0 * nr + c) * S + rr];
   for (int q = q0; q < q1; ++q) {
-    __syncthreads();
+    if (mode == 1 && act) entry[((size_t)q * nr + c) * S + r] = e;
+    double a = pf;
 #pragma unroll
-    for (int u = 0; u < PE; ++u) {
-      const int e = t + 64 * u;
-      if (e < S * S) sP[e] = pre[u];
-      pre[u] = (q + 1 < q1 && e < S * S) ? Phi[(size_t)(q + 1) * S * S + e] : 0.0;
+    for (int u = 0; u < SM; ++u)
+      if (u < S) a = fma(prow[u], read_lane(e, u), a);
+    if (q + 1 < q1) {
+#pragma unroll
+      for (int u = 0; u < SM; ++u) prow[u] = u < S ? Phi[((size_t)(q + 1) * S + rr) * S + u] : 0.0;
+      pf = phi[((size_t)(q + 1) * nr + c) * S + rr];
     }
-    __syncthreads();
-    if (c < nr) {
-#pragma unroll
-      for (int r = 0; r < SM; ++r)
-        if (r < S) entry[((size_t)q * nr + c) * S + r] = e[r];
-    }
-    double a[SM];
-#pragma unroll
-    for (int r = 0; r < SM; ++r) {
-      double x = pf[r];
-#pragma unroll
-      for (int u = 0; u < SM; ++u)
-        if (r < S && u < S) x = fma(sP[r * S + u], e[u], x);
-      a[r] = x;
-    }
-#pragma unroll
-    for (int r = 0; r < SM; ++r) {
-      e[r] = a[r];
-      pf[r] = (c < nr && r < S && q + 1 < q1) ? phi[((size_t)(q + 1) * nr + c) * S + r] : 0.0;
-    }
+    e = act ? a : 0.0;
   }
+  if (mode == 0 && act) msup[((size_t)sg * nr + c) * S + r] = e;
 }
 
 // phase 3: replay every chunk from its entry state (right-hand sides c0 .. c0+nc-1).
@@ -514,12 +498,12 @@ static hipError_t sweep(const BandSweep& B, const double* Xin, int ldi, double* 
       hipLaunchKernelGGL((k_band_phase1<KIND, SM>), dim3(grid), dim3(256), lds13, st, B, nchunks, 1, c0, nc, Xin,
                          ldi, Phi, sc.phi, (double*)nullptr, Xout, ldo, pred, pred_val);
     }
-    hipLaunchKernelGGL((k_band_compose<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B,
-                       nchunks, G, 2, Phi, sc.phi, Msup, sc.msup, pred, pred_val);
+    hipLaunchKernelGGL((k_band_vec_chain<KIND, SM>), dim3(nsup, B.nrhs_all), dim3(64), 0, st, B, nchunks, G, 0,
+                       Phi, sc.phi, sc.esup, sc.msup, sc.entry, pred, pred_val);
     hipLaunchKernelGGL((k_band_chain<KIND, SM>), dim3(B.nrhs_all), dim3(64), 0, st, B, nsup, Xin, ldi, Msup,
                        sc.msup, sc.esup, pred, pred_val);
-    hipLaunchKernelGGL((k_band_fill<KIND, SM>), dim3(nsup, (B.nrhs_all + 63) / 64), dim3(64), 0, st, B, nchunks,
-                       G, Phi, sc.phi, sc.esup, sc.entry, pred, pred_val);
+    hipLaunchKernelGGL((k_band_vec_chain<KIND, SM>), dim3(nsup, B.nrhs_all), dim3(64), 0, st, B, nchunks, G, 1,
+                       Phi, sc.phi, sc.esup, sc.msup, sc.entry, pred, pred_val);
     // outputs = the particular part phase 1 wrote + H times the chunk's entry state
     const size_t total = (size_t)B.n * B.nrhs_all;
     const int cblocks = (int)((total + 255) / 256 < 8192 ? (total + 255) / 256 : 8192);
