@@ -251,6 +251,18 @@ enum {
   ADA_KF_JACOBI = 9, /* one-sided Jacobi rounds */
   ADA_KF_COUNT = 10
 };
+/* Autotuner of the row-parallel band solve (band routes with n >= 512): times each candidate LDS
+ * staging piece (8, 16, 32, 64 rows of a chunk at a time; those whose LDS fits) on a synthetic
+ * band factor of order n with the given band widths and number of right-hand sides, on `stream`,
+ * and keeps the fastest in ctx for every later band solve with the same kl + ku, one (nrhs = 1) or
+ * several right-hand sides, and the same floor(log2 n) (the best piece depends on how many chunks
+ * the order gives the compute units). The choice changes the speed only: every piece gives
+ * bit-identical results. Allocates and frees its own device memory (about
+ * 8 n (2kl+ku+1 + 2 nrhs + 5 (kl+ku)) bytes); synchronises the stream. 512 <= n <= 2^26,
+ * 1 <= kl + ku <= 31, 1 <= nrhs <= 64. Returns ADA_OK, ADA_ERR_ARG, ADA_ERR_NOMEM or ADA_ERR_HIP;
+ * *piece_out and *ms_out (either may be NULL) receive the chosen piece and its time per solve in ms. */
+int ada_autotune_band(ada_ctx ctx, int n, int kl, int ku, int nrhs, void* stream, int* piece_out, double* ms_out);
+
 int ada_profile_enable(ada_ctx ctx, int on);
 /* kind: ADA_KF_*; any output pointer may be NULL. */
 int ada_profile_read(ada_ctx ctx, int kind, int64_t* launches, double* total_ms, double* total_flops,

@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
         L.ada_profile_enable.restype = i
         L.ada_profile_reset.argtypes = [vp]
         L.ada_profile_reset.restype = i
+        L.ada_autotune_band.argtypes = [vp, i, i, i, i, vp, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double)]
+        L.ada_autotune_band.restype = i
         L.ada_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.ada_profile_read.restype = i
@@ -177,6 +179,18 @@ class Context:
 
     def profile_reset(self):
         lib().ada_profile_reset(self.handle)
+
+    def autotune_band(self, n: int, kl: int, ku: int, nrhs: int = 1):
+        """Time the band solve's LDS staging pieces for this order and these widths on a synthetic
+        factor and keep the fastest in this context. Returns (piece, ms per solve)."""
+        import torch
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        piece, ms = ctypes.c_int(), ctypes.c_double()
+        rc = lib().ada_autotune_band(self.handle, int(n), int(kl), int(ku), int(nrhs), ctypes.c_void_p(st),
+                                     ctypes.byref(piece), ctypes.byref(ms))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+        return piece.value, ms.value
 
     def profile_read(self, family: str):
         """(launches, total_ms, algorithmic flops, algorithmic bytes) of one kernel family."""

@@ -259,7 +259,13 @@ BandScratch band_chunked_scratch(double* base, int n, int kl, int ku, int nrhs);
 hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv,
                                 bool trans, double* X, int ldx, double* T, int ldt, BandScratch sc, const int* pred,
                                 int pred_val, const int* map_pred, int map_pred_val, unsigned* maps_ready,
-                                hipStream_t st);
+                                int piece_hint, hipStream_t st);
+// rows of a chunk staged through LDS at a time that the band solve may take (the autotuner's candidates)
+constexpr int kBandPieces[4] = {8, 16, 32, 64};
+bool band_piece_fits(int piece, int kl, int ku);
+// a synthetic band factor for timing: diagonal 4, other band entries in [-0.25, 0.25], no interchanges
+hipError_t launch_band_tune_fill(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, double* X, int nrhs,
+                                 hipStream_t st);
 size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs);
 hipError_t launch_band_resid(int n, int kl, int ku, int nrhs, const double* AB, int ldab, int ku_in,
                              const double* B, int ldb, const double* X, int ldx, double* R, int ldr,

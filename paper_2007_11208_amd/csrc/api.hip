@@ -6,6 +6,7 @@
 // condition estimate's control flow kept on the device.
 #include <cfloat>
 #include <climits>
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -154,6 +155,12 @@ bool read_opts(const ada_opts* in, ada_opts& o) {
   return true;
 }
 
+int ilog2(int n) {
+  int b = 0;
+  while (b < 31 && (2LL << b) <= n) ++b;
+  return b;
+}
+
 bool is_banded(int64_t n, int64_t kl, int64_t ku) {
   const int64_t nnz = n * (kl + ku + 1) - kl * (kl + 1) / 2 - ku * (ku + 1) / 2;
   return 4 * nnz <= n * n;
@@ -189,6 +196,10 @@ struct ada_ctx_s {
     int64_t launches = 0;
     double ms = 0.0, flops = 0.0, bytes = 0.0;
   } acc[ADA_KF_COUNT];
+  // autotuned LDS staging piece of the row-parallel band solve, by kl + ku, one / several right-hand
+  // sides and floor(log2 n) (the best piece depends on how many chunks compete for the compute units);
+  // 0 = the built-in choice
+  int band_piece[32][2][32] = {};
 };
 
 namespace {
@@ -311,7 +322,8 @@ int band_solve(Solve& s, const double* GB, int kl, int ku, bool trans, double* X
     BandScratch sc = band_chunked_scratch(s.at<double>(s.p.bsc), n, kl, ku, nrhs);
     HIPCHK(s.timed(kind, fl, by, [&] {
       return launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, trans, X, ldx, T, ldt, sc, pred, pred_val,
-                                  &s.rec->stop, 0, &s.band_maps, s.st);
+                                  &s.rec->stop, 0, &s.band_maps, s.ctx->band_piece[kl + ku][nrhs > 1 ? 1 : 0][ilog2(n)],
+                                  s.st);
     }));
   } else {
     HIPCHK(s.timed(kind, fl, by, [&] {
@@ -741,6 +753,66 @@ int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const doub
 int ada_profile_enable(ada_ctx ctx, int on) {
   if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
   ctx->prof = on != 0;
+  return ADA_OK;
+}
+
+int ada_autotune_band(ada_ctx ctx, int n, int kl, int ku, int nrhs, void* stream, int* piece_out,
+                      double* ms_out) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  if (kl < 0 || ku < 0 || kl + ku < 1 || kl + ku > 31 || nrhs < 1 || nrhs > 64 || n < kBandChunkMin || n > (1 << 26))
+    return fail(ADA_ERR_ARG, "autotune: need 1 <= kl + ku <= 31, 1 <= nrhs <= 64 and 512 <= n <= 2^26");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int ldgb = 2 * kl + ku + 1;
+  const size_t scd = band_chunked_scratch_doubles(n, kl, ku, nrhs);
+  const size_t bytes = ((size_t)n * ldgb + 2 * (size_t)n * nrhs + scd) * sizeof(double) + (size_t)n * sizeof(int) + 1024;
+  char* buf = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return fail(ADA_ERR_NOMEM, "autotune: device allocation failed");
+  double* GB = reinterpret_cast<double*>(buf);
+  double* X = GB + (size_t)n * ldgb;
+  double* T = X + (size_t)n * nrhs;
+  double* scb = T + (size_t)n * nrhs;
+  int* ipiv = reinterpret_cast<int*>(scb + scd);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = ADA_OK;
+  int best = 0;
+  double best_ms = INFINITY;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      launch_band_tune_fill(n, kl, ku, GB, ldgb, ipiv, X, nrhs, st) != hipSuccess) {
+    rc = fail(ADA_ERR_HIP, "autotune: set-up failed");
+  }
+  const BandScratch sc = band_chunked_scratch(scb, n, kl, ku, nrhs);
+  for (int k = 0; rc == ADA_OK && k < 4; ++k) {
+    const int piece = kBandPieces[k];
+    if (!band_piece_fits(piece, kl, ku)) continue;
+    unsigned maps = 0;
+    // first solve forms the maps (not timed); then the best of three solves with the maps kept
+    auto one = [&]() {
+      return launch_gbtrs_chunked(n, kl, ku, nrhs, GB, ldgb, ipiv, false, X, n, T, n, sc, nullptr, 0, nullptr, 0,
+                                  &maps, piece, st);
+    };
+    if (one() != hipSuccess) { rc = fail(ADA_ERR_HIP, "autotune: band solve launch failed"); break; }
+    double ms = INFINITY;
+    for (int rep = 0; rep < 3; ++rep) {
+      float t = 0.0f;
+      if (hipEventRecord(e0, st) != hipSuccess || one() != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        rc = fail(ADA_ERR_HIP, "autotune: timing failed");
+        break;
+      }
+      ms = std::min(ms, (double)t);
+    }
+    if (rc == ADA_OK && ms < best_ms) { best_ms = ms; best = piece; }
+  }
+  if (hipStreamSynchronize(st) != hipSuccess && rc == ADA_OK) rc = fail(ADA_ERR_HIP, "autotune: stream failed");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (rc != ADA_OK) return rc;
+  ctx->band_piece[kl + ku][nrhs > 1 ? 1 : 0][ilog2(n)] = best;
+  if (piece_out) *piece_out = best;
+  if (ms_out) *ms_out = best_ms;
   return ADA_OK;
 }
 

@@ -537,11 +537,12 @@ static hipError_t sweep_any(const BandSweep& B, const double* Xin, int ldi, doub
 hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv,
                                 bool trans, double* X, int ldx, double* T, int ldt, BandScratch sc, const int* pred,
                                 int pred_val, const int* map_pred, int map_pred_val, unsigned* maps_ready,
-                                hipStream_t st) {
+                                int piece_hint, hipStream_t st) {
   if (kl + ku > 31 || nrhs < 1) return hipErrorInvalidValue;
   // rows staged through LDS per step of a chunk: short pieces keep the LDS of a workgroup small, so
-  // that more chunks run side by side (measured: 16 beats 8, 32 and 64 at kl + ku = 10)
-  int piece = 16;
+  // that more chunks run side by side (measured: 16 beats 8, 32 and 64 at kl + ku = 10); the
+  // autotuner may name another one for a band width (the results do not depend on it)
+  int piece = piece_hint > 0 ? piece_hint : 16;
   while (piece > 8 && chunk_lds(piece, kl + ku, ldgb) > kLdsMax) piece /= 2;
   if (chunk_lds(piece, kl + ku, ldgb) > kLdsMax) return hipErrorInvalidValue;
   BandSweep B{GB, ldgb, kl, ku, n, ipiv, nrhs, piece};
@@ -554,6 +555,37 @@ hipError_t launch_gbtrs_chunked(int n, int kl, int ku, int nrhs, const double* G
   e = sweep_any<SW_UT>(B, X, ldx, T, ldt, sc, pred, pred_val, map_pred, map_pred_val, maps_ready, st);
   if (e != hipSuccess) return e;
   return sweep_any<SW_LT>(B, T, ldt, X, ldx, sc, pred, pred_val, map_pred, map_pred_val, maps_ready, st);
+}
+
+bool band_piece_fits(int piece, int kl, int ku) {
+  return piece >= 8 && chunk_lds(piece, kl + ku, 2 * kl + ku + 1) <= kLdsMax;
+}
+
+__global__ void k_band_tune_fill(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, double* X, int nrhs) {
+  const size_t total = (size_t)n * ldgb;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % ldgb), j = (int)(e / ldgb);
+    double v = 0.0;
+    if (r == kl + ku) v = 4.0;
+    else if (r >= kl) {
+      // a fixed hash of the position, mapped to [-0.25, 0.25]
+      unsigned h = (unsigned)e * 2654435761u;
+      h ^= h >> 15;
+      v = ((double)(h & 0xffff) / 65535.0 - 0.5) * 0.5;
+    }
+    (void)j;
+    GB[e] = v;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    ipiv[i] = i;
+    for (int c = 0; c < nrhs; ++c) X[(size_t)i + (size_t)c * n] = 1.0;
+  }
+}
+
+hipError_t launch_band_tune_fill(int n, int kl, int ku, double* GB, int ldgb, int* ipiv, double* X, int nrhs,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_band_tune_fill, dim3(1024), dim3(256), 0, st, n, kl, ku, GB, ldgb, ipiv, X, nrhs);
+  return hipGetLastError();
 }
 
 size_t band_chunked_scratch_doubles(int n, int kl, int ku, int nrhs) {
