@@ -83,15 +83,33 @@ hipError_t launch_band_to_dense(int n, int kl_in, int ku_in, const double* AB, i
 }
 
 // ||A||_1 (max column sum) and ||A||_inf (max row sum) of the band before factorisation
-__global__ void k_band_norms(int n, int kl, int ku, const double* __restrict__ GB, int ldgb, DevRec* rec) {
+__global__ __launch_bounds__(256) void k_band_norms(int n, int kl, int ku, const double* __restrict__ GB, int ldgb,
+                                                    DevRec* rec) {
   const int kd = kl + ku;
   double c1 = 0.0, ri = 0.0;
+  // fixed-length predicated loops (kl + ku <= 31): the loads of a column or row are independent and
+  // issue together; the sums still run in increasing row / column order
   for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    double v[32];
+#pragma unroll
+    for (int d = 0; d < 32; ++d) {
+      const int i = x - ku + d;
+      v[d] = (d <= kd && i >= 0 && i < n) ? fabs(GB[(size_t)(kd + i - x) + (size_t)x * ldgb]) : 0.0;
+    }
     double s = 0.0;
-    for (int i = max(0, x - ku); i <= min(n - 1, x + kl); ++i) s += fabs(GB[(size_t)(kd + i - x) + (size_t)x * ldgb]);
+#pragma unroll
+    for (int d = 0; d < 32; ++d)
+      if (d <= kd) s += v[d];
     c1 = fmax(c1, s);
+#pragma unroll
+    for (int d = 0; d < 32; ++d) {
+      const int j = x - kl + d;
+      v[d] = (d <= kd && j >= 0 && j < n) ? fabs(GB[(size_t)(kd + x - j) + (size_t)j * ldgb]) : 0.0;
+    }
     double r = 0.0;
-    for (int j = max(0, x - kl); j <= min(n - 1, x + ku); ++j) r += fabs(GB[(size_t)(kd + x - j) + (size_t)j * ldgb]);
+#pragma unroll
+    for (int d = 0; d < 32; ++d)
+      if (d <= kd) r += v[d];
     ri = fmax(ri, r);
   }
   c1 = wave_max(c1);
@@ -103,6 +121,7 @@ __global__ void k_band_norms(int n, int kl, int ku, const double* __restrict__ G
 }
 
 hipError_t launch_band_norms(int n, int kl, int ku, const double* GB, int ldgb, DevRec* rec, hipStream_t st) {
+  if (kl + ku > 31) return hipErrorInvalidValue;  // the sums cover at most 32 entries
   int blocks = (n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(k_band_norms, dim3(blocks), dim3(256), 0, st, n, kl, ku, GB, ldgb, rec);
