@@ -51,7 +51,9 @@ struct DevRec {
   int jacobi_rotated;         // a rotation happened in the current sweep
   int sweeps;                 // Jacobi sweeps used
   int asym;                   // some A_ij != A_ji exactly (the LDL^T extension needs A = A^T)
-  int ldlt_kb;                // columns the last LDL^T panel factored
+  int ldlt_kb;                // columns the last LDL^T panel factored, from position ldlt_first
+  int ldlt_first;
+  int ldlt_delta;             // 1: the next LDL^T panel's first position is already factored (2x2 block)
   // ---- synchronisation counters (zeroed per solve) ----
   unsigned int counters[512];  // grid barriers / tickets, one per launch that needs one
   int panel_flags[2 * 64];     // LU panel: per-workgroup publication epochs (two column parities)
@@ -312,14 +314,19 @@ hipError_t launch_jacobi_blk(int n, int round, bool intra, double* U, int ldu, d
 // identity); W NULL: C already holds the projections W^T Q^T B (rotated along with the columns); also sets
 // rec->sigma_max and rec->rank
 // ---- symmetric indefinite LDL^T, Bunch-Kaufman pivoting (ldlt.hip) ----
-// One panel of at most b columns from k0 (one workgroup): the updated columns (L D) go to Wp (n x b,
-// ld ldp), L to W, the interchange partner of each factored position to swp, D to d (diagonal) and
-// e (sub-diagonal of 2x2 blocks); the number of columns factored to rec->ldlt_kb; a zero pivot
-// column to rec->info.
+// One panel from nominal position k0 (one workgroup; panels start every b-1 positions): it factors
+// positions k0+delta .. up to k0+b-2, or k0+b-1 when its last pivot is a 2x2 block (delta = 1 when
+// the previous panel's block took position k0), writes L to W, the updated columns (L D) to Wp
+// (n x b, ld ldp; columns of positions it does not factor are zero), the interchange partner of each
+// factored position to swp, D to d (diagonal) and e (sub-diagonal of 2x2 blocks), and applies its
+// update to position k0+b-1 when it leaves that one to the next panel; the range it factored and
+// the next delta go to rec, a zero pivot column to rec->info. The trailing update then always covers
+// rows and columns from k0+b with the b columns of W and Wp from k0.
 hipError_t launch_sytrf_panel(int n, int k0, int b, double* W, int ldw, double* Wp, int ldp, int* swp, double* d,
                               double* e, DevRec* rec, hipStream_t st);
-// the panel's interchanges applied to the rows of the columns left of it and to perm
-hipError_t launch_ldlt_swap_left(int n, int k0, int kb, double* W, int ldw, const int* swp, int* perm,
+// the interchanges of the range the last panel factored, applied to the rows of the columns left of
+// k0 and to perm
+hipError_t launch_ldlt_swap_left(int n, int k0, double* W, int ldw, const int* swp, int* perm, const DevRec* rec,
                                  hipStream_t st);
 // X = D^{-1} X for the block diagonal D (predicated like the triangular solves)
 hipError_t launch_ldlt_dsolve(int n, int nrhs, const double* d, const double* e, double* X, int ldx,

@@ -477,13 +477,13 @@ int route_tri(Solve& s, const double* A, int lda, bool lower, const double* B, i
   return estimate(s, 2, A, lda, lower, 0, 0);
 }
 
-constexpr int kSyPanel = 16;  // LDL^T panel width (the last step may leave one column to the next)
+constexpr int kSyPanel = 16;  // LDL^T panel width (panels start every kSyPanel - 1 columns)
 
-// Symmetric indefinite route (Section V future work): Bunch-Kaufman LDL^T, panels of up to kSyPanel
-// columns; the host reads back how many columns each panel factored (a 2x2 pivot may not straddle
-// the panel edge) and stops at the first zero pivot column.
+// Symmetric indefinite route (Section V future work): Bunch-Kaufman LDL^T. Panels start at fixed
+// positions every kSyPanel - 1 columns; whether a 2x2 pivot crossed a panel edge is decided and read
+// on the device, so the host enqueues the whole factorisation and reads the record once at the end.
 int route_ldlt(Solve& s, const double* A, int lda, const double* B, int ldb, double* X, int ldx) {
-  const int n = s.n, ldw = s.p.ldw;
+  const int n = s.n, ldw = s.p.ldw, b = kSyPanel;
   double* W = s.at<double>(s.p.W);
   double* Wp = s.at<double>(s.p.V);
   int* swp = s.at<int>(s.p.ipiv);
@@ -493,28 +493,24 @@ int route_ldlt(Solve& s, const double* A, int lda, const double* B, int ldb, dou
   HIPCHK(launch_copy(n, n, A, lda, W, ldw, s.st));
   HIPCHK(launch_iota(perm, n, s.st));
   DevRec& h = *s.ctx->host_rec;
-  for (int k0 = 0; k0 < n;) {
-    const double m = (double)(n - k0), b = (double)(kSyPanel < n - k0 ? kSyPanel : n - k0);
+  for (int k0 = 0; k0 < n; k0 += b - 1) {
+    const double m = (double)(n - k0), bb = (double)(b < n - k0 ? b : n - k0);
     // delayed updates of the panel's columns: sum over its columns of 2 m c flops; reads m x b twice
-    HIPCHK(s.timed(ADA_KF_PANEL, m * b * b, 16.0 * m * b, [&] {
-      return launch_sytrf_panel(n, k0, kSyPanel, W, ldw, Wp, n, swp, d, e, s.rec, s.st);
+    HIPCHK(s.timed(ADA_KF_PANEL, m * bb * bb, 16.0 * m * bb, [&] {
+      return launch_sytrf_panel(n, k0, b, W, ldw, Wp, n, swp, d, e, s.rec, s.st);
     }));
-    TRY(s.sync_read());
-    const int kb = h.ldlt_kb;
-    if (kb < 1 || kb > n - k0) return fail(ADA_ERR_HIP, "LDL^T panel reported an impossible width");
-    HIPCHK(launch_ldlt_swap_left(n, k0, kb, W, ldw, swp, perm, s.st));
-    if (h.info != INT_MAX) {
-      HIPCHK(launch_mark_stop(s.rec, s.st));
-      return ADA_OK;
-    }
-    const int rest = n - k0 - kb;
-    if (rest > 0) {
-      const double* L21 = W + (k0 + kb) + (size_t)k0 * ldw;
-      const double* W21 = Wp + (k0 + kb);
-      double* A22 = W + (k0 + kb) + (size_t)(k0 + kb) * ldw;
-      TRY(s.gemm(rest, rest, kb, L21, ldw, W21, n, true, A22, ldw, true));
-    }
-    k0 += kb;
+    HIPCHK(launch_ldlt_swap_left(n, k0, W, ldw, swp, perm, s.rec, s.st));
+    const int rest = n - k0 - b;
+    if (rest <= 0) break;
+    const double* L21 = W + (k0 + b) + (size_t)k0 * ldw;
+    const double* W21 = Wp + (k0 + b);
+    double* A22 = W + (k0 + b) + (size_t)(k0 + b) * ldw;
+    TRY(s.gemm(rest, rest, b, L21, ldw, W21, n, true, A22, ldw, true));
+  }
+  TRY(s.sync_read());
+  if (h.info != INT_MAX) {
+    HIPCHK(launch_mark_stop(s.rec, s.st));
+    return ADA_OK;
   }
   // X = P^T L^{-T} D^{-1} L^{-1} P B
   int* stop = &s.rec->stop;

@@ -80,7 +80,14 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
   __shared__ double s_val[8];
   const int t = threadIdx.x;
   const bool last = n - k0 <= b;
-  int jj = 0;
+  // panels start every b-1 columns; when the previous panel's last pivot was a 2x2 block it has
+  // already factored position k0 (delta = 1): its L.D column here is zero, so the delayed updates and
+  // the trailing update of this panel take nothing from it
+  const int delta = rec->ldlt_delta;
+  if (delta)
+    for (int i = k0 + t; i < n; i += SP_T) Wp[i] = 0.0;
+  __syncthreads();
+  int jj = delta;
   while (true) {
     const int j = k0 + jj;
     if (j >= n || (!last && jj >= b - 1)) break;
@@ -225,24 +232,51 @@ __global__ __launch_bounds__(SP_T) void k_sytrf_panel(int n, int k0, int b, doub
     }
     __syncthreads();
   }
-  if (t == 0) rec->ldlt_kb = jj;
+  int next_delta = 0;
+  if (!last && jj == b - 1) {
+    // position k0+b-1 is left to the next panel: it takes this panel's update here (the trailing update
+    // covers the rows and columns from k0+b on), and its L.D column stays zero
+    const int j = k0 + b - 1;
+    if (t < jj) s_wj[t] = Wp[j + (size_t)t * ldp];
+    __syncthreads();
+    for (int i0 = j + t; i0 < n; i0 += 4 * SP_T) {
+      double v[4];
+      panel_rows(n, i0, j, -1, k0, jj, W, ldw, s_wj, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q * SP_T;
+        if (i >= n) break;
+        W[i + (size_t)j * ldw] = v[q];
+        Wp[i + (size_t)jj * ldp] = 0.0;
+      }
+    }
+  } else if (!last) {
+    next_delta = 1;  // a 2x2 block ended on position k0+b-1
+  }
+  if (t == 0) {
+    rec->ldlt_first = k0 + delta;
+    rec->ldlt_kb = jj - delta;
+    rec->ldlt_delta = next_delta;
+  }
 }
 
 hipError_t launch_sytrf_panel(int n, int k0, int b, double* W, int ldw, double* Wp, int ldp, int* swp, double* d,
                               double* e, DevRec* rec, hipStream_t st) {
-  if (b < 2 || b > SP_BMAX || k0 < 0 || k0 >= n) return hipErrorInvalidValue;
+  if (b < 3 || b > SP_BMAX || k0 < 0 || k0 >= n) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sytrf_panel, dim3(1), dim3(SP_T), 0, st, n, k0, b, W, ldw, Wp, ldp, swp, d, e, rec);
   return hipGetLastError();
 }
 
-// one thread per column c < k0 walks the panel's interchanges in order; thread 0 of
-// workgroup 0 also carries them into perm
-__global__ __launch_bounds__(256) void k_ldlt_swap_left(int n, int k0, int kb, double* __restrict__ W, int ldw,
-                                                        const int* __restrict__ swp, int* __restrict__ perm) {
+// one thread per column c < k0 walks the interchanges of the positions the last panel factored
+// (rec->ldlt_first .. +ldlt_kb) in order; thread 0 of workgroup 0 also carries them into perm
+__global__ __launch_bounds__(256) void k_ldlt_swap_left(int n, int k0, double* __restrict__ W, int ldw,
+                                                        const int* __restrict__ swp, int* __restrict__ perm,
+                                                        const DevRec* rec) {
+  const int q0 = rec->ldlt_first, q1 = q0 + rec->ldlt_kb;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < k0) {
     double* col = W + (size_t)c * ldw;
-    for (int q = k0; q < k0 + kb; ++q) {
+    for (int q = q0; q < q1; ++q) {
       const int r = swp[q];
       if (r != q) {
         const double x = col[q];
@@ -252,7 +286,7 @@ __global__ __launch_bounds__(256) void k_ldlt_swap_left(int n, int k0, int kb, d
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int q = k0; q < k0 + kb; ++q) {
+    for (int q = q0; q < q1; ++q) {
       const int r = swp[q];
       if (r != q) {
         const int x = perm[q];
@@ -263,10 +297,10 @@ __global__ __launch_bounds__(256) void k_ldlt_swap_left(int n, int k0, int kb, d
   }
 }
 
-hipError_t launch_ldlt_swap_left(int n, int k0, int kb, double* W, int ldw, const int* swp, int* perm,
+hipError_t launch_ldlt_swap_left(int n, int k0, double* W, int ldw, const int* swp, int* perm, const DevRec* rec,
                                  hipStream_t st) {
   const int blocks = k0 > 0 ? (k0 + 255) / 256 : 1;
-  hipLaunchKernelGGL(k_ldlt_swap_left, dim3(blocks), dim3(256), 0, st, n, k0, kb, W, ldw, swp, perm);
+  hipLaunchKernelGGL(k_ldlt_swap_left, dim3(blocks), dim3(256), 0, st, n, k0, W, ldw, swp, perm, rec);
   return hipGetLastError();
 }
 
