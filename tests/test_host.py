@@ -83,3 +83,31 @@ def test_poisson_arrivals():
     assert abs(len(t) - 4000) < 4 * math.sqrt(4000)  # Poisson count within four standard deviations
     gaps = np.diff(t)
     assert abs(gaps.mean() - 1 / 2000.0) < 0.1 / 2000.0
+
+
+def test_extension_option_and_footprint():
+    """The Section V extensions are bits of the options; a small request that asks for them takes a
+    solve worker (the batched kernel runs the paper's routes only), so it has a footprint."""
+    L = _lib()
+    assert ada.make_opts().extensions == 0
+    assert ada.make_opts(extensions=("sym",)).extensions == ada.EXT_SYM
+    assert ada.make_opts(extensions=("sym", "tridiag")).extensions == ada.EXT_SYM | ada.EXT_TRIDIAG
+    with pytest.raises(ValueError):
+        ada.make_opts(extensions=("ldlt",))
+    assert ctypes.sizeof(ada.Opts) == ada.make_opts().struct_size
+    r = ada.Request()
+    r.n, r.nrhs, r.lda, r.ldb, r.ldx = 100, 1, 100, 100, 100
+    assert L.ada_request_footprint(ctypes.byref(r)) == 0
+    r.opts = ada.make_opts(extensions=("sym",))
+    assert L.ada_request_footprint(ctypes.byref(r)) == ada.workspace_size(100, 1, r.opts)
+    assert ada.ROUTE_NAMES[ada.ROUTE_LDLT] == "ldlt" and ada.CLASS_NAMES[ada.CLASS_SYM] == "sym"
+
+
+def test_band_workspace_keeps_the_maps():
+    """The band-solve scratch holds the factor's chunk maps and output responses for the four sweep
+    kinds (4 n (kl+ku) doubles for the responses alone), independent of the right-hand sides."""
+    o = ada.make_opts(layout=ada.LAYOUT_BAND, kl_in=5, ku_in=5)
+    w1 = ada.workspace_size(1_000_000, 1, o)
+    assert w1 > 4 * 1_000_000 * 10 * 8
+    w8 = ada.workspace_size(1_000_000, 8, o)
+    assert w8 > w1
