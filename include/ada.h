@@ -56,13 +56,13 @@ enum {
 /* detected structure (Section II detection order; bit-exact with the definition) */
 enum { ADA_CLASS_GENERAL = 0, ADA_CLASS_BANDED = 1, ADA_CLASS_TRI_UPPER = 2, ADA_CLASS_TRI_LOWER = 3,
        ADA_CLASS_SYMPD = 4,
-       ADA_CLASS_SYM = 5 /* only with ADA_EXT_SYM: equal to its transpose, not judged sympd */ };
+       ADA_CLASS_SYM = 5 /* only with ADA_EXT_SYM: equal to its transpose, fails the Fig. 4 test */ };
 /* solver whose x is returned */
 enum { ADA_ROUTE_NONE = 0, ADA_ROUTE_BAND_LU = 1, ADA_ROUTE_TRI = 2, ADA_ROUTE_CHOL = 3, ADA_ROUTE_LU = 4,
        ADA_ROUTE_SVD = 5, ADA_ROUTE_LDLT = 6, ADA_ROUTE_TRIDIAG = 7 };
 /* Routes the paper's conclusion (Section V) names as future work; off by default, so that the
    classes and routes are the paper's. Bits of ada_opts.extensions:
-   ADA_EXT_SYM: a dense matrix exactly equal to its transpose that is not judged sympd (Fig. 4), or
+   ADA_EXT_SYM: a dense matrix exactly equal to its transpose that fails the sympd test of Fig. 4, or
      whose Cholesky factorisation fails, is solved by LDL^T with Bunch-Kaufman pivoting
      (P A P^T = L D L^T, D of 1x1 and 2x2 blocks) instead of LU; its condition estimate and the
      fallback rule are those of every route (an exactly singular D block is a solver failure);

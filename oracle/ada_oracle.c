@@ -1076,7 +1076,7 @@ void orc_solve_ext(int n, int nrhs, const double* A, int lda, const double* B, i
     res->cls = d.cls;
     res->kl = d.kl;
     res->ku = d.ku;
-    /* extension: a plain symmetric matrix (equal to its transpose, not judged sympd) */
+    /* extension: a plain symmetric matrix (equal to its transpose, failing the Fig. 4 test) */
     if (res->cls == ORC_GENERAL && (ext & ORC_EXT_SYM) && exactly_symmetric(n, A, lda)) res->cls = ORC_SYM;
   }
   res->rank = n;

@@ -28,7 +28,7 @@ enum { ORC_GENERAL = 0, ORC_BANDED = 1, ORC_TRI_UPPER = 2, ORC_TRI_LOWER = 3, OR
 enum { ORC_ROUTE_NONE = 0, ORC_ROUTE_BAND_LU = 1, ORC_ROUTE_TRI = 2, ORC_ROUTE_CHOL = 3,
        ORC_ROUTE_LU = 4, ORC_ROUTE_SVD = 5, ORC_ROUTE_LDLT = 6, ORC_ROUTE_GT = 7 };
 /* extensions named as future work in Section V (off by default: the paper's classes and routes):
-   ORC_EXT_SYM: a matrix equal to its transpose that is not judged sympd (or whose Cholesky fails)
+   ORC_EXT_SYM: a matrix equal to its transpose that fails the Fig. 4 test (or whose Cholesky fails)
    is solved by LDL^T with Bunch-Kaufman pivoting; ORC_EXT_TRIDIAG: a banded matrix with
    kl = ku = 1 is solved by tridiagonal LU with partial pivoting. */
 enum { ORC_EXT_SYM = 1, ORC_EXT_TRIDIAG = 2 };
