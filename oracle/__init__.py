@@ -267,6 +267,14 @@ class Oracle:
         w = self.lib.orc_berr(n, b2.shape[1], _dp(a), n, _dp(b2), n, _dp(x2), n, _dp(per))
         return w, per
 
+    def berr_band(self, ab, kl, ku, b, x):
+        """Backward error of x for the band-storage matrix (kl+ku+1) x n (accurate residual)."""
+        ab, b, x = self._mat(ab), self._mat(b), self._mat(x)
+        b2 = b.reshape(b.shape[0], -1, order="F")
+        x2 = x.reshape(x.shape[0], -1, order="F")
+        n = ab.shape[1]
+        return self.lib.orc_berr_band(n, kl, ku, b2.shape[1], _dp(ab), ab.shape[0], _dp(b2), n, _dp(x2), n)
+
     def sytrf_bk(self, a):
         """Bunch-Kaufman LDL^T of the lower triangle: returns L (unit lower, as a full matrix), d, e
         (the sub-diagonal of the 2x2 blocks), perm (P A P^T = L D L^T, row i of P A is row perm[i])

@@ -10,6 +10,8 @@ import json
 import os
 from fractions import Fraction
 
+import math
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -544,6 +546,63 @@ def test_berr_definition(o=O):
     b2 = F([[3.5], [4.0]])  # residual 0.5; ||A||_inf = 4, ||x|| = 1, ||b|| = 4
     w, per = o.berr(a, b2, x)
     assert w == pytest.approx(0.5 / (4 * 1 + 4))
+
+
+def _eta_exact(a, b, x):
+    """Normwise backward error of x in exact rational arithmetic (the definition, no rounding but the last)."""
+    n = a.shape[0]
+    A = [[Fraction(float(a[i, j])) for j in range(n)] for i in range(n)]
+    anorm = max(sum(abs(v) for v in row) for row in A)
+    out = []
+    for k in range(b.shape[1]):
+        X = [Fraction(float(v)) for v in x[:, k]]
+        r = [Fraction(float(b[i, k])) - sum(A[i][j] * X[j] for j in range(n)) for i in range(n)]
+        rn = max(abs(v) for v in r)
+        den = anorm * max(abs(v) for v in X) + max(abs(Fraction(float(v))) for v in b[:, k])
+        out.append(float(rn / den) if den else (0.0 if rn == 0 else math.inf))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [3, 8, 25, 60])
+def test_berr_exact_rational(n, o=O):
+    """The residual of a backward-stable solution is as small as the rounding of a plain FP64
+    evaluation of b - A x; the oracle's backward error must still be exact to a few ulps: it equals the
+    exact rational value for a LAPACK solution (tiny residual), a perturbed one and a mixed scale."""
+    rng = np.random.default_rng(40 + n)
+    a = F(rng.standard_normal((n, n)) * np.exp(rng.uniform(-3, 3, (n, n))))
+    b = F(rng.standard_normal((n, 3)))
+    x = F(np.linalg.solve(a, b))
+    x[:, 1] *= 1.0 + 1e-9 * rng.standard_normal(n)  # a genuine residual
+    x[:, 2] = x[:, 2] * 1e6  # large scale
+    b[:, 2] *= 1e6
+    w, per = o.berr(a, b, x)
+    ex = _eta_exact(a, b, x)
+    assert np.all(ex[[0, 2]] < 1e-14) and ex[1] > 1e-12
+    assert np.allclose(per, ex, rtol=1e-13, atol=0.0), (per, ex)
+    assert w == per.max()
+
+
+def test_berr_band_hand_and_against_dense(o=O):
+    # hand-worked: A = [[4,1,0],[2,5,1],[0,3,6]] (kl = ku = 1), x = (1,1,1), b = (5,8.5,9): residual (0,0.5,0);
+    # ||A||_inf = 9, ||x|| = 1, ||b|| = 9: eta = 0.5 / 18
+    ab = F([[0.0, 1.0, 1.0], [4.0, 5.0, 6.0], [2.0, 3.0, 0.0]])
+    x = F([[1.0], [1.0], [1.0]])
+    b = F([[5.0], [8.5], [9.0]])
+    xl = x.ctypes.data_as(oracle._P)
+    w = o.lib.orc_berr_band(3, 1, 1, 1, ab.ctypes.data_as(oracle._P), 3, b.ctypes.data_as(oracle._P), 3, xl, 3)
+    assert w == 0.5 / 18.0
+    # a random band with a backward-stable solution: the band evaluation equals the dense one and the exact value
+    rng = np.random.default_rng(3)
+    n, kl, ku = 40, 3, 2
+    ab = W.banded_storage(n, kl, ku, rng)
+    a = W.band_to_dense(ab, kl, ku)
+    b = F(rng.standard_normal((n, 2)))
+    xs = F(np.linalg.solve(a, b))
+    wb = o.lib.orc_berr_band(n, kl, ku, 2, ab.ctypes.data_as(oracle._P), ab.shape[0], b.ctypes.data_as(oracle._P), n,
+                             xs.ctypes.data_as(oracle._P), n)
+    wd, _ = o.berr(a, b, xs)
+    ex = _eta_exact(a, b, xs).max()
+    assert wb == pytest.approx(ex, rel=1e-13) and wd == pytest.approx(ex, rel=1e-13)
 
 
 # ---------------------------------------------------------------- whole small configuration

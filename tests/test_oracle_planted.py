@@ -77,9 +77,21 @@ MUTATIONS = [
      "  if (failed) res->fallback = 1;\n  else if (res->rcond != res->rcond) res->fallback = 3;\n  else if (res->rcond <= thr) res->fallback = 2;\n  if (res->fallback) {\n    if (no_approx) {",
      [P.test_rule_threshold_is_half_eps]),
     ("berr drops ||b||",
-     "    const double den = anorm_inf * xn + bn;\n    const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);\n    if (per_rhs)",
-     "    const double den = anorm_inf * xn;\n    const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);\n    if (per_rhs)",
+     "  const double den = anorm_inf * xn + bn;\n  return den > 0.0",
+     "  const double den = anorm_inf * xn;\n  return den > 0.0",
      [P.test_berr_definition]),
+    ("berr residual drops the low part of the products",
+     "*lo = al * bl - (((*hi - ah * bh) - al * bh) - ah * bl);",
+     "*lo = 0.0;",
+     [P.test_berr_exact_rational]),
+    ("berr residual drops the summation's compensation",
+     "    for (int i = 0; i < n; ++i) r[i] = acc[i].s + acc[i].c;",
+     "    for (int i = 0; i < n; ++i) r[i] = acc[i].s;",
+     [P.test_berr_exact_rational]),
+    ("band berr reads the wrong band row",
+     "exact_product(AB[(size_t)(ku + i - j) + (size_t)j * ldab], x[j], &hi, &lo);",
+     "exact_product(AB[(size_t)(ku + j - i) + (size_t)j * ldab], x[j], &hi, &lo);",
+     [P.test_berr_band_hand_and_against_dense]),
     ("bunch-kaufman alpha", "BK_ALPHA = 0.64038820320220756872767623199676;", "BK_ALPHA = 0.5;",
      [P.test_sytrf_bk_matches_lapack_ldl, P.test_sytrf_bk_pivot_rules_by_hand]),
     ("bunch-kaufman rowmax takes the diagonal",
