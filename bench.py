@@ -80,37 +80,60 @@ def traffic_for(kernel_src: str, kernel: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(nrhs: int, budget_s: float = 25.0):
-    """The oracle on this host's cores over a bounded sample of the same step."""
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(host_cases):
+    """The oracle on this host's cores, at full size, on the same inputs the GPU solved: one oracle
+    solve of each system with every core; the two systems whose oracle solve is O(n^2) or less
+    (banded, lower triangular) also on one thread."""
     import oracle
     O = oracle.get()
     cores = O.num_threads()
-    per = {}
-    spent = 0.0
-    sample_n = 2048
-    for name in ("banded", "lower_scaled", "symindef", "spd", "dense"):
-        cubic = name in ("dense", "spd", "symindef")
-        full_n = 4096 if name == "symindef" else (8192 if name != "banded" else 1_000_000)
-        n = sample_n if cubic else None
-        a, b, lay = W.large_case(name, nrhs=nrhs, n=n)
+
+    def one(name, a, b, lay):
         t0 = time.perf_counter()
         if lay[0] == "band":
             O.solve_band(a, lay[1], lay[2], b)
         else:
             O.solve(a, b)
-        dt = time.perf_counter() - t0
-        spent += dt
-        scale = (full_n / sample_n) ** 3 if cubic else 1.0
-        per[name] = dt * scale
-        if spent > budget_s:
-            break
-    if len(per) < len(SYSTEMS):
-        return None
+        return time.perf_counter() - t0
+
+    per = {name: one(name, a, b, lay) for name, a, b, lay in host_cases}
+    single = {}
+    O.set_threads(1)
+    try:
+        for name, a, b, lay in host_cases:
+            if name in ("banded", "lower_scaled"):
+                single[name] = round(one(name, a, b, lay), 4)
+    finally:
+        O.set_threads(cores)
     step = sum(per.values())
-    sample = ("one oracle solve of each system; banded n=1e6 and lower-triangular n=8192 at full size, "
-              f"dense/SPD/symmetric-indefinite at n={sample_n} scaled by (n/{sample_n})^3 to full size")
-    return {"value": len(SYSTEMS) / step, "unit": "solves/s", "cores": cores, "kind": "oracle", "sample": sample,
-            "per_system_s": {k: round(v, 4) for k, v in per.items()}}
+    return {"value": len(per) / step, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": "one oracle solve of each system of the step at full size, on the same inputs as the GPU",
+            "per_system_s": {k: round(v, 4) for k, v in per.items()}, "single_thread_s": single,
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def oracle_backward_errors(host_cases, xs):
+    """The oracle's backward error of each x the GPU returned (exact products, compensated sums)."""
+    import oracle
+    O = oracle.get()
+    out = {}
+    for (name, a, b, lay), x in zip(host_cases, xs):
+        if lay[0] == "band":
+            out[name] = float(O.berr_band(a, lay[1], lay[2], b, x))
+        else:
+            out[name] = float(O.berr(a, b, x)[0])
+    return out
 
 
 def batched_flops(kind_route, n, nrhs):
@@ -203,26 +226,10 @@ def bench_batched(args):
 
 
 def spectrum_system_gpu(n, kappa, spd, nrhs, seed, dev):
-    """U diag(s) V^T (V = U for SPD) with Haar U, V (QR of a Gaussian, signs fixed), s log-spaced
-    from 1 to 1/kappa; b = A x_true, x_true ~ N(0,1). Generated on the device (input generation,
-    outside the timed solves)."""
-    import torch
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-
-    def haar():
-        q, r = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device=dev, generator=g))
-        return q * torch.sign(torch.diagonal(r))[None, :]
-
-    u = haar()
-    v = u if spd else haar()
-    s = torch.logspace(0.0, -math.log10(kappa), n, dtype=torch.float64, device=dev)
-    a = (u * s[None, :]) @ v.T
-    del u, v
-    x = torch.randn(n, nrhs, dtype=torch.float64, device=dev, generator=g)
-    b = a @ x
-    # column-major storage for the library
-    return a.T.contiguous().T, b.T.contiguous().T
+    """The prescribed-spectrum system of the mixed-precision configuration, generated on the device
+    (input generation, outside the timed solves)."""
+    a, b, _ = W.spectrum_system_torch(n, kappa, spd, nrhs, seed, dev)
+    return a, b
 
 
 def bench_mixed(args):
@@ -550,8 +557,10 @@ def main():
         return bench_serving(args)
     names = [s for s in args.systems.split(",") if s]
     cases = []
+    host_cases = []  # the same inputs on the host, for the oracle after the timed region
     for name in names:
         a, b, lay = W.large_case(name, nrhs=args.nrhs)
+        host_cases.append((name, a, b, lay))
         A = torch.from_numpy(np.asfortranarray(a)).to(dev)
         B = torch.from_numpy(np.asfortranarray(b)).to(dev)
         kw = dict(layout="band", kl_in=lay[1], ku_in=lay[2]) if lay[0] == "band" else {}
@@ -561,7 +570,6 @@ def main():
         work = torch.empty(ada.workspace_size(n, args.nrhs, opts), dtype=torch.uint8, device=dev)
         X = torch.empty((args.nrhs, n), dtype=torch.float64, device=dev).t()
         cases.append((name, A, B, kw, work, X, n))
-        del a, b
     torch.cuda.synchronize()
     ctx = ada.context(0)
     # set-up, not timed: the band-solve autotuner picks its LDS staging piece for the band widths
@@ -615,6 +623,18 @@ def main():
 
     nsolves = len(cases) * args.steps
     value = nsolves / total
+
+    # after the timed region: the oracle's backward error of every x the GPU returned, which the
+    # library's own value must match
+    xs_host = [np.asfortranarray(c[5].cpu().numpy()) for c in cases]
+    oracle_eta = oracle_backward_errors(host_cases, xs_host)
+    for name, _, _, _, _, _, _ in cases:
+        eo, eg = oracle_eta[name], info[name].berr
+        per_sys[name]["berr_oracle"] = eo
+        if not (eo <= BERR_BAR) or not (abs(eg - eo) <= 1e-6 * eo + 1e-300):
+            print(f"{name}: oracle backward error {eo} (library {eg}) misses the bar or disagrees",
+                  file=sys.stderr)
+            sys.exit(1)
 
     # roofline of the dominant single-kernel family over the timed region
     fam = max(FAMILY_KERNEL, key=lambda f: prof[f][1])
@@ -674,7 +694,7 @@ def main():
 
     cpu = None
     if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
-        cpu = cpu_baseline(args.nrhs)
+        cpu = cpu_baseline(host_cases)
 
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -685,7 +705,8 @@ def main():
                                f"n=4096; nrhs={args.nrhs}", "systems": names, "nrhs": args.nrhs},
         "tflops": round(flops_step * args.steps / total / 1e12, 4),
         "p50_step_ms": round(pct(step_times, 50) * 1e3, 3), "p99_step_ms": round(pct(step_times, 99) * 1e3, 3),
-        "max_berr": worst_berr, "per_system": per_sys, "kernel_families": families,
+        "max_berr": worst_berr, "max_berr_oracle": max(oracle_eta.values()), "per_system": per_sys,
+        "kernel_families": families,
         "roofline": roofline, "cpu_baseline": cpu, "concurrent": concurrent, "extensions": extensions,
     }
     print(json.dumps(out), flush=True)

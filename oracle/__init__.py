@@ -128,6 +128,10 @@ class Oracle:
     def num_threads(self) -> int:
         return int(self.lib.orc_num_threads())
 
+    def set_threads(self, k: int) -> None:
+        """Threads of the oracle's parallel loops from now on (OpenMP's runtime setting)."""
+        self.lib.omp_set_num_threads(ctypes.c_int(int(k)))
+
     def band_scan(self, a):
         a = self._mat(a)
         kl, ku = ctypes.c_int(), ctypes.c_int()

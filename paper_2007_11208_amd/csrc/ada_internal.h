@@ -119,6 +119,29 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
+// Accurate residual entries (the backward error of a backward-stable solution
+// is as small as the rounding of a plain evaluation of b - A x): Dot2 of
+// Ogita, Rump and Oishi (Accurate sum and dot product, SIAM J. Sci. Comput.
+// 26(6), 2005). Each product is split exactly by a fused multiply-add
+// (TwoProduct), the running sum by Knuth's TwoSum, and both errors gather in c;
+// s + c is as accurate as a sum formed in twice the working precision. The
+// bodies must not be contracted into other fused operations.
+__device__ __forceinline__ void two_sum_acc(double& s, double& c, double p) {
+#pragma clang fp contract(off)
+  const double t = s + p;
+  const double z = t - s;
+  c += (s - (t - z)) + (p - z);
+  s = t;
+}
+// (s, c) += -(a * x)
+__device__ __forceinline__ void dot2_sub(double& s, double& c, double a, double x) {
+#pragma clang fp contract(off)
+  const double p = -a * x;
+  const double h = fma(-a, x, -p);
+  two_sum_acc(s, c, p);
+  c += h;
+}
+
 __device__ __forceinline__ unsigned agent_load(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -286,6 +309,7 @@ hipError_t launch_finalize_rcond(DevRec* rec, hipStream_t st);
 // residual and backward error
 // X += D (n x nrhs)
 hipError_t launch_add_to(int n, int nrhs, const double* D, int ldd, double* X, int ldx, hipStream_t st);
+size_t resid_partial_doubles(int n, int nrhs);  // scratch of launch_resid_gemv
 hipError_t launch_resid_gemv(int n, int nrhs, const double* A, int lda, const double* B, int ldb, const double* X,
                              int ldx, double* R, int ldr, double* P, hipStream_t st);
 hipError_t launch_x_finite(int n, int nrhs, const double* X, int ldx, DevRec* rec, hipStream_t st);

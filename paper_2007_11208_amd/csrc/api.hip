@@ -88,7 +88,7 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     p.bsc_doubles = band_chunked_scratch_doubles(n, kd, 0, nrhs);
     p.bsc = take(cur, p.bsc_doubles * 8);
   }
-  if (p.dense) p.P = take(cur, (size_t)((n + 511) / 512) * 8 * N * 8);
+  if (p.dense) p.P = take(cur, resid_partial_doubles(n, nrhs) * 8);
   // W: dense working copy (LU/Cholesky factor, Jacobi U) and/or the band factor (2kl+ku+1 rows)
   size_t wrows = (size_t)n;
   if (p.band) {
@@ -600,12 +600,7 @@ int route_svd(Solve& s, const double* A, int lda, const double* B, int ldb, doub
 int backward_error_dense(Solve& s, const double* A, int lda, const double* B, int ldb, const double* X, int ldx) {
   const int n = s.n, nrhs = s.nrhs;
   double* R = s.at<double>(s.p.R);
-  if (nrhs <= 8) {
-    HIPCHK(launch_resid_gemv(n, nrhs, A, lda, B, ldb, X, ldx, R, n, s.at<double>(s.p.P), s.st));
-  } else {
-    HIPCHK(launch_copy(n, nrhs, B, ldb, R, n, s.st));
-    HIPCHK(launch_gemm_sub(n, nrhs, n, A, lda, X, ldx, false, R, n, false, nullptr, s.st, nullptr, nullptr));
-  }
+  HIPCHK(launch_resid_gemv(n, nrhs, A, lda, B, ldb, X, ldx, R, n, s.at<double>(s.p.P), s.st));
   HIPCHK(launch_berr(n, nrhs, R, n, B, ldb, X, ldx, s.at<double>(s.p.percol), s.rec, s.st));
   return ADA_OK;
 }

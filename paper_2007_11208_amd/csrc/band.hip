@@ -758,10 +758,10 @@ __global__ void k_band_resid(int n, int kl, int ku, int nrhs, const double* __re
                              double* __restrict__ R, int ldr) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     for (int c = 0; c < nrhs; ++c) {
-      double s = B[(size_t)i + (size_t)c * ldb];
+      double s = B[(size_t)i + (size_t)c * ldb], e = 0.0;  // accurate residual (Dot2)
       for (int j = max(0, i - kl); j <= min(n - 1, i + ku); ++j)
-        s = fma(-AB[(size_t)(ku_in + i - j) + (size_t)j * ldab], X[(size_t)j + (size_t)c * ldx], s);
-      R[(size_t)i + (size_t)c * ldr] = s;
+        dot2_sub(s, e, AB[(size_t)(ku_in + i - j) + (size_t)j * ldab], X[(size_t)j + (size_t)c * ldx]);
+      R[(size_t)i + (size_t)c * ldr] = s + e;
     }
   }
 }

@@ -1340,9 +1340,10 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
         double rn = 0.0, xn = 0.0, bn = 0.0;
         int xbad = 0;
         for (int i = c.t; i < n; i += BT) {
-          double s = B[i + (size_t)r * d.ldb];
+          double s = B[i + (size_t)r * d.ldb], e = 0.0;  // accurate residual (Dot2)
 #pragma unroll 8
-          for (int j = 0; j < n; ++j) s = fma(-A[i + (size_t)j * d.lda], X[j + (size_t)r * d.ldx], s);
+          for (int j = 0; j < n; ++j) dot2_sub(s, e, A[i + (size_t)j * d.lda], X[j + (size_t)r * d.ldx]);
+          s += e;
           const double xi = X[i + (size_t)r * d.ldx];
           xbad |= !isfinite(xi);
           rn = fmax(rn, fabs(s));

@@ -73,23 +73,27 @@ hipError_t launch_scatter_rows(int n, int nrhs, const int* perm, const double* S
   return hipGetLastError();
 }
 
-// R = B - A X for up to 8 right-hand sides: rows over threads, the n columns of A
-// split into chunks over blockIdx.y; partial sums go to P[chunk][c][i] and are
-// added in chunk order by k_resid_sum (deterministic).
+// R = B - A X, accurately (Dot2: every product split exactly, the sums
+// compensated), for right-hand sides in groups of 8 (blockIdx.z): rows over
+// threads, the n columns of A split into chunks over blockIdx.y; each chunk's
+// compensated partial sum (s, c) goes to P[group][chunk][c][i] and k_resid_sum
+// adds them in chunk order, again compensated (deterministic).
 constexpr int RCH = 512;  // columns of A per chunk
 __global__ __launch_bounds__(256) void k_resid_part(int n, int nrhs, const double* __restrict__ A, int lda,
                                                     const double* __restrict__ X, int ldx, double* __restrict__ P) {
   __shared__ double sx[64][8];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g0 = blockIdx.z * 8, ng = min(8, nrhs - g0);
+  const int nch = gridDim.y;
   const int j0 = blockIdx.y * RCH, j1 = min(n, j0 + RCH);
-  double acc[8];
+  double s[8], c[8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int q = 0; q < 8; ++q) s[q] = c[q] = 0.0;
   for (int jb = j0; jb < j1; jb += 64) {
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * 8; e += blockDim.x) {
-      const int jj = e / 8, c = e % 8;
-      sx[jj][c] = (jb + jj < j1 && c < nrhs) ? X[(size_t)(jb + jj) + (size_t)c * ldx] : 0.0;
+      const int jj = e / 8, q = e % 8;
+      sx[jj][q] = (jb + jj < j1 && q < ng) ? X[(size_t)(jb + jj) + (size_t)(g0 + q) * ldx] : 0.0;
     }
     __syncthreads();
     if (i < n) {
@@ -97,32 +101,47 @@ __global__ __launch_bounds__(256) void k_resid_part(int n, int nrhs, const doubl
       for (int jj = 0; jj < jn; ++jj) {
         const double a = A[(size_t)i + (size_t)(jb + jj) * lda];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = fma(a, sx[jj][c], acc[c]);
+        for (int q = 0; q < 8; ++q) dot2_sub(s[q], c[q], a, sx[jj][q]);
       }
     }
   }
-  if (i < n)
-    for (int c = 0; c < nrhs; ++c) P[((size_t)blockIdx.y * nrhs + c) * n + i] = acc[c];
+  if (i < n) {
+    double* Pg = P + (size_t)blockIdx.z * nch * 8 * 2 * n;
+    for (int q = 0; q < ng; ++q) {
+      Pg[(((size_t)blockIdx.y * 8 + q) * 2 + 0) * n + i] = s[q];
+      Pg[(((size_t)blockIdx.y * 8 + q) * 2 + 1) * n + i] = c[q];
+    }
+  }
 }
 
 __global__ void k_resid_sum(int n, int nrhs, int nch, const double* __restrict__ B, int ldb,
                             const double* __restrict__ P, double* __restrict__ R, int ldr) {
   const size_t total = (size_t)n * nrhs;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n), c = (int)(e / n);
-    double s = 0.0;
-    for (int q = 0; q < nch; ++q) s += P[((size_t)q * nrhs + c) * n + i];
-    R[(size_t)i + (size_t)c * ldr] = B[(size_t)i + (size_t)c * ldb] - s;
+    const int i = (int)(e % n), col = (int)(e / n);
+    const int g = col / 8, q = col % 8;
+    const double* Pg = P + (size_t)g * nch * 8 * 2 * n;
+    double s = B[(size_t)i + (size_t)col * ldb], c = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      two_sum_acc(s, c, Pg[(((size_t)ch * 8 + q) * 2 + 0) * n + i]);
+      c += Pg[(((size_t)ch * 8 + q) * 2 + 1) * n + i];
+    }
+    R[(size_t)i + (size_t)col * ldr] = s + c;
   }
 }
 
-// P must hold ceil(n/RCH) * nrhs * n doubles (nrhs <= 8); for more right-hand
-// sides the caller uses the matrix-core GEMM.
+size_t resid_partial_doubles(int n, int nrhs) {
+  const size_t nch = (size_t)((n + RCH - 1) / RCH);
+  return (size_t)((nrhs + 7) / 8) * nch * 8 * 2 * (size_t)n;
+}
+
+// P must hold resid_partial_doubles(n, nrhs) doubles.
 hipError_t launch_resid_gemv(int n, int nrhs, const double* A, int lda, const double* B, int ldb, const double* X,
                              int ldx, double* R, int ldr, double* P, hipStream_t st) {
-  if (nrhs > 8) return hipErrorInvalidValue;
   const int nch = (n + RCH - 1) / RCH;
-  hipLaunchKernelGGL(k_resid_part, dim3((n + 255) / 256, nch), dim3(256), 0, st, n, nrhs, A, lda, X, ldx, P);
+  const int groups = (nrhs + 7) / 8;
+  if (groups > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_resid_part, dim3((n + 255) / 256, nch, groups), dim3(256), 0, st, n, nrhs, A, lda, X, ldx, P);
   size_t total = (size_t)n * nrhs;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;

@@ -163,6 +163,31 @@ def rhs_for(a: np.ndarray, x: np.ndarray) -> np.ndarray:
     return _f(a @ x)
 
 
+def spectrum_system_torch(n: int, kappa: float, spd: bool, nrhs: int, seed: int, device):
+    """U diag(s) V^T (V = U for SPD) with Haar U, V (QR of a Gaussian, signs fixed), s log-spaced
+    from 1 to 1/kappa, so the 2-norm condition number is kappa by construction; b = A x_true,
+    x_true ~ N(0,1). Formed with torch on `device` (input generation only: at n = 16384 the host
+    QR takes minutes). Returns column-major (A, B, x_true)."""
+    import math
+
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar():
+        q, r = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device=device, generator=g))
+        return q * torch.sign(torch.diagonal(r))[None, :]
+
+    u = haar()
+    v = u if spd else haar()
+    s = torch.logspace(0.0, -math.log10(kappa), n, dtype=torch.float64, device=device)
+    a = (u * s[None, :]) @ v.T
+    del u, v
+    x = torch.randn(n, nrhs, dtype=torch.float64, device=device, generator=g)
+    b = a @ x
+    return a.T.contiguous().T, b.T.contiguous().T, x
+
+
 # ---- the benchmark systems -------------------------------------------------
 
 SMALL_CASES = ("a_dense", "b_spd", "c_upper", "c_upper_scaled", "d_banded", "e_illcond", "e_illcond_1e18")

@@ -1,15 +1,18 @@
 """GPU parity of the batched solve (many small systems in one launch) against the oracle.
 
 Same bars as the single-system parity tests: class and band widths bit-exact,
-route / Cholesky failure / fallback reason exact, rcond within a factor 2,
-backward error <= 1e-12 (or twice the oracle's for inconsistent least-squares
-systems), x within 32 n kappa eps |x| off the SVD route, SVD rank exact.
+route / Cholesky failure / fallback reason exact outside a factor 4 of the rcond
+threshold (systems inside it are reported), rcond within a factor 2, the
+reported backward error equal to the oracle's on the GPU's x and <= 1e-12 (or
+twice the oracle's for inconsistent least-squares systems), x within
+32 n kappa eps |x| off the SVD route, SVD rank exact.
 """
 import numpy as np
 import pytest
 
 import oracle
 from paper_2007_11208_amd import workloads as W
+from paritycheck import check_berr, near_threshold, note_near_threshold
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -29,22 +32,29 @@ def ada():
 
 def check(ada, a, b, x, r, **okw):
     xr, rr = O.solve(a, b, **okw)
-    assert r.status == rr["status"], (r, rr)
+    assert r.status == rr["status"] or (rr["info"] == 0 and near_threshold(rr["rcond"])), (r, rr)
     if r.status not in (0, -3):
         return
     assert r.cls == ada.CLASS_NAMES[rr["cls"]], (r, rr)
     assert (r.kl, r.ku) == (rr["kl"], rr["ku"])
+    xg = x.reshape(xr.shape)
+    if rr["info"] == 0 and near_threshold(rr["rcond"]):
+        note_near_threshold(f"n={a.shape[0]}", rr, r)
+        if r.status == 0:
+            check_berr(r.berr, a, b, xg)
+        return
     assert r.route == ada.ROUTE_NAMES[rr["route"]], (r, rr)
     assert r.chol_failed == bool(rr["chol_failed"])
     assert r.fallback == rr["fallback"]
     if rr["fallback"] == 0:
         assert 0.5 * rr["rcond"] <= r.rcond <= 2.0 * rr["rcond"], (r.rcond, rr["rcond"])
     if r.status == 0:
-        assert r.berr <= max(1e-12, 2.0 * rr["berr"]), (r.berr, rr["berr"])
+        eta = check_berr(r.berr, a, b, xg)
+        assert eta <= max(1e-12, 2.0 * rr["berr"]), (eta, rr["berr"])
         if r.route != "svd":
             kappa = 1.0 / max(rr["rcond"], 1e-300)
             tol = 32 * a.shape[0] * kappa * EPS * max(1.0, np.max(np.abs(xr)))
-            assert np.max(np.abs(x.reshape(xr.shape) - xr)) <= tol
+            assert np.max(np.abs(xg - xr)) <= tol
         else:
             assert r.rank == rr["rank"]
 
@@ -126,6 +136,10 @@ def test_batched_fp32_refined_mix(ada):
         print(f"{kind} n={a.shape[0]} nrhs={b.shape[1]} -> {r.cls}/{r.route} it={r.refine_iters}", flush=True)
         assert r.status == rr["status"] == 0
         assert r.cls == ada.CLASS_NAMES[rr["cls"]] and (r.kl, r.ku) == (rr["kl"], rr["ku"])
+        eta = check_berr(r.berr, a, b, x.reshape(xr.shape))
+        if rr["info"] == 0 and near_threshold(rr["rcond"]):
+            note_near_threshold(f"{kind} n={a.shape[0]}", rr, r)
+            continue
         assert r.route == ada.ROUTE_NAMES[rr["route"]], (r, rr)
         assert r.fallback == rr["fallback"]
         if r.route == "tri":
@@ -136,7 +150,7 @@ def test_batched_fp32_refined_mix(ada):
             refined += r.refine_iters > 0
             assert 0.5 * rr["rcond"] <= r.rcond <= 2.0 * rr["rcond"], (r.rcond, rr["rcond"])
         if r.route != "svd":
-            assert r.berr <= 1e-10, r
+            assert eta <= 1e-10, r
             kappa = 1.0 / max(rr["rcond"], 1e-300)
             tol = 32 * a.shape[0] * kappa * EPS * max(1.0, np.max(np.abs(xr)))
             assert np.max(np.abs(x.reshape(xr.shape) - xr)) <= tol
@@ -163,7 +177,7 @@ def test_batched_fp32_refinement_falls_back_to_fp64(ada):
         assert (r32[k].route, r32[k].rcond, r32[k].berr) == (r64[k].route, r64[k].rcond, r64[k].berr)
     for k in (2, 3):
         assert r32[k].refine_iters > 0 and r32[k].route == r64[k].route
-        assert r32[k].berr <= 1e-10
+        assert check_berr(r32[k].berr, As[k], Bs[k], x32[k]) <= 1e-10
     with pytest.raises(ValueError):
         ada.make_opts(precision="bf16")
 

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paritycheck import check_berr
 from paper_2007_11208_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -56,10 +57,11 @@ def check(ada, a, b, ext, oext, layout="dense", kl_in=0, ku_in=0):
     assert r.chol_failed == bool(rr["chol_failed"]) and r.fallback == rr["fallback"]
     if rr["fallback"] == 0:
         assert 0.5 * rr["rcond"] <= r.rcond <= 2.0 * rr["rcond"], (r.rcond, rr["rcond"])
-        assert r.berr <= max(1e-12, 2.0 * rr["berr"]), (r.berr, rr["berr"])
+        xg = x.cpu().numpy().reshape(xr.shape)
+        eta = check_berr(r.berr, a, b, xg, band=(kl_in, ku_in) if layout == "band" else None)
+        assert eta <= max(1e-12, 2.0 * rr["berr"]), (eta, rr["berr"])
         kappa = 1.0 / max(rr["rcond"], 1e-300)
         tol = 32 * n * kappa * EPS * max(1.0, float(np.max(np.abs(xr))))
-        xg = x.cpu().numpy().reshape(xr.shape)
         assert float(np.max(np.abs(xg - xr))) <= tol
     else:
         assert r.info == rr["info"] and r.rank == rr["rank"]
@@ -174,7 +176,7 @@ def test_server_keeps_ldlt_factors(ada):
             kappa = 1.0 / rr["rcond"]
             tol = 32 * 700 * kappa * EPS * max(1.0, float(np.max(np.abs(xr))))
             assert float(np.max(np.abs(X2.cpu().numpy().reshape(xr.shape) - xr))) <= tol
-            assert r2.berr <= 1e-12
+            assert check_berr(r2.berr, a, b2, X2.cpu().numpy()) <= 1e-12
         srv.release(f)
     finally:
         srv.close()

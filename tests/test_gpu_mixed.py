@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paritycheck import check_berr
 from paper_2007_11208_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -59,13 +60,14 @@ def check(ada, a, b, precision):
     assert r.fallback == rr["fallback"]
     if rr["fallback"] == 0:
         assert 0.5 * rr["rcond"] <= r.rcond <= 2.0 * rr["rcond"], (r.rcond, rr["rcond"])
+        xg = x.cpu().numpy().reshape(xr.shape)
+        eta = check_berr(r.berr, a, b, xg)
         if r.refine_iters > 0:
-            assert r.berr <= math.sqrt(n) * EPS
+            assert eta <= math.sqrt(n) * EPS
         else:
-            assert r.berr <= max(1e-12, 2.0 * rr["berr"])
+            assert eta <= max(1e-12, 2.0 * rr["berr"])
         kappa = 1.0 / max(rr["rcond"], 1e-300)
         tol = 32 * n * kappa * EPS * max(1.0, np.max(np.abs(xr)))
-        xg = x.cpu().numpy().reshape(xr.shape)
         assert np.max(np.abs(xg - xr)) <= tol, (np.max(np.abs(xg - xr)), tol)
     return r
 

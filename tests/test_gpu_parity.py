@@ -2,14 +2,21 @@
 
 Bars (written here, derived in the design doc):
   * class and band widths: bit-exact;
-  * route: bit-exact (no test input sits near the rcond threshold);
+  * route, Cholesky failure and fallback reason: exact, except for systems whose
+    oracle rcond lies within a factor 4 of the threshold, which are reported
+    (the estimate is only good to a factor ~3; either side is correct there);
   * rcond: the GPU value is within a factor 2 of the oracle's (same estimator,
-    different summation order; the estimate itself is only good to a factor ~3);
-  * x: normwise backward error <= 1e-12 and |x - x_oracle| <= 32 n kappa eps |x|
-    elementwise-max (both are backward stable solves of the same system);
-  * SVD route: rank exact and x within the kept-spectrum conditioning.
+    different summation order);
+  * backward error: the value the library reports equals the oracle's
+    evaluation on the GPU's x to a relative 1e-6, and that value is <= 1e-12
+    (or twice the oracle's own for inconsistent least-squares systems);
+  * x: |x - x_oracle| <= 32 n kappa eps |x| elementwise-max, kappa from the
+    oracle's rcond or from the construction (both are backward stable solves
+    of the same system);
+  * SVD route: rank exact; x against the oracle's minimum-norm solution where
+    the spectrum has a clear gap at the cut.
 Sizes span several 64/128 tiles and ragged tails; the large single-system
-workloads are checked through properties that hold at any size.
+workloads are checked against the oracle at their full sizes.
 """
 import math
 
@@ -18,6 +25,7 @@ import pytest
 
 import oracle
 from paper_2007_11208_amd import workloads as W
+from paritycheck import check_berr, near_threshold, note_near_threshold
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -48,6 +56,13 @@ def check_against_oracle(ada, a, b, *, kappa=None, **kw):
     assert r.status in (0, -3), (r.status, ada.last_error())
     assert r.cls == ada.CLASS_NAMES[rr["cls"]]
     assert (r.kl, r.ku) == (rr["kl"], rr["ku"])
+    xg = x.cpu().numpy().reshape(xr.shape)
+    thr = kw.get("rcond_threshold", 0.5 * EPS)
+    if rr["info"] == 0 and near_threshold(rr["rcond"], thr):
+        note_near_threshold(f"n={a.shape[0]}", rr, r)
+        if r.status == 0:
+            check_berr(r.berr, a, b, xg)
+        return x, r, rr
     assert r.route == ada.ROUTE_NAMES[rr["route"]], (r, rr)
     assert r.chol_failed == bool(rr["chol_failed"])
     assert r.fallback == rr["fallback"]
@@ -55,9 +70,10 @@ def check_against_oracle(ada, a, b, *, kappa=None, **kw):
     if rr["fallback"] == 0:
         assert 0.5 * rr["rcond"] <= r.rcond <= 2.0 * rr["rcond"], (r.rcond, rr["rcond"])
     if r.status == 0:
-        # a least-squares solution of an inconsistent system has a genuine residual
-        assert r.berr <= max(1e-12, 2.0 * rr["berr"]), (r.berr, rr["berr"])
-        xg = x.cpu().numpy().reshape(xr.shape)
+        # the reported backward error is the oracle's value on the GPU's x, and it meets the bar
+        # (a least-squares solution of an inconsistent system has a genuine residual)
+        eta = check_berr(r.berr, a, b, xg)
+        assert eta <= max(1e-12, 2.0 * rr["berr"]), (eta, rr["berr"])
         if r.route != "svd":
             if kappa is None:
                 kappa = 1.0 / max(rr["rcond"], 1e-300)
@@ -241,6 +257,10 @@ def test_svd_fallback_ill_conditioned_blocked(ada):
     b = W.rhs_for(a, W.x_true(n, 2, np.random.default_rng(6)))
     x, r, rr = check_against_oracle(ada, a, b)
     assert r.route == "svd" and r.fallback == 2 and r.rank == n - 10
+    # the kept spectrum spans [1e-8, 1] and the cut falls in a gap of 1e12: the minimum-norm
+    # solution is well defined, with condition 1e8
+    xr, _ = O.solve(a, b)
+    assert np.max(np.abs(x.cpu().numpy().reshape(xr.shape) - xr)) <= 32 * n * 1e8 * EPS * np.max(np.abs(xr))
 
 
 def test_solver_failures(ada):
@@ -300,13 +320,14 @@ def test_band_layout_input(ada):
     xr, rr = O.solve_band(ab, kl, ku, b)
     assert (r.cls, r.kl, r.ku, r.route) == ("banded", kl, ku, "band_lu")
     assert 0.5 * rr["rcond"] <= r.rcond <= 2 * rr["rcond"]
-    assert r.berr <= 1e-14
+    assert check_berr(r.berr, ab, b, xs.cpu().numpy(), band=(kl, ku)) <= 1e-14
     assert np.max(np.abs(xs.cpu().numpy() - xr)) <= 1e-12 * np.max(np.abs(xr))
     # stored band wider than the true band: detection finds the true widths
     ab2 = np.zeros((kl + ku + 5, n), order="F")
     ab2[2:2 + kl + ku + 1, :] = ab
     xs2, r2 = ada.solve(T(ab2), T(b), layout="band", kl_in=kl + 2, ku_in=ku + 2)
     assert (r2.kl, r2.ku) == (kl, ku)
+    check_berr(r2.berr, ab2, b, xs2.cpu().numpy(), band=(kl + 2, ku + 2))
     assert np.max(np.abs(xs2.cpu().numpy() - xr)) <= 1e-12 * np.max(np.abs(xr))
 
 
@@ -333,24 +354,67 @@ def test_band_row_parallel_solve(ada, n, kl, ku, nrhs, shift):
     assert r.status == rr["status"] == 0, ada.last_error()
     assert (r.cls, r.kl, r.ku, r.route) == ("banded", kl, ku, "band_lu")
     assert 0.5 * rr["rcond"] <= r.rcond <= 2 * rr["rcond"], (r.rcond, rr["rcond"])
-    assert r.berr <= max(1e-13, 4 * rr["berr"]), (r.berr, rr["berr"])
+    eta = check_berr(r.berr, ab, b, xs.cpu().numpy(), band=(kl, ku))
+    assert eta <= max(1e-13, 4 * rr["berr"]), (eta, rr["berr"])
     tol = 32 * n * EPS / rr["rcond"] * max(1.0, np.max(np.abs(xr)))
     assert np.max(np.abs(xs.cpu().numpy().reshape(xr.shape) - xr)) <= tol
 
 
 @pytest.mark.parametrize("n", [3000, 6000])
 def test_lu_many_panel_workgroups(ada, n):
-    """LU whose panels span up to 24 workgroups (one cross-workgroup exchange per column): properties
-    that hold at any size: backward error, error against the known solution within kappa eps, route."""
+    """LU whose panels span 12 and 24 workgroups (one cross-workgroup exchange per column),
+    against the oracle."""
     rng = np.random.default_rng(n)
     a = W.dense_general(n, rng)
-    xt = W.x_true(n, 2, rng)
-    b = W.rhs_for(a, xt)
-    x, r = ada.solve(T(a), T(b))
+    b = W.rhs_for(a, W.x_true(n, 2, rng))
+    x, r, rr = check_against_oracle(ada, a, b)
+    assert r.route == "lu" and r.cls == "general"
+
+
+@pytest.mark.parametrize("name", ["dense", "spd", "symindef", "lower_scaled"])
+def test_large_single_systems(ada, name):
+    """The single large systems the benchmark times (dense and SPD n = 8192: 32 panel workgroups;
+    symmetric indefinite n = 4096: Cholesky fails and re-routes to LU; lower triangular n = 8192),
+    at their full sizes, against the oracle."""
+    a, b, _ = W.large_case(name, nrhs=1)
+    x, r, rr = check_against_oracle(ada, a, b)
+    expect = {"dense": ("general", "lu"), "spd": ("sympd", "chol"), "symindef": ("sympd", "lu"),
+              "lower_scaled": ("tri_lower", "tri")}[name]
+    assert (r.cls, r.route) == expect
+    assert r.chol_failed == (name == "symindef")
+
+
+def test_large_banded_system(ada):
+    """The banded system the benchmark times (n = 1e6, kl = ku = 5, band layout), against the oracle."""
+    ab, b, (_, kl, ku) = W.large_case("banded", nrhs=1)
+    xs, r = ada.solve(T(ab), T(b), layout="band", kl_in=kl, ku_in=ku)
     torch.cuda.synchronize()
-    print(f"n={n} route={r.route} rcond={r.rcond:.2e} berr={r.berr:.2e}", flush=True)
-    assert r.status == 0 and r.route == "lu" and r.cls == "general"
-    assert r.berr <= 1e-14
+    xr, rr = O.solve_band(ab, kl, ku, b)
+    assert (r.cls, r.kl, r.ku, r.route) == ("banded", kl, ku, "band_lu") and rr["status"] == 0
+    assert 0.5 * rr["rcond"] <= r.rcond <= 2 * rr["rcond"]
+    eta = check_berr(r.berr, ab, b, xs.cpu().numpy(), band=(kl, ku))
+    assert eta <= 1e-14
+    tol = 32 * ab.shape[1] * EPS / rr["rcond"] * max(1.0, np.max(np.abs(xr)))
+    assert np.max(np.abs(xs.cpu().numpy().reshape(xr.shape) - xr)) <= tol
+
+
+def test_lu_n16384_prescribed_condition(ada):
+    """Dense LU at the largest order the dense routes take (n = 16384: the panel spans 64
+    workgroups): U diag(s) V^T with condition number 1e3 by construction. The backward error
+    is the oracle's on the GPU's x, and x is within 32 n kappa eps of the known solution
+    (the oracle's O(n^3) solve at this size would take minutes)."""
+    n, kappa = 16384, 1e3
+    A, B, xt = W.spectrum_system_torch(n, kappa, False, 2, 4242, torch.device("cuda:0"))
+    torch.cuda.synchronize()
+    x, r = ada.solve(A, B)
+    torch.cuda.synchronize()
+    print(f"n={n} route={r.route} rcond={r.rcond:.3e} berr={r.berr:.3e}", flush=True)
+    assert r.status == 0 and (r.cls, r.route) == ("general", "lu")
+    # kappa_1 lies within a factor n of kappa_2 and the estimate within a factor 3 of kappa_1
+    assert 1.0 / (n * kappa) <= r.rcond <= 3.0 * n / kappa
+    a = np.asfortranarray(A.cpu().numpy())
+    b = np.asfortranarray(B.cpu().numpy())
     xg = x.cpu().numpy()
-    kappa = 1.0 / r.rcond
-    assert np.max(np.abs(xg - xt)) <= 32 * n * kappa * EPS * max(1.0, np.max(np.abs(xt)))
+    assert check_berr(r.berr, a, b, xg) <= 1e-13
+    xtn = xt.cpu().numpy()
+    assert np.max(np.abs(xg - xtn)) <= 32 * n * kappa * EPS * np.max(np.abs(xtn))
