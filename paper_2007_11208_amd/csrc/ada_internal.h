@@ -56,7 +56,6 @@ struct DevRec {
   int ldlt_delta;             // 1: the next LDL^T panel's first position is already factored (2x2 block)
   // ---- synchronisation counters (zeroed per solve) ----
   unsigned int counters[512];  // grid barriers / tickets, one per launch that needs one
-  int panel_flags[2 * 64];     // LU panel: per-workgroup publication epochs (two column parities)
 };
 
 // Raise a kernel's dynamic-LDS limit when a launch needs more than the default
@@ -206,15 +205,13 @@ hipError_t launch_gemm_sub(int m, int n, int k, const double* A, int lda, const 
 
 // LU
 struct PanelScratch {
-  double* slot_val;   // [2][64]
-  int* slot_row;      // [2][64]
-  double* slot_rows;  // [2][64][128]
-  double* diag_rows;  // [2][128]
-  int* moves;         // [2*128+1]: count, then (dst,src) pairs
+  unsigned long long* recs;  // [2][64][2]: each workgroup's candidate record, by column parity
+  double* slot_rows;         // [2][64][128]: each workgroup's candidate row
+  int* moves;                // [2*256+1]: count, then (dst,src) pairs
 };
-// seq: index of this panel within the solve (makes the publication epochs unique)
-hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec, int seq,
-                              PanelScratch ps, hipStream_t st);
+hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec, PanelScratch ps,
+                              hipStream_t st);
+hipError_t launch_panel_reset(PanelScratch ps, hipStream_t st);
 hipError_t launch_laswp_moves(int n, int k0, int nbw, double* W, int ldw, const int* moves, int* perm,
                               DevRec* rec, hipStream_t st);
 hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st);

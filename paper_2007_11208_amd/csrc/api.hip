@@ -44,8 +44,8 @@ constexpr int kBandChunkMin = 2 * LC;  // band solves parallel over the rows fro
 struct Plan {
   size_t total = 0;
   // offsets (bytes)
-  size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, slot_val, slot_row,
-      slot_rows, diag_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec, estpart, Q, tau;
+  size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, recs,
+      slot_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec, estpart, Q, tau;
   size_t bsc_doubles, gbspec_doubles;
   int n, nrhs, ldw, T64, nflags;
   bool dense, band, band_dense;
@@ -126,10 +126,8 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     p.sigma = take(cur, N * 8);
     p.Q = take(cur, N * N * 8);  // Householder reflectors of the SVD route's QR preconditioner
     p.tau = take(cur, N * 8);
-    p.slot_val = take(cur, 2 * 64 * 8);
-    p.slot_row = take(cur, 2 * 64 * 4);
-    p.slot_rows = take(cur, 2 * 64 * 128 * 8);
-    p.diag_rows = take(cur, 2 * 128 * 8);
+    p.recs = take(cur, 2 * 64 * 2 * 8);
+    p.slot_rows = take(cur, (size_t)2 * 64 * 128 * 8);
     p.moves = take(cur, (1 + 2 * 256) * 4);
     if (p.band) p.Adense = take(cur, N * N * 8);  // dense expansion of band-layout input
   }
@@ -388,8 +386,9 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
   int* perm = s.at<int>(s.p.perm);
   HIPCHK(launch_copy(n, n, A, lda, W, ldw, s.st));
   HIPCHK(launch_iota(perm, n, s.st));
-  PanelScratch ps{s.at<double>(s.p.slot_val), s.at<int>(s.p.slot_row), s.at<double>(s.p.slot_rows),
-                  s.at<double>(s.p.diag_rows), s.at<int>(s.p.moves)};
+  PanelScratch ps{s.at<unsigned long long>(s.p.recs), s.at<double>(s.p.slot_rows),
+                  s.at<int>(s.p.moves)};
+  HIPCHK(launch_panel_reset(ps, s.st));
   // look-ahead: the trailing update of block k is split into the next block column (on st, ahead of
   // panel k+1) and the rest (on the side stream, alongside panel k+1); the interchanges of panel k+1
   // wait for the rest, since they move rows in every column
@@ -400,7 +399,7 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
     // panel: sum over its columns s of 2 (m - s - 1)(b - s - 1) + (m - s - 1); reads and writes m x b
     const double pfl = b * (b - 1) * (3.0 * m - b - 1) / 3.0 + b * m - b * (b + 1) / 2.0;
     HIPCHK(s.timed(ADA_KF_PANEL, pfl, 16.0 * m * b,
-                   [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, k0 / kNB, ps, s.st); }));
+                   [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, ps, s.st); }));
     if (pending) TRY(s.join());
     pending = false;
     HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * (n - nbw),

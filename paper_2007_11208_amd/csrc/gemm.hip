@@ -4,7 +4,9 @@
 //
 // Tiling: 128x128 C tile per 256-thread workgroup (4 waves, 64x64 each =
 // 4x4 MFMA blocks of 16x16), K staged through LDS in chunks of 16, double
-// buffered. The MFMA is issued as D = B^T A^T so that the accumulator layout
+// buffered. The accumulators are loaded from C first and the A operand is
+// negated, so the matrix cores form C - A op(B) directly. The MFMA is issued
+// as D = B^T A^T so that the accumulator layout
 // (lane l, register r -> row 4r + l/16, column l%16 of D) puts 16 consecutive
 // rows of C in consecutive lanes: the read-modify-write of C is coalesced.
 // Tile ids are spread so that each XCD (workgroups are dealt round-robin to
@@ -19,7 +21,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int TM = 128, TN = 128, BK = 16, PADK = 4;
 
 template <bool TRANSB>
-__global__ __launch_bounds__(256) void k_gemm_sub(int m, int n, int k, const double* __restrict__ A, int lda,
+__global__ __launch_bounds__(256, 2) void k_gemm_sub(int m, int n, int k, const double* __restrict__ A, int lda,
                                                   const double* __restrict__ B, int ldb, double* __restrict__ C,
                                                   int ldc, int lower, int tiles_m, int ntiles,
                                                   const int* __restrict__ skip) {
@@ -91,17 +93,27 @@ __global__ __launch_bounds__(256) void k_gemm_sub(int m, int n, int k, const dou
     }
   };
 
+  // the accumulators start from C (loads in flight beside the first K chunk's) and the matrix cores
+  // subtract A * op(B) from them, so the epilogue is a store
+  const int lr = lane & 15, lk = lane >> 4;
   d4 acc[4][4];
 #pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
+  for (int bi = 0; bi < 4; ++bi) {
+    const int i = row0 + wm * 64 + bi * 16 + lr;
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = col0 + wn * 64 + bj * 16 + 4 * r + lk;
+        acc[bi][bj][r] = (i < m && j < n) ? C[(size_t)i + (size_t)j * ldc] : 0.0;
+      }
+    }
+  }
 
   const int nch = (k + BK - 1) / BK;
   load_regs(0);
   store_lds(0);
   __syncthreads();
-  const int lr = lane & 15, lk = lane >> 4;
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
     if (c + 1 < nch) load_regs((c + 1) * BK);
@@ -109,7 +121,7 @@ __global__ __launch_bounds__(256) void k_gemm_sub(int m, int n, int k, const dou
     for (int kk = 0; kk < BK; kk += 4) {
       double af[4], bf[4];
 #pragma unroll
-      for (int bi = 0; bi < 4; ++bi) af[bi] = As[buf][kk + lk][wm * 64 + bi * 16 + lr];
+      for (int bi = 0; bi < 4; ++bi) af[bi] = -As[buf][kk + lk][wm * 64 + bi * 16 + lr];
 #pragma unroll
       for (int bj = 0; bj < 4; ++bj) bf[bj] = Bs[buf][kk + lk][wn * 64 + bj * 16 + lr];
 #pragma unroll
@@ -121,7 +133,7 @@ __global__ __launch_bounds__(256) void k_gemm_sub(int m, int n, int k, const dou
     if (c + 1 < nch) store_lds(buf ^ 1);
     __syncthreads();
   }
-  // C -= acc ; acc[bi][bj][r] = (A*B)[row0+wm*64+bi*16+lr][col0+wn*64+bj*16+4r+lk]
+  // acc[bi][bj][r] = (C - A*op(B))[row0+wm*64+bi*16+lr][col0+wn*64+bj*16+4r+lk]
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi) {
     const int i = row0 + wm * 64 + bi * 16 + lr;
@@ -131,10 +143,7 @@ __global__ __launch_bounds__(256) void k_gemm_sub(int m, int n, int k, const dou
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = col0 + wn * 64 + bj * 16 + 4 * r + lk;
-        if (j < n) {
-          double* p = C + (size_t)i + (size_t)j * ldc;
-          *p = *p - acc[bi][bj][r];
-        }
+        if (j < n) C[(size_t)i + (size_t)j * ldc] = acc[bi][bj][r];
       }
     }
   }

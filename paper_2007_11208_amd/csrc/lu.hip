@@ -36,12 +36,21 @@ constexpr int PROWS = 256;  // panel rows per workgroup = threads per workgroup 
 // k_laswp_moves.
 //
 // With several workgroups, every column needs one exchange: each workgroup
-// publishes its best candidate (modulus, position, row) and then an epoch flag
-// of its own; wave 0 of every workgroup polls all the flags at once (one lane
-// per workgroup, no read-modify-write on a shared counter), picks the winner
-// (largest modulus, lowest position on ties) and stages the winner's row in
-// LDS. The hand-off uses agent-scope relaxed accesses and a wait for store
-// completion (no cache write-back or invalidation). All waits are bounded.
+// publishes its best candidate's row and, once those stores have completed, a
+// 16-byte record: word 0 = the bits of the candidate's modulus with a toggle in
+// bit 63 (the sign bit of a non-negative double is free), word 1 = its position
+// and the column's epoch. Each word is written and read as one 64-bit
+// agent-scope atomic, so a reader that sees the current epoch in word 1 and the
+// current toggle in word 0 has the current candidate: the toggle flips between
+// successive uses of a record, and a reader has already seen the previous use
+// (or the reset state, whose toggle is the opposite of the first use's), so
+// word 0 cannot be older than that. Wave 0 of every workgroup polls all the
+// records at once (one lane per workgroup, no read-modify-write on a shared
+// counter), picks the winner (largest modulus, lowest position on ties) and
+// stages the winner's row, complete before its record was written, in LDS.
+// The hand-off uses agent-scope relaxed accesses and a wait for store
+// completion (no cache write-back or invalidation). All waits are bounded;
+// once one gives up (rec->timeout) the others stop waiting too.
 constexpr int HC = 32;                   // columns per thread
 constexpr int PTH = (PNB / HC) * PROWS;  // 1024 threads
 
@@ -82,9 +91,17 @@ __device__ __forceinline__ void update_from(double (&d)[HC], int first, double l
   }
 }
 
+__device__ __forceinline__ unsigned long long relaxed_load_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void relaxed_store_u64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr unsigned kNoCand = 0xffffffffu;  // position word of a workgroup without a candidate
+
 __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, double* __restrict__ W, int ldw,
-                                                     int* __restrict__ ipiv, DevRec* rec, int seq,
-                                                     PanelScratch ps) {
+                                                     int* __restrict__ ipiv, DevRec* rec, PanelScratch ps) {
   if (rec->stop) return;
   const int m = n - k0;
   const int P = gridDim.x;
@@ -150,36 +167,45 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
       __syncthreads();
       p = bp;
     } else {
-      // 2. publish the candidate, then this workgroup's epoch flag
-      const int epoch = seq * 256 + s + 1;
+      // 2. publish the candidate row, then (once those stores have completed) the candidate's record
+      const unsigned G = (unsigned)(k0 + s);  // column of the factorisation: contiguous over panels
+      const unsigned epoch = G + 1;
+      const unsigned long long toggle = (unsigned long long)((G >> 1) & 1u) << 63;
       double* myslot = ps.slot_rows + ((size_t)par * 64 + wg) * PNB;
       if (holder) {
 #pragma unroll
         for (int c = 0; c < HC; ++c) relaxed_store(myslot + HC * h + c, d[c]);
         wait_stores_done();
       }
-      if (t == 0) {
-        relaxed_store(ps.slot_val + par * 64 + wg, bv);
-        relaxed_store(ps.slot_row + par * 64 + wg, bp);
-        wait_stores_done();
-      }
       __syncthreads();
-      if (t == 0) relaxed_store(&rec->panel_flags[par * 64 + wg], epoch);
-      // 3. wave 0: wait for every flag (lane q polls workgroup q), pick the winner, stage its row
+      if (t == 0) {
+        unsigned long long* myrec = ps.recs + ((size_t)par * 64 + wg) * 2;
+        relaxed_store_u64(myrec, (bp >= 0 ? dbits(bv) : 0ull) | toggle);
+        relaxed_store_u64(myrec + 1, ((unsigned long long)epoch << 32) | (bp >= 0 ? (unsigned)bp : kNoCand));
+      }
+      // 3. wave 0: every workgroup's record (lane q reads workgroup q's), the winner, its row into LDS
       if (w == 0) {
         double cv = -1.0;
         int ck = -1;
         if (lane < P) {
+          const unsigned long long* rp = ps.recs + ((size_t)par * 64 + lane) * 2;
+          unsigned long long w0 = 0, w1 = 0;
           long spins = 0;
-          while (relaxed_load(&rec->panel_flags[par * 64 + lane]) != epoch) {
-            if (++spins > kSpinLimit) {
+          for (;;) {
+            w0 = relaxed_load_u64(rp);
+            w1 = relaxed_load_u64(rp + 1);
+            if ((unsigned)(w1 >> 32) == epoch && (w0 & (1ull << 63)) == toggle) break;
+            if (++spins > kSpinLimit || ((spins & 1023) == 0 && relaxed_load(&rec->timeout))) {
               atomicOr(&rec->timeout, 1);
+              w1 = kNoCand;
               break;
             }
             __builtin_amdgcn_s_sleep(0);
           }
-          cv = relaxed_load(ps.slot_val + par * 64 + lane);
-          ck = relaxed_load(ps.slot_row + par * 64 + lane);
+          if ((unsigned)(w1 & 0xffffffffull) != kNoCand) {
+            cv = __longlong_as_double((long long)(w0 & ~(1ull << 63)));
+            ck = (int)(unsigned)(w1 & 0xffffffffull);
+          }
         }
         int cw = lane;
 #pragma unroll
@@ -230,12 +256,29 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
   }
 }
 
-hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec, int seq,
-                              PanelScratch ps, hipStream_t st) {
+hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec, PanelScratch ps,
+                              hipStream_t st) {
   const int m = n - k0;
   const int P = (m + PROWS - 1) / PROWS;
-  if (P > 64) return hipErrorInvalidValue;  // n - k0 <= 16384 per panel
-  hipLaunchKernelGGL(k_getrf_panel, dim3(P), dim3(PTH), 0, st, n, k0, nbw, W, ldw, ipiv, rec, seq, ps);
+  if (P > 64 || nbw > PNB || nbw > m) return hipErrorInvalidValue;  // n - k0 <= 16384 per panel
+  hipLaunchKernelGGL(k_getrf_panel, dim3(P), dim3(PTH), 0, st, n, k0, nbw, W, ldw, ipiv, rec, ps);
+  return hipGetLastError();
+}
+
+// Resets the panel records before a factorisation: epochs 0 (they count the
+// factorisation's columns from 1) and the toggle of every record 1, the
+// opposite of its first use's toggle (columns 0 and 1), so that a reader can
+// never take the initial word 0 for a current one.
+__global__ void k_panel_reset(PanelScratch ps) {
+  const int t = threadIdx.x;
+  if (t < 2 * 64) {
+    ps.recs[2 * t] = 1ull << 63;
+    ps.recs[2 * t + 1] = 0ull;
+  }
+}
+
+hipError_t launch_panel_reset(PanelScratch ps, hipStream_t st) {
+  hipLaunchKernelGGL(k_panel_reset, dim3(1), dim3(128), 0, st, ps);
   return hipGetLastError();
 }
 
