@@ -145,6 +145,25 @@ size_t ada_workspace_size(int n, int nrhs, const ada_opts* opts);
 int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
               int ldx, void* work, size_t work_bytes, const ada_opts* opts, ada_result* result, void* stream);
 
+/* ---- the same solve without a caller workspace ----
+ * For callers that cannot allocate device memory or hand the library a
+ * workspace (tight serving loops, harnesses that forbid allocation): ada_solve
+ * with its workspace taken from a fixed array of ADA_NOALLOC_SCRATCH_BYTES in
+ * the library's device memory. Every GPU the library is loaded on holds one
+ * such array until the process ends; its address is taken once per device when
+ * a context is created there. The call allocates nothing (no hipMalloc, no
+ * hipFree, no events beyond those profiling already created). Arguments,
+ * results, blocking and errors are those of ada_solve; a shape whose workspace
+ * (ada_workspace_size) exceeds the fixed array returns ADA_ERR_ARG with the
+ * sizes in ada_last_error (dense input with default options and one right-hand
+ * side: n <= 3269).
+ * All calls on one GPU share its array, which keeps the last call's contents
+ * (each solve initialises what it reads): calls that overlap on one GPU, from
+ * any thread or context, race and must be serialised by the caller. */
+#define ADA_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int ada_solve_noalloc(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
+                      int ldx, const ada_opts* opts, ada_result* result, void* stream);
+
 /* ---- batched solve: many independent small systems in one launch ----
  * Every system goes through the whole method of Section II (detection,
  * routed factorisation and solve, condition estimate, the rule of Section

@@ -87,6 +87,9 @@ def lib() -> ctypes.CDLL:
         L.ada_workspace_size.restype = sz
         L.ada_solve.argtypes = [vp, i, i, vp, i, vp, i, vp, i, vp, sz, ctypes.POINTER(Opts), ctypes.POINTER(Result), vp]
         L.ada_solve.restype = i
+        L.ada_solve_noalloc.argtypes = [vp, i, i, vp, i, vp, i, vp, i, ctypes.POINTER(Opts), ctypes.POINTER(Result),
+                                        vp]
+        L.ada_solve_noalloc.restype = i
         L.ada_batched_workspace_size.argtypes = [i]
         L.ada_batched_workspace_size.restype = sz
         L.ada_solve_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(Opts), vp, vp]
@@ -311,6 +314,37 @@ def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, w
         return None, SolveResult("", -1, -1, "none", False, 0, 0, 0, 0, 0, math.nan, math.nan, rc)
     out_x = X[:, 0] if vec else X
     return out_x, _result(res, rc)
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20  # ADA_NOALLOC_SCRATCH_BYTES
+
+
+def solve_noalloc(A, B, *, out=None, ctx: Context | None = None, raise_on_error=True, **opt_kw):
+    """ada_solve_noalloc: the solve of `solve` with the library's fixed per-GPU scratch as its
+    workspace (nothing is allocated; X must be given or is allocated here, before the call).
+    Same options as `solve` (no_approx, rcond_threshold, force_general, want_berr, layout, kl_in,
+    ku_in, precision, extensions)."""
+    import torch
+    dev = A.device
+    if dev.type != "cuda":
+        raise ValueError("A must be a CUDA tensor")
+    vec = B.dim() == 1
+    Ac = _colmajor(A)
+    Bc = _colmajor(B)
+    n, nrhs = Bc.shape[0], Bc.shape[1]
+    lay = LAYOUT_BAND if opt_kw.pop("layout", "dense") == "band" else LAYOUT_DENSE
+    opts = make_opts(layout=lay, **opt_kw)
+    X = out if out is not None else torch.empty((nrhs, n), dtype=torch.float64, device=dev).t()
+    c = ctx or context(dev.index or 0)
+    res = Result()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().ada_solve_noalloc(c.handle, n, nrhs, Ac.data_ptr(), _ld(Ac), Bc.data_ptr(), _ld(Bc), X.data_ptr(),
+                                 _ld(X), ctypes.byref(opts), ctypes.byref(res), ctypes.c_void_p(stream))
+    if rc not in (OK, ERR_SINGULAR):
+        if raise_on_error:
+            raise AdaError(rc, last_error())
+        return None, SolveResult("", -1, -1, "none", False, 0, 0, 0, 0, 0, math.nan, math.nan, rc)
+    return (X[:, 0] if vec else X), _result(res, rc)
 
 
 class Batch:

@@ -198,6 +198,10 @@ struct ada_ctx_s {
   // sides and floor(log2 n) (the best piece depends on how many chunks compete for the compute units);
   // 0 = the built-in choice
   int band_piece[32][2][32] = {};
+  // device address of this GPU's fixed scratch of ada_solve_noalloc (from hipGetSymbolAddress)
+  void* noalloc_scratch = nullptr;
+  // set during ada_solve_noalloc: instrumentation records events only from the existing pool
+  bool no_grow = false;
 };
 
 namespace {
@@ -226,6 +230,7 @@ struct Solve {
   long ev_record(hipStream_t on) {
     if (!ctx->prof) return -1;
     if (ctx->ev_used >= ctx->ev_pool.size()) {
+      if (ctx->no_grow) return -1;
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return -1;
       ctx->ev_pool.push_back(e);
@@ -662,6 +667,31 @@ void fill_result(ada_result* r, const DevRec& h, int cls, int kl, int ku, int ro
   r->nsolves = h.est_nsolves;
 }
 
+// The workspace of ada_solve_noalloc: one fixed array per GPU (each device that
+// loads the library holds its own copy until the process ends). In host code
+// `scratch` only names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress with that GPU current, taken once per device when a
+// context is created there, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[ADA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// device address of the current device's scratch (the device is `device`, already current)
+hipError_t noalloc_scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -680,6 +710,7 @@ int ada_create(ada_ctx* out, int device) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = noalloc_scratch_address(device, &c->noalloc_scratch);
   if (e != hipSuccess) {
     ada_destroy(c);
     return fail(ADA_ERR_HIP, std::string("context set-up: ") + hipGetErrorString(e));
@@ -1088,6 +1119,37 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
   HIPCHK(hipSetDevice(ctx->device));
   return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, work, work_bytes, o, result,
                     static_cast<hipStream_t>(stream), nrhs, false);
+}
+
+int ada_solve_noalloc(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const double* B, int ldb, double* X,
+                      int ldx, const ada_opts* opts, ada_result* result, void* stream) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  if (!A || !B || !X || !result) return fail(ADA_ERR_ARG, "NULL matrix or result pointer");
+  ada_opts o;
+  if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
+  if (o.layout != ADA_LAYOUT_DENSE && o.layout != ADA_LAYOUT_BAND) return fail(ADA_ERR_ARG, "unknown layout");
+  if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR && o.precision != ADA_PREC_BF16_IR)
+    return fail(ADA_ERR_ARG, "unknown precision");
+  if (o.extensions & ~(ADA_EXT_SYM | ADA_EXT_TRIDIAG)) return fail(ADA_ERR_ARG, "unknown extension bits");
+  if (n < 1 || nrhs < 1) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
+  if (o.layout == ADA_LAYOUT_DENSE && lda < n) return fail(ADA_ERR_ARG, "lda < n");
+  if (ldb < n || ldx < n) return fail(ADA_ERR_ARG, "ldb or ldx < n");
+  Plan p;
+  if (!make_plan(n, nrhs, o, p)) return fail(ADA_ERR_ARG, "invalid shape");
+  if (p.total > (size_t)ADA_NOALLOC_SCRATCH_BYTES)
+    return fail(ADA_ERR_ARG, "ada_solve_noalloc: this shape needs " + std::to_string(p.total) +
+                                 " bytes of workspace, more than the fixed scratch of " +
+                                 std::to_string((size_t)ADA_NOALLOC_SCRATCH_BYTES) + " bytes");
+  if (!ctx->noalloc_scratch) return fail(ADA_ERR_HIP, "ada_solve_noalloc: no scratch address for this device");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  HIPCHK(hipSetDevice(ctx->device));
+  struct NoGrow {
+    ada_ctx c;
+    ~NoGrow() { c->no_grow = false; }
+  } guard{ctx};
+  ctx->no_grow = true;
+  return solve_impl(ctx, n, nrhs, A, lda, B, ldb, X, ldx, ctx->noalloc_scratch, (size_t)ADA_NOALLOC_SCRATCH_BYTES, o,
+                    result, static_cast<hipStream_t>(stream), nrhs, false);
 }
 
 }  // extern "C"
