@@ -13,59 +13,129 @@
 namespace ada {
 
 // Diagonal block (nbw <= 128) in LDS, in sub-blocks of 32 columns:
-//   1. wave 0 factors the 32x32 diagonal sub-block with lane = row and the
-//      row in registers (the column-j values of other rows come by readlane,
-//      so the 32 steps need no barrier);
-//   2. the rows below solve x L_kk^T = a (one thread per row, L_kk from LDS);
+//   1. wave 0 factors the 32x32 diagonal sub-block, two lanes per row (each
+//      with 16 of its columns in registers): the pivot of column j comes by
+//      readlane, the scaled column goes through LDS and every lane reads the
+//      entries it needs as broadcasts (the 32 steps need no barrier and keep
+//      scalar registers free); the reciprocals of the diagonal go to LDS for
+//      step 2;
+//   2. the rows below solve x L_kk^T = a (one thread per row, L_kk and the
+//      reciprocals of its diagonal from LDS, as LAPACK's triangular solve
+//      does it: multiply by the reciprocal);
 //   3. the trailing lower triangle takes the symmetric rank-32 update (4x4 register tiles).
 // A pivot that is not positive (or NaN) ends the factorisation: the matrix is
 // then not taken to be sympd and the system is re-solved by LU on the
 // original A (Section II-C).
+// A zero the compiler cannot see through: added to an LDS index it makes the
+// broadcast loads of steps 1 and 2 per-lane values, so that the compiler keeps
+// them in vector registers instead of hoisting hundreds of them into scalar
+// registers (and spilling those).
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+// the same once v is known: loads indexed with it cannot be issued before v is computed
+__device__ __forceinline__ int zero_after(double v) {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z) : "v"(v));
+  return z;
+}
+
 constexpr int PB = 32;
+constexpr int PLD = 129;  // LDS column stride of the diagonal block (nbw <= 128)
+// Row r of the rows below a 32-column diagonal sub-block at column kb: x L_kk^T = a, L_kk and the
+// reciprocals of its diagonal in LDS (stride PLD), x in registers, as LAPACK's triangular solve does it
+// (multiply by the reciprocal). FULL: cb == 32, no column bounds.
+template <bool FULL>
+__device__ __forceinline__ void trsm_row(double* sA, int kb, int r, int cb, const double* s_rinv) {
+  double x[PB];
+#pragma unroll
+  for (int j = 0; j < PB; ++j) x[j] = (FULL || j < cb) ? sA[(kb + j) * PLD + r] : 0.0;
+  // column j's entries of L are loaded once x[j-1] is known (a data dependence through an opaque
+  // zero), so they are not all hoisted to the start and kept in registers
+  int z = opaque_zero();
+#pragma unroll
+  for (int j = 0; j < PB; ++j) {
+    if (FULL || j < cb) {
+      x[j] = x[j] * s_rinv[j + z];
+      const int zn = zero_after(x[j]);
+#pragma unroll
+      for (int k = j + 1; k < PB; ++k)
+        if (FULL || k < cb) x[k] = fma(-x[j], sA[(kb + j) * PLD + kb + k + z], x[k]);
+      z = zn;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PB; ++j)
+    if (FULL || j < cb) sA[(kb + j) * PLD + r] = x[j];
+}
+
 __global__ __launch_bounds__(256) void k_potrf_diag(int k0, int nbw, double* __restrict__ W, int ldw, DevRec* rec) {
   if (rec->stop) return;
-  extern __shared__ double sA[];  // sA[c * ld + r], ld = nbw + 1 (lower triangle used)
-  const int ld = nbw + 1;
+  extern __shared__ double sA[];  // sA[c * ld + r] (lower triangle used)
+  constexpr int ld = PLD;         // a constant stride: every LDS offset below is an immediate
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  // 16 loads in flight per thread
-  for (int e0 = t; e0 < nbw * nbw; e0 += 256 * 16) {
+  // 16 loads in flight per thread; element e of the 128 x 128 frame is row e % 128 of column e / 128
+  for (int e0 = t; e0 < PB * 4 * PB * 4; e0 += 256 * 16) {
     double tmp[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 256 * u, rr = e % nbw, c = e / nbw;
-      tmp[u] = (e < nbw * nbw && rr >= c) ? W[(size_t)(k0 + rr) + (size_t)(k0 + c) * ldw] : 0.0;
+      const int e = e0 + 256 * u, rr = e & 127, c = e >> 7;
+      tmp[u] = (rr < nbw && c < nbw && rr >= c) ? W[(size_t)(k0 + rr) + (size_t)(k0 + c) * ldw] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 256 * u, rr = e % nbw, c = e / nbw;
-      if (e < nbw * nbw && rr >= c) sA[c * ld + rr] = tmp[u];
+      const int e = e0 + 256 * u, rr = e & 127, c = e >> 7;
+      if (rr < nbw && c < nbw && rr >= c) sA[c * ld + rr] = tmp[u];
     }
   }
   __shared__ int s_fail;
+  __shared__ double s_col[PB];   // the column being scaled (step 1)
+  __shared__ double s_rinv[PB];  // reciprocals of the sub-block's diagonal (step 2)
   if (t == 0) s_fail = 0;
   __syncthreads();
   for (int kb = 0; kb < nbw; kb += PB) {
     const int cb = min(PB, nbw - kb);
-    // 1. diagonal sub-block
+    // 1. diagonal sub-block: wave 0, lane = (row i, half h) holding the row's columns 16h .. 16h+15
     if (w == 0) {
-      double v[PB];
+      // the lane index through an opaque zero: the per-lane masks below are then formed where they are
+      // used instead of being hoisted out of the sub-block loop into scalar registers
+      const int ln = lane + opaque_zero();
+      const int i = ln & 31, h = ln >> 5;
+      double v[PB / 2];
 #pragma unroll
-      for (int j = 0; j < PB; ++j) v[j] = (lane < cb && j <= lane) ? sA[(kb + j) * ld + kb + lane] : 0.0;
+      for (int c = 0; c < PB / 2; ++c)
+        v[c] = (i < cb && 16 * h + c <= i) ? sA[(kb + 16 * h + c) * ld + kb + i] : 0.0;
       int fail = 0;
 #pragma unroll
       for (int j = 0; j < PB; ++j) {
+        const int hj = j >> 4, cj = j & 15;
         if (j < cb && !fail) {
-          const double dj = read_lane(v[j], j);
+          const double dj = read_lane(v[cj], j + 32 * hj);
           if (!(dj > 0.0)) {
             fail = j + 1;
           } else {
             const double sd = sqrt(dj);
-            v[j] = (lane == j) ? sd : (lane > j ? v[j] / sd : v[j]);
-#pragma unroll
-            for (int k = j + 1; k < PB; ++k) {
-              const double lkj = read_lane(v[j], k);
-              if (lane >= k && k < cb) v[k] = fma(-v[j], lkj, v[k]);
+            if (h == hj) {
+              const double l = (i == j) ? sd : (i > j ? v[cj] / sd : v[cj]);
+              v[cj] = l;
+              s_col[i] = l;
             }
+            if (ln == 0) s_rinv[j] = 1.0 / sd;
+            __builtin_amdgcn_wave_barrier();
+            const double lij = s_col[i];
+            // columns right of j: all of the upper half when j is in the lower one, the rest of j's half
+#pragma unroll
+            for (int c = 0; c < PB / 2; ++c) {
+              if (c > cj) {
+                if (hj == 0) v[c] = fma(-lij, s_col[16 * h + c], v[c]);
+                else if (h == 1) v[c] = fma(-lij, s_col[16 + c], v[c]);
+              } else if (hj == 0 && h == 1) {
+                v[c] = fma(-lij, s_col[16 + c], v[c]);
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
           }
         }
       }
@@ -75,34 +145,21 @@ __global__ __launch_bounds__(256) void k_potrf_diag(int k0, int nbw, double* __r
           rec->stop = 1;
           s_fail = 1;
         }
-      } else if (lane < cb) {
+      } else if (i < cb) {
 #pragma unroll
-        for (int j = 0; j < PB; ++j)
-          if (j <= lane) sA[(kb + j) * ld + kb + lane] = v[j];
+        for (int c = 0; c < PB / 2; ++c)
+          if (16 * h + c <= i) sA[(kb + 16 * h + c) * ld + kb + i] = v[c];
       }
     }
     __syncthreads();
     if (s_fail) break;
     const int r0 = kb + cb, rest = nbw - r0;
     if (rest <= 0) break;
-    // 2. rows below: x L_kk^T = a
-    for (int i = t; i < rest; i += blockDim.x) {
-      const int r = r0 + i;
-      double x[PB];
-#pragma unroll
-      for (int j = 0; j < PB; ++j) x[j] = j < cb ? sA[(kb + j) * ld + r] : 0.0;
-#pragma unroll
-      for (int j = 0; j < PB; ++j) {
-        if (j < cb) {
-          x[j] = x[j] / sA[(kb + j) * ld + kb + j];
-#pragma unroll
-          for (int k = j + 1; k < PB; ++k)
-            if (k < cb) x[k] = fma(-x[j], sA[(kb + j) * ld + kb + k], x[k]);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < PB; ++j)
-        if (j < cb) sA[(kb + j) * ld + r] = x[j];
+    // 2. rows below: x L_kk^T = a (a full 32-column sub-block needs no column bounds)
+    if (cb == PB) {
+      for (int i = t; i < rest; i += blockDim.x) trsm_row<true>(sA, kb, r0 + i, PB, s_rinv);
+    } else {
+      for (int i = t; i < rest; i += blockDim.x) trsm_row<false>(sA, kb, r0 + i, cb, s_rinv);
     }
     __syncthreads();
     // 3. trailing lower triangle: A(r, c) -= sum_j L(r, j) L(c, j), r >= c >= r0, in 4x4 register tiles
@@ -150,14 +207,15 @@ __global__ __launch_bounds__(256) void k_potrf_diag(int k0, int nbw, double* __r
   }
   __syncthreads();
   if (s_fail) return;
-  for (int e = t; e < nbw * nbw; e += blockDim.x) {
-    const int rr = e % nbw, c = e / nbw;
-    if (rr >= c) W[(size_t)(k0 + rr) + (size_t)(k0 + c) * ldw] = sA[c * ld + rr];
+  for (int e = t; e < PB * 4 * PB * 4; e += blockDim.x) {
+    const int rr = e & 127, c = e >> 7;
+    if (rr < nbw && c < nbw && rr >= c) W[(size_t)(k0 + rr) + (size_t)(k0 + c) * ldw] = sA[c * ld + rr];
   }
 }
 
 hipError_t launch_potrf_diag(int k0, int nbw, double* W, int ldw, DevRec* rec, hipStream_t st) {
-  const size_t lds = (size_t)nbw * (nbw + 1) * sizeof(double);
+  if (nbw > PLD - 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)nbw * PLD * sizeof(double);
   static size_t done = 0;
   hipError_t e = ensure_lds((const void*)k_potrf_diag, lds, done);
   if (e != hipSuccess) return e;
