@@ -422,60 +422,82 @@ struct WVec {
 };
 
 // op(T) y = y in place; T (ld ldt) lower or upper as stored, op = transpose if trans.
-// FWD: forward substitution (op(T) lower). Register blocks are visited in a
-// compile-time order so every register index is a constant. stg: this wave's LDS staging area of
-// scol * BNM elements (matrix in HBM; scol divides 64), or null (matrix in LDS; scol = 64).
+// FWD: forward substitution (op(T) lower). The columns are taken in groups of scol (scol divides 64), in
+// solve order; a group's diagonal entries are inverted together (one division per lane), and each column's
+// entries are loaded one column ahead so that their latency hides behind the previous column's update.
+// stg: this wave's LDS staging area of scol * BNM elements (matrix in HBM; scol <= SPF), or null (matrix
+// in LDS; scol = 64). A staged group is copied into registers while the group before it is solved: lane i
+// loads row i of the group, a column segment of T (coalesced over the lanes) or a row segment (contiguous
+// for each lane).
+constexpr int SPF = 8;   // most columns of a staged group
 template <bool FWD, int NRC, class TF>
 __device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v,
                                            int nr, int lane, TF* stg, int scol) {
+  const size_t pr = trans ? (size_t)ldt : 1, pc = trans ? 1 : (size_t)ldt;  // op(T)(i, c) = T[i*pr + c*pc]
+  if (stg) scol = min(scol, SPF);
+  const int ngr = (n + scol - 1) / scol;
+  TF pf[SPF][BRB];
+  auto fetch = [&](int g) {
+    const int c0 = g * scol, scnt = min(scol, n - c0);
 #pragma unroll
-  for (int jbi = 0; jbi < BRB; ++jbi) {
-    const int jb = FWD ? jbi : BRB - 1 - jbi;
-    if (64 * jb >= n) continue;
-    const int cnt = min(64, n - 64 * jb);
-    // columns of the block in groups of scol, in solve order
-    const int ngr = (cnt + scol - 1) / scol;
-    for (int sgi = 0; sgi < ngr; ++sgi) {
-      const int s0 = scol * (FWD ? sgi : ngr - 1 - sgi);
-      const int scnt = min(scol, cnt - s0);
-      const int c0 = 64 * jb + s0;  // first column of the group
-      // op(T)(i, c0 + k) for every row i: from LDS directly, or staged into this wave's LDS quarter (matrix
-      // in HBM), with the loads unrolled so that many are in flight
-      const TF* P;
-      int pr, pc;  // element (i, k) at P[i * pr + k * pc]
-      if (stg) {
-        if (!trans) {
-#pragma unroll 4
-          for (int k = 0; k < scnt; ++k)
+    for (int kk = 0; kk < SPF; ++kk)
 #pragma unroll
-            for (int b = 0; b < BRB; ++b) {
-              const int i = lane + 64 * b;
-              if (i < n) stg[k * BNM + i] = T[i + (size_t)(c0 + k) * ldt];
-            }
-        } else {
-#pragma unroll 16
-          for (int i = 0; i < n; ++i)
-            if (lane < scnt) stg[lane * BNM + i] = T[(c0 + lane) + (size_t)i * ldt];
-        }
-        __builtin_amdgcn_wave_barrier();
-        P = stg;
-        pr = 1;
-        pc = BNM;
-      } else {
-        P = trans ? T + (size_t)c0 : T + (size_t)c0 * ldt;
-        pr = trans ? ldt : 1;
-        pc = trans ? 1 : ldt;
+      for (int b = 0; b < BRB; ++b) {
+        const int i = lane + 64 * b;
+        pf[kk][b] = (kk < scnt && i < n) ? T[i * pr + (size_t)(c0 + kk) * pc] : TF(0);
       }
+  };
+  if (stg) fetch(FWD ? 0 : ngr - 1);
+  for (int gi = 0; gi < ngr; ++gi) {
+    const int g = FWD ? gi : ngr - 1 - gi;
+    const int c0 = g * scol, scnt = min(scol, n - c0);
+    const TF* P;
+    size_t qr, qc;  // op(T)(i, c0 + k) = P[i*qr + k*qc]
+    if (stg) {
+#pragma unroll
+      for (int kk = 0; kk < SPF; ++kk)
+#pragma unroll
+        for (int b = 0; b < BRB; ++b) {
+          const int i = lane + 64 * b;
+          if (kk < scnt && i < n) stg[kk * BNM + i] = pf[kk][b];
+        }
+      __builtin_amdgcn_wave_barrier();
+      if (gi + 1 < ngr) fetch(FWD ? g + 1 : g - 1);
+      P = stg;
+      qr = 1;
+      qc = BNM;
+    } else {
+      P = T + (size_t)c0 * pc;
+      qr = pr;
+      qc = pc;
+    }
+    double rk = 1.0;  // lane k: 1 / op(T)(c0 + k, c0 + k)
+    if (!unit && lane < scnt) rk = 1.0 / (double)P[(c0 + lane) * qr + lane * qc];
+    const int gjb = c0 >> 6, s0 = c0 & 63;
+#pragma unroll
+    for (int jb = 0; jb < BRB; ++jb) {
+      if (jb != gjb) continue;
+      TF tc[BRB];
+      auto col = [&](int k, TF* t) {
+#pragma unroll
+        for (int b = 0; b < BRB; ++b) {
+          const int i = lane + 64 * b;
+          t[b] = i < n ? P[i * qr + k * qc] : TF(0);
+        }
+      };
+      col(FWD ? 0 : scnt - 1, tc);
       for (int k0 = 0; k0 < scnt; ++k0) {
         const int k = FWD ? k0 : scnt - 1 - k0;
+        TF tn[BRB];
+        if (k0 + 1 < scnt) col(FWD ? k + 1 : k - 1, tn);
         const int jj = s0 + k;  // column within the block
-        const int j = 64 * jb + jj;
-        const double d = unit ? 1.0 : (double)P[j * pr + k * pc];
+        const int j = c0 + k;
+        const double ri = unit ? 1.0 : read_lane(rk, k);
         double xj[NRC];
 #pragma unroll
         for (int r = 0; r < NRC; ++r) {
           if (r < nr) {
-            xj[r] = read_lane(v.x[jb][r], jj) / d;
+            xj[r] = read_lane(v.x[jb][r], jj) * ri;
             if (lane == jj) v.x[jb][r] = xj[r];
           } else {
             xj[r] = 0.0;
@@ -486,15 +508,17 @@ __device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool tra
           const int i = lane + 64 * b;
           const bool rel = FWD ? (i > j) : (i < j);
           if (i < n && rel) {
-            const double tij = (double)P[i * pr + k * pc];
+            const double tij = (double)tc[b];
 #pragma unroll
             for (int r = 0; r < NRC; ++r)
               if (r < nr) v.x[b][r] = fma(-tij, xj[r], v.x[b][r]);
           }
         }
+#pragma unroll
+        for (int b = 0; b < BRB; ++b) tc[b] = tn[b];
       }
-      __builtin_amdgcn_wave_barrier();
     }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 template <int NRC, class TF>
