@@ -160,6 +160,13 @@ def bench_batched(args):
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
+    # the launch shape: the autotuner's choice for this batch (set-up, outside the timed region)
+    tuned = None
+    if not args.no_tune:
+        t_tune = time.perf_counter()
+        shape, tuned_ms = batch.tune()
+        torch.cuda.synchronize()
+        tuned = {"shape": shape, "ms_per_batch": round(tuned_ms, 3), "tune_s": round(time.perf_counter() - t_tune, 2)}
     times = []
     ev = []
     t0 = time.perf_counter()
@@ -220,7 +227,8 @@ def bench_batched(args):
                    "count": args.count},
         "tflops": round(flops * args.steps / total / 1e12, 4),
         "p50_step_ms": round(pct(times, 50) * 1e3, 3), "p99_step_ms": round(pct(times, 99) * 1e3, 3),
-        "max_berr": worst, "routes": routes, "refinement": refine, "roofline": roof, "cpu_baseline": cpu,
+        "max_berr": worst, "routes": routes, "refinement": refine, "launch_shape": batch.shape(), "autotune": tuned,
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -508,6 +516,7 @@ def main():
                     help="single: the five large systems; batched: many small systems in one launch per step")
     ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
     ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
+    ap.add_argument("--no-tune", action="store_true", help="batched workload: keep the default launch shape")
     ap.add_argument("--ext-steps", type=int, default=3,
                     help="single workload: also time the Section V extension routes (LDL^T, tridiagonal) "
                          "against the paper's routes on systems of the same shapes")

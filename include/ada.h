@@ -192,12 +192,53 @@ size_t ada_batched_workspace_size(int count);
  * system's status. Asynchronous: returns once the work is enqueued on
  * `stream`; it enqueues kernels only (no host synchronisation, no memset,
  * no allocation), so it may be captured into a HIP graph and replayed.
- * Systems are taken largest first (a device-side ordering by n); each
- * system's result does not depend on the others in the batch.
+ * Systems are taken largest first (a device-side ordering by n), in the
+ * launch shape ctx keeps for the precision (ada_set_batched_shape,
+ * ada_autotune_batched); each system's result depends neither on the
+ * others in the batch nor on the shape.
  * Returns ADA_ERR_ARG for invalid arguments (nothing enqueued). */
 int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
                       double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
                       void* stream);
+
+/* Launch shape of ada_solve_batched. It changes the speed only: every valid shape gives
+ * bit-identical results. The systems are split by order into `buckets` ranges launched one after
+ * the other, largest orders first: range k holds the orders in (max_n[k+1], max_n[k]]
+ * (max_n[buckets] = 0), with max_n[0] = 256 > max_n[1] > max_n[2] >= 16. Each launch sizes its LDS
+ * for its largest order and runs wg_per_cu[k] workgroups per compute unit (1: the kernel variant
+ * with 512 registers per lane; 2: the variant with 256, for ranges with max_n <= 96, whose LDS fits
+ * twice) and workgroups[k] persistent workgroups in all (at most what the workspace of
+ * ada_batched_workspace_size holds: 256 at max_n = 256). stage_cols: columns of a triangle held in
+ * HBM (orders above 128) that a wave stages into LDS at a time, 4 or 8. The default: one launch,
+ * 256 workgroups, stage_cols = 8. */
+typedef struct {
+  int32_t buckets;
+  int32_t max_n[3];
+  int32_t wg_per_cu[3];
+  int32_t workgroups[3];
+  int32_t stage_cols;
+} ada_batched_shape;
+
+/* Sets the shape ctx's ada_solve_batched calls use for `precision` (ADA_PREC_FP64 or
+ * ADA_PREC_FP32_IR): shape (host pointer) is validated, ADA_ERR_ARG with the reason otherwise;
+ * shape NULL restores the default. */
+int ada_set_batched_shape(ada_ctx ctx, int precision, const ada_batched_shape* shape);
+/* The shape ctx uses for `precision` (host pointer out). */
+int ada_get_batched_shape(ada_ctx ctx, int precision, ada_batched_shape* shape);
+
+/* Autotuner of the batched launch. Arguments as ada_solve_batched: the caller's own batch is solved
+ * under each candidate shape and the fastest is kept in ctx for opts->precision. Candidates: one
+ * launch, or launches split at orders 128, 96 or 64 (and 128 + 64, 96 + 48); for each range, one or
+ * (max_n <= 96) two workgroups per compute unit; stage_cols 4 or 8. Each candidate runs once after a
+ * warm-up, timed per range with events on `stream`; every range takes its fastest variant, the
+ * split with the smallest sum wins, and the winner is timed once more. On return X_pool and
+ * d_results hold the batch's solution (the same under every shape). Synchronises the stream;
+ * allocates nothing but events. shape_out and ms_out (either may be NULL) receive the chosen shape
+ * and its time per batch in ms. Returns ADA_OK, ADA_ERR_ARG or ADA_ERR_HIP. */
+int ada_autotune_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool,
+                         const double* B_pool, double* X_pool, void* work, size_t work_bytes,
+                         const ada_opts* opts, ada_result* d_results, void* stream, ada_batched_shape* shape_out,
+                         double* ms_out);
 
 /* ---- solve server: continuous batching over a caller-provided HBM arena ----
  * Requests are independent systems (each solved by the method of Section II, as ada_solve or, for

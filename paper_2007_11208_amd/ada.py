@@ -47,6 +47,30 @@ class Result(ctypes.Structure):
                 ("rcond", ctypes.c_double), ("berr", ctypes.c_double)]
 
 
+class BatchedShape(ctypes.Structure):
+    """ada_batched_shape: the launch shape of the batched solve (speed only, results identical)."""
+    _fields_ = [("buckets", ctypes.c_int32), ("max_n", ctypes.c_int32 * 3), ("wg_per_cu", ctypes.c_int32 * 3),
+                ("workgroups", ctypes.c_int32 * 3), ("stage_cols", ctypes.c_int32)]
+
+    def as_dict(self):
+        k = self.buckets
+        return {"max_n": list(self.max_n[:k]), "wg_per_cu": list(self.wg_per_cu[:k]),
+                "workgroups": list(self.workgroups[:k]), "stage_cols": self.stage_cols}
+
+
+def batched_shape(max_n=(256,), wg_per_cu=None, workgroups=None, stage_cols=8) -> BatchedShape:
+    """An ada_batched_shape: one entry per range of orders (largest first)."""
+    k = len(max_n)
+    wpc = list(wg_per_cu or [1] * k)
+    wg = list(workgroups or [256 * w for w in wpc])
+    s = BatchedShape()
+    s.buckets = k
+    for j in range(k):
+        s.max_n[j], s.wg_per_cu[j], s.workgroups[j] = int(max_n[j]), int(wpc[j]), int(wg[j])
+    s.stage_cols = int(stage_cols)
+    return s
+
+
 class Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("lda", ctypes.c_int32), ("ldb", ctypes.c_int32),
                 ("ldx", ctypes.c_int32), ("pad", ctypes.c_int32), ("a_off", ctypes.c_int64),
@@ -94,6 +118,14 @@ def lib() -> ctypes.CDLL:
         L.ada_batched_workspace_size.restype = sz
         L.ada_solve_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(Opts), vp, vp]
         L.ada_solve_batched.restype = i
+        bsp = ctypes.POINTER(BatchedShape)
+        L.ada_set_batched_shape.argtypes = [vp, i, bsp]
+        L.ada_set_batched_shape.restype = i
+        L.ada_get_batched_shape.argtypes = [vp, i, bsp]
+        L.ada_get_batched_shape.restype = i
+        L.ada_autotune_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(Opts), vp, vp, bsp,
+                                           ctypes.POINTER(ctypes.c_double)]
+        L.ada_autotune_batched.restype = i
         L.ada_profile_enable.argtypes = [vp, i]
         L.ada_profile_enable.restype = i
         L.ada_profile_reset.argtypes = [vp]
@@ -396,6 +428,35 @@ class Batch:
                                      ctypes.byref(self.opts), self.res.data_ptr(), ctypes.c_void_p(stream))
         if rc != OK:
             raise AdaError(rc, last_error())
+
+    def tune(self):
+        """ada_autotune_batched on this batch: the fastest launch shape is kept in the context for this
+        precision (and X, results hold the solution). Returns (shape dict, ms per batch)."""
+        import torch
+        stream = torch.cuda.current_stream(self.A.device).cuda_stream
+        out = BatchedShape()
+        ms = ctypes.c_double()
+        rc = lib().ada_autotune_batched(self.ctx.handle, self.count, self.desc.data_ptr(), self.A.data_ptr(),
+                                        self.B.data_ptr(), self.X.data_ptr(), self.work.data_ptr(),
+                                        self.work.numel(), ctypes.byref(self.opts), self.res.data_ptr(),
+                                        ctypes.c_void_p(stream), ctypes.byref(out), ctypes.byref(ms))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+        return out.as_dict(), ms.value
+
+    def set_shape(self, shape: "BatchedShape | None"):
+        """ada_set_batched_shape for this batch's precision (None: the default shape)."""
+        rc = lib().ada_set_batched_shape(self.ctx.handle, self.opts.precision,
+                                         ctypes.byref(shape) if shape is not None else None)
+        if rc != OK:
+            raise AdaError(rc, last_error())
+
+    def shape(self) -> dict:
+        out = BatchedShape()
+        rc = lib().ada_get_batched_shape(self.ctx.handle, self.opts.precision, ctypes.byref(out))
+        if rc != OK:
+            raise AdaError(rc, last_error())
+        return out.as_dict()
 
     def results(self):
         raw = bytes(self.res.cpu().numpy().tobytes())

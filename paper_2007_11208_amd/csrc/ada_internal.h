@@ -245,13 +245,16 @@ hipError_t launch_gbtrf(int n, int kl, int ku, const double* GBin, double* GB, i
                         double* spec_scratch, size_t spec_doubles, hipStream_t st);
 hipError_t launch_gbtrs(int n, int kl, int ku, int nrhs, const double* GB, int ldgb, const int* ipiv, bool trans,
                         double* X, int ldx, const int* pred, int pred_val, hipStream_t st);
-// batched solve of many small systems (n <= 256, nrhs <= 8): one persistent launch of at most max_wg
-// workgroups (one per compute unit)
-size_t batched_workspace_bytes(int count, int max_workgroups);
-int batched_workgroups(int count, int max_wg = 256);
+// batched solve of many small systems (n <= 256, nrhs <= 8): one persistent launch per range of orders of
+// the shape (the default: one launch of at most max_wg workgroups, one per compute unit). The workspace
+// size covers every valid shape.
+ada_batched_shape batched_default_shape(int max_wg = 256);
+const char* batched_shape_problem(const ada_batched_shape& s);  // null when the shape is valid
+size_t batched_workspace_bytes(int count);
 hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
                                 void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st,
-                                int max_wg = 256);
+                                const ada_batched_shape& shape, hipEvent_t* ev = nullptr);
+// ev (optional): ev[0] is recorded after the ordering kernel, ev[k + 1] after launch k
 // band solves parallel over the rows (long bands); T: n x nrhs scratch (ldt); sc: see band_chunked_scratch_doubles.
 // The chunk maps of a sweep kind (bit 1<<kind of *maps_ready) are computed at its first use after the
 // factorisation, predicated on map_pred == map_pred_val only (not on the solve's own predicate), and

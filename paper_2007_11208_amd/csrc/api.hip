@@ -202,6 +202,8 @@ struct ada_ctx_s {
   void* noalloc_scratch = nullptr;
   // set during ada_solve_noalloc: instrumentation records events only from the existing pool
   bool no_grow = false;
+  // launch shape of the batched solve, by precision (0: FP64, 1: FP32 factors with FP64 refinement)
+  ada_batched_shape bshape[2] = {ada::batched_default_shape(), ada::batched_default_shape()};
 };
 
 namespace {
@@ -746,29 +748,152 @@ size_t ada_workspace_size(int n, int nrhs, const ada_opts* opts) {
 
 size_t ada_batched_workspace_size(int count) {
   if (count < 1) return 0;
-  return batched_workspace_bytes(count, batched_workgroups(count));
+  return batched_workspace_bytes(count);
+}
+
+namespace {
+int batched_prec_index(int precision) {
+  return precision == ADA_PREC_FP64 ? 0 : (precision == ADA_PREC_FP32_IR ? 1 : -1);
+}
+// arguments of ada_solve_batched and ada_autotune_batched
+int check_batched_args(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
+                       double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
+                       ada_opts& o) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  if (count < 1) return fail(ADA_ERR_ARG, "count must be >= 1");
+  if (!d_desc || !A_pool || !B_pool || !X_pool || !work || !d_results)
+    return fail(ADA_ERR_ARG, "NULL descriptor, pool, workspace or result pointer");
+  if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
+  if (o.layout != ADA_LAYOUT_DENSE) return fail(ADA_ERR_ARG, "batched solves take dense input only");
+  if (batched_prec_index(o.precision) < 0)
+    return fail(ADA_ERR_ARG, "batched solves take precision ADA_PREC_FP64 or ADA_PREC_FP32_IR");
+  if (o.extensions != 0) return fail(ADA_ERR_ARG, "batched solves take the paper's routes only (extensions = 0)");
+  if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(ADA_ERR_ARG, "work must be 256-byte aligned");
+  if (work_bytes < ada_batched_workspace_size(count)) return fail(ADA_ERR_ARG, "workspace too small");
+  return ADA_OK;
+}
+}  // namespace
+
+int ada_set_batched_shape(ada_ctx ctx, int precision, const ada_batched_shape* shape) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  const int pi = batched_prec_index(precision);
+  if (pi < 0) return fail(ADA_ERR_ARG, "precision must be ADA_PREC_FP64 or ADA_PREC_FP32_IR");
+  ada_batched_shape sh = shape ? *shape : batched_default_shape();
+  if (const char* why = batched_shape_problem(sh)) return fail(ADA_ERR_ARG, std::string("batched shape: ") + why);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->bshape[pi] = sh;
+  return ADA_OK;
+}
+
+int ada_get_batched_shape(ada_ctx ctx, int precision, ada_batched_shape* shape) {
+  if (!ctx || !shape) return fail(ADA_ERR_ARG, "ctx or shape is NULL");
+  const int pi = batched_prec_index(precision);
+  if (pi < 0) return fail(ADA_ERR_ARG, "precision must be ADA_PREC_FP64 or ADA_PREC_FP32_IR");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  *shape = ctx->bshape[pi];
+  return ADA_OK;
 }
 
 int ada_solve_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
                       double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
                       void* stream) {
-  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
-  if (count < 1) return fail(ADA_ERR_ARG, "count must be >= 1");
-  if (!d_desc || !A_pool || !B_pool || !X_pool || !work || !d_results)
-    return fail(ADA_ERR_ARG, "NULL descriptor, pool, workspace or result pointer");
   ada_opts o;
-  if (!read_opts(opts, o)) return fail(ADA_ERR_ARG, "opts->struct_size is not a known size");
-  if (o.layout != ADA_LAYOUT_DENSE) return fail(ADA_ERR_ARG, "batched solves take dense input only");
-  if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR)
-    return fail(ADA_ERR_ARG, "batched solves take precision ADA_PREC_FP64 or ADA_PREC_FP32_IR");
-  if (o.extensions != 0) return fail(ADA_ERR_ARG, "batched solves take the paper's routes only (extensions = 0)");
-  if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(ADA_ERR_ARG, "work must be 256-byte aligned");
-  if (work_bytes < ada_batched_workspace_size(count)) return fail(ADA_ERR_ARG, "workspace too small");
+  if (int rc = check_batched_args(ctx, count, d_desc, A_pool, B_pool, X_pool, work, work_bytes, opts, d_results, o))
+    return rc;
   std::lock_guard<std::mutex> lk(ctx->mu);
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(launch_solve_batched(count, d_desc, A_pool, B_pool, X_pool, work, work_bytes, o, d_results,
-                              static_cast<hipStream_t>(stream)));
+                              static_cast<hipStream_t>(stream), ctx->bshape[batched_prec_index(o.precision)]));
   return ADA_OK;
+}
+
+int ada_autotune_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const double* A_pool, const double* B_pool,
+                         double* X_pool, void* work, size_t work_bytes, const ada_opts* opts, ada_result* d_results,
+                         void* stream, ada_batched_shape* shape_out, double* ms_out) {
+  ada_opts o;
+  if (int rc = check_batched_args(ctx, count, d_desc, A_pool, B_pool, X_pool, work, work_bytes, opts, d_results, o))
+    return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t ev[4] = {};
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : ev)
+        if (f) (void)hipEventDestroy(f);
+      return fail(ADA_ERR_HIP, "autotune: event creation failed");
+    }
+  int rc = ADA_OK;
+  // runs the batch under shape s and returns the time of each of its launches (ms)
+  auto run = [&](const ada_batched_shape& s, float* ms) -> bool {
+    if (launch_solve_batched(count, d_desc, A_pool, B_pool, X_pool, work, work_bytes, o, d_results, st, s, ev) !=
+            hipSuccess ||
+        hipEventSynchronize(ev[s.buckets]) != hipSuccess)
+      return false;
+    for (int k = 0; k < s.buckets; ++k)
+      if (hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]) != hipSuccess) return false;
+    return true;
+  };
+  // the splits (largest order of each range after the first) and the per-range variants
+  static const int splits[][2] = {{0, 0}, {128, 0}, {96, 0}, {64, 0}, {128, 64}, {96, 48}};
+  struct Variant { int wg_per_cu, stage_cols; };
+  static const Variant variants[] = {{1, 8}, {1, 4}, {2, 8}};
+  ada_batched_shape best = batched_default_shape();
+  double best_ms = 1e300;
+  float ms[3];
+  if (!run(best, ms)) rc = fail(ADA_ERR_HIP, "autotune: warm-up launch failed");
+  for (const auto& sp : splits) {
+    if (rc != ADA_OK) break;
+    ada_batched_shape base = batched_default_shape();
+    base.buckets = 1 + (sp[0] > 0) + (sp[1] > 0);
+    base.max_n[1] = sp[0];
+    base.max_n[2] = sp[1];
+    // fastest variant of each range under this split
+    double range_ms[3] = {1e300, 1e300, 1e300};
+    ada_batched_shape pick = base;
+    for (const auto& v : variants) {
+      ada_batched_shape s = base;
+      bool any = v.wg_per_cu == 1;  // a two-per-unit variant only where some range can take it
+      for (int k = 0; k < s.buckets; ++k) {
+        const bool two = v.wg_per_cu == 2 && s.max_n[k] <= 96;
+        s.wg_per_cu[k] = two ? 2 : 1;
+        s.workgroups[k] = two ? 512 : 256;
+        any |= two;
+      }
+      s.stage_cols = v.stage_cols;
+      if (!any || batched_shape_problem(s)) continue;
+      if (!run(s, ms)) {
+        rc = fail(ADA_ERR_HIP, "autotune: launch failed");
+        break;
+      }
+      for (int k = 0; k < s.buckets; ++k)
+        if (ms[k] < range_ms[k]) {
+          range_ms[k] = ms[k];
+          pick.wg_per_cu[k] = s.wg_per_cu[k];
+          pick.workgroups[k] = s.workgroups[k];
+          if (k == 0) pick.stage_cols = s.stage_cols;  // only the first range holds orders above 128
+        }
+    }
+    double total = 0.0;
+    for (int k = 0; k < base.buckets; ++k) total += range_ms[k];
+    if (rc == ADA_OK && total < best_ms && !batched_shape_problem(pick)) {
+      best_ms = total;
+      best = pick;
+    }
+  }
+  if (rc == ADA_OK) {
+    if (!run(best, ms)) {
+      rc = fail(ADA_ERR_HIP, "autotune: launch failed");
+    } else {
+      double t = 0.0;
+      for (int k = 0; k < best.buckets; ++k) t += ms[k];
+      ctx->bshape[batched_prec_index(o.precision)] = best;
+      if (shape_out) *shape_out = best;
+      if (ms_out) *ms_out = t;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return rc;
 }
 
 int ada_profile_enable(ada_ctx ctx, int on) {

@@ -16,6 +16,7 @@
 #include "ada.h"
 #include "ada_internal.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace ada {
@@ -25,7 +26,6 @@ constexpr int BNM = 256;      // largest order
 constexpr int BRM = 8;        // most right-hand sides
 constexpr int BNL = 128;      // orders up to this keep the matrix in LDS
 constexpr int BRB = BNM / 64; // rows per lane in the one-wave solves
-constexpr int SCOL = 16;      // columns of a triangle a wave stages into LDS at a time (matrix in HBM)
 constexpr int BNL32 = 181;    // orders up to this keep an FP32 matrix in LDS (181^2 * 4 bytes <= 128 KB)
 constexpr int kMaxRefine = 30;  // refinement steps at most (the limit of LAPACK's mixed-precision driver)
 constexpr double kRcondRefine = 1e-9;  // FP32 factors with a smaller rcond estimate are not refined
@@ -35,12 +35,16 @@ struct BDesc {
   int64_t a_off, b_off, x_off;
 };
 
-// per-workgroup slice of the workspace (doubles, then ints)
-constexpr size_t kBW = (size_t)BNM * BNM;  // matrix (orders > BNL) / Jacobi U
-constexpr size_t kBV = (size_t)BNM * BNM;  // Jacobi V
-constexpr size_t kBSliceD = kBW + kBV + (size_t)BNM * BRM * 2 + (size_t)BNM * 4;
-constexpr size_t kBSliceI = (size_t)BNM * 2;
-constexpr size_t kBSliceBytes = kBSliceD * 8 + kBSliceI * 4;
+// per-workgroup slice of the workspace for systems of order <= hi (doubles, then ints): the matrix
+// (orders > BNL) or Jacobi U, hi * hi; the Jacobi V / FP32 copy, hi * hi; right-hand-side buffers
+__host__ __device__ constexpr size_t b_slice_doubles(int hi) {
+  return 2 * (size_t)hi * hi + (size_t)BNM * BRM * 2 + (size_t)BNM * 4;
+}
+__host__ __device__ constexpr size_t b_slice_bytes(int hi) { return b_slice_doubles(hi) * 8 + (size_t)BNM * 2 * 4; }
+// LDS of a launch for orders <= hi: the matrix region (the matrix itself up to order BNL; above that the
+// blocked factorisations' panels and the staging of the triangles), then hi * BRM doubles of vectors
+__host__ __device__ constexpr size_t b_lds_matrix(int hi) { return hi <= BNL ? (size_t)hi * hi : (size_t)BNL * BNL; }
+__host__ __device__ constexpr size_t b_lds_bytes(int hi) { return 8 * (b_lds_matrix(hi) + (size_t)hi * BRM); }
 
 struct BCtx {
   int t, lane, w;
@@ -540,7 +544,7 @@ struct BFactor {
   int scol;    // columns staged at a time (64 when one wave has the whole staging region)
 };
 
-// y = inv(A) y (trans = false) or inv(A)^T y (trans = true); wave 0 only; sbuf: LDS, BNM * BRM doubles
+// y = inv(A) y (trans = false) or inv(A)^T y (trans = true); one wave; sbuf: LDS, n * BRM doubles
 template <int NRC, class TF>
 __device__ __forceinline__ void w_apply_inv(const BFactor<TF>& f, int n, bool trans, WVec<NRC>& v, int nr, int lane,
                                             double* sbuf) {
@@ -837,12 +841,17 @@ __device__ void b_house_qr(const BCtx& c, double* M, int n, double* tau, double*
   }
 }
 
-__global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __restrict__ desc,
-                                                      const double* __restrict__ Apool,
-                                                      const double* __restrict__ Bpool, double* Xpool,
-                                                      char* work, ada_opts o, ada_result* results,
-                                                      unsigned* queue, const int* __restrict__ order) {
-  extern __shared__ double lds[];  // BNL * BNL matrix, then BNM * BRM vector buffer
+// One launch takes the systems of one range of orders (the systems at order[range[0] .. range[1]), all of
+// order <= hi). OCC: workgroups per compute unit the register budget allows (1: 512 registers per lane,
+// 2: 256). scol: columns of a triangle in HBM a wave stages into LDS at a time.
+template <int OCC>
+__global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restrict__ desc,
+                                                           const double* __restrict__ Apool,
+                                                           const double* __restrict__ Bpool, double* Xpool,
+                                                           char* work, ada_opts o, ada_result* results,
+                                                           unsigned* queue, const int* __restrict__ order,
+                                                           const int* __restrict__ range, int hi, int scol) {
+  extern __shared__ double lds[];  // matrix region (b_lds_matrix(hi)), then hi * BRM vector buffer
   __shared__ double s_red[8];
   __shared__ int s_ired[8];
   __shared__ int s_idx;
@@ -852,20 +861,21 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
   c.w = c.t >> 6;
   c.red = s_red;
   c.ired = s_ired;
-  double* sbuf = lds + (size_t)BNL * BNL;
-  char* slice = work + (size_t)blockIdx.x * kBSliceBytes;
+  double* sbuf = lds + b_lds_matrix(hi);
+  char* slice = work + (size_t)blockIdx.x * b_slice_bytes(hi);
   double* gW = reinterpret_cast<double*>(slice);
-  double* gV = gW + kBW;
-  double* gX = gV + kBV;                     // BNM * BRM
-  int* perm = reinterpret_cast<int*>(gW + kBSliceD);
+  double* gV = gW + (size_t)hi * hi;
+  double* gX = gV + (size_t)hi * hi;         // BNM * BRM
+  int* perm = reinterpret_cast<int*>(gW + b_slice_doubles(hi));
+  const int first = range[0], last = range[1];
   const double thr = o.rcond_threshold >= 0.0 ? o.rcond_threshold : 0.5 * kEps;
 
   while (true) {
-    if (c.t == 0) s_idx = (int)atomicAdd(queue, 1u);
+    if (c.t == 0) s_idx = first + (int)atomicAdd(queue, 1u);
     __syncthreads();
     const int idx = s_idx;
     __syncthreads();
-    if (idx >= count) break;
+    if (idx >= last) break;
     const int sys = order[idx];  // largest systems first
     const BDesc d = desc[sys];
     ada_result res;
@@ -884,7 +894,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
     res.rcond = __longlong_as_double(0x7ff8000000000000LL);
     res.berr = __longlong_as_double(0x7ff8000000000000LL);
     const int n = d.n, nr = d.nrhs;
-    if (n < 1 || n > BNM || nr < 1 || nr > BRM || d.lda < n || d.ldb < n || d.ldx < n) {
+    if (n < 1 || n > hi || nr < 1 || nr > BRM || d.lda < n || d.ldb < n || d.ldx < n) {
       res.status = ADA_ERR_ARG;
       if (c.t == 0) results[sys] = res;
       continue;
@@ -1020,8 +1030,8 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
         double* Rv = gX;  // residuals, BNM x BRM
         BFactor<float> gw = g;
         if (g.stg) {
-          gw.stg = g.stg + (size_t)c.w * SCOL * BNM;
-          gw.scol = SCOL;
+          gw.stg = g.stg + (size_t)c.w * scol * BNM;
+          gw.scol = scol;
         }
         double* sbw = sbuf + c.w;
         // the condition estimate (wave 0) beside x0 = solve(b) for every right-hand side (waves 1-3)
@@ -1226,8 +1236,8 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       __syncthreads();
       BFactor<double> fw = f;
       if (f.stg) {
-        fw.stg = f.stg + (size_t)c.w * SCOL * BNM;
-        fw.scol = SCOL;
+        fw.stg = f.stg + (size_t)c.w * scol * BNM;
+        fw.scol = scol;
       }
       double* sbw = sbuf + c.w;
       double rcond = __longlong_as_double(0x7ff8000000000000LL);
@@ -1323,7 +1333,7 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
       __syncthreads();
       res.sweeps = b_jacobi(c, gW, Y, nr, n, 30);
       // sigma_j = ||u_j||, cut at eps * sigma_max
-      double* sig = sbuf;  // BNM
+      double* sig = sbuf;  // n
       for (int j = c.t; j < n; j += BT) {
         double s = 0.0;
 #pragma unroll 8
@@ -1392,11 +1402,13 @@ __global__ __launch_bounds__(BT) void k_solve_batched(int count, const BDesc* __
 }
 
 // order[] = the systems by decreasing n (a counting sort; systems outside the kernel's limits last), so
-// that the persistent workgroups take the longest systems first and the launch does not end on a tail of
+// that the persistent workgroups take the longest systems first and a launch does not end on a tail of
 // large systems picked up late. The order among systems of equal n is arbitrary: each system's result does
-// not depend on when or where it runs. Also zeroes the queue counter. One workgroup.
+// not depend on when or where it runs. range[2k], range[2k+1]: the part of order[] that launch k takes
+// (orders in (max_n[k+1], max_n[k]]; the last launch also takes the systems outside the limits). Also
+// zeroes the launches' queue counters. One workgroup.
 __global__ __launch_bounds__(1024) void k_batch_order(int count, const BDesc* __restrict__ desc, int* order,
-                                                      unsigned* queue) {
+                                                      unsigned* queue, int* range, int nb, int m0, int m1, int m2) {
   __shared__ int cnt[BNM + 1];
   for (int b = threadIdx.x; b <= BNM; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
@@ -1413,37 +1425,87 @@ __global__ __launch_bounds__(1024) void k_batch_order(int count, const BDesc* __
       cnt[b] = run;
       run += c;
     }
-    *queue = 0u;
+    const int mx[3] = {m0, m1, m2};
+    for (int k = 0; k < nb; ++k) {
+      range[2 * k] = cnt[BNM - mx[k]];
+      range[2 * k + 1] = k + 1 < nb ? cnt[BNM - mx[k + 1]] : count;
+      queue[k] = 0u;
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < count; i += blockDim.x) order[atomicAdd(&cnt[bin_of(i)], 1)] = i;
 }
 
-size_t batched_workspace_bytes(int count, int max_workgroups) {
-  const size_t order = ((size_t)count * 4 + 255) / 256 * 256;
-  return 256 + order + (size_t)max_workgroups * kBSliceBytes;
+namespace {
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t kStaticLds = 2048;  // the kernel's own shared variables (1.4 KB) with room to spare
+size_t slice_budget() { return (size_t)BNM * b_slice_bytes(BNM); }  // 256 workgroups at the largest order
+size_t order_bytes(int count) { return ((size_t)count * 4 + 255) / 256 * 256; }
+}  // namespace
+
+ada_batched_shape batched_default_shape(int max_wg) {
+  ada_batched_shape s{};
+  s.buckets = 1;
+  s.max_n[0] = BNM;
+  s.wg_per_cu[0] = 1;
+  s.workgroups[0] = max_wg < 1 ? 1 : (max_wg > 256 ? 256 : max_wg);  // one per compute unit
+  s.stage_cols = 8;
+  return s;
 }
 
-int batched_workgroups(int count, int max_wg) {
-  int g = max_wg < 1 ? 1 : (max_wg > 256 ? 256 : max_wg);  // one per compute unit: each holds up to 160 KB of LDS
-  return count < g ? (count < 1 ? 1 : count) : g;
+const char* batched_shape_problem(const ada_batched_shape& s) {
+  if (s.buckets < 1 || s.buckets > 3) return "buckets must be 1, 2 or 3";
+  if (s.max_n[0] != BNM) return "max_n[0] must be 256";
+  for (int k = 0; k < s.buckets; ++k) {
+    if (k > 0 && !(s.max_n[k] < s.max_n[k - 1])) return "max_n must decrease";
+    if (s.max_n[k] < 16) return "max_n must be >= 16";
+    if (s.wg_per_cu[k] != 1 && s.wg_per_cu[k] != 2) return "wg_per_cu must be 1 or 2";
+    if (s.wg_per_cu[k] == 2 && 2 * (b_lds_bytes(s.max_n[k]) + kStaticLds) > kLdsPerCu)
+      return "two workgroups per compute unit need max_n <= 96 (LDS)";
+    if (s.workgroups[k] < 1 || (size_t)s.workgroups[k] * b_slice_bytes(s.max_n[k]) > slice_budget())
+      return "workgroups out of range for the workspace";
+  }
+  if (s.stage_cols != 4 && s.stage_cols != SPF) return "stage_cols must be 4 or 8";
+  return nullptr;
 }
+
+size_t batched_workspace_bytes(int count) { return 256 + order_bytes(count) + slice_budget(); }
 
 hipError_t launch_solve_batched(int count, const void* desc, const double* A, const double* B, double* X,
                                 void* work, size_t work_bytes, const ada_opts& o, void* results, hipStream_t st,
-                                int max_wg) {
-  const int G = batched_workgroups(count, max_wg);
-  if (count < 1 || work_bytes < batched_workspace_bytes(count, G)) return hipErrorInvalidValue;
-  unsigned* queue = reinterpret_cast<unsigned*>(work);
+                                const ada_batched_shape& shape, hipEvent_t* ev) {
+  if (count < 1 || work_bytes < batched_workspace_bytes(count) || batched_shape_problem(shape))
+    return hipErrorInvalidValue;
+  unsigned* queue = reinterpret_cast<unsigned*>(work);                    // 3 counters
+  int* range = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + 64);  // 3 ranges
   int* order = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + 256);
-  char* slices = reinterpret_cast<char*>(work) + 256 + ((size_t)count * 4 + 255) / 256 * 256;
-  const size_t lds = sizeof(double) * ((size_t)BNL * BNL + (size_t)BNM * BRM);
-  static size_t done = 0;
-  hipError_t e = ensure_lds((const void*)k_solve_batched, lds, done);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, count, (const BDesc*)desc, order, queue);
-  hipLaunchKernelGGL(k_solve_batched, dim3(G), dim3(BT), lds, st, count, (const BDesc*)desc, A, B, X, slices, o,
-                     (ada_result*)results, queue, (const int*)order);
+  char* slices = reinterpret_cast<char*>(work) + 256 + order_bytes(count);
+  const int nb = shape.buckets;
+  hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, count, (const BDesc*)desc, order, queue, range, nb,
+                     shape.max_n[0], nb > 1 ? shape.max_n[1] : 0, nb > 2 ? shape.max_n[2] : 0);
+  if (ev) hipEventRecord(ev[0], st);
+  for (int k = 0; k < nb; ++k) {
+    const int hi = shape.max_n[k];
+    const size_t lds = b_lds_bytes(hi);
+    const int G = std::min(shape.workgroups[k], count);
+    hipError_t e;
+    if (shape.wg_per_cu[k] == 2) {
+      static size_t done2 = 0;
+      e = ensure_lds((const void*)k_solve_batched<2>, lds, done2);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_solve_batched<2>, dim3(G), dim3(BT), lds, st, (const BDesc*)desc, A, B, X, slices, o,
+                         (ada_result*)results, queue + k, (const int*)order, (const int*)(range + 2 * k), hi,
+                         shape.stage_cols);
+    } else {
+      static size_t done1 = 0;
+      e = ensure_lds((const void*)k_solve_batched<1>, lds, done1);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_solve_batched<1>, dim3(G), dim3(BT), lds, st, (const BDesc*)desc, A, B, X, slices, o,
+                         (ada_result*)results, queue + k, (const int*)order, (const int*)(range + 2 * k), hi,
+                         shape.stage_cols);
+    }
+    if (ev) hipEventRecord(ev[k + 1], st);
+  }
   return hipGetLastError();
 }
 

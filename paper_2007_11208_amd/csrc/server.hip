@@ -205,7 +205,8 @@ void batch_worker(ada_server s, int w) {
     hipError_t e = hipMemcpyAsync(d_desc, s->h_desc, sizeof(ada_desc) * count, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
       e = ada::launch_solve_batched(count, d_desc, base, base, const_cast<double*>(base), s->base + s->bwork_off,
-                                    s->bwork_bytes, batch[0]->req.opts, d_res, st, kBatchWg);
+                                    s->bwork_bytes, batch[0]->req.opts, d_res, st,
+                                    ada::batched_default_shape(kBatchWg));
     if (e == hipSuccess) e = hipMemcpyAsync(s->h_res, d_res, sizeof(ada_result) * count, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     std::lock_guard<std::mutex> lk(s->mu);

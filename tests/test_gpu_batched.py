@@ -7,6 +7,8 @@ reported backward error equal to the oracle's on the GPU's x and <= 1e-12 (or
 twice the oracle's for inconsistent least-squares systems), x within
 32 n kappa eps |x| off the SVD route, SVD rank exact.
 """
+import re
+
 import numpy as np
 import pytest
 
@@ -210,3 +212,65 @@ def test_batched_launch_in_a_hip_graph(ada):
         assert torch.equal(batch.X, x_ref), f"replay {rep}: x differs"
         assert torch.equal(batch.res, r_ref), f"replay {rep}: results differ"
         del junk
+
+
+def test_batched_shapes_bit_identical_and_tuned(ada):
+    """Every launch shape (ranges of orders, workgroups per compute unit, staging width) gives the same
+    bits; the autotuner keeps one of them in its context, and the tuned run matches the oracle."""
+    cases = W.batched_case(160, k=5, n_lo=8, n_hi=256)
+    As = [c[1] for c in cases]
+    Bs = [c[2] for c in cases]
+    ctx = ada.Context(0)
+    batch = ada.Batch(As, Bs, ctx=ctx)
+    assert batch.shape() == {"max_n": [256], "wg_per_cu": [1], "workgroups": [256], "stage_cols": 8}
+    batch.run()
+    torch.cuda.synchronize()
+    x_ref, r_ref = batch.X.clone(), batch.res.clone()
+    shapes = [ada.batched_shape((256, 96), (1, 2)),
+              ada.batched_shape((256, 128, 64), (1, 1, 2), stage_cols=4),
+              ada.batched_shape((256, 64), (1, 1), workgroups=(37, 5)),
+              ada.batched_shape((256, 200, 17), (1, 1, 2), workgroups=(1, 300, 512))]
+    for sh in shapes:
+        print("shape", sh.as_dict(), flush=True)
+        batch.set_shape(sh)
+        assert batch.shape() == sh.as_dict()
+        batch.X.zero_()
+        batch.res.zero_()
+        batch.run()
+        torch.cuda.synchronize()
+        assert torch.equal(batch.X, x_ref), sh.as_dict()
+        assert torch.equal(batch.res, r_ref), sh.as_dict()
+    batch.set_shape(None)
+    batch.X.zero_()
+    batch.res.zero_()
+    tuned, ms = batch.tune()
+    torch.cuda.synchronize()
+    print("tuned", tuned, f"{ms:.3f} ms", flush=True)
+    assert ms > 0 and batch.shape() == tuned
+    assert torch.equal(batch.X, x_ref) and torch.equal(batch.res, r_ref)
+    # the other precision keeps its default
+    b32 = ada.Batch(As[:4], Bs[:4], ctx=ctx, precision="fp32_ir")
+    assert b32.shape()["max_n"] == [256] and len(b32.shape()["wg_per_cu"]) == 1
+    batch.X.zero_()
+    batch.run()
+    xs, rs = batch.solutions(), batch.results()
+    for (kind, a, b), x, r in zip(cases, xs, rs):
+        check(ada, a, b, x, r)
+    ctx.close()
+
+
+def test_batched_shape_rejects(ada):
+    ctx = ada.Context(0)
+    batch = ada.Batch([np.eye(3)], [np.ones((3, 1))], ctx=ctx)
+    bad = [(ada.batched_shape((200,)), "max_n[0] must be 256"),
+           (ada.batched_shape((256, 128, 128)), "max_n must decrease"),
+           (ada.batched_shape((256, 8)), "max_n must be >= 16"),
+           (ada.batched_shape((256, 128), (1, 2)), "max_n <= 96"),
+           (ada.batched_shape((256, 64), (1, 3)), "wg_per_cu must be 1 or 2"),
+           (ada.batched_shape((256,), workgroups=(257,)), "workgroups out of range"),
+           (ada.batched_shape((256,), stage_cols=16), "stage_cols must be 4 or 8")]
+    for sh, msg in bad:
+        with pytest.raises(ada.AdaError, match=re.escape(msg)):
+            batch.set_shape(sh)
+    assert batch.shape()["max_n"] == [256]
+    ctx.close()
