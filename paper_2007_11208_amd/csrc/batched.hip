@@ -30,6 +30,14 @@ constexpr int BNL32 = 181;    // orders up to this keep an FP32 matrix in LDS (1
 constexpr int kMaxRefine = 30;  // refinement steps at most (the limit of LAPACK's mixed-precision driver)
 constexpr double kRcondRefine = 1e-9;  // FP32 factors with a smaller rcond estimate are not refined
 
+// Pointers with their memory named in the type. The routines below are compiled as functions of their own;
+// a plain pointer there is a flat address, whose loads wait on the LDS counter as well as the memory one
+// and so complete one after another. Naming the memory gives global (buffer) and LDS instructions.
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+template <class T> using lptr = __attribute__((address_space(3))) T*;
+template <class T> __device__ __forceinline__ gptr<T> as_global(T* p) { return (gptr<T>)p; }
+template <class T> __device__ __forceinline__ lptr<T> as_lds(T* p) { return (lptr<T>)p; }
+
 struct BDesc {
   int32_t n, nrhs, lda, ldb, ldx, pad;
   int64_t a_off, b_off, x_off;
@@ -48,11 +56,11 @@ __host__ __device__ constexpr size_t b_lds_bytes(int hi) { return 8 * (b_lds_mat
 
 struct BCtx {
   int t, lane, w;
-  double* red;  // LDS scratch for reductions (8 doubles)
-  int* ired;    // 8 ints
+  lptr<double> red;  // LDS scratch for reductions (8 doubles)
+  lptr<int> ired;    // 8 ints
 };
 
-__device__ __forceinline__ double b_sum(const BCtx& c, double v) {
+__device__ __forceinline__ double b_sum(const BCtx c, double v) {
   v = wave_sum(v);
   if (c.lane == 0) c.red[c.w] = v;
   __syncthreads();
@@ -60,7 +68,7 @@ __device__ __forceinline__ double b_sum(const BCtx& c, double v) {
   __syncthreads();
   return s;
 }
-__device__ __forceinline__ double b_max(const BCtx& c, double v) {
+__device__ __forceinline__ double b_max(const BCtx c, double v) {
   v = wave_max(v);
   if (c.lane == 0) c.red[c.w] = v;
   __syncthreads();
@@ -68,7 +76,7 @@ __device__ __forceinline__ double b_max(const BCtx& c, double v) {
   __syncthreads();
   return s;
 }
-__device__ __forceinline__ int b_max_int(const BCtx& c, int v) {
+__device__ __forceinline__ int b_max_int(const BCtx c, int v) {
   v = wave_max_int(v);
   if (c.lane == 0) c.ired[c.w] = v;
   __syncthreads();
@@ -76,7 +84,7 @@ __device__ __forceinline__ int b_max_int(const BCtx& c, int v) {
   __syncthreads();
   return s;
 }
-__device__ __forceinline__ int b_or(const BCtx& c, int v) {
+__device__ __forceinline__ int b_or(const BCtx c, int v) {
   v = wave_or(v);
   if (c.lane == 0) c.ired[c.w] = v;
   __syncthreads();
@@ -85,7 +93,7 @@ __device__ __forceinline__ int b_or(const BCtx& c, int v) {
   return s;
 }
 // largest |v| with the lowest index on ties (idx < 0: no candidate)
-__device__ __forceinline__ int b_argmax(const BCtx& c, double v, int idx) {
+__device__ __forceinline__ int b_argmax(const BCtx c, double v, int idx) {
   wave_argmax(v, idx);
   if (c.lane == 0) { c.red[c.w] = v; c.ired[c.w] = idx; }
   __syncthreads();
@@ -103,7 +111,7 @@ __device__ __forceinline__ int b_argmax(const BCtx& c, double v, int idx) {
 // ---------------------------------------------------------------- factorisations (four waves)
 // LU with partial pivoting of M (ld n) in place; perm tracks the row order. Returns info (0 or 1-based column).
 template <class T>
-__device__ int b_getrf(const BCtx& c, T* M, int n, int* perm) {
+__device__ int b_getrf(const BCtx c, lptr<T> M, int n, gptr<int> perm) {
   int info = 0;
   for (int i = c.t; i < n; i += BT) perm[i] = i;
   __syncthreads();
@@ -165,9 +173,9 @@ static_assert(2 * PW * BNM <= BNL * BNL, "the blocked factorisations' LDS scratc
 
 // LU with partial pivoting (ties to the lowest row, as b_getrf), same result up to rounding order
 template <class T>
-__device__ int b_getrf_blk(const BCtx& c, T* M, int n, int* perm, T* S) {
-  T* P = S;               // panel: P[r + cc * LDP] = M(k0 + r, k0 + cc)
-  T* U = S + PW * LDP;    // U12: U[kk * BNM + q] = M(k0 + kk, k0 + nbw + q)
+__device__ int b_getrf_blk(const BCtx c, gptr<T> M, int n, gptr<int> perm, lptr<T> S) {
+  lptr<T> P = S;             // panel: P[r + cc * LDP] = M(k0 + r, k0 + cc)
+  lptr<T> U = S + PW * LDP;  // U12: U[kk * BNM + q] = M(k0 + kk, k0 + nbw + q)
   __shared__ int s_piv[PW];       // panel row that column jj's pivot came from (jj: no interchange)
   __shared__ int s_rows[2 * PW];  // rows touched by the panel's interchanges (offsets from k0)
   __shared__ int s_from[2 * PW];  // ... and which of them each one takes its value from (index into s_rows)
@@ -256,7 +264,7 @@ __device__ int b_getrf_blk(const BCtx& c, T* M, int n, int* perm, T* S) {
       const int qi = b0 + c.t;
       if (c.t < 128 && qi < n - nbw) {
         const int q = qi < k0 ? qi : qi + nbw;  // the columns left and right of the panel
-        T* col = M + (size_t)q * n + k0;
+        gptr<T> col = M + (size_t)q * n + k0;
 #pragma unroll 16
         for (int i = 0; i < nr; ++i) U[i * 128 + c.t] = col[s_rows[i]];
 #pragma unroll 16
@@ -267,7 +275,7 @@ __device__ int b_getrf_blk(const BCtx& c, T* M, int n, int* perm, T* S) {
     if (rest <= 0) break;
     // U12 = L11^{-1} A12 (unit lower L11), one thread per column
     for (int q = c.t; q < rest; q += BT) {
-      T* col = M + (size_t)(k0 + nbw + q) * n + k0;
+      gptr<T> col = M + (size_t)(k0 + nbw + q) * n + k0;
       T x[PW];
 #pragma unroll
       for (int kk = 0; kk < PW; ++kk) x[kk] = kk < nbw ? col[kk] : T(0);
@@ -320,8 +328,8 @@ __device__ int b_getrf_blk(const BCtx& c, T* M, int n, int* perm, T* S) {
 
 // Cholesky A = L L^T from the lower triangle (as b_potrf): 0 or the 1-based failing column
 template <class T>
-__device__ int b_potrf_blk(const BCtx& c, T* M, int n, T* S) {
-  T* P = S;  // panel: P[r + cc * LDP] = M(k0 + r, k0 + cc), r >= cc
+__device__ int b_potrf_blk(const BCtx c, gptr<T> M, int n, lptr<T> S) {
+  lptr<T> P = S;  // panel: P[r + cc * LDP] = M(k0 + r, k0 + cc), r >= cc
   for (int k0 = 0; k0 < n; k0 += PW) {
     const int nbw = min(PW, n - k0), m = n - k0, rest = m - nbw;
     for (int e = c.t; e < m * nbw; e += BT) {
@@ -391,7 +399,7 @@ __device__ int b_potrf_blk(const BCtx& c, T* M, int n, T* S) {
 
 // Cholesky A = L L^T from the lower triangle of M; returns 0 or the 1-based failing column
 template <class T>
-__device__ int b_potrf(const BCtx& c, T* M, int n) {
+__device__ int b_potrf(const BCtx c, lptr<T> M, int n) {
   for (int j = 0; j < n; ++j) {
     const T d = M[j + j * n];
     if (!(d > T(0))) return j + 1;
@@ -441,37 +449,38 @@ __device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool tra
   if (stg) scol = min(scol, SPF);
   const int ngr = (n + scol - 1) / scol;
   TF pf[SPF][BRB];
-  auto fetch = [&](int g) {
+  auto fetch = [&](int g) {  // the triangle is in HBM when it is staged
+    gptr<const TF> Tg = as_global(T);
     const int c0 = g * scol, scnt = min(scol, n - c0);
 #pragma unroll
     for (int kk = 0; kk < SPF; ++kk)
 #pragma unroll
       for (int b = 0; b < BRB; ++b) {
         const int i = lane + 64 * b;
-        pf[kk][b] = (kk < scnt && i < n) ? T[i * pr + (size_t)(c0 + kk) * pc] : TF(0);
+        pf[kk][b] = (kk < scnt && i < n) ? Tg[i * pr + (size_t)(c0 + kk) * pc] : TF(0);
       }
   };
   if (stg) fetch(FWD ? 0 : ngr - 1);
   for (int gi = 0; gi < ngr; ++gi) {
     const int g = FWD ? gi : ngr - 1 - gi;
     const int c0 = g * scol, scnt = min(scol, n - c0);
-    const TF* P;
-    size_t qr, qc;  // op(T)(i, c0 + k) = P[i*qr + k*qc]
+    lptr<const TF> P;  // the stage, or the triangle itself when it is held in LDS
+    size_t qr, qc;     // op(T)(i, c0 + k) = P[i*qr + k*qc]
     if (stg) {
 #pragma unroll
       for (int kk = 0; kk < SPF; ++kk)
 #pragma unroll
         for (int b = 0; b < BRB; ++b) {
           const int i = lane + 64 * b;
-          if (kk < scnt && i < n) stg[kk * BNM + i] = pf[kk][b];
+          if (kk < scnt && i < n) as_lds(stg)[kk * BNM + i] = pf[kk][b];
         }
       __builtin_amdgcn_wave_barrier();
       if (gi + 1 < ngr) fetch(FWD ? g + 1 : g - 1);
-      P = stg;
+      P = as_lds<const TF>(stg);
       qr = 1;
       qc = BNM;
     } else {
-      P = T + (size_t)c0 * pc;
+      P = as_lds(T) + (size_t)c0 * pc;
       qr = pr;
       qc = pc;
     }
@@ -716,15 +725,20 @@ __device__ __forceinline__ void b_rr_pair(int m, int r, int pi, int& a, int& b) 
 }
 
 // One-sided Jacobi on the n columns of U (ld n), round-robin pairs, the rotation rule and Rutishauser's
-// formulas of the single-system route. Each quarter-wave (16 lanes) takes one pair, so a workgroup has 16
-// pairs in flight; the two columns stay in registers between the dot products and the rotation (up to 16
-// elements per lane). Y (n x BRM, row j = the nr projections w_j^T c) takes every rotation as well.
+// formulas of the single-system route. Each quarter-wave (16 lanes) takes one pair at a time, so a
+// workgroup has 16 pairs in flight; the two columns stay in registers between the dot products and the
+// rotation (up to 16 elements per lane), and with PF the columns of the quarter's next pair of the same
+// round are loaded while the current pair is rotated (PF = false: the kernel variant with half the
+// registers loads each pair when it starts on it). Y (n x BRM, row j = the nr projections w_j^T c) takes
+// every rotation as well.
 constexpr int JQ = BNM / 16;  // elements of a column per lane of a quarter-wave
-__device__ int b_jacobi(const BCtx& c, double* U, double* Y, int nr, int n, int max_sweeps) {
+template <bool PF>
+__device__ int b_jacobi(const BCtx c, gptr<double> U, gptr<double> Y, int nr, int n, int max_sweeps) {
   const int m = (n + 1) & ~1;
   const double tol = (double)n * kEps;
   const int q = c.lane >> 4, ql = c.lane & 15;  // quarter of the wave, lane in it
   const int slot = c.w * 4 + q;                 // 16 pair slots per workgroup
+  const int npairs = m / 2;
   __shared__ int s_rot;
   int sweeps = 0;
   for (; sweeps < max_sweeps; ++sweeps) {
@@ -732,23 +746,55 @@ __device__ int b_jacobi(const BCtx& c, double* U, double* Y, int nr, int n, int 
     __syncthreads();
     int rot = 0;
     for (int r = 0; r < m - 1; ++r) {
-      for (int pi0 = 0; pi0 < m / 2; pi0 += 16) {
-        const int pi = pi0 + slot;
+      // pair pi of round r (pi = slot, slot + 16, ...): its columns p < qq, or live = false
+      auto pair_of = [&](int pi, int& p, int& qq) -> bool {
         int a = 0, b = 0;
-        bool live = pi < m / 2;
+        bool live = pi < npairs;
         if (live) {
           b_rr_pair(m, r, pi, a, b);
           live = a < n && b < n;
         }
-        const int p = min(a, b), qq = max(a, b);
-        double* up = U + (size_t)p * n;
-        double* uq = U + (size_t)qq * n;
-        double x[JQ], y[JQ];
+        p = min(a, b);
+        qq = max(a, b);
+        return live;
+      };
+      auto load = [&](bool live, int p, int qq, double* x, double* y) {
+        gptr<const double> up = U + (size_t)p * n;
+        gptr<const double> uq = U + (size_t)qq * n;
 #pragma unroll
         for (int k = 0; k < JQ; ++k) {
           const int i = ql + 16 * k;
           x[k] = (live && i < n) ? up[i] : 0.0;
           y[k] = (live && i < n) ? uq[i] : 0.0;
+        }
+      };
+      int pn = 0, qn = 0;
+      bool liven = false;
+      double xn[PF ? JQ : 1], yn[PF ? JQ : 1];
+      if (PF) {
+        liven = pair_of(slot, pn, qn);
+        load(liven, pn, qn, xn, yn);
+      }
+      for (int pi = slot; pi < npairs; pi += 16) {
+        int p, qq;
+        bool live;
+        double x[JQ], y[JQ];
+        if (PF) {
+          p = pn;
+          qq = qn;
+          live = liven;
+#pragma unroll
+          for (int k = 0; k < JQ; ++k) {
+            x[k] = xn[PF ? k : 0];
+            y[k] = yn[PF ? k : 0];
+          }
+          if (pi + 16 < npairs) {  // the next pair's columns are disjoint from this one's
+            liven = pair_of(pi + 16, pn, qn);
+            load(liven, pn, qn, xn, yn);
+          }
+        } else {
+          live = pair_of(pi, p, qq);
+          load(live, p, qq, x, y);
         }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -767,6 +813,8 @@ __device__ int b_jacobi(const BCtx& c, double* U, double* Y, int nr, int n, int 
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          gptr<double> up = U + (size_t)p * n;
+          gptr<double> uq = U + (size_t)qq * n;
 #pragma unroll
           for (int k = 0; k < JQ; ++k) {
             const int i = ql + 16 * k;
@@ -777,8 +825,8 @@ __device__ int b_jacobi(const BCtx& c, double* U, double* Y, int nr, int n, int 
           }
           // the same rotation on the projections y_j = w_j^T c (the accumulated rotations W are not needed)
           if (ql < nr) {
-            double* yp = Y + (size_t)p * BRM + ql;
-            double* yq = Y + (size_t)qq * BRM + ql;
+            gptr<double> yp = Y + (size_t)p * BRM + ql;
+            gptr<double> yq = Y + (size_t)qq * BRM + ql;
             const double xv = *yp, yv = *yq;
             *yp = cs * xv - sn * yv;
             *yq = sn * xv + cs * yv;
@@ -806,9 +854,10 @@ __device__ int b_jacobi(const BCtx& c, double* U, double* Y, int nr, int n, int 
 // reflectors applied to the ncol columns of C (ld ldc). Reflector k maps M[k.., k] to (beta, 0, ...):
 // beta = -sign(alpha) ||M[k.., k]||, tau_k = (beta - alpha) / beta, v = (1, M[k+1.., k] / (alpha - beta));
 // tau_k = 0 when the part below the diagonal is zero. Columns are updated one per wave.
-__device__ void b_house_qr(const BCtx& c, double* M, int n, double* tau, double* C, int ldc, int ncol) {
+__device__ void b_house_qr(const BCtx c, gptr<double> M, int n, lptr<double> tau, gptr<double> C, int ldc,
+                           int ncol) {
   for (int k = 0; k < n; ++k) {
-    double* col = M + (size_t)k * n;
+    gptr<double> col = M + (size_t)k * n;
     double s = 0.0;
     for (int i = k + 1 + c.t; i < n; i += BT) s = fma(col[i], col[i], s);
     const double sig2 = b_sum(c, s);
@@ -829,7 +878,7 @@ __device__ void b_house_qr(const BCtx& c, double* M, int n, double* tau, double*
     if (tk != 0.0) {
       const int ncols = (n - k - 1) + ncol;
       for (int q = c.w; q < ncols; q += BT / 64) {
-        double* a = q < n - k - 1 ? M + (size_t)(k + 1 + q) * n : C + (size_t)(q - (n - k - 1)) * ldc;
+        gptr<double> a = q < n - k - 1 ? M + (size_t)(k + 1 + q) * n : C + (size_t)(q - (n - k - 1)) * ldc;
         double dd = 0.0;
         for (int i = k + 1 + c.lane; i < n; i += 64) dd = fma(col[i], a[i], dd);
         dd = (wave_sum(dd) + a[k]) * tk;
@@ -859,8 +908,8 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
   c.t = threadIdx.x;
   c.lane = c.t & 63;
   c.w = c.t >> 6;
-  c.red = s_red;
-  c.ired = s_ired;
+  c.red = as_lds(s_red);
+  c.ired = as_lds(s_ired);
   double* sbuf = lds + b_lds_matrix(hi);
   char* slice = work + (size_t)blockIdx.x * b_slice_bytes(hi);
   double* gW = reinterpret_cast<double*>(slice);
@@ -1016,11 +1065,13 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       g.scol = 64;  // wave 0 alone solves on this route: the whole staging region
       int ok;
       if (sym_class) {
-        ok = (n <= BNL32 ? b_potrf<float>(c, M32, n) : b_potrf_blk<float>(c, M32, n, reinterpret_cast<float*>(lds))) == 0;
+        ok = (n <= BNL32 ? b_potrf<float>(c, as_lds(M32), n)
+                          : b_potrf_blk<float>(c, as_global(M32), n, as_lds(reinterpret_cast<float*>(lds)))) == 0;
         g.kind = 1;
       } else {
-        ok = (n <= BNL32 ? b_getrf<float>(c, M32, n, perm)
-                         : b_getrf_blk<float>(c, M32, n, perm, reinterpret_cast<float*>(lds))) == 0;
+        ok = (n <= BNL32 ? b_getrf<float>(c, as_lds(M32), n, as_global(perm))
+                         : b_getrf_blk<float>(c, as_global(M32), n, as_global(perm),
+                                              as_lds(reinterpret_cast<float*>(lds)))) == 0;
         g.kind = 0;
       }
       __syncthreads();
@@ -1205,7 +1256,7 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       } else {
         bool fresh = true;  // M still holds A
         if (cls == ADA_CLASS_SYMPD) {
-          const int ci = n <= BNL ? b_potrf(c, M, n) : b_potrf_blk(c, M, n, lds);
+          const int ci = n <= BNL ? b_potrf(c, as_lds(M), n) : b_potrf_blk(c, as_global(M), n, as_lds(lds));
           fresh = false;
           __syncthreads();
           if (ci == 0) {
@@ -1222,7 +1273,8 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
             for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
             __syncthreads();
           }
-          info = n <= BNL ? b_getrf(c, M, n, perm) : b_getrf_blk(c, M, n, perm, lds);
+          info = n <= BNL ? b_getrf(c, as_lds(M), n, as_global(perm))
+                          : b_getrf_blk(c, as_global(M), n, as_global(perm), as_lds(lds));
           __syncthreads();
           f.kind = 0;
         }
@@ -1321,7 +1373,7 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       for (int e = c.t; e < n * n; e += BT) gV[e] = A[e % n + (size_t)perm[e / n] * d.lda];
       for (int e = c.t; e < n * nr; e += BT) C[e % n + (size_t)(e / n) * BNM] = B[e % n + (size_t)(e / n) * d.ldb];
       __syncthreads();
-      b_house_qr(c, gV, n, tau, C, BNM, nr);
+      b_house_qr(c, as_global(gV), n, as_lds(tau), as_global(C), BNM, nr);
       for (int e = c.t; e < n * n; e += BT) {
         const int i = e % n, j = e / n;
         gW[e] = i >= j ? gV[j + (size_t)i * n] : 0.0;
@@ -1331,7 +1383,7 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       double* Y = gV;  // n x BRM (the reflectors are no longer needed)
       for (int e = c.t; e < n * nr; e += BT) Y[(size_t)(e % n) * BRM + e / n] = C[e % n + (size_t)(e / n) * BNM];
       __syncthreads();
-      res.sweeps = b_jacobi(c, gW, Y, nr, n, 30);
+      res.sweeps = b_jacobi<OCC == 1>(c, as_global(gW), as_global(Y), nr, n, 30);
       // sigma_j = ||u_j||, cut at eps * sigma_max
       double* sig = sbuf;  // n
       for (int j = c.t; j < n; j += BT) {
