@@ -849,6 +849,157 @@ __device__ int b_jacobi(const BCtx c, gptr<double> U, gptr<double> Y, int nr, in
   return sweeps;
 }
 
+// Sum over the 16 lanes of a quarter-wave by DPP exchanges within rows of 16 (lane i^1, i^2, then the
+// mirror images in 8 and in 16); every lane of the quarter ends with the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double quarter_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
+// One Jacobi rotation of columns p and q of S (LDS, n rows, ld n) by one quarter-wave (lane ql of 16), with
+// rows p and q of the projections Ys (LDS, BRM per row); the rotation rule and Rutishauser's formulas of
+// b_jacobi. Returns whether it rotated (the same in every lane of the quarter).
+__device__ __forceinline__ bool q_rotate_lds(lptr<double> S, lptr<double> Ys, int p, int q, int n, int nr, int ql,
+                                             double tol) {
+  lptr<double> sp = S + p * n;
+  lptr<double> sq = S + q * n;
+  double x[JQ], y[JQ];
+#pragma unroll
+  for (int k = 0; k < JQ; ++k) {
+    const int i = ql + 16 * k;
+    x[k] = i < n ? sp[i] : 0.0;
+    y[k] = i < n ? sq[i] : 0.0;
+  }
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int k = 0; k < JQ; ++k) {
+    al = fma(x[k], x[k], al);
+    be = fma(y[k], y[k], be);
+    ga = fma(x[k], y[k], ga);
+  }
+  al = quarter_sum(al);
+  be = quarter_sum(be);
+  ga = quarter_sum(ga);
+  if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+  for (int k = 0; k < JQ; ++k) {
+    const int i = ql + 16 * k;
+    if (i < n) {
+      sp[i] = cs * x[k] - sn * y[k];
+      sq[i] = sn * x[k] + cs * y[k];
+    }
+  }
+  if (ql < nr) {
+    const double xv = Ys[p * BRM + ql], yv = Ys[q * BRM + ql];
+    Ys[p * BRM + ql] = cs * xv - sn * yv;
+    Ys[q * BRM + ql] = sn * xv + cs * yv;
+  }
+  return true;
+}
+
+// One-sided Jacobi of b_jacobi for a matrix U in HBM, by blocks of JB columns staged in LDS: a sweep takes
+// each block in turn, rotates the pairs inside it (round robin over its columns), then the JB * JB pairs
+// across it and each later block (JB rounds; round r pairs column k of the first with column (k + r) mod JB
+// of the second), so every pair of columns once per sweep. The first block stays in LDS (S columns 0..JB-1)
+// while the later ones pass through S columns JB..2JB-1, with their rows of Y in Ys (2 * JB * BRM doubles);
+// a block goes back to HBM when a rotation changed it. Sixteen quarter-waves take the pairs of a round.
+constexpr int JB = 32;
+__device__ int b_jacobi_blk(const BCtx c, gptr<double> U, gptr<double> Y, int nr, int n, int max_sweeps,
+                            lptr<double> S, lptr<double> Ys) {
+  const double tol = (double)n * kEps;
+  const int ql = c.lane & 15;
+  const int slot = c.w * 4 + (c.lane >> 4);
+  const int nbk = (n + JB - 1) / JB;
+  __shared__ int s_any;
+  // columns c0 .. c0+cnt-1 of U (contiguous, cnt * n doubles) <-> S columns s0 .., and their rows of Y
+  auto stage = [&](int c0, int cnt, int s0, bool in) {
+    gptr<double> g = U + (size_t)c0 * n;
+    lptr<double> l = S + s0 * n;
+    const int tot = cnt * n;
+    if (in) {
+#pragma unroll 16
+      for (int e = c.t; e < tot; e += BT) l[e] = g[e];
+      for (int e = c.t; e < cnt * BRM; e += BT) Ys[s0 * BRM + e] = Y[(size_t)c0 * BRM + e];
+    } else {
+#pragma unroll 16
+      for (int e = c.t; e < tot; e += BT) g[e] = l[e];
+      for (int e = c.t; e < cnt * BRM; e += BT) Y[(size_t)c0 * BRM + e] = Ys[s0 * BRM + e];
+    }
+  };
+  // every thread learns whether any quarter rotated (any: this thread's flag); resets the flag after use
+  auto any_of = [&](int any) -> bool {
+    if (wave_or(any) && c.lane == 0) s_any = 1;
+    __syncthreads();
+    const bool r = s_any != 0;
+    __syncthreads();
+    if (c.t == 0) s_any = 0;
+    return r;
+  };
+  if (c.t == 0) s_any = 0;
+  int sweeps = 0;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    bool rot = false;
+    for (int bi = 0; bi < nbk; ++bi) {
+      const int c0 = bi * JB, cnt0 = min(JB, n - c0);
+      __syncthreads();  // the previous write-back has read S
+      stage(c0, cnt0, 0, true);
+      __syncthreads();
+      int any = 0;
+      const int m = (cnt0 + 1) & ~1;
+      for (int r = 0; r < m - 1; ++r) {
+        if (slot < m / 2) {
+          int a = 0, b = 0;
+          b_rr_pair(m, r, slot, a, b);
+          if (a < cnt0 && b < cnt0) any |= q_rotate_lds(S, Ys, min(a, b), max(a, b), n, nr, ql, tol);
+        }
+        __syncthreads();
+      }
+      bool dirty0 = any_of(any);
+      for (int bj = bi + 1; bj < nbk; ++bj) {
+        const int c1 = bj * JB, cnt1 = min(JB, n - c1);
+        stage(c1, cnt1, JB, true);
+        __syncthreads();
+        any = 0;
+        for (int r = 0; r < JB; ++r) {
+          for (int k = slot; k < JB; k += 16) {
+            const int b = (k + r) & (JB - 1);
+            if (k < cnt0 && b < cnt1) any |= q_rotate_lds(S, Ys, k, JB + b, n, nr, ql, tol);
+          }
+          __syncthreads();
+        }
+        if (any_of(any)) {
+          dirty0 = true;
+          stage(c1, cnt1, JB, false);
+        }
+        __syncthreads();  // the write-back has read S before the next block comes in
+      }
+      if (dirty0) {
+        rot = true;
+        stage(c0, cnt0, 0, false);
+      }
+    }
+    __syncthreads();  // the last write-back is complete
+    if (!rot) {
+      ++sweeps;
+      break;
+    }
+  }
+  return sweeps;
+}
+
 // ---------------------------------------------------------------- the solve of one system
 // Householder QR of M (n x n, ld n) in place, reflectors below the diagonal, tau[n] (LDS); the same
 // reflectors applied to the ncol columns of C (ld ldc). Reflector k maps M[k.., k] to (beta, 0, ...):
@@ -951,7 +1102,10 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
     const double* A = Apool + d.a_off;
     const double* B = Bpool + d.b_off;
     double* X = Xpool + d.x_off;
-    double* M = (n <= BNL) ? lds : gW;  // working matrix, ld n
+    // the matrix is held in LDS up to order BNL (FP32 copy: BNL32); the variant with two workgroups per
+    // compute unit only takes orders <= 96 (the launch's range), so it compiles the LDS paths alone
+    const bool lds64 = OCC == 2 || n <= BNL, lds32 = OCC == 2 || n <= BNL32;
+    double* M = lds64 ? lds : gW;  // working matrix, ld n
     // ---- S1/S2: copy A to the working matrix (coalesced), non-finite check, band scan, norms
     int nf = 0;
     for (int e = c.t; e < n * n; e += BT) {
@@ -1052,8 +1206,8 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
     }
     if (o.precision == ADA_PREC_FP32_IR &&
         (cls == ADA_CLASS_SYMPD || cls == ADA_CLASS_GENERAL || cls == ADA_CLASS_BANDED)) {
-      float* M32 = (n <= BNL32) ? reinterpret_cast<float*>(lds) : reinterpret_cast<float*>(gV);
-      m_clobbered = n <= BNL;  // the FP64 copy shared the LDS region
+      float* M32 = lds32 ? reinterpret_cast<float*>(lds) : reinterpret_cast<float*>(gV);
+      m_clobbered = lds64;  // the FP64 copy shared the LDS region
       for (int e = c.t; e < n * n; e += BT) M32[e] = (float)A[e % n + (size_t)(e / n) * d.lda];
       __syncthreads();
       BFactor<float> g;
@@ -1061,15 +1215,15 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       g.ld = n;
       g.perm = perm;
       g.lower = false;
-      g.stg = (n <= BNL32) ? nullptr : reinterpret_cast<float*>(lds);
+      g.stg = lds32 ? nullptr : reinterpret_cast<float*>(lds);
       g.scol = 64;  // wave 0 alone solves on this route: the whole staging region
       int ok;
       if (sym_class) {
-        ok = (n <= BNL32 ? b_potrf<float>(c, as_lds(M32), n)
+        ok = (lds32 ? b_potrf<float>(c, as_lds(M32), n)
                           : b_potrf_blk<float>(c, as_global(M32), n, as_lds(reinterpret_cast<float*>(lds)))) == 0;
         g.kind = 1;
       } else {
-        ok = (n <= BNL32 ? b_getrf<float>(c, as_lds(M32), n, as_global(perm))
+        ok = (lds32 ? b_getrf<float>(c, as_lds(M32), n, as_global(perm))
                          : b_getrf_blk<float>(c, as_global(M32), n, as_global(perm),
                                               as_lds(reinterpret_cast<float*>(lds)))) == 0;
         g.kind = 0;
@@ -1237,7 +1391,7 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       f.ld = n;
       f.perm = perm;
       f.lower = false;
-      f.stg = (n <= BNL) ? nullptr : lds;  // the LDS matrix region is free when the matrix lives in HBM
+      f.stg = lds64 ? nullptr : lds;  // the LDS matrix region is free when the matrix lives in HBM
       f.scol = 64;
       bool routed_sym = false;
       if (m_clobbered) {
@@ -1256,7 +1410,7 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       } else {
         bool fresh = true;  // M still holds A
         if (cls == ADA_CLASS_SYMPD) {
-          const int ci = n <= BNL ? b_potrf(c, as_lds(M), n) : b_potrf_blk(c, as_global(M), n, as_lds(lds));
+          const int ci = lds64 ? b_potrf(c, as_lds(M), n) : b_potrf_blk(c, as_global(M), n, as_lds(lds));
           fresh = false;
           __syncthreads();
           if (ci == 0) {
@@ -1273,7 +1427,7 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
             for (int e = c.t; e < n * n; e += BT) M[e] = A[e % n + (size_t)(e / n) * d.lda];
             __syncthreads();
           }
-          info = n <= BNL ? b_getrf(c, as_lds(M), n, as_global(perm))
+          info = lds64 ? b_getrf(c, as_lds(M), n, as_global(perm))
                           : b_getrf_blk(c, as_global(M), n, as_global(perm), as_lds(lds));
           __syncthreads();
           f.kind = 0;
@@ -1383,7 +1537,9 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       double* Y = gV;  // n x BRM (the reflectors are no longer needed)
       for (int e = c.t; e < n * nr; e += BT) Y[(size_t)(e % n) * BRM + e / n] = C[e % n + (size_t)(e / n) * BNM];
       __syncthreads();
-      res.sweeps = b_jacobi<OCC == 1>(c, as_global(gW), as_global(Y), nr, n, 30);
+      // the whole of U in HBM above order BNL: by blocks staged in the LDS matrix region (free after the QR)
+      res.sweeps = !lds64 ? b_jacobi_blk(c, as_global(gW), as_global(Y), nr, n, 30, as_lds(lds), as_lds(sbuf))
+                           : b_jacobi<OCC == 1>(c, as_global(gW), as_global(Y), nr, n, 30);
       // sigma_j = ||u_j||, cut at eps * sigma_max
       double* sig = sbuf;  // n
       for (int j = c.t; j < n; j += BT) {
