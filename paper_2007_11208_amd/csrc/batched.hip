@@ -866,48 +866,67 @@ __device__ __forceinline__ double quarter_sum(double v) {
   return v;
 }
 
-// One Jacobi rotation of columns p and q of S (LDS, n rows, ld n) by one quarter-wave (lane ql of 16), with
-// rows p and q of the projections Ys (LDS, BRM per row); the rotation rule and Rutishauser's formulas of
-// b_jacobi. Returns whether it rotated (the same in every lane of the quarter).
-__device__ __forceinline__ bool q_rotate_lds(lptr<double> S, lptr<double> Ys, int p, int q, int n, int nr, int ql,
-                                             double tol) {
-  lptr<double> sp = S + p * n;
-  lptr<double> sq = S + q * n;
-  double x[JQ], y[JQ];
+// Jacobi rotations of NP disjoint column pairs (p[j], q[j]) of S (LDS, n rows, ld n) by one quarter-wave
+// (lane ql of 16), the pairs' loads and arithmetic interleaved; rows p and q of the projections Ys (LDS, BRM
+// per row) along; the rotation rule and Rutishauser's formulas of b_jacobi. live[j] = false skips pair j.
+// Returns whether any pair rotated (the same in every lane of the quarter).
+template <int NP>
+__device__ __forceinline__ bool q_rotate_lds(lptr<double> S, lptr<double> Ys, const int* p, const int* q,
+                                             const bool* live, int n, int nr, int ql, double tol) {
+  double x[NP][JQ], y[NP][JQ];
 #pragma unroll
-  for (int k = 0; k < JQ; ++k) {
-    const int i = ql + 16 * k;
-    x[k] = i < n ? sp[i] : 0.0;
-    y[k] = i < n ? sq[i] : 0.0;
-  }
-  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int j = 0; j < NP; ++j) {
+    lptr<double> sp = S + p[j] * n;
+    lptr<double> sq = S + q[j] * n;
 #pragma unroll
-  for (int k = 0; k < JQ; ++k) {
-    al = fma(x[k], x[k], al);
-    be = fma(y[k], y[k], be);
-    ga = fma(x[k], y[k], ga);
-  }
-  al = quarter_sum(al);
-  be = quarter_sum(be);
-  ga = quarter_sum(ga);
-  if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-#pragma unroll
-  for (int k = 0; k < JQ; ++k) {
-    const int i = ql + 16 * k;
-    if (i < n) {
-      sp[i] = cs * x[k] - sn * y[k];
-      sq[i] = sn * x[k] + cs * y[k];
+    for (int k = 0; k < JQ; ++k) {
+      const int i = ql + 16 * k;
+      x[j][k] = (live[j] && i < n) ? sp[i] : 0.0;
+      y[j][k] = (live[j] && i < n) ? sq[i] : 0.0;
     }
   }
-  if (ql < nr) {
-    const double xv = Ys[p * BRM + ql], yv = Ys[q * BRM + ql];
-    Ys[p * BRM + ql] = cs * xv - sn * yv;
-    Ys[q * BRM + ql] = sn * xv + cs * yv;
+  bool any = false;
+  double al[NP], be[NP], ga[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    al[j] = be[j] = ga[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < JQ; ++k) {
+      al[j] = fma(x[j][k], x[j][k], al[j]);
+      be[j] = fma(y[j][k], y[j][k], be[j]);
+      ga[j] = fma(x[j][k], y[j][k], ga[j]);
+    }
   }
-  return true;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    al[j] = quarter_sum(al[j]);
+    be[j] = quarter_sum(be[j]);
+    ga[j] = quarter_sum(ga[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    if (!(live[j] && fabs(ga[j]) > tol * sqrt(al[j]) * sqrt(be[j]))) continue;
+    const double zeta = (be[j] - al[j]) / (2.0 * ga[j]);
+    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+    lptr<double> sp = S + p[j] * n;
+    lptr<double> sq = S + q[j] * n;
+#pragma unroll
+    for (int k = 0; k < JQ; ++k) {
+      const int i = ql + 16 * k;
+      if (i < n) {
+        sp[i] = cs * x[j][k] - sn * y[j][k];
+        sq[i] = sn * x[j][k] + cs * y[j][k];
+      }
+    }
+    if (ql < nr) {
+      const double xv = Ys[p[j] * BRM + ql], yv = Ys[q[j] * BRM + ql];
+      Ys[p[j] * BRM + ql] = cs * xv - sn * yv;
+      Ys[q[j] * BRM + ql] = sn * xv + cs * yv;
+    }
+    any = true;
+  }
+  return any;
 }
 
 // One-sided Jacobi of b_jacobi for a matrix U in HBM, by blocks of JB columns staged in LDS: a sweep takes
@@ -963,7 +982,9 @@ __device__ int b_jacobi_blk(const BCtx c, gptr<double> U, gptr<double> Y, int nr
         if (slot < m / 2) {
           int a = 0, b = 0;
           b_rr_pair(m, r, slot, a, b);
-          if (a < cnt0 && b < cnt0) any |= q_rotate_lds(S, Ys, min(a, b), max(a, b), n, nr, ql, tol);
+          const int pp = min(a, b), qq = max(a, b);
+          const bool lv = a < cnt0 && b < cnt0;
+          any |= q_rotate_lds<1>(S, Ys, &pp, &qq, &lv, n, nr, ql, tol);
         }
         __syncthreads();
       }
@@ -974,10 +995,17 @@ __device__ int b_jacobi_blk(const BCtx c, gptr<double> U, gptr<double> Y, int nr
         __syncthreads();
         any = 0;
         for (int r = 0; r < JB; ++r) {
-          for (int k = slot; k < JB; k += 16) {
-            const int b = (k + r) & (JB - 1);
-            if (k < cnt0 && b < cnt1) any |= q_rotate_lds(S, Ys, k, JB + b, n, nr, ql, tol);
+          // this quarter's two pairs of the round: columns slot and slot + 16 of the first block
+          int pp[2], qq[2];
+          bool lv[2];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int k = slot + 16 * j, b = (k + r) & (JB - 1);
+            pp[j] = k;
+            qq[j] = JB + b;
+            lv[j] = k < cnt0 && b < cnt1;
           }
+          any |= q_rotate_lds<2>(S, Ys, pp, qq, lv, n, nr, ql, tol);
           __syncthreads();
         }
         if (any_of(any)) {
@@ -1005,6 +1033,7 @@ __device__ int b_jacobi_blk(const BCtx c, gptr<double> U, gptr<double> Y, int nr
 // reflectors applied to the ncol columns of C (ld ldc). Reflector k maps M[k.., k] to (beta, 0, ...):
 // beta = -sign(alpha) ||M[k.., k]||, tau_k = (beta - alpha) / beta, v = (1, M[k+1.., k] / (alpha - beta));
 // tau_k = 0 when the part below the diagonal is zero. Columns are updated one per wave.
+template <int QB>
 __device__ void b_house_qr(const BCtx c, gptr<double> M, int n, lptr<double> tau, gptr<double> C, int ldc,
                            int ncol) {
   for (int k = 0; k < n; ++k) {
@@ -1027,14 +1056,50 @@ __device__ void b_house_qr(const BCtx c, gptr<double> M, int n, lptr<double> tau
     }
     __syncthreads();
     if (tk != 0.0) {
+      // wave w updates the columns q = w, w + 4, ...; QB of them at a time so that their loads are in flight
+      // together (per column the same operations in the same order as one at a time)
       const int ncols = (n - k - 1) + ncol;
-      for (int q = c.w; q < ncols; q += BT / 64) {
-        gptr<double> a = q < n - k - 1 ? M + (size_t)(k + 1 + q) * n : C + (size_t)(q - (n - k - 1)) * ldc;
-        double dd = 0.0;
-        for (int i = k + 1 + c.lane; i < n; i += 64) dd = fma(col[i], a[i], dd);
-        dd = (wave_sum(dd) + a[k]) * tk;
-        if (c.lane == 0) a[k] -= dd;
-        for (int i = k + 1 + c.lane; i < n; i += 64) a[i] = fma(-dd, col[i], a[i]);
+      double v[BRB];  // the reflector on this lane's rows k + 1 + lane + 64 j
+#pragma unroll
+      for (int j = 0; j < BRB; ++j) {
+        const int i = k + 1 + c.lane + 64 * j;
+        v[j] = i < n ? col[i] : 0.0;
+      }
+      for (int q0 = c.w; q0 < ncols; q0 += QB * (BT / 64)) {
+        auto colp = [&](int q) {
+          return q < n - k - 1 ? M + (size_t)(k + 1 + q) * n : C + (size_t)(q - (n - k - 1)) * ldc;
+        };
+        double av[QB][BRB], ak[QB];
+#pragma unroll
+        for (int cb = 0; cb < QB; ++cb) {
+          const int q = q0 + cb * (BT / 64);
+          const bool live = q < ncols;
+          gptr<double> a = colp(live ? q : 0);
+          ak[cb] = live ? a[k] : 0.0;
+#pragma unroll
+          for (int j = 0; j < BRB; ++j) {
+            const int i = k + 1 + c.lane + 64 * j;
+            av[cb][j] = (live && i < n) ? a[i] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < QB; ++cb) {
+          const int q = q0 + cb * (BT / 64);
+          double dd = 0.0;
+#pragma unroll
+          for (int j = 0; j < BRB; ++j)
+            if (k + 1 + c.lane + 64 * j < n) dd = fma(v[j], av[cb][j], dd);
+          dd = (wave_sum(dd) + ak[cb]) * tk;
+          if (q < ncols) {
+            gptr<double> a = colp(q);
+            if (c.lane == 0) a[k] = ak[cb] - dd;
+#pragma unroll
+            for (int j = 0; j < BRB; ++j) {
+              const int i = k + 1 + c.lane + 64 * j;
+              if (i < n) a[i] = fma(-dd, v[j], av[cb][j]);
+            }
+          }
+        }
       }
     }
     __syncthreads();
@@ -1527,7 +1592,7 @@ __global__ __launch_bounds__(BT, OCC) void k_solve_batched(const BDesc* __restri
       for (int e = c.t; e < n * n; e += BT) gV[e] = A[e % n + (size_t)perm[e / n] * d.lda];
       for (int e = c.t; e < n * nr; e += BT) C[e % n + (size_t)(e / n) * BNM] = B[e % n + (size_t)(e / n) * d.ldb];
       __syncthreads();
-      b_house_qr(c, as_global(gV), n, as_lds(tau), as_global(C), BNM, nr);
+      b_house_qr<OCC == 1 ? 8 : 2>(c, as_global(gV), n, as_lds(tau), as_global(C), BNM, nr);
       for (int e = c.t; e < n * n; e += BT) {
         const int i = e % n, j = e / n;
         gW[e] = i >= j ? gV[j + (size_t)i * n] : 0.0;
