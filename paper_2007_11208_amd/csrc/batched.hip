@@ -929,6 +929,65 @@ __device__ __forceinline__ bool q_rotate_lds(lptr<double> S, lptr<double> Ys, co
   return any;
 }
 
+// q_rotate_lds for pairs whose first columns a quarter-wave holds in registers (xr[j]: its 16 elements of
+// lane ql; yr[j]: the first column's projection on lane ql < nr), updated in place; the second columns q[j]
+// and their projection rows are in S and Ys.
+template <int NP>
+__device__ __forceinline__ bool q_rotate_xreg(double (&xr)[NP][JQ], double (&yr)[NP], lptr<double> S,
+                                              lptr<double> Ys, const int* q, const bool* live, int n, int nr,
+                                              int ql, double tol) {
+  double y[NP][JQ];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    lptr<double> sq = S + q[j] * n;
+#pragma unroll
+    for (int k = 0; k < JQ; ++k) {
+      const int i = ql + 16 * k;
+      y[j][k] = (live[j] && i < n) ? sq[i] : 0.0;
+    }
+  }
+  bool any = false;
+  double al[NP], be[NP], ga[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    al[j] = be[j] = ga[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < JQ; ++k) {
+      al[j] = fma(xr[j][k], xr[j][k], al[j]);
+      be[j] = fma(y[j][k], y[j][k], be[j]);
+      ga[j] = fma(xr[j][k], y[j][k], ga[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    al[j] = quarter_sum(al[j]);
+    be[j] = quarter_sum(be[j]);
+    ga[j] = quarter_sum(ga[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    if (!(live[j] && fabs(ga[j]) > tol * sqrt(al[j]) * sqrt(be[j]))) continue;
+    const double zeta = (be[j] - al[j]) / (2.0 * ga[j]);
+    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+    lptr<double> sq = S + q[j] * n;
+#pragma unroll
+    for (int k = 0; k < JQ; ++k) {
+      const int i = ql + 16 * k;
+      const double xv = xr[j][k];
+      xr[j][k] = cs * xv - sn * y[j][k];
+      if (i < n) sq[i] = sn * xv + cs * y[j][k];
+    }
+    if (ql < nr) {
+      const double xv = yr[j], yv = Ys[q[j] * BRM + ql];
+      yr[j] = cs * xv - sn * yv;
+      Ys[q[j] * BRM + ql] = sn * xv + cs * yv;
+    }
+    any = true;
+  }
+  return any;
+}
+
 // One-sided Jacobi of b_jacobi for a matrix U in HBM, by blocks of JB columns staged in LDS: a sweep takes
 // each block in turn, rotates the pairs inside it (round robin over its columns), then the JB * JB pairs
 // across it and each later block (JB rounds; round r pairs column k of the first with column (k + r) mod JB
@@ -989,23 +1048,34 @@ __device__ int b_jacobi_blk(const BCtx c, gptr<double> U, gptr<double> Y, int nr
         __syncthreads();
       }
       bool dirty0 = any_of(any);
+      // the cross rounds: this quarter's first columns (slot, slot + 16 of the block) and their projections
+      // stay in registers for all the later blocks
+      double xr[2][JQ], yr[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        lptr<double> sp = S + (slot + 16 * j) * n;
+#pragma unroll
+        for (int k = 0; k < JQ; ++k) {
+          const int i = ql + 16 * k;
+          xr[j][k] = i < n ? sp[i] : 0.0;
+        }
+        yr[j] = ql < nr ? Ys[(slot + 16 * j) * BRM + ql] : 0.0;
+      }
       for (int bj = bi + 1; bj < nbk; ++bj) {
         const int c1 = bj * JB, cnt1 = min(JB, n - c1);
         stage(c1, cnt1, JB, true);
         __syncthreads();
         any = 0;
         for (int r = 0; r < JB; ++r) {
-          // this quarter's two pairs of the round: columns slot and slot + 16 of the first block
-          int pp[2], qq[2];
+          int qq[2];
           bool lv[2];
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             const int k = slot + 16 * j, b = (k + r) & (JB - 1);
-            pp[j] = k;
             qq[j] = JB + b;
             lv[j] = k < cnt0 && b < cnt1;
           }
-          any |= q_rotate_lds<2>(S, Ys, pp, qq, lv, n, nr, ql, tol);
+          any |= q_rotate_xreg<2>(xr, yr, S, Ys, qq, lv, n, nr, ql, tol);
           __syncthreads();
         }
         if (any_of(any)) {
@@ -1014,6 +1084,18 @@ __device__ int b_jacobi_blk(const BCtx c, gptr<double> U, gptr<double> Y, int nr
         }
         __syncthreads();  // the write-back has read S before the next block comes in
       }
+      // the first block's columns back into S (for its write-back)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        lptr<double> sp = S + (slot + 16 * j) * n;
+#pragma unroll
+        for (int k = 0; k < JQ; ++k) {
+          const int i = ql + 16 * k;
+          if (i < n && slot + 16 * j < cnt0) sp[i] = xr[j][k];
+        }
+        if (ql < nr && slot + 16 * j < cnt0) Ys[(slot + 16 * j) * BRM + ql] = yr[j];
+      }
+      __syncthreads();
       if (dirty0) {
         rot = true;
         stage(c0, cnt0, 0, false);
