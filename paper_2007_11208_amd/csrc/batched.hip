@@ -442,11 +442,13 @@ struct WVec {
 // loads row i of the group, a column segment of T (coalesced over the lanes) or a row segment (contiguous
 // for each lane).
 constexpr int SPF = 8;   // most columns of a staged group
-template <bool FWD, int NRC, class TF>
-__device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool trans, bool unit, WVec<NRC>& v,
-                                           int nr, int lane, TF* stg, int scol) {
+// A function of its own (the vector in and out by value): its column loop gets registers of its own
+// rather than what the whole kernel leaves over.
+template <bool FWD, bool STG, int NRC, class TF>
+__device__ __noinline__ WVec<NRC> w_trsv_dir(const TF* T, int ldt, int n, bool trans, bool unit, WVec<NRC> v,
+                                             int nr, int lane, TF* stg, int scol) {
   const size_t pr = trans ? (size_t)ldt : 1, pc = trans ? 1 : (size_t)ldt;  // op(T)(i, c) = T[i*pr + c*pc]
-  if (stg) scol = min(scol, SPF);
+  if (STG) scol = min(scol, SPF);
   const int ngr = (n + scol - 1) / scol;
   TF pf[SPF][BRB];
   auto fetch = [&](int g) {  // the triangle is in HBM when it is staged
@@ -460,13 +462,13 @@ __device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool tra
         pf[kk][b] = (kk < scnt && i < n) ? Tg[i * pr + (size_t)(c0 + kk) * pc] : TF(0);
       }
   };
-  if (stg) fetch(FWD ? 0 : ngr - 1);
+  if (STG) fetch(FWD ? 0 : ngr - 1);
   for (int gi = 0; gi < ngr; ++gi) {
     const int g = FWD ? gi : ngr - 1 - gi;
     const int c0 = g * scol, scnt = min(scol, n - c0);
     lptr<const TF> P;  // the stage, or the triangle itself when it is held in LDS
     size_t qr, qc;     // op(T)(i, c0 + k) = P[i*qr + k*qc]
-    if (stg) {
+    if (STG) {
 #pragma unroll
       for (int kk = 0; kk < SPF; ++kk)
 #pragma unroll
@@ -533,12 +535,19 @@ __device__ __forceinline__ void w_trsv_dir(const TF* T, int ldt, int n, bool tra
     }
     __builtin_amdgcn_wave_barrier();
   }
+  return v;
 }
+
 template <int NRC, class TF>
 __device__ __forceinline__ void w_trsv(const TF* T, int ldt, int n, bool lower, bool trans, bool unit,
                                        WVec<NRC>& v, int nr, int lane, TF* stg, int scol) {
-  if (lower != trans) w_trsv_dir<true, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
-  else w_trsv_dir<false, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
+  if (stg) {
+    if (lower != trans) v = w_trsv_dir<true, true, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
+    else v = w_trsv_dir<false, true, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
+  } else {
+    if (lower != trans) v = w_trsv_dir<true, false, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
+    else v = w_trsv_dir<false, false, NRC, TF>(T, ldt, n, trans, unit, v, nr, lane, stg, scol);
+  }
 }
 
 // routed factor: 0 LU (M = L\U, perm), 1 Cholesky (M = L), 2 triangular (T = A as given)
