@@ -318,6 +318,119 @@ def bench_mixed(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_paper(args):
+    """The paper's own comparisons on the GPU (Section III, Tables I-IV): each system solved one call at a
+    time through ada_solve, timed per call with events on the solve's stream (device) and on the host
+    clock around call + synchronize (wall).
+
+    * small: the five seeded systems of the small configuration (dense, SPD, upper-triangular n=256,
+      banded n=1024 kl=ku=2, ill-conditioned n=64 that must take the SVD fallback), --paper-reps calls each;
+    * compare: adaptive against the plain LU route (force_general: LU with partial pivoting, its solve and
+      the condition estimate, the 'standard' solver of Section II-D) on banded (kl=ku=2, five diagonals),
+      lower-triangular (off-diagonals scaled by 1/sqrt(n), so that the triangular route is the one taken),
+      SPD and dense systems at n in {100, 250, 500, 1000}: a pool of eight seeded systems per cell,
+      --paper-reps calls cycling through it, p50/p99 per call and the speedup of the medians;
+    * lower_literal: the lower-triangular n=8192 system with N(0,1) off-diagonals as the large
+      configuration states it; its condition number grows exponentially with n, so the rule of Section
+      II-E sends it to the SVD fallback (one call, --no-literal skips it)."""
+    import torch
+    from paper_2007_11208_amd import ada
+    dev = torch.device("cuda:0")
+    ctx = ada.context(0)
+    stream = torch.cuda.current_stream(dev)
+    reps = args.paper_reps
+
+    def timed_calls(systems, k_calls, **kw):
+        dev_ms, wall_ms, res = [], [], []
+        work = None
+        outs = [torch.empty((b.shape[1], b.shape[0]), dtype=torch.float64, device=dev).t() for _, b in systems]
+        for (A, B), X in zip(systems, outs):  # warm-up: one call per system
+            ada.solve(A, B, out=X, ctx=ctx, **kw)
+        torch.cuda.synchronize()
+        for k in range(k_calls):
+            A, B = systems[k % len(systems)]
+            X = outs[k % len(systems)]
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            _, r = ada.solve(A, B, out=X, ctx=ctx, **kw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall_ms.append((time.perf_counter() - t0) * 1e3)
+            dev_ms.append(e0.elapsed_time(e1))
+            if k < len(systems):
+                res.append(r)
+        return dev_ms, wall_ms, res
+
+    def stats(v):
+        return {"p50": round(pct(v, 50), 4), "p99": round(pct(v, 99), 4), "mean": round(float(np.mean(v)), 4)}
+
+    to_dev = lambda a: torch.from_numpy(np.asfortranarray(a)).to(dev)
+    out = {"metric": METRIC, "workload": "paper", "n_gpus": 1, "data": "synthetic", "dtype": "f64", "reps": reps}
+    # small configuration
+    small = {}
+    for name in ("a_dense", "b_spd", "c_upper", "d_banded", "e_illcond"):
+        a, b = W.small_case(name)
+        sysd = [(to_dev(a), to_dev(b))]
+        dms, wms, res = timed_calls(sysd, reps)
+        r = res[0]
+        if r.status == 0 and not (r.berr <= BERR_BAR):
+            print(f"{name}: backward error {r.berr} above the bar", file=sys.stderr)
+            sys.exit(1)
+        small[name] = {"n": a.shape[0], "class": r.cls, "route": r.route, "rcond": r.rcond, "rank": r.rank,
+                       "berr": r.berr, "device_ms": stats(dms), "wall_ms": stats(wms)}
+        print(f"small {name}: {r.cls}/{r.route} device p50 {pct(dms, 50):.3f} ms p99 {pct(dms, 99):.3f} ms",
+              file=sys.stderr, flush=True)
+    out["small"] = small
+    # adaptive against the plain LU route
+    gens = {"banded": lambda n, g: W.banded_dense(n, 2, 2, g),
+            "lower_triangular": lambda n, g: W.triangular(n, g, upper=False, scaled=True),
+            "spd": W.spd, "dense": W.dense_general}
+    comp = []
+    for cname, gen in gens.items():
+        for n in (100, 250, 500, 1000):
+            g = np.random.default_rng(7000 + n)
+            pool = []
+            for _ in range(8):
+                a = gen(n, g)
+                x = W.x_true(n, 1, g)
+                pool.append((to_dev(a), to_dev(W.rhs_for(a, x))))
+            ad, aw, ar = timed_calls(pool, reps)
+            gd, gw, gr = timed_calls(pool, reps, force_general=True)
+            worst = max(r.berr for r in ar + gr)
+            if not (worst <= BERR_BAR):
+                print(f"{cname} n={n}: backward error {worst} above the bar", file=sys.stderr)
+                sys.exit(1)
+            row = {"class": cname, "n": n, "route": ar[0].route, "general_route": gr[0].route,
+                   "adaptive_device_ms": stats(ad), "general_device_ms": stats(gd),
+                   "adaptive_wall_ms": stats(aw), "general_wall_ms": stats(gw),
+                   "speedup_p50_device": round(pct(gd, 50) / pct(ad, 50), 3),
+                   "speedup_p50_wall": round(pct(gw, 50) / pct(aw, 50), 3)}
+            comp.append(row)
+            print(f"compare {cname} n={n}: {row['route']} {pct(ad, 50):.3f} ms vs lu {pct(gd, 50):.3f} ms "
+                  f"-> x{row['speedup_p50_device']}", file=sys.stderr, flush=True)
+    out["compare"] = comp
+    # the literal lower-triangular system of the large configuration
+    if not args.no_literal:
+        a, b, _ = W.large_case("lower")
+        A, B = to_dev(a), to_dev(b)
+        del a
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, r = ada.solve(A, B, ctx=ctx)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["lower_literal"] = {"n": 8192, "class": r.cls, "route": r.route, "fallback": r.fallback,
+                                "rcond": r.rcond, "rank": r.rank, "sweeps": r.sweeps, "berr": r.berr,
+                                "status": r.status, "device_ms": round(e0.elapsed_time(e1), 3),
+                                "wall_ms": round((time.perf_counter() - t0) * 1e3, 3)}
+        print(f"lower_literal: {r.cls}/{r.route} rcond {r.rcond:.3e} rank {r.rank} sweeps {r.sweeps} "
+              f"{out['lower_literal']['device_ms']:.1f} ms", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args):
     """Poisson request stream into the solve server: requests draw a system from a seeded pool
     (sizes log-uniform in [16, 4096], the batched class mix); a fraction reuse one of the
@@ -512,11 +625,14 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None, help="right-hand sides (default 1; 16 for --workload mixed)")
     ap.add_argument("--systems", default=",".join(SYSTEMS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="single", choices=("single", "batched", "mixed", "serving"),
+    ap.add_argument("--workload", default="single", choices=("single", "batched", "mixed", "serving", "paper"),
                     help="single: the five large systems; batched: many small systems in one launch per step")
     ap.add_argument("--count", type=int, default=20000, help="systems per step of the batched workload")
     ap.add_argument("--n-range", default="8,256", help="batched workload: smallest and largest order")
     ap.add_argument("--no-tune", action="store_true", help="batched workload: keep the default launch shape")
+    ap.add_argument("--paper-reps", type=int, default=1000, help="paper workload: timed calls per system or cell")
+    ap.add_argument("--no-literal", action="store_true",
+                    help="paper workload: skip the literal lower-triangular n=8192 system (SVD fallback)")
     ap.add_argument("--ext-steps", type=int, default=3,
                     help="single workload: also time the Section V extension routes (LDL^T, tridiagonal) "
                          "against the paper's routes on systems of the same shapes")
@@ -564,6 +680,8 @@ def main():
         return bench_mixed(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "paper":
+        return bench_paper(args)
     names = [s for s in args.systems.split(",") if s]
     cases = []
     host_cases = []  # the same inputs on the host, for the oracle after the timed region

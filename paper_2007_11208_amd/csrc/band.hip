@@ -82,49 +82,58 @@ hipError_t launch_band_to_dense(int n, int kl_in, int ku_in, const double* AB, i
   return hipGetLastError();
 }
 
-// ||A||_1 (max column sum) and ||A||_inf (max row sum) of the band before factorisation
+// ||A||_1 (max column sum) and ||A||_inf (max row sum) of the band before factorisation. A workgroup
+// copies the band storage of its BNT columns and the kl + ku columns around them into LDS (one contiguous
+// stretch of the layout, read coalesced), then threads 0..BNT-1 sum columns and BNT..2BNT-1 sum rows from
+// LDS, each in increasing row / column order.
+constexpr int BNT = 128;
 __global__ __launch_bounds__(256) void k_band_norms(int n, int kl, int ku, const double* __restrict__ GB, int ldgb,
                                                     DevRec* rec) {
-  const int kd = kl + ku;
+  extern __shared__ double tile[];  // columns lo .. hi-1 of the band storage
+  const int kd = kl + ku, t = threadIdx.x;
+  const int c0 = blockIdx.x * BNT;
+  const int lo = max(0, c0 - kl), hi = min(n, c0 + BNT + ku);
+  const int cnt = (hi - lo) * ldgb;
+  const double* src = GB + (size_t)lo * ldgb;
+  for (int e = t; e < cnt; e += 256) tile[e] = src[e];
+  __syncthreads();
   double c1 = 0.0, ri = 0.0;
-  // fixed-length predicated loops (kl + ku <= 31): the loads of a column or row are independent and
-  // issue together; the sums still run in increasing row / column order
-  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
-    double v[32];
-#pragma unroll
-    for (int d = 0; d < 32; ++d) {
-      const int i = x - ku + d;
-      v[d] = (d <= kd && i >= 0 && i < n) ? fabs(GB[(size_t)(kd + i - x) + (size_t)x * ldgb]) : 0.0;
+  if (t < BNT) {
+    const int x = c0 + t;  // column x: rows x - ku .. x + kl
+    if (x < n) {
+      double s = 0.0;
+      for (int d = 0; d <= kd; ++d) {
+        const int i = x - ku + d;
+        if (i >= 0 && i < n) s += fabs(tile[(x - lo) * ldgb + kd + i - x]);
+      }
+      c1 = s;
     }
-    double s = 0.0;
-#pragma unroll
-    for (int d = 0; d < 32; ++d)
-      if (d <= kd) s += v[d];
-    c1 = fmax(c1, s);
-#pragma unroll
-    for (int d = 0; d < 32; ++d) {
-      const int j = x - kl + d;
-      v[d] = (d <= kd && j >= 0 && j < n) ? fabs(GB[(size_t)(kd + x - j) + (size_t)j * ldgb]) : 0.0;
+  } else {
+    const int x = c0 + t - BNT;  // row x: columns x - kl .. x + ku
+    if (x < n) {
+      double r = 0.0;
+      for (int d = 0; d <= kd; ++d) {
+        const int j = x - kl + d;
+        if (j >= 0 && j < n) r += fabs(tile[(j - lo) * ldgb + kd + x - j]);
+      }
+      ri = r;
     }
-    double r = 0.0;
-#pragma unroll
-    for (int d = 0; d < 32; ++d)
-      if (d <= kd) r += v[d];
-    ri = fmax(ri, r);
   }
   c1 = wave_max(c1);
   ri = wave_max(ri);
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(reinterpret_cast<unsigned long long*>(&rec->anorm1), dbits(c1));
-    atomicMax(reinterpret_cast<unsigned long long*>(&rec->anorm_inf), dbits(ri));
+  if ((t & 63) == 0) {
+    if (c1 > 0.0) atomicMax(reinterpret_cast<unsigned long long*>(&rec->anorm1), dbits(c1));
+    if (ri > 0.0) atomicMax(reinterpret_cast<unsigned long long*>(&rec->anorm_inf), dbits(ri));
   }
 }
 
 hipError_t launch_band_norms(int n, int kl, int ku, const double* GB, int ldgb, DevRec* rec, hipStream_t st) {
-  if (kl + ku > 31) return hipErrorInvalidValue;  // the sums cover at most 32 entries
-  int blocks = (n + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_band_norms, dim3(blocks), dim3(256), 0, st, n, kl, ku, GB, ldgb, rec);
+  if (kl + ku > 31 || ldgb < 2 * kl + ku + 1 || ldgb > 63) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(BNT + kl + ku) * ldgb * sizeof(double);  // <= 159 * 63 * 8 bytes
+  static size_t done = 0;
+  hipError_t e = ensure_lds((const void*)k_band_norms, lds, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_norms, dim3((n + BNT - 1) / BNT), dim3(256), lds, st, n, kl, ku, GB, ldgb, rec);
   return hipGetLastError();
 }
 

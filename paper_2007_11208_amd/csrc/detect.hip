@@ -283,20 +283,34 @@ hipError_t launch_anorm(int n, const double* col_total, const double* col_sym, c
   return hipGetLastError();
 }
 
-// Band-layout input: the scan of Section II-A restricted to the stored rows
-// (everything outside the stored band is zero by definition of the layout).
-__global__ void k_detect_band(int n, int kl_in, int ku_in, const double* __restrict__ AB, int ldab, DevRec* rec) {
+// Band-layout input: the scan of Section II-A restricted to the stored rows (everything outside the
+// stored band is zero by definition of the layout). The storage is read as one flat array, coalesced:
+// element e is row r = e mod ldab of column j = e / ldab, entry (j + r - ku_in, j) of A (rows r >
+// kl_in + ku_in, and entries outside the matrix, are not part of it). Each thread keeps (j, r) of its
+// element and advances them by the grid stride.
+__global__ __launch_bounds__(256) void k_detect_band(int n, int kl_in, int ku_in, const double* __restrict__ AB,
+                                                     int ldab, DevRec* rec) {
   int kl_c = 0, ku_c = 0, nonfin = 0;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    const double* col = AB + (size_t)j * ldab;
-    const int i0 = max(0, j - ku_in), i1 = min(n - 1, j + kl_in);
-    for (int i = i0; i <= i1; ++i) {
-      const double v = col[ku_in + i - j];
+  const long long total = (long long)n * ldab;
+  const long long e0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int sj = (int)(stride / ldab), sr = (int)(stride % ldab);
+  int j = (int)(e0 / ldab), r = (int)(e0 % ldab);
+  for (long long e = e0; e < total; e += stride) {
+    const int i = j + r - ku_in;
+    if (r <= kl_in + ku_in && i >= 0 && i < n) {
+      const double v = AB[e];
       nonfin |= !isfinite(v);
       if (v != 0.0) {
         if (i < j) ku_c = max(ku_c, j - i);
         if (i > j) kl_c = max(kl_c, i - j);
       }
+    }
+    j += sj;
+    r += sr;
+    if (r >= ldab) {
+      r -= ldab;
+      ++j;
     }
   }
   kl_c = wave_max_int(kl_c);
@@ -311,9 +325,11 @@ __global__ void k_detect_band(int n, int kl_in, int ku_in, const double* __restr
 
 hipError_t launch_detect_band(int n, int kl_in, int ku_in, const double* AB, int ldab, DevRec* rec,
                               hipStream_t st) {
-  int blocks = (n + 255) / 256;
+  const long long total = (long long)n * ldab;
+  long long blocks = (total + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_detect_band, dim3(blocks), dim3(256), 0, st, n, kl_in, ku_in, AB, ldab, rec);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_detect_band, dim3((unsigned)blocks), dim3(256), 0, st, n, kl_in, ku_in, AB, ldab, rec);
   return hipGetLastError();
 }
 
