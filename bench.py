@@ -563,8 +563,8 @@ def bench_serving(args):
 
 def bench_extensions(args, cases, ctx, dev):
     """The routes the paper names as future work, beside the paper's routes on the same systems:
-    the symmetric-indefinite system (Cholesky fails; LU vs LDL^T), a plain symmetric n=4096 system
-    (LU vs LDL^T) and a tridiagonal n=1e6 band-layout system (band LU vs the tridiagonal route)."""
+    the symmetric-indefinite system (Cholesky fails; LU vs LDL^T) and a plain symmetric n=4096 system
+    (LU vs LDL^T)."""
     import torch
     from paper_2007_11208_amd import ada
     out = {}
@@ -601,18 +601,6 @@ def bench_extensions(args, cases, ctx, dev):
         for label, exts in (("plain_sym_n4096_paper", ()), ("plain_sym_n4096_ldlt", ("sym",))):
             timed(label, M, B, X, work, exts)
         del M
-    nt = 1_000_000
-    g = torch.Generator(device=dev).manual_seed(4343)
-    ab = torch.randn((nt, 3), generator=g, dtype=torch.float64, device=dev).t()  # (3, n) column-major
-    ab[1] += 3.0 * torch.sign(ab[1])  # well conditioned; interchanges still occur where |dl| > |d|
-    ab[0, 0] = 0.0
-    ab[2, nt - 1] = 0.0
-    bt = torch.randn((args.nrhs, nt), generator=g, dtype=torch.float64, device=dev).t()
-    xt = torch.empty_like(bt)
-    o = ada.make_opts(layout=ada.LAYOUT_BAND, kl_in=1, ku_in=1)
-    wt = torch.empty(ada.workspace_size(nt, args.nrhs, o), dtype=torch.uint8, device=dev)
-    for label, exts in (("tridiag_n1e6_paper", ()), ("tridiag_n1e6_ext", ("tridiag",))):
-        timed(label, ab, bt, xt, wt, exts, layout="band", kl_in=1, ku_in=1)
     torch.cuda.synchronize()
     return out
 
@@ -634,7 +622,7 @@ def main():
     ap.add_argument("--no-literal", action="store_true",
                     help="paper workload: skip the literal lower-triangular n=8192 system (SVD fallback)")
     ap.add_argument("--ext-steps", type=int, default=3,
-                    help="single workload: also time the Section V extension routes (LDL^T, tridiagonal) "
+                    help="single workload: also time the Section V extension route (LDL^T) "
                          "against the paper's routes on systems of the same shapes")
     ap.add_argument("--concurrent-steps", type=int, default=3,
                     help="single workload: also time this many steps with the systems solved concurrently "

@@ -59,17 +59,16 @@ enum { ADA_CLASS_GENERAL = 0, ADA_CLASS_BANDED = 1, ADA_CLASS_TRI_UPPER = 2, ADA
        ADA_CLASS_SYM = 5 /* only with ADA_EXT_SYM: equal to its transpose, fails the Fig. 4 test */ };
 /* solver whose x is returned */
 enum { ADA_ROUTE_NONE = 0, ADA_ROUTE_BAND_LU = 1, ADA_ROUTE_TRI = 2, ADA_ROUTE_CHOL = 3, ADA_ROUTE_LU = 4,
-       ADA_ROUTE_SVD = 5, ADA_ROUTE_LDLT = 6, ADA_ROUTE_TRIDIAG = 7 };
-/* Routes the paper's conclusion (Section V) names as future work; off by default, so that the
+       ADA_ROUTE_SVD = 5, ADA_ROUTE_LDLT = 6 };
+/* A route the paper's conclusion (Section V) names as future work; off by default, so that the
    classes and routes are the paper's. Bits of ada_opts.extensions:
    ADA_EXT_SYM: a dense matrix exactly equal to its transpose that fails the sympd test of Fig. 4, or
      whose Cholesky factorisation fails, is solved by LDL^T with Bunch-Kaufman pivoting
      (P A P^T = L D L^T, D of 1x1 and 2x2 blocks) instead of LU; its condition estimate and the
-     fallback rule are those of every route (an exactly singular D block is a solver failure);
-   ADA_EXT_TRIDIAG: a banded matrix with kl = ku = 1 is solved by tridiagonal LU with partial
-     pivoting instead of the general band LU.
+     fallback rule are those of every route (an exactly singular D block is a solver failure).
+   Tridiagonal matrices (the other case Section V names) take the band route at kl = ku = 1.
    ada_solve only (ada_solve_batched returns ADA_ERR_ARG when any bit is set). */
-enum { ADA_EXT_SYM = 1, ADA_EXT_TRIDIAG = 2 };
+enum { ADA_EXT_SYM = 1 };
 /* arithmetic of the LU / Cholesky factorisation. FP64: FP64 throughout. FP32_IR, BF16_IR: a
    factorisation in lower precision (ada_solve: the trailing-matrix updates take FP32 or BF16 operands
    with FP32 accumulation, panels and pivot search stay FP64; ada_solve_batched: FP32_IR only, the

@@ -19,17 +19,17 @@ LIB_PATH = os.path.join(HERE, "libada.so")
 OK, ERR_ARG, ERR_NONFINITE, ERR_SINGULAR, ERR_NOMEM, ERR_HIP, ERR_FALLBACK_INFEASIBLE = 0, -1, -2, -3, -4, -5, -6
 PENDING = 1
 CLASS_GENERAL, CLASS_BANDED, CLASS_TRI_UPPER, CLASS_TRI_LOWER, CLASS_SYMPD, CLASS_SYM = 0, 1, 2, 3, 4, 5
-ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD, ROUTE_LDLT, ROUTE_TRIDIAG = range(8)
+ROUTE_NONE, ROUTE_BAND_LU, ROUTE_TRI, ROUTE_CHOL, ROUTE_LU, ROUTE_SVD, ROUTE_LDLT = range(7)
 # routes the paper names as future work (Section V), off by default: bits of Opts.extensions
-EXT_SYM, EXT_TRIDIAG = 1, 2
-EXTENSIONS = {"sym": EXT_SYM, "tridiag": EXT_TRIDIAG}
+EXT_SYM = 1
+EXTENSIONS = {"sym": EXT_SYM}
 LAYOUT_DENSE, LAYOUT_BAND = 0, 1
 PREC_FP64, PREC_FP32_IR, PREC_BF16_IR = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR, "bf16_ir": PREC_BF16_IR}
 # kernel families of the instrumentation (ADA_KF_*)
 KERNEL_FAMILIES = ("gemm", "panel", "laswp", "trsm_block", "potrf", "trsv", "gbtrf", "gbtrs", "detect", "jacobi")
 CLASS_NAMES = {0: "general", 1: "banded", 2: "tri_upper", 3: "tri_lower", 4: "sympd", 5: "sym"}
-ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd", 6: "ldlt", 7: "tridiag"}
+ROUTE_NAMES = {0: "none", 1: "band_lu", 2: "tri", 3: "chol", 4: "lu", 5: "svd", 6: "ldlt"}
 
 
 class Opts(ctypes.Structure):
@@ -302,8 +302,8 @@ def solve(A, B, *, no_approx=False, rcond_threshold=-1.0, force_general=False, w
           extensions=()):
     """Adaptive solve of A X = B on the GPU.
 
-    extensions: any of "sym" (plain symmetric matrices by Bunch-Kaufman LDL^T) and "tridiag"
-    (tridiagonal matrices by tridiagonal LU), the routes the paper names as future work.
+    extensions: "sym" (plain symmetric matrices by Bunch-Kaufman LDL^T), the route the paper names
+    as future work.
 
     A: (n, n) float64 CUDA tensor, or for layout="band" the (kl_in+ku_in+1, n)
     LAPACK band storage (A[ku_in+i-j, j] = A(i, j)). B: (n,) or (n, nrhs).

@@ -1163,10 +1163,6 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
     else
       HIPCHK(launch_band_pack_dense(n, bkl, bku, Ad, ldad, G0, ldgb, st));
     HIPCHK(launch_band_norms(n, bkl, bku, G0, ldgb, s.rec, st));
-    // tridiagonal extension: LU with partial pivoting of the three diagonals; at kl = ku = 1 the band
-    // kernels run exactly the tridiagonal eliminations (pivot between rows i and i+1, one fill
-    // diagonal), so the route shares them
-    if ((o.extensions & ADA_EXT_TRIDIAG) && bkl == 1 && bku == 1) route = ADA_ROUTE_TRIDIAG;
     TRY(route_band(s, G0, W, bkl, bku, B, ldb, X, ldx));
   }
   // backward error of the routed x (also flags a non-finite x)
@@ -1236,7 +1232,7 @@ int ada_solve(ada_ctx ctx, int n, int nrhs, const double* A, int lda, const doub
   if (o.layout != ADA_LAYOUT_DENSE && o.layout != ADA_LAYOUT_BAND) return fail(ADA_ERR_ARG, "unknown layout");
   if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR && o.precision != ADA_PREC_BF16_IR)
     return fail(ADA_ERR_ARG, "unknown precision");
-  if (o.extensions & ~(ADA_EXT_SYM | ADA_EXT_TRIDIAG)) return fail(ADA_ERR_ARG, "unknown extension bits");
+  if (o.extensions & ~ADA_EXT_SYM) return fail(ADA_ERR_ARG, "unknown extension bits");
   if (n < 1 || nrhs < 1) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
   if (o.layout == ADA_LAYOUT_DENSE && lda < n) return fail(ADA_ERR_ARG, "lda < n");
   if (ldb < n || ldx < n) return fail(ADA_ERR_ARG, "ldb or ldx < n");
@@ -1255,7 +1251,7 @@ int ada_solve_noalloc(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
   if (o.layout != ADA_LAYOUT_DENSE && o.layout != ADA_LAYOUT_BAND) return fail(ADA_ERR_ARG, "unknown layout");
   if (o.precision != ADA_PREC_FP64 && o.precision != ADA_PREC_FP32_IR && o.precision != ADA_PREC_BF16_IR)
     return fail(ADA_ERR_ARG, "unknown precision");
-  if (o.extensions & ~(ADA_EXT_SYM | ADA_EXT_TRIDIAG)) return fail(ADA_ERR_ARG, "unknown extension bits");
+  if (o.extensions & ~ADA_EXT_SYM) return fail(ADA_ERR_ARG, "unknown extension bits");
   if (n < 1 || nrhs < 1) return fail(ADA_ERR_ARG, "n and nrhs must be >= 1");
   if (o.layout == ADA_LAYOUT_DENSE && lda < n) return fail(ADA_ERR_ARG, "lda < n");
   if (ldb < n || ldx < n) return fail(ADA_ERR_ARG, "ldb or ldx < n");
@@ -1350,7 +1346,6 @@ int solve_factored(ada_ctx ctx, int n, int nrhs, int plan_nrhs, const double* A,
       TRY(s.trsm(A, lda, orig.cls == ADA_CLASS_TRI_LOWER, false, false, X, ldx, nrhs, stop, 0));
       break;
     case ADA_ROUTE_BAND_LU:
-    case ADA_ROUTE_TRIDIAG:
       HIPCHK(launch_copy(n, nrhs, B, ldb, X, ldx, st));
       TRY(band_solve(s, W, orig.kl, orig.ku, false, X, ldx, nrhs, s.at<double>(p.T), n, stop, 0));
       break;

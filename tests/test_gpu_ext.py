@@ -1,6 +1,6 @@
 """GPU parity of the routes the paper names as future work (Section V), selected with the
-extension option: plain symmetric matrices by Bunch-Kaufman LDL^T, tridiagonal matrices by
-tridiagonal LU. The oracle runs the same option.
+extension option: plain symmetric matrices by Bunch-Kaufman LDL^T. The oracle runs the same option.
+Tridiagonal matrices take the band route.
 
 Bars: class, band widths, route, Cholesky failure, fallback reason and info exact; rcond within
 a factor 2 of the oracle's (same estimator; the GPU's blocked LDL^T sums in another order and
@@ -136,16 +136,33 @@ def tridiag_band(n, rng):
 
 
 @pytest.mark.parametrize("n", [12, 13, 100, 5000, 200_000])
-def test_tridiagonal_route(ada, n):
+def test_tridiagonal_takes_the_band_route(ada, n):
+    """Tridiagonal matrices (kl = ku = 1) have no route of their own: the band LU, as the oracle."""
     rng = np.random.default_rng(600 + n)
     ab = tridiag_band(n, rng)
     b = np.asfortranarray(rng.standard_normal((n, 2)))
-    r = check(ada, ab, b, ("tridiag",), oracle.EXT_TRIDIAG, layout="band", kl_in=1, ku_in=1)
-    assert r.route == "tridiag"
+    r = check(ada, ab, b, (), 0, layout="band", kl_in=1, ku_in=1)
+    assert r.route == "band_lu"
     if n <= 5000:
         dense = np.diag(ab[1]) + np.diag(ab[2, :-1], -1) + np.diag(ab[0, 1:], 1)
-        r2 = check(ada, np.asfortranarray(dense), b, ("tridiag",), oracle.EXT_TRIDIAG)
-        assert r2.route == ("tridiag" if r2.cls == "banded" else "lu")
+        r2 = check(ada, np.asfortranarray(dense), b, (), 0)
+        assert r2.route == ("band_lu" if r2.cls == "banded" else "lu")
+
+
+def test_unknown_extension_bits_are_rejected(ada):
+    import torch
+    A = torch.eye(4, dtype=torch.float64, device="cuda:0")
+    B = torch.ones((4, 1), dtype=torch.float64, device="cuda:0")
+    o = ada.make_opts()
+    o.extensions = 2
+    X = torch.empty_like(B)
+    ws = ada.workspace_size(4, 1, ada.make_opts())
+    work = torch.empty(ws, dtype=torch.uint8, device="cuda:0")
+    res = ada.Result()
+    import ctypes
+    rc = ada.lib().ada_solve(ada.context(0).handle, 4, 1, A.data_ptr(), 4, B.data_ptr(), 4, X.data_ptr(), 4,
+                             work.data_ptr(), work.numel(), ctypes.byref(o), ctypes.byref(res), None)
+    assert rc == ada.ERR_ARG and "unknown extension bits" in ada.last_error()
 
 
 def test_batched_rejects_extensions(ada):

@@ -91,7 +91,7 @@ def test_extension_option_and_footprint():
     L = _lib()
     assert ada.make_opts().extensions == 0
     assert ada.make_opts(extensions=("sym",)).extensions == ada.EXT_SYM
-    assert ada.make_opts(extensions=("sym", "tridiag")).extensions == ada.EXT_SYM | ada.EXT_TRIDIAG
+    assert ada.make_opts(extensions=("sym",)).extensions == ada.EXT_SYM
     with pytest.raises(ValueError):
         ada.make_opts(extensions=("ldlt",))
     assert ctypes.sizeof(ada.Opts) == ada.make_opts().struct_size
