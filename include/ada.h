@@ -73,10 +73,13 @@ enum { ADA_EXT_SYM = 1 };
    factorisation in lower precision (ada_solve: the trailing-matrix updates take FP32 or BF16 operands
    with FP32 accumulation, panels and pivot search stay FP64; ada_solve_batched: FP32_IR only, the
    whole factorisation in FP32), then FP64 iterative refinement (FP64 residuals and corrections) until
-   the backward error reaches sqrt(n)*eps; when it stalls, grows or needs more than 30 steps, or when
-   the condition estimate of the low-precision factors is below 1e-9 (FP32) or 1e-4 (BF16), the
-   system is solved again by the FP64 route (the result's refine_iters is then negative). Triangular,
-   banded and SVD routes always run in FP64. */
+   the backward error reaches sqrt(n)*eps. FP32: the correction is the solve with the FP32 factors;
+   BF16: the correction equation is solved by GMRES (FP64 vectors, each right-hand side with its own
+   Krylov basis of up to 50 vectors) preconditioned by the BF16 factors. When the refinement stalls,
+   grows or needs more than 30 steps, or when the condition estimate of the low-precision factors is
+   below 1e-9, the system is solved again by the FP64 route (the result's refine_iters is then
+   negative; otherwise the number of refinement steps). Triangular, banded and SVD routes always run
+   in FP64. */
 enum { ADA_PREC_FP64 = 0, ADA_PREC_FP32_IR = 1, ADA_PREC_BF16_IR = 2 };
 /* input layout */
 enum { ADA_LAYOUT_DENSE = 0, ADA_LAYOUT_BAND = 1 };

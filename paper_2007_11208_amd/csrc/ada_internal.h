@@ -306,6 +306,14 @@ hipError_t launch_est_step(int n, int slot_type, int tag, const double* result, 
 size_t est_part_bytes();
 hipError_t launch_finalize_rcond(DevRec* rec, hipStream_t st);
 
+// column-wise vectors of the GMRES correction solve (gmres.hip): V_i = V + i * vstride, n x nrhs, ld n
+hipError_t launch_col_dots(int n, int nrhs, int kk, const double* V, size_t vstride, const double* W, int ldw,
+                           double* h, int ldh, hipStream_t st);  // h[i + j ldh] = V_i(:,j) . W(:,j), i < kk
+hipError_t launch_col_axpy(int n, int nrhs, int kk, const double* V, size_t vstride, const double* h, int ldh,
+                           double sign, double* W, int ldw, hipStream_t st);  // W(:,j) += sign sum_i h_ij V_i(:,j)
+hipError_t launch_col_normalize(int n, int nrhs, const double* S, int lds, const double* nrm2, int ldn, double sign,
+                                double* D, int ldd, hipStream_t st);  // D(:,j) = sign S(:,j) / sqrt(nrm2_j)
+
 // residual and backward error
 // X += D (n x nrhs)
 hipError_t launch_add_to(int n, int nrhs, const double* D, int ldd, double* X, int ldx, hipStream_t st);

@@ -40,12 +40,13 @@ constexpr int kBandKdMax = 31;    // band kernels: kl + ku
 constexpr int kBandDenseMax = 4096;  // band-layout input expanded to dense when needed (not banded / SVD)
 constexpr int kJacobiSmall = 256;    // one-workgroup Jacobi up to this n
 constexpr int kBandChunkMin = 2 * LC;  // band solves parallel over the rows from this n on
+constexpr int kGmresM = 50;             // Krylov dimension of one GMRES correction solve
 
 struct Plan {
   size_t total = 0;
   // offsets (bytes)
   size_t rec, pcol, prow, cld, rld, diag, ctot, csym, rtot, W, V, ipiv, perm, flags, ev, et, exi, recs,
-      slot_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec, estpart, Q, tau;
+      slot_rows, moves, R, P, percol, T, sigma, Adense, bsc, gb0, gbspec, estpart, Q, tau, gmV, gmW, gmH;
   size_t bsc_doubles, gbspec_doubles;
   int n, nrhs, ldw, T64, nflags;
   bool dense, band, band_dense;
@@ -130,6 +131,13 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     p.slot_rows = take(cur, (size_t)2 * 64 * 128 * 8);
     p.moves = take(cur, (1 + 2 * 256) * 4);
     if (p.band) p.Adense = take(cur, N * N * 8);  // dense expansion of band-layout input
+    if (o.precision == ADA_PREC_BF16_IR) {
+      // GMRES correction solves: the Krylov bases of every right-hand side, the work vectors, the
+      // Arnoldi coefficients (two Gram-Schmidt passes and the norm) and the combination weights
+      p.gmV = take(cur, (size_t)(kGmresM + 1) * N * nrhs * 8);
+      p.gmW = take(cur, N * nrhs * 8);
+      p.gmH = take(cur, (size_t)(3 * (kGmresM + 2)) * nrhs * 8);
+    }
   }
   p.total = cur + 256;
   return true;
@@ -612,8 +620,9 @@ int backward_error_dense(Solve& s, const double* A, int lda, const double* B, in
 }
 
 constexpr int kMaxRefine = 30;  // refinement steps at most (as LAPACK's mixed-precision drivers)
-// low-precision factors with a smaller rcond estimate are not refined (kappa_1 * u > 50; BF16: u = 2^-8)
-constexpr double kRcondRefine32 = 1e-9, kRcondRefine16 = 1e-4;
+// low-precision factors with a smaller rcond estimate are not refined (kappa_1 * u_FP32 > 50; the BF16
+// factors are refined by GMRES, whose reach does not end at kappa_1 * u_BF16 = 1)
+constexpr double kRcondRefine = 1e-9;
 
 // FP64 iterative refinement of X with the factors in W (chol: L of the Cholesky route; else the LU
 // route's LU and row permutation): r = B - A X, stop when the backward error of every column is at
@@ -650,6 +659,135 @@ int refine(Solve& s, bool chol, const double* A, int lda, const double* B, int l
       TRY(s.trsm(W, ldw, false, false, false, T, n, nrhs, stop, 0));
       HIPCHK(launch_add_to(n, nrhs, T, n, X, ldx, s.st));
     }
+  }
+}
+
+// D = M^{-1} S with the low-precision factors in W (the preconditioner of the GMRES correction solves):
+// Cholesky: L L^T; LU: the row permutation, then L (unit) and U
+int precondition(Solve& s, bool chol, const double* S, int lds, double* D) {
+  const int n = s.n, nrhs = s.nrhs, ldw = s.p.ldw;
+  const double* W = s.at<double>(s.p.W);
+  int* stop = &s.rec->stop;
+  if (chol) {
+    HIPCHK(launch_copy(n, nrhs, S, lds, D, n, s.st));
+    TRY(s.trsm(W, ldw, true, false, false, D, n, nrhs, stop, 0));
+    TRY(s.trsm(W, ldw, true, true, false, D, n, nrhs, stop, 0));
+  } else {
+    HIPCHK(launch_gather_rows(n, nrhs, s.at<int>(s.p.perm), S, lds, D, n, stop, 0, s.st));
+    TRY(s.trsm(W, ldw, true, false, true, D, n, nrhs, stop, 0));
+    TRY(s.trsm(W, ldw, false, false, false, D, n, nrhs, stop, 0));
+  }
+  return ADA_OK;
+}
+
+// Iterative refinement whose correction equation A d = r is solved by GMRES preconditioned with the
+// low-precision factors (left preconditioning, M^{-1} A d = M^{-1} r), every right-hand side with its own
+// Krylov basis: Arnoldi with two classical Gram-Schmidt passes, the small least-squares problems by Givens
+// rotations on the host, at most kGmresM steps or until the preconditioned residual of every column has
+// dropped by kGmresTol; x += V y. The outer loop and its stopping rules are those of refine(). This is the
+// refinement of the BF16 factors, whose error is too large for the plain correction x += M^{-1} r.
+constexpr double kGmresTol = 1e-10;
+int refine_gmres(Solve& s, bool chol, const double* A, int lda, const double* B, int ldb, double* X, int ldx,
+                 bool& conv, int& steps) {
+  const int n = s.n, nrhs = s.nrhs, m = kGmresM, ldh = kGmresM + 2;
+  const double tol = std::sqrt((double)n) * DBL_EPSILON;
+  double* R = s.at<double>(s.p.R);
+  double* T = s.at<double>(s.p.T);
+  double* V = s.at<double>(s.p.gmV);
+  double* Wv = s.at<double>(s.p.gmW);
+  double* H1 = s.at<double>(s.p.gmH);       // ldh x nrhs
+  double* H2 = H1 + (size_t)ldh * nrhs;     // ldh x nrhs
+  double* H3 = H2 + (size_t)ldh * nrhs;     // norms, then the weights y
+  const size_t vs = (size_t)n * nrhs;
+  const int cbase = s.counter_idx;  // the synchronisation counters the corrections reuse
+  std::vector<double> h1((size_t)ldh * nrhs), h2((size_t)ldh * nrhs), h3((size_t)ldh * nrhs);
+  std::vector<double> Hh((size_t)(m + 1) * m * nrhs), cs((size_t)m * nrhs), sn((size_t)m * nrhs),
+      g((size_t)(m + 1) * nrhs), beta(nrhs), y((size_t)ldh * nrhs);
+  auto fetch = [&](const double* d, std::vector<double>& hv, size_t cnt) -> int {
+    HIPCHK(hipMemcpyAsync(hv.data(), d, cnt * sizeof(double), hipMemcpyDeviceToHost, s.st));
+    HIPCHK(hipStreamSynchronize(s.st));
+    return ADA_OK;
+  };
+  double prev = INFINITY;
+  conv = false;
+  for (steps = 0;; ++steps) {
+    TRY(backward_error_dense(s, A, lda, B, ldb, X, ldx));
+    TRY(s.sync_read());
+    const double eta = s.ctx->host_rec->berr;
+    if (eta <= tol) {
+      conv = true;
+      return ADA_OK;
+    }
+    if (!(eta <= 0.5 * prev) || steps == kMaxRefine) return ADA_OK;
+    prev = eta;
+    if (s.counter_idx > cbase) {  // the kernels that used them have completed (the stream was synchronised)
+      HIPCHK(hipMemsetAsync(&s.rec->counters[cbase], 0, sizeof(unsigned) * (s.counter_idx - cbase), s.st));
+      s.counter_idx = cbase;
+    }
+    // z0 = M^{-1} r, beta = ||z0||, V_0 = z0 / beta
+    TRY(precondition(s, chol, R, n, T));
+    HIPCHK(launch_col_dots(n, nrhs, 1, T, 0, T, n, H3, 1, s.st));
+    HIPCHK(launch_col_normalize(n, nrhs, T, n, H3, 1, 1.0, V, n, s.st));
+    TRY(fetch(H3, h3, nrhs));
+    for (int j = 0; j < nrhs; ++j) {
+      beta[j] = std::sqrt(h3[j]);
+      g[(size_t)j * (m + 1)] = beta[j];
+      for (int i = 1; i <= m; ++i) g[(size_t)j * (m + 1) + i] = 0.0;
+    }
+    int kd = 0;  // Arnoldi steps taken
+    for (int k = 0; k < m; ++k) {
+      // T = -M^{-1} A V_k (the MFMA update subtracts A V_k from zero)
+      HIPCHK(hipMemsetAsync(Wv, 0, vs * sizeof(double), s.st));
+      HIPCHK(launch_gemm_sub(n, nrhs, n, A, lda, V + (size_t)k * vs, n, false, Wv, n, false, nullptr, s.st, nullptr,
+                             nullptr));
+      TRY(precondition(s, chol, Wv, n, T));
+      // two Gram-Schmidt passes against V_0..V_k (on -w: h = -(H1 + H2)), the norm, V_{k+1} = w / ||w||
+      HIPCHK(launch_col_dots(n, nrhs, k + 1, V, vs, T, n, H1, ldh, s.st));
+      HIPCHK(launch_col_axpy(n, nrhs, k + 1, V, vs, H1, ldh, -1.0, T, n, s.st));
+      HIPCHK(launch_col_dots(n, nrhs, k + 1, V, vs, T, n, H2, ldh, s.st));
+      HIPCHK(launch_col_axpy(n, nrhs, k + 1, V, vs, H2, ldh, -1.0, T, n, s.st));
+      HIPCHK(launch_col_dots(n, nrhs, 1, T, 0, T, n, H3, 1, s.st));
+      HIPCHK(launch_col_normalize(n, nrhs, T, n, H3, 1, -1.0, V + (size_t)(k + 1) * vs, n, s.st));
+      TRY(fetch(H1, h1, (size_t)ldh * nrhs));
+      TRY(fetch(H2, h2, (size_t)ldh * nrhs));
+      TRY(fetch(H3, h3, nrhs));
+      bool all = true;
+      for (int j = 0; j < nrhs; ++j) {
+        double* hc = &Hh[((size_t)j * m + k) * (m + 1)];  // column k of column j's Hessenberg matrix
+        for (int i = 0; i <= k; ++i) hc[i] = -(h1[i + (size_t)j * ldh] + h2[i + (size_t)j * ldh]);
+        hc[k + 1] = std::sqrt(h3[j]);
+        for (int i = 0; i < k; ++i) {  // the earlier rotations
+          const double c = cs[(size_t)j * m + i], sg = sn[(size_t)j * m + i];
+          const double a = hc[i], b = hc[i + 1];
+          hc[i] = c * a + sg * b;
+          hc[i + 1] = -sg * a + c * b;
+        }
+        const double a = hc[k], b = hc[k + 1];
+        const double rr = std::hypot(a, b);
+        const double c = rr > 0.0 ? a / rr : 1.0, sg = rr > 0.0 ? b / rr : 0.0;
+        cs[(size_t)j * m + k] = c;
+        sn[(size_t)j * m + k] = sg;
+        hc[k] = rr;
+        hc[k + 1] = 0.0;
+        double* gj = &g[(size_t)j * (m + 1)];
+        gj[k + 1] = -sg * gj[k];
+        gj[k] = c * gj[k];
+        if (!(std::fabs(gj[k + 1]) <= kGmresTol * beta[j])) all = false;
+      }
+      kd = k + 1;
+      if (all) break;
+    }
+    // y = H^{-1} g (upper triangular after the rotations), x += V y
+    for (int j = 0; j < nrhs; ++j) {
+      for (int i = kd - 1; i >= 0; --i) {
+        double t = g[(size_t)j * (m + 1) + i];
+        for (int l = i + 1; l < kd; ++l) t -= Hh[((size_t)j * m + l) * (m + 1) + i] * y[l + (size_t)j * ldh];
+        const double d = Hh[((size_t)j * m + i) * (m + 1) + i];
+        y[i + (size_t)j * ldh] = d != 0.0 ? t / d : 0.0;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(H3, y.data(), (size_t)ldh * nrhs * sizeof(double), hipMemcpyHostToDevice, s.st));
+    HIPCHK(launch_col_axpy(n, nrhs, kd, V, vs, H3, ldh, 1.0, X, ldx, s.st));
   }
 }
 
@@ -1106,10 +1244,13 @@ static int solve_impl(ada_ctx ctx, int n, int nrhs, const double* A, int lda, co
     if (h.timeout) return fail(ADA_ERR_HIP, "a bounded device wait timed out");
     const bool fact_ok = chol ? h.chol_info == INT_MAX : h.info == INT_MAX;
     const bool refinable =
-        fact_ok && h.rcond >= (o.precision == ADA_PREC_BF16_IR ? kRcondRefine16 : kRcondRefine32);
+        fact_ok && h.rcond >= kRcondRefine;
     bool conv = false;
     int steps = 0;
-    if (refinable) TRY(refine(s, chol, Ad, ldad, B, ldb, X, ldx, conv, steps));
+    if (refinable) {
+      if (o.precision == ADA_PREC_BF16_IR) TRY(refine_gmres(s, chol, Ad, ldad, B, ldb, X, ldx, conv, steps));
+      else TRY(refine(s, chol, Ad, ldad, B, ldb, X, ldx, conv, steps));
+    }
     if (conv) {
       mixed_done = true;
       route = chol ? ADA_ROUTE_CHOL : ADA_ROUTE_LU;

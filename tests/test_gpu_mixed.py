@@ -3,7 +3,8 @@ iterative refinement) against the FP64 oracle.
 
 Bars: class, band widths, route, Cholesky failure and fallback reason exact (the
 decisions are FP64's); refined x has backward error <= sqrt(n) eps (the refinement's
-stopping test; the stated bar for the refined form is 1e-10), and x is within
+stopping test; the stated bar for the refined form is 1e-10; BF16 factors are refined by
+GMRES preconditioned with them), and x is within
 32 n kappa eps |x| of the oracle's; rcond (estimated on the low-precision factors)
 within a factor 2 of the oracle's. A refinement that cannot converge (kappa beyond
 what the operand precision supports) hands the system to the FP64 route: the result
@@ -87,8 +88,24 @@ def test_fp32_refined_kappa_1e5_nrhs16(ada, spd):
 
 
 @pytest.mark.parametrize("spd", [False, True])
-def test_bf16_refined_kappa_1e2(ada, spd):
+def test_bf16_gmres_refined_kappa_1e2(ada, spd):
+    """BF16 factors are too inexact for the plain correction; GMRES preconditioned by them converges."""
     a, b = spectrum_case(768, 1e2, spd, 4, seed=5)
+    r = check(ada, a, b, "bf16_ir")
+    assert r.refine_iters > 0, "GMRES-based refinement of the BF16 factors converges at kappa 1e2"
+
+
+@pytest.mark.parametrize("n,kappa,nrhs", [(1024, 1e3, 16), (333, 1e4, 1)])
+def test_bf16_gmres_refined_dense(ada, n, kappa, nrhs):
+    a, b = spectrum_case(n, kappa, False, nrhs, seed=n + 3)
+    r = check(ada, a, b, "bf16_ir")
+    assert r.refine_iters > 0
+
+
+def test_bf16_kappa_1e5_refined_or_fp64(ada):
+    """At kappa 1e5 (kappa u_BF16 about 400) fifty GMRES steps reduce the preconditioned residual by
+    about 50 only and the refinement stalls: the FP64 route then solves the system, to its bars."""
+    a, b = spectrum_case(1024, 1e5, False, 16, seed=1027)
     r = check(ada, a, b, "bf16_ir")
     assert r.refine_iters != 0
 
