@@ -173,8 +173,12 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
       const unsigned long long toggle = (unsigned long long)((G >> 1) & 1u) << 63;
       double* myslot = ps.slot_rows + ((size_t)par * 64 + wg) * PNB;
       if (holder) {
+        // only the columns s.. of the row are read (the pivot and the update's row): the quarters left of
+        // column s publish nothing
+        if (HC * h + HC > s) {
 #pragma unroll
-        for (int c = 0; c < HC; ++c) relaxed_store(myslot + HC * h + c, d[c]);
+          for (int c = 0; c < HC; ++c) relaxed_store(myslot + HC * h + c, d[c]);
+        }
         wait_stores_done();
       }
       __syncthreads();
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
           if (k2 >= 0 && (ck < 0 || v2 > cv || (v2 == cv && k2 < ck))) { cv = v2; ck = k2; cw = w2; }
         }
         const double* win = ps.slot_rows + ((size_t)par * 64 + cw) * PNB;
-        s_u[lane] = relaxed_load(win + lane);
+        s_u[lane] = relaxed_load(win + lane);  // (columns left of s: stale, never read)
         s_u[lane + 64] = relaxed_load(win + lane + 64);
         if (lane == 0) s_win = ck;
       }
