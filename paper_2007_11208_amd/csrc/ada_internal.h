@@ -212,9 +212,12 @@ struct PanelScratch {
 hipError_t launch_getrf_panel(int n, int k0, int nbw, double* W, int ldw, int* ipiv, DevRec* rec, PanelScratch ps,
                               hipStream_t st);
 hipError_t launch_panel_reset(PanelScratch ps, hipStream_t st);
-hipError_t launch_laswp_moves(int n, int k0, int nbw, double* W, int ldw, const int* moves, int* perm,
-                              DevRec* rec, hipStream_t st);
-hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st);
+// the panel's row moves applied to columns [a0, a1) and [b0, b1); with_perm: to the permutation too
+hipError_t launch_laswp_moves(int a0, int a1, int b0, int b1, bool with_perm, double* W, int ldw, const int* moves,
+                              int* perm, DevRec* rec, hipStream_t st);
+// U12 = L11^{-1} A12 for the ncols columns starting first columns right of the panel
+hipError_t launch_trsm_llnu(int k0, int nbw, int first, int ncols, double* W, int ldw, const DevRec* rec,
+                            hipStream_t st);
 
 // Cholesky
 hipError_t launch_potrf_diag(int k0, int nbw, double* W, int ldw, DevRec* rec, hipStream_t st);

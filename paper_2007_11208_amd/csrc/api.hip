@@ -35,6 +35,7 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 constexpr int kNB = 128;          // LU / Cholesky block width
+constexpr int kMovesInts = 1 + 2 * 256;  // a panel's row-move list: count, then (destination, source) pairs
 constexpr int kDenseMax = 16384;  // dense routes: the panel kernel spreads at most 64 x 256 rows
 constexpr int kBandKdMax = 31;    // band kernels: kl + ku
 constexpr int kBandDenseMax = 4096;  // band-layout input expanded to dense when needed (not banded / SVD)
@@ -129,7 +130,7 @@ bool make_plan(int n, int nrhs, const ada_opts& o, Plan& p) {
     p.tau = take(cur, N * 8);
     p.recs = take(cur, 2 * 64 * 2 * 8);
     p.slot_rows = take(cur, (size_t)2 * 64 * 128 * 8);
-    p.moves = take(cur, (1 + 2 * 256) * 4);
+    p.moves = take(cur, 2 * kMovesInts * 4);
     if (p.band) p.Adense = take(cur, N * N * 8);  // dense expansion of band-layout input
     if (o.precision == ADA_PREC_BF16_IR) {
       // GMRES correction solves: the Krylov bases of every right-hand side, the work vectors, the
@@ -404,35 +405,50 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
   PanelScratch ps{s.at<unsigned long long>(s.p.recs), s.at<double>(s.p.slot_rows),
                   s.at<int>(s.p.moves)};
   HIPCHK(launch_panel_reset(ps, s.st));
-  // look-ahead: the trailing update of block k is split into the next block column (on st, ahead of
-  // panel k+1) and the rest (on the side stream, alongside panel k+1); the interchanges of panel k+1
-  // wait for the rest, since they move rows in every column
+  // look-ahead: after panel k, only the next block column takes its interchanges, its block row of U
+  // and its trailing update on st, ahead of panel k+1; the interchanges, the block row of U and the
+  // trailing update of every other column go on the side stream alongside panel k+1 (disjoint
+  // columns), which st joins after panel k+1. The panels' row-move lists alternate between two
+  // buffers, so that panel k+1 does not overwrite the list the side stream is still reading.
   bool pending = false;
-  for (int k0 = 0; k0 < n; k0 += kNB) {
+  int kb = 0;
+  for (int k0 = 0; k0 < n; k0 += kNB, ++kb) {
     const int nbw = n - k0 < kNB ? n - k0 : kNB;
     const double m = (double)(n - k0), b = (double)nbw;
+    PanelScratch pk = ps;
+    pk.moves = ps.moves + (kb & 1) * kMovesInts;
     // panel: sum over its columns s of 2 (m - s - 1)(b - s - 1) + (m - s - 1); reads and writes m x b
     const double pfl = b * (b - 1) * (3.0 * m - b - 1) / 3.0 + b * m - b * (b + 1) / 2.0;
     HIPCHK(s.timed(ADA_KF_PANEL, pfl, 16.0 * m * b,
-                   [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, ps, s.st); }));
+                   [&] { return launch_getrf_panel(n, k0, nbw, W, ldw, ipiv, s.rec, pk, s.st); }));
     if (pending) TRY(s.join());
     pending = false;
-    HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * (n - nbw),
-                   [&] { return launch_laswp_moves(n, k0, nbw, W, ldw, ps.moves, perm, s.rec, s.st); }));
     const int rest = n - k0 - nbw;
+    const int nb2 = rest < kNB ? rest : kNB;
+    const int c1 = k0 + nbw, c2 = c1 + nb2;  // the next block column: [c1, c2)
+    HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * nb2, [&] {
+      return launch_laswp_moves(c1, c2, 0, 0, true, W, ldw, pk.moves, perm, s.rec, s.st);
+    }));
+    const double* L21 = W + c1 + (size_t)k0 * ldw;
     if (rest > 0) {
-      HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * rest, 8.0 * (b * b / 2.0 + 2.0 * b * rest),
-                     [&] { return launch_trsm_llnu(k0, nbw, rest, W, ldw, s.rec, s.st); }));
-      const double* L21 = W + (k0 + nbw) + (size_t)k0 * ldw;
-      const double* U12 = W + k0 + (size_t)(k0 + nbw) * ldw;
-      double* A22 = W + (k0 + nbw) + (size_t)(k0 + nbw) * ldw;
-      const int nb2 = rest < kNB ? rest : kNB;
-      TRY(s.gemm(rest, nb2, nbw, L21, ldw, U12, ldw, false, A22, ldw, false));
+      HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * nb2, 8.0 * (b * b / 2.0 + 2.0 * b * nb2),
+                     [&] { return launch_trsm_llnu(k0, nbw, 0, nb2, W, ldw, s.rec, s.st); }));
+      TRY(s.gemm(rest, nb2, nbw, L21, ldw, W + k0 + (size_t)c1 * ldw, ldw, false, W + c1 + (size_t)c1 * ldw, ldw,
+                 false));
+    }
+    TRY(s.fork());
+    HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * (n - nbw - nb2), [&] {
+      return launch_laswp_moves(0, k0, c2, n, false, W, ldw, pk.moves, perm, s.rec, s.ctx->side);
+    }, s.ctx->side));
+    pending = true;
+    if (rest > 0) {
       if (rest > nb2) {
-        TRY(s.fork());
-        TRY(s.gemm(rest, rest - nb2, nbw, L21, ldw, U12 + (size_t)nb2 * ldw, ldw, false, A22 + (size_t)nb2 * ldw, ldw,
-                   false, s.ctx->side));
-        pending = true;
+        const double r2 = (double)(rest - nb2);
+        HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * r2, 8.0 * (b * b / 2.0 + 2.0 * b * r2), [&] {
+          return launch_trsm_llnu(k0, nbw, nb2, rest - nb2, W, ldw, s.rec, s.ctx->side);
+        }, s.ctx->side));
+        TRY(s.gemm(rest, rest - nb2, nbw, L21, ldw, W + k0 + (size_t)c2 * ldw, ldw, false,
+                   W + c1 + (size_t)c2 * ldw, ldw, false, s.ctx->side));
       }
     }
   }

@@ -286,11 +286,12 @@ hipError_t launch_panel_reset(PanelScratch ps, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Apply the panel's row moves to all columns outside the panel (32 per
-// workgroup) and, in workgroup 0, to the permutation vector.
-__global__ __launch_bounds__(256) void k_laswp_moves(int n, int k0, int nbw, double* __restrict__ W, int ldw,
-                                                     const int* __restrict__ moves, int* __restrict__ perm,
-                                                     DevRec* rec) {
+// Apply the panel's row moves to the columns [a0, a1) and [b0, b1) (32 per workgroup; the panel's own
+// columns are never among them) and, when `with_perm`, in workgroup 0 to the permutation vector. The
+// next block column and the rest are separate launches, so that only the former sits between two panels.
+__global__ __launch_bounds__(256) void k_laswp_moves(int a0, int a1, int b0, int b1, int with_perm,
+                                                     double* __restrict__ W, int ldw, const int* __restrict__ moves,
+                                                     int* __restrict__ perm, DevRec* rec) {
   if (rec->stop) return;
   if (rec->info != INT_MAX) {
     // the panel met an exact zero pivot: the routed solve has failed; later kernels skip
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(256) void k_laswp_moves(int n, int k0, int nbw, dou
   __shared__ double sv[2 * PNB][33];
   __shared__ int sp[2 * PNB];
   const int t = threadIdx.x;
-  const int outside = n - nbw;
+  const int na = a1 - a0, outside = na + (b1 - b0);
   const int c0 = blockIdx.x * 32;
   if (c0 < outside) {
     for (int mi = t; mi < cnt; mi += blockDim.x) {
@@ -310,12 +311,12 @@ __global__ __launch_bounds__(256) void k_laswp_moves(int n, int k0, int nbw, dou
       for (int c = 0; c < 32; ++c) {
         const int oc = c0 + c;
         if (oc >= outside) break;
-        const int col = oc < k0 ? oc : oc + nbw;
+        const int col = oc < na ? a0 + oc : b0 + (oc - na);
         sv[mi][c] = W[(size_t)src + (size_t)col * ldw];
       }
     }
   }
-  if (blockIdx.x == 0)
+  if (with_perm && blockIdx.x == 0)
     for (int mi = t; mi < cnt; mi += blockDim.x) sp[mi] = perm[moves[2 + 2 * mi]];
   __syncthreads();
   if (c0 < outside) {
@@ -324,21 +325,24 @@ __global__ __launch_bounds__(256) void k_laswp_moves(int n, int k0, int nbw, dou
       for (int c = 0; c < 32; ++c) {
         const int oc = c0 + c;
         if (oc >= outside) break;
-        const int col = oc < k0 ? oc : oc + nbw;
+        const int col = oc < na ? a0 + oc : b0 + (oc - na);
         W[(size_t)dst + (size_t)col * ldw] = sv[mi][c];
       }
     }
   }
-  if (blockIdx.x == 0)
+  if (with_perm && blockIdx.x == 0)
     for (int mi = t; mi < cnt; mi += blockDim.x) perm[moves[1 + 2 * mi]] = sp[mi];
 }
 
-hipError_t launch_laswp_moves(int n, int k0, int nbw, double* W, int ldw, const int* moves, int* perm,
-                              DevRec* rec, hipStream_t st) {
-  const int outside = n - nbw;
+hipError_t launch_laswp_moves(int a0, int a1, int b0, int b1, bool with_perm, double* W, int ldw, const int* moves,
+                              int* perm, DevRec* rec, hipStream_t st) {
+  if (a1 < a0 || b1 < b0) return hipErrorInvalidValue;
+  const int outside = (a1 - a0) + (b1 - b0);
+  if (outside == 0 && !with_perm) return hipSuccess;
   int grid = (outside + 31) / 32;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_laswp_moves, dim3(grid), dim3(256), 0, st, n, k0, nbw, W, ldw, moves, perm, rec);
+  hipLaunchKernelGGL(k_laswp_moves, dim3(grid), dim3(256), 0, st, a0, a1, b0, b1, (int)with_perm, W, ldw, moves, perm,
+                     rec);
   return hipGetLastError();
 }
 

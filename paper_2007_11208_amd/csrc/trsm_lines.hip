@@ -2,7 +2,10 @@
 //   LU (Section II-D)         U12 = L11^{-1} A12, L11 unit lower: every column of A12 is a line;
 //   Cholesky (Section II-C)   L21 = A21 L11^{-T}: every row of A21 is a line (x L11^T = a).
 // Both are forward substitution with the lower-triangular L11 on each line:
-//   for i: v_i /= L(i,i) (non-unit only); v_r -= L(r,i) v_i for r > i.
+//   for i: v_i *= 1 / L(i,i) (non-unit only); v_r -= L(r,i) v_i for r > i.
+// The non-unit solve multiplies by the reciprocals of the diagonal (computed once per workgroup, as
+// LAPACK's triangular solve does it), so that a step is as short as the unit one and the whole loop
+// unrolls with constant register indices.
 // Eight threads share a line (thread g holds elements g, g+8, ..., g+120 in
 // registers), 32 lines per workgroup, so a 128 x 8064 block fills the chip;
 // L11 sits in LDS transposed (LDS row i = column i of L11), the solved v_i goes
@@ -20,8 +23,8 @@ constexpr int TLK = TLB / TLG;     // elements per thread
 constexpr int TLL = 256 / TLG;     // lines per workgroup
 
 template <bool LINE_IS_ROW, bool UNIT>
-__global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int nlines, double* __restrict__ W, int ldw,
-                                                    const DevRec* rec) {
+__global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int first, int nlines, double* __restrict__ W,
+                                                    int ldw, const DevRec* rec) {
   if (rec->stop) return;
   extern __shared__ double sL[];  // sL[i * TLB + r] = L11(r, i), r >= i; identity padding past nbw
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -44,9 +47,11 @@ __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int nlines,
   }
   // element i of this line
   auto at = [&](int i) -> double* {
-    return LINE_IS_ROW ? W + (size_t)(k0 + nbw + line) + (size_t)(k0 + i) * ldw
-                       : W + (size_t)(k0 + i) + (size_t)(k0 + nbw + line) * ldw;
+    return LINE_IS_ROW ? W + (size_t)(k0 + nbw + first + line) + (size_t)(k0 + i) * ldw
+                       : W + (size_t)(k0 + i) + (size_t)(k0 + nbw + first + line) * ldw;
   };
+  __shared__ double s_rd[TLB];  // 1 / L11(i, i) (non-unit)
+  if (!UNIT && t < TLB) s_rd[t] = t < nbw ? 1.0 / W[(size_t)(k0 + t) + (size_t)(k0 + t) * ldw] : 1.0;
   double v[TLK];
 #pragma unroll
   for (int k = 0; k < TLK; ++k) {
@@ -59,7 +64,7 @@ __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int nlines,
     const int ki = i / TLG, gi = i % TLG;
     double xi = v[ki];
     if (!UNIT) {
-      xi = xi / sL[i * TLB + i];
+      xi = xi * s_rd[i];
       v[ki] = (g == gi) ? xi : v[ki];
     }
     const int src = LINE_IS_ROW ? (li + 8 * gi) : (gi + 8 * li);
@@ -81,7 +86,8 @@ __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int nlines,
 }
 
 template <bool LINE_IS_ROW, bool UNIT>
-static hipError_t launch_lines(int k0, int nbw, int nlines, double* W, int ldw, const DevRec* rec, hipStream_t st) {
+static hipError_t launch_lines(int k0, int nbw, int first, int nlines, double* W, int ldw, const DevRec* rec,
+                               hipStream_t st) {
   if (nlines <= 0) return hipSuccess;
   if (nbw > TLB) return hipErrorInvalidValue;
   const size_t lds = (size_t)TLB * TLB * sizeof(double);
@@ -89,16 +95,17 @@ static hipError_t launch_lines(int k0, int nbw, int nlines, double* W, int ldw, 
   hipError_t e = ensure_lds((const void*)k_trsm_lines<LINE_IS_ROW, UNIT>, lds, done);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_trsm_lines<LINE_IS_ROW, UNIT>), dim3((nlines + TLL - 1) / TLL), dim3(256), lds, st, k0, nbw,
-                     nlines, W, ldw, rec);
+                     first, nlines, W, ldw, rec);
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const DevRec* rec, hipStream_t st) {
-  return launch_lines<false, true>(k0, nbw, ncols, W, ldw, rec, st);
+hipError_t launch_trsm_llnu(int k0, int nbw, int first, int ncols, double* W, int ldw, const DevRec* rec,
+                            hipStream_t st) {
+  return launch_lines<false, true>(k0, nbw, first, ncols, W, ldw, rec, st);
 }
 
 hipError_t launch_trsm_rltn(int k0, int nbw, int mrows, double* W, int ldw, const DevRec* rec, hipStream_t st) {
-  return launch_lines<true, false>(k0, nbw, mrows, W, ldw, rec, st);
+  return launch_lines<true, false>(k0, nbw, 0, mrows, W, ldw, rec, st);
 }
 
 }  // namespace ada
