@@ -286,9 +286,10 @@ hipError_t launch_panel_reset(PanelScratch ps, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Apply the panel's row moves to the columns [a0, a1) and [b0, b1) (32 per workgroup; the panel's own
+// Apply the panel's row moves to the columns [a0, a1) and [b0, b1) (LCW per workgroup; the panel's own
 // columns are never among them) and, when `with_perm`, in workgroup 0 to the permutation vector. The
 // next block column and the rest are separate launches, so that only the former sits between two panels.
+constexpr int LCW = 8;  // columns per workgroup: the next block column alone spreads over 16 workgroups
 __global__ __launch_bounds__(256) void k_laswp_moves(int a0, int a1, int b0, int b1, int with_perm,
                                                      double* __restrict__ W, int ldw, const int* __restrict__ moves,
                                                      int* __restrict__ perm, DevRec* rec) {
@@ -300,15 +301,15 @@ __global__ __launch_bounds__(256) void k_laswp_moves(int a0, int a1, int b0, int
   }
   const int cnt = moves[0];
   if (cnt == 0) return;
-  __shared__ double sv[2 * PNB][33];
+  __shared__ double sv[2 * PNB][LCW + 1];
   __shared__ int sp[2 * PNB];
   const int t = threadIdx.x;
   const int na = a1 - a0, outside = na + (b1 - b0);
-  const int c0 = blockIdx.x * 32;
+  const int c0 = blockIdx.x * LCW;
   if (c0 < outside) {
     for (int mi = t; mi < cnt; mi += blockDim.x) {
       const int src = moves[2 + 2 * mi];
-      for (int c = 0; c < 32; ++c) {
+      for (int c = 0; c < LCW; ++c) {
         const int oc = c0 + c;
         if (oc >= outside) break;
         const int col = oc < na ? a0 + oc : b0 + (oc - na);
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(256) void k_laswp_moves(int a0, int a1, int b0, int
   if (c0 < outside) {
     for (int mi = t; mi < cnt; mi += blockDim.x) {
       const int dst = moves[1 + 2 * mi];
-      for (int c = 0; c < 32; ++c) {
+      for (int c = 0; c < LCW; ++c) {
         const int oc = c0 + c;
         if (oc >= outside) break;
         const int col = oc < na ? a0 + oc : b0 + (oc - na);
@@ -339,7 +340,7 @@ hipError_t launch_laswp_moves(int a0, int a1, int b0, int b1, bool with_perm, do
   if (a1 < a0 || b1 < b0) return hipErrorInvalidValue;
   const int outside = (a1 - a0) + (b1 - b0);
   if (outside == 0 && !with_perm) return hipSuccess;
-  int grid = (outside + 31) / 32;
+  int grid = (outside + LCW - 1) / LCW;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_laswp_moves, dim3(grid), dim3(256), 0, st, a0, a1, b0, b1, (int)with_perm, W, ldw, moves, perm,
                      rec);

@@ -8,7 +8,8 @@
 // unrolls with constant register indices.
 // Eight threads share a line (thread g holds elements g, g+8, ..., g+120 in
 // registers), 32 lines per workgroup, so a 128 x 8064 block fills the chip;
-// L11 sits in LDS transposed (LDS row i = column i of L11), the solved v_i goes
+// L11's lower triangle sits in LDS packed by columns (66 KB, so that a workgroup fits beside one of the
+// trailing update's: the Cholesky's block solve runs while that update is in flight), the solved v_i goes
 // to the line's other threads with one cross-lane read, and the loop over i is
 // unrolled so that every register index is a constant. Lanes are laid out so
 // that the loads and stores of the block are coalesced: consecutive lanes hold
@@ -21,12 +22,15 @@ constexpr int TLB = 128;           // block width (the factorisation's panel wid
 constexpr int TLG = 8;             // threads per line
 constexpr int TLK = TLB / TLG;     // elements per thread
 constexpr int TLL = 256 / TLG;     // lines per workgroup
+// start of column i of the packed lower triangle (columns of TLB - i entries)
+__host__ __device__ constexpr int tri_col(int i) { return i * TLB - i * (i - 1) / 2; }
+constexpr int TLPACK = tri_col(TLB);  // 8256 doubles
 
 template <bool LINE_IS_ROW, bool UNIT>
 __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int first, int nlines, double* __restrict__ W,
                                                     int ldw, const DevRec* rec) {
   if (rec->stop) return;
-  extern __shared__ double sL[];  // sL[i * TLB + r] = L11(r, i), r >= i; identity padding past nbw
+  extern __shared__ double sL[];  // sL[tri_col(i) + r - i] = L11(r, i), r >= i; identity padding past nbw
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int g = LINE_IS_ROW ? (lane >> 3) : (lane & 7);
   const int li = LINE_IS_ROW ? (lane & 7) : (lane >> 3);
@@ -43,7 +47,10 @@ __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int first, 
       tmp[u] = x;
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) sL[e0 + 256 * u] = tmp[u];
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u, r = e % TLB, i = e / TLB;
+      if (r >= i) sL[tri_col(i) + r - i] = tmp[u];
+    }
   }
   // element i of this line
   auto at = [&](int i) -> double* {
@@ -69,7 +76,9 @@ __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int first, 
     }
     const int src = LINE_IS_ROW ? (li + 8 * gi) : (gi + 8 * li);
     xi = __shfl(xi, src, 64);
-    const double* Li = sL + i * TLB;
+    // column i from row 0 on: the rows above i that the lanes below read there belong to column i - 1,
+    // and their products are discarded (g <= gi in the first element block)
+    const double* Li = sL + tri_col(i) - i;
 #pragma unroll
     for (int k = ki; k < TLK; ++k) {
       const double l = Li[g + TLG * k];
@@ -90,7 +99,7 @@ static hipError_t launch_lines(int k0, int nbw, int first, int nlines, double* W
                                hipStream_t st) {
   if (nlines <= 0) return hipSuccess;
   if (nbw > TLB) return hipErrorInvalidValue;
-  const size_t lds = (size_t)TLB * TLB * sizeof(double);
+  const size_t lds = (size_t)TLPACK * sizeof(double);
   static size_t done = 0;
   hipError_t e = ensure_lds((const void*)k_trsm_lines<LINE_IS_ROW, UNIT>, lds, done);
   if (e != hipSuccess) return e;
