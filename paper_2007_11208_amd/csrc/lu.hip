@@ -113,7 +113,7 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
   int pos = rvalid ? prow : INT_MAX;
 
   __shared__ double s_u[PNB];
-  __shared__ double s_l[PROWS];
+  __shared__ double s_x[2][PROWS];  // column s of every row, from the quarter holding it (by column parity)
   __shared__ double s_cv[4];
   __shared__ int s_cp[4];
   __shared__ int s_win;
@@ -140,6 +140,7 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
       double v = -1.0;
       int key = -1;
       const double x = get_col(d, sl);
+      s_x[par][r] = x;  // read by every quarter after the exchange's barrier: each forms the multiplier itself
       if (rvalid && pos >= s) {
         v = fabs(x);
         key = pos;
@@ -234,16 +235,12 @@ __global__ __launch_bounds__(PTH) void k_getrf_panel(int n, int k0, int nbw, dou
     if (is_win) pos = s;
     const double piv = s_u[s];
     if (piv == 0.0 && wg == 0 && t == 0) atomicMin(&rec->info, k0 + s + 1);  // exact zero pivot: failure
-    // 5. multiplier in the current quarter, to the other quarters through LDS; rank-1 update
+    // 5. multiplier (every quarter forms it from column s of its row, written before the barriers above),
+    //    rank-1 update; the next column's LDS writes are separated from these reads by its first barrier
+    //    (s_u, s_cv) or go to the other parity's buffer (s_x)
     const bool active = piv != 0.0 && rvalid && pos > s;
-    if (cur) {
-      const double x = get_col(d, sl);
-      const double l = active ? x / piv : 0.0;
-      if (active) set_col(d, sl, l);
-      s_l[r] = l;
-    }
-    __syncthreads();
-    const double l = s_l[r];  // 0 for rows that are not updated: the update is then exact no-op
+    const double l = active ? s_x[par][r] / piv : 0.0;  // 0 for rows that are not updated: exact no-op
+    if (cur && active) set_col(d, sl, l);
     if (h > hc) update_from(d, 0, l, s_u + HC * h);
     else if (cur && sl + 1 < HC) update_from(d, sl + 1, l, s_u + HC * h);
   }
