@@ -1,4 +1,4 @@
-// Block triangular solves inside the blocked factorisations:
+// Block triangular solves inside the blocked factorisations (k_trsm_cols below takes the LU's):
 //   LU (Section II-D)         U12 = L11^{-1} A12, L11 unit lower: every column of A12 is a line;
 //   Cholesky (Section II-C)   L21 = A21 L11^{-T}: every row of A21 is a line (x L11^T = a).
 // Both are forward substitution with the lower-triangular L11 on each line:
@@ -94,6 +94,80 @@ __global__ __launch_bounds__(256) void k_trsm_lines(int k0, int nbw, int first, 
   }
 }
 
+// LU's U12 = L11^{-1} A12 (unit lower): a column of A12 is contiguous, so sixteen threads share one, a
+// whole 16-lane row of the wave (thread g holds elements g, g+16, ..., g+112), and the solved v_i reaches
+// the other fifteen by a DPP row broadcast instead of a cross-lane read through the LDS crossbar: the
+// step's latency is a register move, not an LDS round trip. The steps are a template recursion so that
+// each broadcast's source lane is a constant.
+constexpr int TCG = 16;           // threads per column
+constexpr int TCK = TLB / TCG;    // elements per thread
+constexpr int TCL = 256 / TCG;    // columns per workgroup
+
+// lane G of each 16-lane row, to the whole row
+template <int G>
+__device__ __forceinline__ double row_bcast(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + G, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + G, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int I>
+__device__ __forceinline__ void cols_step(double (&v)[TCK], int g, const double* sL) {
+  if constexpr (I < TLB) {
+    constexpr int ki = I / TCG, gi = I % TCG;
+    const double xi = row_bcast<gi>(v[ki]);
+    const double* Li = sL + tri_col(I) - I;  // as in k_trsm_lines: rows above I are discarded
+#pragma unroll
+    for (int k = ki; k < TCK; ++k) {
+      const double l = Li[g + TCG * k];
+      if (k == ki) v[k] = (g > gi) ? fma(-l, xi, v[k]) : v[k];
+      else v[k] = fma(-l, xi, v[k]);
+    }
+    cols_step<I + 1>(v, g, sL);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trsm_cols(int k0, int nbw, int first, int ncols, double* __restrict__ W,
+                                                   int ldw, const DevRec* rec) {
+  if (rec->stop) return;
+  extern __shared__ double sL[];  // packed L11 as in k_trsm_lines
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane & 15;
+  const int col = blockIdx.x * TCL + w * 4 + (lane >> 4);
+  const bool live = col < ncols;
+  for (int e0 = t; e0 < TLB * TLB; e0 += 256 * 16) {
+    double tmp[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u, r = e % TLB, i = e / TLB;
+      double x = (r == i) ? 1.0 : 0.0;
+      if (r >= i && r < nbw && i < nbw) x = W[(size_t)(k0 + r) + (size_t)(k0 + i) * ldw];
+      tmp[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u, r = e % TLB, i = e / TLB;
+      if (r >= i) sL[tri_col(i) + r - i] = tmp[u];
+    }
+  }
+  double* x = W + k0 + (size_t)(k0 + nbw + first + (live ? col : 0)) * ldw;
+  double v[TCK];
+#pragma unroll
+  for (int k = 0; k < TCK; ++k) {
+    const int i = g + TCG * k;
+    v[k] = (live && i < nbw) ? x[i] : 0.0;
+  }
+  __syncthreads();
+  cols_step<0>(v, g, sL);  // every lane of a row takes part (a row is one column, live or not)
+  if (!live) return;
+#pragma unroll
+  for (int k = 0; k < TCK; ++k) {
+    const int i = g + TCG * k;
+    if (i < nbw) x[i] = v[k];
+  }
+}
+
 template <bool LINE_IS_ROW, bool UNIT>
 static hipError_t launch_lines(int k0, int nbw, int first, int nlines, double* W, int ldw, const DevRec* rec,
                                hipStream_t st) {
@@ -110,7 +184,15 @@ static hipError_t launch_lines(int k0, int nbw, int first, int nlines, double* W
 
 hipError_t launch_trsm_llnu(int k0, int nbw, int first, int ncols, double* W, int ldw, const DevRec* rec,
                             hipStream_t st) {
-  return launch_lines<false, true>(k0, nbw, first, ncols, W, ldw, rec, st);
+  if (ncols <= 0) return hipSuccess;
+  if (nbw > TLB) return hipErrorInvalidValue;
+  const size_t lds = (size_t)TLPACK * sizeof(double);
+  static size_t done = 0;
+  hipError_t e = ensure_lds((const void*)k_trsm_cols, lds, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_trsm_cols, dim3((ncols + TCL - 1) / TCL), dim3(256), lds, st, k0, nbw, first, ncols, W, ldw,
+                     rec);
+  return hipGetLastError();
 }
 
 hipError_t launch_trsm_rltn(int k0, int nbw, int mrows, double* W, int ldw, const DevRec* rec, hipStream_t st) {
