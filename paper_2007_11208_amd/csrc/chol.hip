@@ -13,12 +13,11 @@
 namespace ada {
 
 // Diagonal block (nbw <= 128) in LDS, in sub-blocks of 32 columns:
-//   1. wave 0 factors the 32x32 diagonal sub-block, two lanes per row (each
-//      with 16 of its columns in registers): the pivot of column j comes by
-//      readlane, the scaled column goes through LDS and every lane reads the
-//      entries it needs as broadcasts (the 32 steps need no barrier and keep
-//      scalar registers free); the reciprocals of the diagonal go to LDS for
-//      step 2;
+//   1. wave 0 factors the 32x32 diagonal sub-block, one lane per row with its
+//      32 columns in registers: the pivot of column j comes by readlane, the
+//      scaled column through LDS as broadcast reads (the 32 steps need no
+//      barrier of the workgroup); the reciprocals of the diagonal go to LDS
+//      for step 2;
 //   2. the rows below solve x L_kk^T = a (one thread per row, L_kk and the
 //      reciprocals of its diagonal from LDS, as LAPACK's triangular solve
 //      does it: multiply by the reciprocal);
@@ -91,50 +90,49 @@ __global__ __launch_bounds__(256) void k_potrf_diag(int k0, int nbw, double* __r
     }
   }
   __shared__ int s_fail;
-  __shared__ double s_col[PB];   // the column being scaled (step 1)
   __shared__ double s_rinv[PB];  // reciprocals of the sub-block's diagonal (step 2)
+  __shared__ double s_col[PB];   // the column being scaled (step 1)
   if (t == 0) s_fail = 0;
   __syncthreads();
   for (int kb = 0; kb < nbw; kb += PB) {
     const int cb = min(PB, nbw - kb);
-    // 1. diagonal sub-block: wave 0, lane = (row i, half h) holding the row's columns 16h .. 16h+15
+    // 1. diagonal sub-block: wave 0, lane i < 32 holding row i's 32 columns (lanes 32-63 repeat rows 0-31
+    //    and store nothing): A(i, c) -= L(i, j) L(c, j) for c > j, L(c, j) read from LDS where lane c
+    //    wrote it. Entries right of a row's diagonal take the same arithmetic and are never stored.
     if (w == 0) {
-      // the lane index through an opaque zero: the per-lane masks below are then formed where they are
-      // used instead of being hoisted out of the sub-block loop into scalar registers
-      const int ln = lane + opaque_zero();
-      const int i = ln & 31, h = ln >> 5;
-      double v[PB / 2];
+      const int i = lane & 31;
+      double v[PB];
 #pragma unroll
-      for (int c = 0; c < PB / 2; ++c)
-        v[c] = (i < cb && 16 * h + c <= i) ? sA[(kb + 16 * h + c) * ld + kb + i] : 0.0;
+      for (int c = 0; c < PB; ++c) v[c] = (i < cb && c <= i) ? sA[(kb + c) * ld + kb + i] : 0.0;
       int fail = 0;
 #pragma unroll
       for (int j = 0; j < PB; ++j) {
-        const int hj = j >> 4, cj = j & 15;
         if (j < cb && !fail) {
-          const double dj = read_lane(v[cj], j + 32 * hj);
+          const double dj = read_lane(v[j], j);
           if (!(dj > 0.0)) {
             fail = j + 1;
           } else {
-            const double sd = sqrt(dj);
-            if (h == hj) {
-              const double l = (i == j) ? sd : (i > j ? v[cj] / sd : v[cj]);
-              v[cj] = l;
-              s_col[i] = l;
-            }
-            if (ln == 0) s_rinv[j] = 1.0 / sd;
-            __builtin_amdgcn_wave_barrier();
-            const double lij = s_col[i];
-            // columns right of j: all of the upper half when j is in the lower one, the rest of j's half
+            // 1/sqrt(dj) by the hardware estimate and two Newton steps (each doubles the correct bits of the
+            // estimate; the second ends at rounding level), so the step's dependent chain is a few FMAs
+            // instead of a correctly rounded square root followed by a division; sqrt(dj) = dj / sqrt(dj).
+            // Pivots below 1e-300 (where the estimate loses range) take the square root and the division.
+            double ri, sd;
+            if (dj >= 1e-300) {
+              ri = __builtin_amdgcn_rsq(dj);
 #pragma unroll
-            for (int c = 0; c < PB / 2; ++c) {
-              if (c > cj) {
-                if (hj == 0) v[c] = fma(-lij, s_col[16 * h + c], v[c]);
-                else if (h == 1) v[c] = fma(-lij, s_col[16 + c], v[c]);
-              } else if (hj == 0 && h == 1) {
-                v[c] = fma(-lij, s_col[16 + c], v[c]);
-              }
+              for (int it = 0; it < 2; ++it) ri = fma(0.5 * ri, fma(-dj * ri, ri, 1.0), ri);
+              sd = dj * ri;
+            } else {
+              sd = sqrt(dj);
+              ri = 1.0 / sd;
             }
+            const double l = (i == j) ? sd : (i > j ? v[j] * ri : v[j]);
+            v[j] = l;
+            if (lane == 0) s_rinv[j] = ri;
+            s_col[i] = l;  // lanes i and i + 32 write the same value
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = j + 1; c < PB; ++c) v[c] = fma(-l, s_col[c], v[c]);
             __builtin_amdgcn_wave_barrier();
           }
         }
@@ -145,10 +143,10 @@ __global__ __launch_bounds__(256) void k_potrf_diag(int k0, int nbw, double* __r
           rec->stop = 1;
           s_fail = 1;
         }
-      } else if (i < cb) {
+      } else if (lane < 32 && i < cb) {
 #pragma unroll
-        for (int c = 0; c < PB / 2; ++c)
-          if (16 * h + c <= i) sA[(kb + 16 * h + c) * ld + kb + i] = v[c];
+        for (int c = 0; c < PB; ++c)
+          if (c <= i) sA[(kb + c) * ld + kb + i] = v[c];
       }
     }
     __syncthreads();
