@@ -218,6 +218,9 @@ hipError_t launch_laswp_moves(int a0, int a1, int b0, int b1, bool with_perm, do
 // U12 = L11^{-1} A12 for the ncols columns starting first columns right of the panel
 hipError_t launch_trsm_llnu(int k0, int nbw, int first, int ncols, double* W, int ldw, const DevRec* rec,
                             hipStream_t st);
+// the next block column: the panel's row moves on its columns (and on perm), then U12 = L11^{-1} A12
+hipError_t launch_swap_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const int* moves, int* perm,
+                                 DevRec* rec, hipStream_t st);
 
 // Cholesky
 hipError_t launch_potrf_diag(int k0, int nbw, double* W, int ldw, DevRec* rec, hipStream_t st);

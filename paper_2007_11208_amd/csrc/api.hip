@@ -426,13 +426,17 @@ int route_lu(Solve& s, const double* A, int lda, const double* B, int ldb, doubl
     const int rest = n - k0 - nbw;
     const int nb2 = rest < kNB ? rest : kNB;
     const int c1 = k0 + nbw, c2 = c1 + nb2;  // the next block column: [c1, c2)
-    HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 32.0 * b * nb2, [&] {
-      return launch_laswp_moves(c1, c2, 0, 0, true, W, ldw, pk.moves, perm, s.rec, s.st);
-    }));
     const double* L21 = W + c1 + (size_t)k0 * ldw;
-    if (rest > 0) {
-      HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * nb2, 8.0 * (b * b / 2.0 + 2.0 * b * nb2),
-                     [&] { return launch_trsm_llnu(k0, nbw, 0, nb2, W, ldw, s.rec, s.st); }));
+    if (rest == 0) {
+      // last panel: only the permutation takes the moves
+      HIPCHK(s.timed(ADA_KF_LASWP, 0.0, 0.0, [&] {
+        return launch_laswp_moves(c1, c2, 0, 0, true, W, ldw, pk.moves, perm, s.rec, s.st);
+      }));
+    } else {
+      // the next block column's interchanges and its block row of U in one launch
+      HIPCHK(s.timed(ADA_KF_TRSM_BLOCK, b * b * nb2, 8.0 * (b * b / 2.0 + 2.0 * b * nb2) + 32.0 * b * nb2, [&] {
+        return launch_swap_trsm_llnu(k0, nbw, nb2, W, ldw, pk.moves, perm, s.rec, s.st);
+      }));
       TRY(s.gemm(rest, nb2, nbw, L21, ldw, W + k0 + (size_t)c1 * ldw, ldw, false, W + c1 + (size_t)c1 * ldw, ldw,
                  false));
     }

@@ -16,6 +16,8 @@
 // consecutive rows of the matrix in both cases.
 #include "ada_internal.h"
 
+#include <climits>
+
 namespace ada {
 
 constexpr int TLB = 128;           // block width (the factorisation's panel width)
@@ -128,14 +130,45 @@ __device__ __forceinline__ void cols_step(double (&v)[TCK], int g, const double*
   }
 }
 
+// SWAP: the workgroup first applies the panel's row moves (count, then (destination, source) pairs) to
+// its own columns, and workgroup 0 to the permutation vector, so that the next block column's
+// interchanges and its block row of U are one launch (a workgroup owns whole columns: no other
+// workgroup's moves are waited for).
+template <bool SWAP>
 __global__ __launch_bounds__(256) void k_trsm_cols(int k0, int nbw, int first, int ncols, double* __restrict__ W,
-                                                   int ldw, const DevRec* rec) {
+                                                   int ldw, const int* __restrict__ moves, int* __restrict__ perm,
+                                                   DevRec* rec) {
   if (rec->stop) return;
   extern __shared__ double sL[];  // packed L11 as in k_trsm_lines
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int g = lane & 15;
   const int col = blockIdx.x * TCL + w * 4 + (lane >> 4);
   const bool live = col < ncols;
+  if constexpr (SWAP) {
+    if (rec->info != INT_MAX) {
+      // the panel met an exact zero pivot: the routed solve has failed; later kernels skip
+      if (blockIdx.x == 0 && t == 0) rec->stop = 1;
+      return;
+    }
+    __shared__ double s_mv[2 * TLB][TCL + 1];
+    __shared__ int s_pv[2 * TLB];
+    const int cnt = moves[0];
+    const int cb = blockIdx.x * TCL;
+    for (int e = t; e < cnt * TCL; e += 256) {
+      const int mi = e / TCL, c = e % TCL;
+      if (cb + c < ncols) s_mv[mi][c] = W[(size_t)moves[2 + 2 * mi] + (size_t)(k0 + nbw + first + cb + c) * ldw];
+    }
+    if (blockIdx.x == 0)
+      for (int mi = t; mi < cnt; mi += 256) s_pv[mi] = perm[moves[2 + 2 * mi]];
+    __syncthreads();
+    for (int e = t; e < cnt * TCL; e += 256) {
+      const int mi = e / TCL, c = e % TCL;
+      if (cb + c < ncols) W[(size_t)moves[1 + 2 * mi] + (size_t)(k0 + nbw + first + cb + c) * ldw] = s_mv[mi][c];
+    }
+    if (blockIdx.x == 0)
+      for (int mi = t; mi < cnt; mi += 256) perm[moves[1 + 2 * mi]] = s_pv[mi];
+    __syncthreads();  // the moved rows are read below (and L11 is not among them: the panel's own columns)
+  }
   for (int e0 = t; e0 < TLB * TLB; e0 += 256 * 16) {
     double tmp[16];
 #pragma unroll
@@ -188,10 +221,23 @@ hipError_t launch_trsm_llnu(int k0, int nbw, int first, int ncols, double* W, in
   if (nbw > TLB) return hipErrorInvalidValue;
   const size_t lds = (size_t)TLPACK * sizeof(double);
   static size_t done = 0;
-  hipError_t e = ensure_lds((const void*)k_trsm_cols, lds, done);
+  hipError_t e = ensure_lds((const void*)k_trsm_cols<false>, lds, done);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trsm_cols, dim3((ncols + TCL - 1) / TCL), dim3(256), lds, st, k0, nbw, first, ncols, W, ldw,
-                     rec);
+  hipLaunchKernelGGL(k_trsm_cols<false>, dim3((ncols + TCL - 1) / TCL), dim3(256), lds, st, k0, nbw, first, ncols, W,
+                     ldw, (const int*)nullptr, (int*)nullptr, const_cast<DevRec*>(rec));
+  return hipGetLastError();
+}
+
+hipError_t launch_swap_trsm_llnu(int k0, int nbw, int ncols, double* W, int ldw, const int* moves, int* perm,
+                                 DevRec* rec, hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  if (nbw > TLB) return hipErrorInvalidValue;
+  const size_t lds = (size_t)TLPACK * sizeof(double);
+  static size_t done = 0;
+  hipError_t e = ensure_lds((const void*)k_trsm_cols<true>, lds, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_trsm_cols<true>, dim3((ncols + TCL - 1) / TCL), dim3(256), lds, st, k0, nbw, 0, ncols, W, ldw,
+                     moves, perm, rec);
   return hipGetLastError();
 }
 
