@@ -325,7 +325,15 @@ enum {
  * *piece_out and *ms_out (either may be NULL) receive the chosen piece and its time per solve in ms. */
 int ada_autotune_band(ada_ctx ctx, int n, int kl, int ku, int nrhs, void* stream, int* piece_out, double* ms_out);
 
+/* Kernel-family timing: while on != 0, every later solve on ctx brackets each launch of a selected
+ * family (see ada_profile_families) with two HIP events on the stream the launch goes to; the
+ * durations accumulate per family until ada_profile_reset. Each event is a packet in the stream's
+ * queue between dependent kernels, so timing slows the solves a little: select only the families
+ * to be measured. Returns ADA_OK or ADA_ERR_ARG (ctx NULL). */
 int ada_profile_enable(ada_ctx ctx, int on);
+/* The families ada_profile_enable times: bit (1 << ADA_KF_*) set = timed. The default (and the
+ * state after ada_create) is every family. Returns ADA_OK or ADA_ERR_ARG (ctx NULL). */
+int ada_profile_families(ada_ctx ctx, unsigned mask);
 /* kind: ADA_KF_*; any output pointer may be NULL. */
 int ada_profile_read(ada_ctx ctx, int kind, int64_t* launches, double* total_ms, double* total_flops,
                      double* total_bytes);

@@ -128,6 +128,8 @@ def lib() -> ctypes.CDLL:
         L.ada_autotune_batched.restype = i
         L.ada_profile_enable.argtypes = [vp, i]
         L.ada_profile_enable.restype = i
+        L.ada_profile_families.argtypes = [vp, ctypes.c_uint]
+        L.ada_profile_families.restype = i
         L.ada_profile_reset.argtypes = [vp]
         L.ada_profile_reset.restype = i
         L.ada_autotune_band.argtypes = [vp, i, i, i, i, vp, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double)]
@@ -209,7 +211,10 @@ class Context:
         except Exception:
             pass
 
-    def profile(self, on: bool = True):
+    def profile(self, on: bool = True, families=None):
+        """Time kernel launches of the given families (names of KERNEL_FAMILIES; None: all)."""
+        mask = 0xFFFFFFFF if families is None else sum(1 << KERNEL_FAMILIES.index(f) for f in families)
+        lib().ada_profile_families(self.handle, mask)
         lib().ada_profile_enable(self.handle, int(on))
 
     def profile_reset(self):

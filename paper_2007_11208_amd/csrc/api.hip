@@ -191,6 +191,7 @@ struct ada_ctx_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // per-family launch timing (instrumentation)
   bool prof = false;
+  unsigned prof_mask = ~0u;  // kernel families timed while prof is on
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   struct Pending {
@@ -252,7 +253,7 @@ struct Solve {
   // run `launch` (returns hipError_t); when profiling, bracket it with events of family `kind` on stream `on`
   template <class F>
   hipError_t timed(int kind, double flops, double bytes, F&& launch, hipStream_t on = nullptr) {
-    if (kind < 0) return launch();
+    if (kind < 0 || !ctx->prof || !((ctx->prof_mask >> kind) & 1u)) return launch();
     if (!on) on = st;
     const long e0 = ev_record(on);
     const hipError_t e = launch();
@@ -1057,6 +1058,12 @@ int ada_autotune_batched(ada_ctx ctx, int count, const ada_desc* d_desc, const d
 int ada_profile_enable(ada_ctx ctx, int on) {
   if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
   ctx->prof = on != 0;
+  return ADA_OK;
+}
+
+int ada_profile_families(ada_ctx ctx, unsigned mask) {
+  if (!ctx) return fail(ADA_ERR_ARG, "ctx is NULL");
+  ctx->prof_mask = mask;
   return ADA_OK;
 }
 
