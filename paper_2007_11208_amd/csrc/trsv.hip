@@ -277,12 +277,14 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
   double nr[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) nr[k] = (tk > 0) ? near[(16 * cq + k) * LD + lane] : 0.0;
+  // The row is scaled by the reciprocal of its diagonal entry here, so that the substitution's dependent
+  // chain is a readlane and an FMA per step (no multiply by the reciprocal on it).
   double trow[TB];
   double rd = 1.0;
   if (cq == 0) {
-#pragma unroll
-    for (int i = 0; i < TB; ++i) trow[i] = td[i * LD + lane];
     rd = (lane < rows && !unit) ? 1.0 / td[lane * LD + lane] : 1.0;
+#pragma unroll
+    for (int i = 0; i < TB; ++i) trow[i] = td[i * LD + lane] * rd;
   }
   if (tk > 0) {
     wait_flag(bn);
@@ -295,19 +297,18 @@ __global__ __launch_bounds__(256) void k_trsv1(int n, const double* __restrict__
   __syncthreads();
   if (cq == 0) {
     // substitution, lane = row; padded rows (past `rows`) hold zeros and stay zero
-    double a = bval - ((sacc[lane] + sacc[TB + lane]) + (sacc[2 * TB + lane] + sacc[3 * TB + lane]));
+    // a = (b - sum) / T(lane, lane); lane i holds x_i once the steps before i have been applied
+    double a = (bval - ((sacc[lane] + sacc[TB + lane]) + (sacc[2 * TB + lane] + sacc[3 * TB + lane]))) * rd;
     if (eff_lower) {
 #pragma unroll
       for (int i = 0; i < TB; ++i) {
-        const double xi = read_lane(a * rd, i);
-        a = (lane == i) ? xi : a;
+        const double xi = read_lane(a, i);
         a = (lane > i) ? fma(-trow[i], xi, a) : a;
       }
     } else {
 #pragma unroll
       for (int i = TB - 1; i >= 0; --i) {
-        const double xi = read_lane(a * rd, i);
-        a = (lane == i) ? xi : a;
+        const double xi = read_lane(a, i);
         a = (lane < i) ? fma(-trow[i], xi, a) : a;
       }
     }
