@@ -18,8 +18,8 @@ constexpr int TB = 64;
 
 // Several right-hand sides (2..64). The tiles of earlier blocks stream through two LDS buffers (the next
 // tile's loads are in flight while the current one is applied to all columns); the diagonal block is solved
-// by the four waves, each taking every fourth column, lane = row, the lane's row of the diagonal tile and
-// the reciprocal of its diagonal entry in registers, the solved values broadcast by readlane; a wave runs
+// by the four waves, each taking every fourth column, lane = row, the lane's row of the diagonal tile scaled
+// by the reciprocal of its diagonal entry in registers, the solved values broadcast by readlane; a wave runs
 // two of its columns at a time, interleaved step by step, so their broadcasts overlap.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_trsm_dec(
     int n, int nrhs, const double* __restrict__ T, int ldt, int lower,
@@ -119,32 +119,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   store_tile(td);
   __syncthreads();
   {
+    // the row scaled by the reciprocal of its diagonal entry (as in k_trsv1): a step is a readlane and
+    // an FMA per column
+    const double rd = (lane < rows && !unit) ? 1.0 / td[lane * LD + lane] : 1.0;
     double trow[TB];
 #pragma unroll
-    for (int i = 0; i < TB; ++i) trow[i] = td[i * LD + lane];
-    const double rd = (lane < rows && !unit) ? 1.0 / td[lane * LD + lane] : 1.0;
+    for (int i = 0; i < TB; ++i) trow[i] = td[i * LD + lane] * rd;
     // the wave's columns c = w, w + 4, ..., two per pass (their steps interleave)
     for (int c = w; c < nrhs; c += 8) {
       const bool two = c + 4 < nrhs;  // wave-uniform
-      double a0 = acc[c * TB + lane];
-      double a1 = two ? acc[(c + 4) * TB + lane] : 0.0;
+      double a0 = acc[c * TB + lane] * rd;
+      double a1 = two ? acc[(c + 4) * TB + lane] * rd : 0.0;
       if (eff_lower) {
 #pragma unroll
         for (int i = 0; i < TB; ++i) {
-          const double x0 = read_lane(a0 * rd, i);
-          const double x1 = read_lane(a1 * rd, i);
-          a0 = (lane == i) ? x0 : a0;
-          a1 = (lane == i) ? x1 : a1;
+          const double x0 = read_lane(a0, i);
+          const double x1 = read_lane(a1, i);
           a0 = (lane > i) ? fma(-trow[i], x0, a0) : a0;
           a1 = (lane > i) ? fma(-trow[i], x1, a1) : a1;
         }
       } else {
 #pragma unroll
         for (int i = TB - 1; i >= 0; --i) {
-          const double x0 = read_lane(a0 * rd, i);
-          const double x1 = read_lane(a1 * rd, i);
-          a0 = (lane == i) ? x0 : a0;
-          a1 = (lane == i) ? x1 : a1;
+          const double x0 = read_lane(a0, i);
+          const double x1 = read_lane(a1, i);
           a0 = (lane < i) ? fma(-trow[i], x0, a0) : a0;
           a1 = (lane < i) ? fma(-trow[i], x1, a1) : a1;
         }
