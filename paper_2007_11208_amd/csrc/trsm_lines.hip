@@ -1,12 +1,14 @@
-// Block triangular solves inside the blocked factorisations (k_trsm_cols below takes the LU's):
-//   LU (Section II-D)         U12 = L11^{-1} A12, L11 unit lower: every column of A12 is a line;
-//   Cholesky (Section II-C)   L21 = A21 L11^{-T}: every row of A21 is a line (x L11^T = a).
+// Block triangular solves inside the blocked factorisations:
+//   LU (Section II-D)         U12 = L11^{-1} A12, L11 unit lower: every column of A12 is a line
+//                             (k_trsm_cols below);
+//   Cholesky (Section II-C)   L21 = A21 L11^{-T}: every row of A21 is a line, x L11^T = a
+//                             (k_trsm_lines; it can also take columns as lines).
 // Both are forward substitution with the lower-triangular L11 on each line:
 //   for i: v_i *= 1 / L(i,i) (non-unit only); v_r -= L(r,i) v_i for r > i.
 // The non-unit solve multiplies by the reciprocals of the diagonal (computed once per workgroup, as
 // LAPACK's triangular solve does it), so that a step is as short as the unit one and the whole loop
 // unrolls with constant register indices.
-// Eight threads share a line (thread g holds elements g, g+8, ..., g+120 in
+// k_trsm_lines: eight threads share a line (thread g holds elements g, g+8, ..., g+120 in
 // registers), 32 lines per workgroup, so a 128 x 8064 block fills the chip;
 // L11's lower triangle sits in LDS packed by columns (66 KB, so that a workgroup fits beside one of the
 // trailing update's: the Cholesky's block solve runs while that update is in flight), the solved v_i goes
