@@ -3,16 +3,18 @@
 //   k_getrf_panel    factor the m x nb panel W[k0:n, k0:k0+nb] with partial
 //                    pivoting (ties to the lowest row), rows spread over P
 //                    workgroups that keep the panel in registers;
-//   k_laswp_moves    apply the panel's row interchanges to every other column
-//                    (and to the permutation vector used by the solves);
-//   k_trsm_lines     U12 = L11^{-1} A12 (unit lower; trsm_lines.hip);
-//   k_gemm_sub       A22 -= L21 U12 on the matrix cores (gemm.hip).
+//   k_trsm_cols      the next block column: the panel's row interchanges, then
+//                    U12 = L11^{-1} A12 (unit lower; trsm_lines.hip);
+//   k_gemm_sub       its A22 -= L21 U12 on the matrix cores (gemm.hip);
+//   and on a second stream, beside the next panel: k_laswp_moves (the
+//   interchanges of every other column, and of columns left of the panel),
+//   k_trsm_cols and k_gemm_sub for the rest of the trailing matrix.
 //
 // The panel needs one cross-workgroup exchange per column (the pivot search
 // spans all m rows): every workgroup publishes its best candidate and that
-// candidate's row, then all of them meet at a counter; every workgroup then
-// picks the same winner (largest modulus, lowest row on ties) and applies the
-// swap and the rank-1 update to the rows it holds. All waits are bounded.
+// candidate's row, then a record of it (below); every workgroup then picks
+// the same winner (largest modulus, lowest row on ties) and applies the swap
+// and the rank-1 update to the rows it holds. All waits are bounded.
 #include "ada_internal.h"
 
 #include <climits>
